@@ -1,0 +1,102 @@
+/*
+ * Plain CPU oracle for batched CRYSTALS-Dilithium (round-3 parameter sets 2/3/5).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct
+ * definition that the GPU path is checked against.  Only the test suite, the
+ * package's smoke check and the benchmark's CPU-baseline leg may load it; the
+ * product path never calls it and shares no code, header, table or constant
+ * with it.
+ *
+ * Arithmetic is plain int64 with '%' followed by explicit canonicalisation:
+ * no Montgomery, no Barrett, no vector instructions.  Keccak round constants
+ * and rotation offsets are derived at start-up from their FIPS 202
+ * definitions (the rc LFSR and the triangular-number rule), not typed in.
+ *
+ * Citations name the paper's sections, algorithms and tables
+ * ("Alg. 2" = Dilithium.Sign, "Tab. 1" = parameter sets, "Sec. 2.3" =
+ * Preliminaries / Dilithium, "Sec. 2.2" = ring arithmetic and the NTT).
+ * Where the paper is silent the oracle follows the public round-3 (v3.1)
+ * Dilithium specification's byte conventions; each such reading is marked
+ * [R] and listed in the design notes.
+ *
+ * Parity pins (tests under tests/test_oracle_*.py):
+ *   SHAKE128/256            exact vs Python hashlib (FIPS 202)
+ *   NTT / INTT              fast == O(n^2) definition; INTT(NTT(x)) == x;
+ *                           INTT(NTT f o NTT g) == schoolbook negacyclic product
+ *   Power2Round, Decompose  exhaustive identities over all of [0, q)
+ *   MakeHint / UseHint      hint-correctness property over all r
+ *   encodings               pack o unpack == identity, sizes
+ *   scheme                  Verify(Sign) == 1, all single-bit flips rejected,
+ *                           mean Sign loop count vs Sec. 2.3
+ * parity unpinned: the exact byte streams of ExpandA / ExpandS / ExpandMask /
+ *   SampleInBall and the encodings against the official round-3 known-answer
+ *   tests (neither the specification nor its KAT files are available); their
+ *   ranges, counts and distributions are pinned, their nonce and bit-order
+ *   conventions are readings [R].
+ */
+#ifndef DIL_ORACLE_H
+#define DIL_ORACLE_H
+#include <stddef.h>
+#include <stdint.h>
+
+#define ORQ 8380417
+#define ORN 256
+
+typedef struct {
+  int level, k, l, eta, tau, beta, omega;
+  int32_t gamma1, gamma2;
+  int z_bits, w1_bits, eta_bits;
+  size_t pk_bytes, sk_bytes, sig_bytes, w1_poly_bytes;
+} ref_params;
+
+/* parameter set for level 2/3/5 (Tab. 1); returns 0 on success, -1 otherwise */
+int dil_ref_params(int level, ref_params *p);
+
+/* Keccak / SHAKE (Sec. 2.3 "Sampling": SHAKE128/256 as XOF, SHAKE256 as H) */
+void dil_ref_keccak_f1600(uint64_t st[25]);
+void dil_ref_shake128(const uint8_t *in, size_t inlen, uint8_t *out, size_t outlen);
+void dil_ref_shake256(const uint8_t *in, size_t inlen, uint8_t *out, size_t outlen);
+
+/* ring arithmetic (Sec. 2.2) on canonical coefficients in [0, q) */
+void dil_ref_ntt(int32_t a[ORN]);
+void dil_ref_intt(int32_t a[ORN]);
+void dil_ref_ntt_definition(const int32_t a[ORN], int32_t out[ORN]);
+void dil_ref_poly_mul_schoolbook(const int32_t a[ORN], const int32_t b[ORN], int32_t out[ORN]);
+/* c_i = INTT(NTT(a_i) o b_i), b_i read as NTT-domain values; count polys, nthreads workers */
+void dil_ref_ntt_mul_batch(const int32_t *a, const int32_t *b, int32_t *c, size_t count, int nthreads);
+
+/* rounding and hints (Sec. 2.3 "Bits Extraction and Hints"), elementwise over n values */
+void dil_ref_power2round(const int32_t *r, int32_t *r1, int32_t *r0, size_t n);
+void dil_ref_decompose(const int32_t *r, int32_t *r1, int32_t *r0, size_t n, int32_t gamma2);
+void dil_ref_make_hint(const int32_t *z, const int32_t *r, int32_t *h, size_t n, int32_t gamma2);
+void dil_ref_use_hint(const int32_t *h, const int32_t *r, int32_t *out, size_t n, int32_t gamma2);
+
+/* samplers (Sec. 2.3 "Sampling", Alg. 1-2); outputs canonical in [0, q) except where noted */
+void dil_ref_expand_a(int level, const uint8_t rho[32], int32_t *A /* k*l*256 */);
+void dil_ref_expand_a_poly(const uint8_t seed34[34], int32_t out[ORN]);
+void dil_ref_expand_a_polys(const uint8_t *seeds34, int32_t *out, size_t count, int nthreads);
+void dil_ref_expand_s(int level, const uint8_t rhop[64], int32_t *s /* (l+k)*256, centred */);
+void dil_ref_expand_mask(int level, const uint8_t rhop[64], uint32_t kappa, int32_t *y /* l*256, centred */);
+void dil_ref_sample_in_ball(int level, const uint8_t ctilde[32], int32_t c[ORN] /* centred */);
+
+/* generic b-bit LSB-first packing of n coefficients (values must lie in [0, 2^b)) */
+void dil_ref_bitpack(const uint32_t *v, size_t n, int b, uint8_t *out);
+void dil_ref_bitunpack(const uint8_t *in, size_t n, int b, uint32_t *v);
+
+/* scheme (Alg. 1-3), single task */
+int dil_ref_keygen(int level, const uint8_t zeta[32], uint8_t *pk, uint8_t *sk);
+/* returns the number of loop iterations used (>= 1), or -1 on bad level */
+int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, uint8_t *sig);
+/* returns 1 accept, 0 reject, -1 bad level */
+int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen, const uint8_t *sig);
+
+/* batched drivers: same argument conventions as the GPU C-ABI but host pointers, no stream.
+   key_idx may be NULL (task i uses key i).  msg_off has count+1 entries (CSR).
+   iters (optional) receives the Sign loop count per task.  Return 0, or -1 on bad input. */
+int dil_ref_keygen_batch(int level, const uint8_t *seeds, uint8_t *pk, uint8_t *sk, uint32_t count, int nthreads);
+int dil_ref_sign_batch(int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                       const uint64_t *msg_off, uint8_t *sig, uint32_t count, int nthreads, int32_t *iters);
+int dil_ref_verify_batch(int level, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
+                         const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count,
+                         int nthreads);
+#endif

@@ -1,0 +1,124 @@
+"""Oracle Gen / Sign / Verify (Alg. 1-3): round trip, rejection of every single-bit flip,
+determinism, and the mean Sign loop count against Sec. 2.3."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2211_12265_amd import workload
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "params_table1.json")))
+
+
+def _keys(orc, level, n, seed=0):
+    return orc.keygen_batch(level, workload.keygen_seeds(n, seed=seed))
+
+
+@pytest.mark.parametrize("level", [2, 3, 5])
+def test_round_trip(orc, level):
+    n = 24
+    pk, sk = _keys(orc, level, n)
+    lens = workload.uniform_lengths(n, 0, 300, seed=level)
+    msg, off = workload.messages(lens, seed=level)
+    sig, iters = orc.sign_batch(level, sk, msg, off)
+    assert iters.min() >= 1
+    v = orc.verify_batch(level, pk, msg, off, sig)
+    assert v.tolist() == [1] * n
+    # single-task entry points agree with the batch drivers
+    s0, it0 = orc.sign(level, sk[0].tobytes(), msg[int(off[0]):int(off[1])].tobytes())
+    assert s0 == sig[0].tobytes() and it0 == iters[0]
+
+
+@pytest.mark.parametrize("level", [2, 3, 5])
+def test_deterministic_and_key_idx(orc, level):
+    pk, sk = _keys(orc, level, 4, seed=9)
+    pk2, sk2 = _keys(orc, level, 4, seed=9)
+    assert np.array_equal(pk, pk2) and np.array_equal(sk, sk2)
+    msg, off = workload.messages(workload.fixed_lengths(6, 32), seed=4)
+    kidx = np.array([3, 0, 3, 1, 2, 2], dtype=np.uint32)
+    sig, _ = orc.sign_batch(level, sk, msg, off, key_idx=kidx)
+    sig_a, _ = orc.sign_batch(level, sk[kidx], msg, off)
+    assert np.array_equal(sig, sig_a)
+    assert orc.verify_batch(level, pk, msg, off, sig, key_idx=kidx).tolist() == [1] * 6
+    # wrong key rejects
+    wrong = np.array([0, 1, 0, 0, 0, 0], dtype=np.uint32)
+    assert orc.verify_batch(level, pk, msg, off, sig, key_idx=wrong).tolist() == [0] * 6
+
+
+def test_every_signature_bit_flip_rejected_level2(orc):
+    level = 2
+    pk, sk = _keys(orc, level, 1, seed=11)
+    msg = workload.random_bytes("test/m", 0, (32,))
+    off = np.array([0, 32], dtype=np.uint64)
+    sig, _ = orc.sign_batch(level, sk, msg, off)
+    nbits = sig.shape[1] * 8
+    flipped = np.repeat(sig, nbits, axis=0)
+    bit = np.arange(nbits)
+    flipped[bit, bit // 8] ^= (1 << (bit % 8)).astype(np.uint8)
+    msgs = np.tile(msg, nbits)
+    offs = np.arange(nbits + 1, dtype=np.uint64) * 32
+    v = orc.verify_batch(level, pk, msgs, offs, flipped, key_idx=np.zeros(nbits, np.uint32))
+    assert v.sum() == 0
+
+
+@pytest.mark.parametrize("level", [3, 5])
+def test_sampled_signature_bit_flips_rejected(orc, level):
+    pk, sk = _keys(orc, level, 1, seed=12)
+    msg = workload.random_bytes("test/m", level, (32,))
+    off = np.array([0, 32], dtype=np.uint64)
+    sig, _ = orc.sign_batch(level, sk, msg, off)
+    nbits = sig.shape[1] * 8
+    bits = np.unique(np.concatenate([np.arange(0, nbits, 7), np.arange(nbits - 8 * 90, nbits)]))
+    flipped = np.repeat(sig, bits.size, axis=0)
+    flipped[np.arange(bits.size), bits // 8] ^= (1 << (bits % 8)).astype(np.uint8)
+    v = orc.verify_batch(level, pk, np.tile(msg, bits.size), np.arange(bits.size + 1, dtype=np.uint64) * 32,
+                         flipped, key_idx=np.zeros(bits.size, np.uint32))
+    assert v.sum() == 0
+
+
+@pytest.mark.parametrize("level", [2, 3, 5])
+def test_message_bit_flips_rejected(orc, level):
+    pk, sk = _keys(orc, level, 1, seed=13)
+    msg = workload.random_bytes("test/m2", level, (16,))
+    off = np.array([0, 16], dtype=np.uint64)
+    sig, _ = orc.sign_batch(level, sk, msg, off)
+    nb = 128
+    msgs = np.tile(msg, (nb, 1))
+    msgs[np.arange(nb), np.arange(nb) // 8] ^= (1 << (np.arange(nb) % 8)).astype(np.uint8)
+    v = orc.verify_batch(level, pk, msgs.reshape(-1), np.arange(nb + 1, dtype=np.uint64) * 16,
+                         np.repeat(sig, nb, axis=0), key_idx=np.zeros(nb, np.uint32))
+    assert v.sum() == 0
+
+
+def test_cross_level_rejected(orc):
+    pk2, sk2 = _keys(orc, 2, 1)
+    msg = workload.random_bytes("test/m3", 0, (32,))
+    off = np.array([0, 32], dtype=np.uint64)
+    sig2, _ = orc.sign_batch(2, sk2, msg, off)
+    pk5, _ = _keys(orc, 5, 1)
+    # a level-2 signature padded to level-5 size does not verify under a level-5 key
+    padded = np.zeros((1, orc.params(5)["sig_bytes"]), np.uint8)
+    padded[0, :sig2.shape[1]] = sig2[0]
+    assert orc.verify_batch(5, pk5, msg, off, padded).tolist() == [0]
+
+
+def test_empty_message(orc):
+    pk, sk = _keys(orc, 2, 2)
+    msg = np.zeros(0, np.uint8)
+    off = np.zeros(3, np.uint64)
+    sig, _ = orc.sign_batch(2, sk, msg, off)
+    assert orc.verify_batch(2, pk, msg, off, sig).tolist() == [1, 1]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("level", [2, 3, 5])
+def test_mean_loop_count(orc, level):
+    n = 1500
+    pk, sk = _keys(orc, level, n, seed=21)
+    msg, off = workload.messages(workload.fixed_lengths(n, 32), seed=21)
+    sig, iters = orc.sign_batch(level, sk, msg, off)
+    expect = GOLD["levels"][str(level)]["expected_repetitions"]
+    assert abs(iters.mean() - expect) < 0.1 * expect, (iters.mean(), expect)
+    # geometric: P(iters == 1) close to 1/E
+    assert abs((iters == 1).mean() - 1 / expect) < 0.05
