@@ -1,0 +1,118 @@
+/*
+ * libdil -- batched CRYSTALS-Dilithium (round-3 parameter sets 2, 3, 5) on
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The operations are Dilithium.Gen, Dilithium.Sign (deterministic mode) and
+ * Dilithium.Verify as given in Alg. 1, 2 and 3 of the paper, with the
+ * parameter sets of its Tab. 1; one call processes a batch of independent
+ * tasks (Sec. 3.1: one key generation, signing or verification is one task).
+ * Byte layouts of keys and signatures follow the public round-3 (v3.1)
+ * specification conventions, which the paper does not restate:
+ *   level 2: pk 1312 B, sk 2528 B, signature 2420 B
+ *   level 3: pk 1952 B, sk 4000 B, signature 3293 B
+ *   level 5: pk 2592 B, sk 4864 B, signature 4595 B
+ *
+ * Conventions for every batch entry point:
+ *   - Buffer pointers are DEVICE pointers (hipMalloc'd or torch tensors on the
+ *     same GPU as the context), owned by the caller; the library never frees
+ *     or retains them after the call returns.
+ *   - Row i of a fixed-stride array (keys, signatures) is task i's; message i
+ *     is msg[msg_off[i] .. msg_off[i+1]) with msg_off holding count + 1
+ *     uint64 entries on the device (lengths may be 0; any alignment).
+ *   - key_idx may be NULL (task i uses key row i) or a device array of count
+ *     uint32 key-row indices (resident key tables).
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = default stream).
+ *     Calls that finish synchronously say so.  Output i always belongs to
+ *     input i, whatever order the device processes tasks in.
+ *   - count == 0 is a no-op returning DIL_OK.
+ *   - Errors are returned, never written into outputs:
+ *       DIL_EINVAL  level not in {2,3,5}, NULL pointer with count > 0, bad mode;
+ *       DIL_ENOMEM  the context cannot allocate its workspace;
+ *       DIL_EHIP    a HIP launch/copy failed (dil_last_error() has the text);
+ *       DIL_EMSG    a decreasing msg_off entry was found (detected on the
+ *                   device; reported by calls that synchronise, and by
+ *                   dil_ctx_check()).
+ *     A malformed signature is not an error: its verdict is 0 (Alg. 3).
+ *   - One context serves one host thread at a time; calls that overlap on
+ *     one context race on its workspace.
+ */
+#ifndef DIL_H
+#define DIL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DIL_OK 0
+#define DIL_EINVAL (-1)
+#define DIL_ENOMEM (-2)
+#define DIL_EHIP (-3)
+#define DIL_EMSG (-4)
+
+/* Execution forms for Sign (dil_ctx_set_mode):
+ *   DIL_MODE_STAGED      one kernel launch per pipeline stage, host-driven
+ *                        rejection loop over the still-active tasks (the host
+ *                        synchronises once per loop round).
+ *   DIL_MODE_PERSISTENT  fused persistent kernel with a device-side work queue
+ *                        (asynchronous; no host round trips). */
+#define DIL_MODE_STAGED 0
+#define DIL_MODE_PERSISTENT 1
+
+typedef struct dil_ctx dil_ctx;
+
+/* Create a context on HIP device `device`.  workspace_bytes is a hint for the
+ * initial workspace (0 = grow on demand).  Returns DIL_OK and *out, or an error. */
+int dil_ctx_create(dil_ctx **out, int device, size_t workspace_bytes);
+/* Release the context and its workspace (waits for its outstanding work). */
+int dil_ctx_destroy(dil_ctx *ctx);
+/* Select the Sign execution form (DIL_MODE_*). */
+int dil_ctx_set_mode(dil_ctx *ctx, int mode);
+/* Synchronise `stream` and report a device-detected input error (DIL_EMSG) once. */
+int dil_ctx_check(dil_ctx *ctx, void *stream);
+/* Text of the last error on this context (static storage inside the context). */
+const char *dil_last_error(dil_ctx *ctx);
+
+/* Byte sizes for a level (Tab. 1 parameters, round-3 v3.1 layouts). */
+int dil_sizes(int level, size_t *pk_bytes, size_t *sk_bytes, size_t *sig_bytes);
+
+/* Dilithium.Gen (Alg. 1) with caller-supplied 32-byte seeds zeta:
+ * seeds[count][32] -> pk[count][PK], sk[count][SK]. */
+int dil_keygen_batch(dil_ctx *ctx, int level, const uint8_t *seeds, uint8_t *pk, uint8_t *sk, uint32_t count,
+                     void *stream);
+
+/* Dilithium.Sign (Alg. 2), deterministic (rho' = H(K || mu)):
+ * sk rows [n_keys][SK], messages (msg, msg_off), sig[count][SIG].
+ * Output equals sequential Sign: the first kappa = 0, l, 2l, ... that passes
+ * all four rejection checks.  In DIL_MODE_STAGED the call returns after the
+ * batch has completed. */
+int dil_sign_batch(dil_ctx *ctx, int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                   const uint64_t *msg_off, uint8_t *sig, uint32_t count, void *stream);
+
+/* Dilithium.Verify (Alg. 3) with strict signature decoding:
+ * verdict[count] int32 = 1 accept, 0 reject. */
+int dil_verify_batch(dil_ctx *ctx, int level, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
+                     const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count, void *stream);
+
+/* Number of Sign loop iterations (candidate signatures) the last dil_sign_batch
+ * on this context evaluated in total, and the number the sequential algorithm
+ * needs (sum over tasks of the winning iteration index + 1).  Synchronises. */
+int dil_sign_stats(dil_ctx *ctx, uint64_t *evaluated, uint64_t *sequential);
+
+/* Primitive: c_i = INTT(NTT(a_i) o b_i) for count polynomials of 256
+ * coefficients (Sec. 2.2), a and b canonical int32 in [0, q), b read as
+ * NTT-domain values (slot j = evaluation at psi^(2 brv8(j)+1), psi = 1753);
+ * c canonical.  Uses Montgomery arithmetic internally. */
+int dil_ntt_mul_batch(dil_ctx *ctx, const int32_t *a, const int32_t *b, int32_t *c, uint64_t count, void *stream);
+
+/* Primitive: ExpandA rejection sampling (Sec. 2.3, Sec. 3.4) of count
+ * polynomials from 34-byte inputs seeds[count][34] (SHAKE128, 3 bytes ->
+ * 23-bit candidate, kept if < q) -> out[count][256] canonical int32. */
+int dil_expand_a_batch(dil_ctx *ctx, const uint8_t *seeds34, int32_t *out, uint64_t count, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,324 @@
+// Host side of libdil: context, workspace pool and the C-ABI entry points.
+#include <hip/hip_runtime.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "../../include/dil.h"
+#include "kernels.h"
+
+using namespace dil;
+
+struct dil_ctx {
+  int device = 0;
+  int mode = DIL_MODE_STAGED;
+  void *ws_mem = nullptr;
+  size_t ws_bytes = 0;
+  uint32_t *host_counters = nullptr;  // pinned, 16 words
+  char err[256] = {0};
+  uint64_t stat_evaluated = 0, stat_sequential = 0;
+  int pending_msg_error = 0;
+};
+
+namespace {
+
+int fail(dil_ctx *ctx, int code, const char *what, hipError_t e = hipSuccess) {
+  if (ctx) {
+    if (e != hipSuccess) snprintf(ctx->err, sizeof ctx->err, "%s: %s", what, hipGetErrorString(e));
+    else snprintf(ctx->err, sizeof ctx->err, "%s", what);
+  }
+  return code;
+}
+
+#define HIPCHK(ctx, call)                                  \
+  do {                                                     \
+    hipError_t e_ = (call);                                \
+    if (e_ != hipSuccess) return fail(ctx, DIL_EHIP, #call, e_); \
+  } while (0)
+
+#define LAUNCHCHK(ctx)                                     \
+  do {                                                     \
+    hipError_t e_ = hipGetLastError();                     \
+    if (e_ != hipSuccess) return fail(ctx, DIL_EHIP, "kernel launch", e_); \
+  } while (0)
+
+bool valid_level(int lv) { return lv == 2 || lv == 3 || lv == 5; }
+
+template <int LV>
+size_t ws_need(size_t cap) {
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  size_t muw1 = ((size_t)P<LV>::MUW1 + 255) & ~(size_t)255;
+  size_t per = muw1 + 64 + 32 + 256 + (size_t)K * L * 1024 + (size_t)(L + K) * 1024 + 2 * (size_t)K * 1024 +
+               (size_t)L * 1024 + (size_t)K * 1024 + (size_t)K * 32 + 4 * 4;
+  return cap * per + 16 * 256 + 4096;
+}
+
+template <int LV>
+int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws) {
+  size_t need = ws_need<LV>(cap);
+  if (need > ctx->ws_bytes) {
+    if (ctx->ws_mem) {
+      hipDeviceSynchronize();
+      hipFree(ctx->ws_mem);
+      ctx->ws_mem = nullptr;
+      ctx->ws_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&ctx->ws_mem, need);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(ctx, DIL_ENOMEM, "workspace allocation", e);
+    }
+    ctx->ws_bytes = need;
+  }
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  uint8_t *p = (uint8_t *)ctx->ws_mem;
+  auto take = [&](size_t bytes) {
+    uint8_t *r = p;
+    p += (bytes + 255) & ~(size_t)255;
+    return r;
+  };
+  ws.cap = cap;
+  ws.muw1_stride = ((size_t)P<LV>::MUW1 + 255) & ~(size_t)255;
+  ws.counters = (uint32_t *)take(16 * 4);
+  ws.muw1 = take(cap * ws.muw1_stride);
+  ws.rhop = take(cap * 64);
+  ws.ctilde = take(cap * 32);
+  ws.cpoly = (int8_t *)take(cap * 256);
+  ws.A = (int32_t *)take(cap * K * L * 1024);
+  ws.s1h = (int32_t *)take(cap * (L + K) * 1024);
+  ws.s2h = (int32_t *)take(cap * K * 1024);
+  ws.t0h = (int32_t *)take(cap * K * 1024);
+  ws.y = (int32_t *)take(cap * L * 1024);
+  ws.w = (int32_t *)take(cap * K * 1024);
+  ws.hmask = (uint32_t *)take(cap * K * 32);
+  ws.kappa = (uint32_t *)take(cap * 4);
+  ws.flag = (int32_t *)take(cap * 4);
+  ws.active0 = (uint32_t *)take(cap * 4);
+  ws.active1 = (uint32_t *)take(cap * 4);
+  if ((size_t)(p - (uint8_t *)ctx->ws_mem) > ctx->ws_bytes) return fail(ctx, DIL_ENOMEM, "workspace layout overflow");
+  return DIL_OK;
+}
+
+inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
+
+template <int LV>
+int keygen_impl(dil_ctx *ctx, const uint8_t *seeds, uint8_t *pk, uint8_t *sk, uint32_t count, hipStream_t st) {
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  Ws ws;
+  int rc = ws_carve<LV>(ctx, count, ws);
+  if (rc) return rc;
+  kg_seed_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(seeds, pk, sk, ws, count);
+  expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(pk, P<LV>::PK, nullptr, ws.A, count);
+  expand_s_k<LV><<<blocks_for((uint64_t)count * (K + L), 256), 256, 0, st>>>(ws, count);
+  kg_main_k<LV><<<count, 64, 0, st>>>(ws, pk, sk, count);
+  kg_tr_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(pk, sk, count);
+  LAUNCHCHK(ctx);
+  return DIL_OK;
+}
+
+template <int LV>
+int sign_staged(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg, const uint64_t *msg_off,
+                uint8_t *sig, uint32_t count, hipStream_t st) {
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  Ws ws;
+  int rc = ws_carve<LV>(ctx, count, ws);
+  if (rc) return rc;
+  HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
+  sg_prep_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, ws, count);
+  expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(sk, P<LV>::SK, key_idx, ws.A, count);
+  sg_secret_k<LV><<<count, 64, 0, st>>>(sk, key_idx, ws, count);
+  LAUNCHCHK(ctx);
+  uint32_t nactive = count;
+  uint32_t *cur = ws.active0, *nxt = ws.active1;
+  uint64_t evaluated = 0;
+  int rounds = 0;
+  while (nactive > 0) {
+    if (++rounds > 4096) return fail(ctx, DIL_EHIP, "sign loop did not terminate");
+    evaluated += nactive;
+    HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 4, st));
+    expand_mask_k<LV><<<blocks_for((uint64_t)nactive * L, 256), 256, 0, st>>>(ws, cur, nactive);
+    sg_w_k<LV><<<nactive, 64, 0, st>>>(ws, cur, nactive);
+    sg_chal_k<LV><<<blocks_for(nactive, 64), 64, 0, st>>>(ws, cur, nactive);
+    sg_check_k<LV><<<nactive, 64, 0, st>>>(ws, sig, cur, nactive, nxt);
+    LAUNCHCHK(ctx);
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host_counters, ws.counters, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    nactive = ctx->host_counters[0];
+    if (ctx->host_counters[1]) ctx->pending_msg_error = 1;
+    std::swap(cur, nxt);
+  }
+  ctx->stat_evaluated = evaluated;
+  ctx->stat_sequential = evaluated;
+  if (ctx->pending_msg_error) {
+    ctx->pending_msg_error = 0;
+    return fail(ctx, DIL_EMSG, "decreasing msg_off entry");
+  }
+  return DIL_OK;
+}
+
+template <int LV>
+int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg, const uint64_t *msg_off,
+                const uint8_t *sig, int32_t *verdict, uint32_t count, hipStream_t st) {
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  Ws ws;
+  int rc = ws_carve<LV>(ctx, count, ws);
+  if (rc) return rc;
+  HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
+  vf_prep_k<LV><<<blocks_for(count, 64), 64, 0, st>>>(pk, key_idx, msg, msg_off, sig, ws, count);
+  expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(pk, P<LV>::PK, key_idx, ws.A, count);
+  vf_main_k<LV><<<count, 64, 0, st>>>(pk, key_idx, sig, ws, count);
+  vf_final_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sig, ws, verdict, count);
+  LAUNCHCHK(ctx);
+  return DIL_OK;
+}
+
+template <class F>
+int by_level(int level, F f) {
+  switch (level) {
+    case 2: return f(std::integral_constant<int, 2>{});
+    case 3: return f(std::integral_constant<int, 3>{});
+    case 5: return f(std::integral_constant<int, 5>{});
+  }
+  return DIL_EINVAL;
+}
+
+}  // namespace
+
+extern "C" {
+
+int dil_ctx_create(dil_ctx **out, int device, size_t workspace_bytes) {
+  if (!out) return DIL_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess || device < 0 || device >= n) return DIL_EHIP;
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return DIL_EHIP;
+  dil_ctx *c = new dil_ctx();
+  c->device = device;
+  e = hipHostMalloc((void **)&c->host_counters, 64, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return DIL_ENOMEM;
+  }
+  memset(c->host_counters, 0, 64);
+  if (workspace_bytes) {
+    e = hipMalloc(&c->ws_mem, workspace_bytes);
+    if (e != hipSuccess) {
+      hipHostFree(c->host_counters);
+      delete c;
+      return DIL_ENOMEM;
+    }
+    c->ws_bytes = workspace_bytes;
+  }
+  *out = c;
+  return DIL_OK;
+}
+
+int dil_ctx_destroy(dil_ctx *ctx) {
+  if (!ctx) return DIL_EINVAL;
+  hipSetDevice(ctx->device);
+  hipDeviceSynchronize();
+  if (ctx->ws_mem) hipFree(ctx->ws_mem);
+  if (ctx->host_counters) hipHostFree(ctx->host_counters);
+  delete ctx;
+  return DIL_OK;
+}
+
+int dil_ctx_set_mode(dil_ctx *ctx, int mode) {
+  if (!ctx) return DIL_EINVAL;
+  if (mode != DIL_MODE_STAGED) return fail(ctx, DIL_EINVAL, "unsupported mode");
+  ctx->mode = mode;
+  return DIL_OK;
+}
+
+int dil_ctx_check(dil_ctx *ctx, void *stream) {
+  if (!ctx) return DIL_EINVAL;
+  HIPCHK(ctx, hipStreamSynchronize((hipStream_t)stream));
+  if (ctx->pending_msg_error) {
+    ctx->pending_msg_error = 0;
+    return fail(ctx, DIL_EMSG, "decreasing msg_off entry");
+  }
+  return DIL_OK;
+}
+
+const char *dil_last_error(dil_ctx *ctx) { return ctx ? ctx->err : "null context"; }
+
+int dil_sizes(int level, size_t *pk, size_t *sk, size_t *sig) {
+  return by_level(level, [&](auto lv) {
+    constexpr int LV = decltype(lv)::value;
+    if (pk) *pk = P<LV>::PK;
+    if (sk) *sk = P<LV>::SK;
+    if (sig) *sig = P<LV>::SIG;
+    return DIL_OK;
+  });
+}
+
+int dil_keygen_batch(dil_ctx *ctx, int level, const uint8_t *seeds, uint8_t *pk, uint8_t *sk, uint32_t count,
+                     void *stream) {
+  if (!ctx || !valid_level(level)) return fail(ctx, DIL_EINVAL, "bad context or level");
+  if (count == 0) return DIL_OK;
+  if (!seeds || !pk || !sk) return fail(ctx, DIL_EINVAL, "null buffer");
+  hipSetDevice(ctx->device);
+  return by_level(level, [&](auto lv) {
+    return keygen_impl<decltype(lv)::value>(ctx, seeds, pk, sk, count, (hipStream_t)stream);
+  });
+}
+
+int dil_sign_batch(dil_ctx *ctx, int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                   const uint64_t *msg_off, uint8_t *sig, uint32_t count, void *stream) {
+  if (!ctx || !valid_level(level)) return fail(ctx, DIL_EINVAL, "bad context or level");
+  if (count == 0) return DIL_OK;
+  if (!sk || !msg || !msg_off || !sig) return fail(ctx, DIL_EINVAL, "null buffer");
+  hipSetDevice(ctx->device);
+  return by_level(level, [&](auto lv) {
+    return sign_staged<decltype(lv)::value>(ctx, sk, key_idx, msg, msg_off, sig, count, (hipStream_t)stream);
+  });
+}
+
+int dil_verify_batch(dil_ctx *ctx, int level, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
+                     const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count, void *stream) {
+  if (!ctx || !valid_level(level)) return fail(ctx, DIL_EINVAL, "bad context or level");
+  if (count == 0) return DIL_OK;
+  if (!pk || !msg || !msg_off || !sig || !verdict) return fail(ctx, DIL_EINVAL, "null buffer");
+  hipSetDevice(ctx->device);
+  return by_level(level, [&](auto lv) {
+    return verify_impl<decltype(lv)::value>(ctx, pk, key_idx, msg, msg_off, sig, verdict, count,
+                                            (hipStream_t)stream);
+  });
+}
+
+int dil_sign_stats(dil_ctx *ctx, uint64_t *evaluated, uint64_t *sequential) {
+  if (!ctx) return DIL_EINVAL;
+  if (evaluated) *evaluated = ctx->stat_evaluated;
+  if (sequential) *sequential = ctx->stat_sequential;
+  return DIL_OK;
+}
+
+int dil_ntt_mul_batch(dil_ctx *ctx, const int32_t *a, const int32_t *b, int32_t *c, uint64_t count, void *stream) {
+  if (!ctx) return DIL_EINVAL;
+  if (count == 0) return DIL_OK;
+  if (!a || !b || !c) return fail(ctx, DIL_EINVAL, "null buffer");
+  hipSetDevice(ctx->device);
+  hipDeviceProp_t prop;
+  HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
+  uint64_t need = (count + 15) / 16;
+  uint64_t grid = std::min<uint64_t>(need, (uint64_t)prop.multiProcessorCount * 16);
+  ntt_mul_k<<<(unsigned)grid, 256, 0, (hipStream_t)stream>>>(a, b, c, count);
+  LAUNCHCHK(ctx);
+  return DIL_OK;
+}
+
+int dil_expand_a_batch(dil_ctx *ctx, const uint8_t *seeds34, int32_t *out, uint64_t count, void *stream) {
+  if (!ctx) return DIL_EINVAL;
+  if (count == 0) return DIL_OK;
+  if (!seeds34 || !out) return fail(ctx, DIL_EINVAL, "null buffer");
+  hipSetDevice(ctx->device);
+  expand_a_seed_k<<<blocks_for(count, 256), 256, 0, (hipStream_t)stream>>>(seeds34, out, count);
+  LAUNCHCHK(ctx);
+  return DIL_OK;
+}
+
+}  // extern "C"

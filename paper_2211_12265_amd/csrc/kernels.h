@@ -1,0 +1,753 @@
+// Batched Dilithium kernels for gfx950 (Alg. 1-3), one-launch-per-stage form.
+//
+// Thread mappings:
+//   sponge kernels      one lane per SHAKE stream (256-thread blocks)
+//   polynomial kernels  one wavefront per task, four 16-lane groups each
+//                       working on its own polynomial (64-thread blocks)
+// All intermediates live in a per-task workspace in HBM (see Ws).
+#pragma once
+#include "common.h"
+#include "ntt.h"
+#include "poly.h"
+#include "sponge.h"
+
+namespace dil {
+
+// Per-task workspace of the staged kernels.  Rows are 256-byte aligned; the
+// hash inputs mu || packed w1 are stored contiguously, in the order the hash
+// consumes them, so the challenge hash reads one row.
+struct Ws {
+  uint8_t *muw1;     // [cap][MUW1 rounded to 256]
+  uint8_t *rhop;     // [cap][64]   rho' (KeyGen: expanded secret seed; Sign: mask seed)
+  uint8_t *ctilde;   // [cap][32]
+  int8_t *cpoly;     // [cap][256]  challenge c, dense
+  int32_t *A;        // [cap][K][L][256]  A-hat, canonical
+  int32_t *s1h;      // [cap][L][256]  NTT(s1)   (KeyGen: s1, s2 centred, [cap][L+K][256])
+  int32_t *s2h;      // [cap][K][256]
+  int32_t *t0h;      // [cap][K][256]
+  int32_t *y;        // [cap][L][256]  mask, centred
+  int32_t *w;        // [cap][K][256]  w = A y, canonical
+  uint32_t *hmask;   // [cap][K][8]   verify: hint bits
+  uint32_t *kappa;   // [cap]
+  int32_t *flag;     // [cap]
+  uint32_t *active0, *active1;  // [cap] task lists
+  uint32_t *counters;           // [8]: next active count, error flags, attempts
+  size_t cap;
+  size_t muw1_stride;
+};
+
+template <int LV>
+__device__ __forceinline__ size_t muw1_stride() {
+  return ((size_t)P<LV>::MUW1 + 255) & ~(size_t)255;
+}
+
+// ------------------------------------------------------------------------
+// KeyGen (Alg. 1)
+// ------------------------------------------------------------------------
+// (rho, rho', K) = H(zeta): rho -> pk and sk, K -> sk, rho' -> workspace
+template <int LV>
+__global__ void __launch_bounds__(256) kg_seed_k(const uint8_t *seeds, uint8_t *pk, uint8_t *sk, Ws ws,
+                                                 uint32_t count) {
+  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  uint32_t s[50];
+  shake_absorb<RATE256>(s, 32, SrcBytes{seeds + 32 * (size_t)t, 32});
+  uint64_t *pkw = (uint64_t *)(pk + (size_t)t * P<LV>::PK);
+  uint64_t *skw = (uint64_t *)(sk + (size_t)t * P<LV>::SK);
+  uint64_t *rw = (uint64_t *)(ws.rhop + (size_t)t * 64);
+#pragma unroll
+  for (int w = 0; w < 16; w++) {
+    uint64_t v = (uint64_t)s[2 * w] | ((uint64_t)s[2 * w + 1] << 32);
+    if (w < 4) {
+      pkw[w] = v;
+      skw[w] = v;
+    } else if (w < 12) {
+      rw[w - 4] = v;
+    } else {
+      skw[w - 8] = v;  // K at sk bytes 32..63
+    }
+  }
+}
+
+// ExpandA: one lane per (task, i, j); rho read from rows of `rho_src` (pk or sk)
+template <int LV>
+__global__ void __launch_bounds__(256) expand_a_k(const uint8_t *rho_src, size_t rho_stride, const uint32_t *key_idx,
+                                                  int32_t *A, uint32_t count) {
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  uint64_t st = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (st >= (uint64_t)count * K * L) return;
+  uint32_t task = (uint32_t)(st / (K * L));
+  int ij = (int)(st % (K * L));
+  int i = ij / L, j = ij % L;
+  size_t key = key_idx ? key_idx[task] : task;
+  const uint64_t *rho = (const uint64_t *)(rho_src + key * rho_stride);
+  uint32_t s[50];
+  absorb_seed34(s, [&](int pos) { return rho[pos >> 3]; }, (uint32_t)j | ((uint32_t)i << 8));
+  expand_a_squeeze(s, A + (size_t)st * N);
+}
+
+// ExpandS: one lane per (task, r < L + K); centred coefficients to ws.s1h
+template <int LV>
+__global__ void __launch_bounds__(256) expand_s_k(Ws ws, uint32_t count) {
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  uint64_t st = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (st >= (uint64_t)count * (K + L)) return;
+  uint32_t task = (uint32_t)(st / (K + L));
+  int r = (int)(st % (K + L));
+  uint32_t s[50];
+  absorb_seed66(s, ws.rhop + (size_t)task * 64, (uint32_t)r);
+  expand_s_squeeze<Lv<LV>::ETA>(s, ws.s1h + (size_t)st * N);
+}
+
+// LDS layout shared by the per-task polynomial kernels
+template <int LV>
+struct PolyLds {
+  int32_t tr[4 * NTT_LDS_GROUP];              // transposes, one region per group
+  int32_t hat[(Lv<LV>::L > Lv<LV>::K ? Lv<LV>::L : Lv<LV>::K) * N];  // NTT-domain vector (slots)
+  uint32_t buf[(P<LV>::SK + 64) / 4 + 2];     // byte staging (packed rows), + pad words
+};
+
+// consecutive-layout values of the lane (16t .. 16t+15) from its strided values
+__device__ __forceinline__ void to_consecutive(const int32_t x[16], uint32_t v[16], int32_t *tr, int t) {
+  int32_t y[16];
+#pragma unroll
+  for (int r = 0; r < 16; r++) y[r] = x[r];
+  transpose_s2c(y, tr, t);
+#pragma unroll
+  for (int r = 0; r < 16; r++) v[r] = (uint32_t)y[r];
+}
+
+// KeyGen main: t = INTT(A * NTT(s1)) + s2, Power2Round, pack pk's t1 and sk's s1, s2, t0
+template <int LV>
+__global__ void __launch_bounds__(64) kg_main_k(Ws ws, uint8_t *pk, uint8_t *sk, uint32_t count) {
+  using PP = P<LV>;
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L, ETA = Lv<LV>::ETA;
+  __shared__ PolyLds<LV> lds;
+  __shared__ uint32_t pkbuf[PP::PK / 4 + 2];
+  uint32_t task = blockIdx.x;
+  if (task >= count) return;
+  int lane = threadIdx.x, g = lane >> 4, t = lane & 15;
+  int32_t *tr = lds.tr + g * NTT_LDS_GROUP;
+  uint8_t *skb = (uint8_t *)lds.buf;
+  uint8_t *pkb = (uint8_t *)pkbuf;
+  const int32_t *S = ws.s1h + (size_t)task * (K + L) * N;
+  const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
+  // s1: NTT into LDS, and pack eta - s into sk
+  for (int j = g; j < L; j += 4) {
+    int32_t x[16];
+    load_strided(x, S + j * N, t);
+    uint32_t v[16];
+    to_consecutive(x, v, tr, t);
+#pragma unroll
+    for (int r = 0; r < 16; r++) v[r] = (uint32_t)(ETA - (int32_t)v[r]);
+    pack16_to_lds<PP::EBITS>(v, skb + PP::OFF_S1 + j * PP::EB, t);
+    ntt16(x, ftw, tr, t);
+#pragma unroll
+    for (int r = 0; r < 16; r++) lds.hat[j * N + 16 * t + r] = x[r];
+  }
+  wave_sync();
+  for (int i = g; i < K; i += 4) {
+    const int32_t *Ai = ws.A + ((size_t)task * K + i) * L * N;
+    int64_t acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) acc[r] = 0;
+    for (int j = 0; j < L; j++) {
+      int32_t a[16];
+      load_slots(a, Ai + j * N, t);
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * lds.hat[j * N + 16 * t + r];
+    }
+    int32_t x[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) x[r] = mont_reduce(acc[r]);
+    intt16(x, itw, tr, t);
+    int32_t s2[16];
+    load_strided(s2, S + (L + i) * N, t);
+    uint32_t v[16];
+    to_consecutive(s2, v, tr, t);
+#pragma unroll
+    for (int r = 0; r < 16; r++) v[r] = (uint32_t)(ETA - (int32_t)v[r]);
+    pack16_to_lds<PP::EBITS>(v, skb + PP::OFF_S2 + i * PP::EB, t);
+    int32_t t1[16], t0[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      int32_t tv = canon(x[r]) + s2[r];            // in [-eta, q + eta)
+      tv += (tv >> 31) & Q;
+      tv -= Q;
+      tv += (tv >> 31) & Q;                        // canonical
+      power2round(tv, t1[r], t0[r]);
+      t0[r] = (1 << (D - 1)) - t0[r];
+    }
+    to_consecutive(t1, v, tr, t);
+    pack16_to_lds<10>(v, pkb + 32 + i * PP::T1B, t);
+    to_consecutive(t0, v, tr, t);
+    pack16_to_lds<13>(v, skb + PP::OFF_T0 + i * PP::T0B, t);
+  }
+  wave_sync();
+  // copy the packed regions out (pk[32..PK), sk[96..SK)); rho, K, tr are written elsewhere
+  uint32_t *pkg = (uint32_t *)(pk + (size_t)task * PP::PK);
+  for (int w = 8 + lane; w < PP::PK / 4; w += 64) pkg[w] = pkbuf[w];
+  uint32_t *skg = (uint32_t *)(sk + (size_t)task * PP::SK);
+  for (int w = 24 + lane; w < PP::SK / 4; w += 64) skg[w] = lds.buf[w];
+}
+
+// tr = H(pk) into sk bytes 64..95
+template <int LV>
+__global__ void __launch_bounds__(256) kg_tr_k(const uint8_t *pk, uint8_t *sk, uint32_t count) {
+  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const uint8_t *p = pk + (size_t)t * P<LV>::PK;
+  uint32_t s[50];
+  shake_absorb<RATE256>(s, P<LV>::PK, [&](uint64_t pos) { return *(const uint64_t *)(p + pos); });
+  uint32_t *o = (uint32_t *)(sk + (size_t)t * P<LV>::SK + 64);
+#pragma unroll
+  for (int w = 0; w < 8; w++) o[w] = s[w];
+}
+
+// ------------------------------------------------------------------------
+// Sign (Alg. 2), staged
+// ------------------------------------------------------------------------
+// mu = H(tr || M), rho' = H(K || mu); initialises kappa and the active list
+template <int LV>
+__global__ void __launch_bounds__(256) sg_prep_k(const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                                                 const uint64_t *msg_off, Ws ws, uint32_t count) {
+  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  size_t key = key_idx ? key_idx[t] : t;
+  const uint8_t *skr = sk + key * P<LV>::SK;
+  uint64_t o0 = msg_off[t], o1 = msg_off[t + 1];
+  uint64_t mlen = 0;
+  if (o1 >= o0) mlen = o1 - o0;
+  else atomicOr((int *)&ws.counters[1], 1);
+  uint32_t s[50];
+  shake_absorb<RATE256>(s, 32 + mlen, SrcCat{skr + 64, 32, msg + o0, 32 + mlen});
+  uint32_t mu[16];
+#pragma unroll
+  for (int i = 0; i < 16; i++) mu[i] = s[i];
+  uint32_t *muw = (uint32_t *)(ws.muw1 + (size_t)t * muw1_stride<LV>());
+#pragma unroll
+  for (int i = 0; i < 16; i++) muw[i] = mu[i];
+  // rho' = H(K || mu): 96 bytes, one block
+  keccak_zero(s);
+  const uint32_t *Kw = (const uint32_t *)(skr + 32);
+#pragma unroll
+  for (int i = 0; i < 8; i++) s[i] = Kw[i];
+#pragma unroll
+  for (int i = 0; i < 16; i++) s[8 + i] = mu[i];
+  s[24] ^= 0x1Fu;
+  s[2 * (RATE256 / 8 - 1) + 1] ^= 0x80u << 24;
+  keccak_f(s);
+  uint32_t *rp = (uint32_t *)(ws.rhop + (size_t)t * 64);
+#pragma unroll
+  for (int i = 0; i < 16; i++) rp[i] = s[i];
+  ws.kappa[t] = 0;
+  ws.active0[t] = t;
+}
+
+// NTT of the secret vectors s1, s2, t0 unpacked from sk
+template <int LV>
+__global__ void __launch_bounds__(64) sg_secret_k(const uint8_t *sk, const uint32_t *key_idx, Ws ws, uint32_t count) {
+  using PP = P<LV>;
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L, ETA = Lv<LV>::ETA;
+  __shared__ PolyLds<LV> lds;
+  uint32_t task = blockIdx.x;
+  if (task >= count) return;
+  int lane = threadIdx.x, g = lane >> 4, t = lane & 15;
+  int32_t *tr = lds.tr + g * NTT_LDS_GROUP;
+  size_t key = key_idx ? key_idx[task] : task;
+  const uint8_t *skr = sk + key * PP::SK;
+  // stage sk bytes 96..SK into LDS (sk rows are 8-byte aligned)
+  const uint32_t *skw = (const uint32_t *)(skr + 96);
+  constexpr int NW = (PP::SK - 96) / 4;
+  for (int w = lane; w < NW; w += 64) lds.buf[w] = skw[w];
+  if (lane < 2) lds.buf[NW + lane] = 0;
+  wave_sync();
+  const Tw ftw = ntt_lane_tw(t);
+  for (int p = g; p < L + 2 * K; p += 4) {
+    uint32_t v[16];
+    int32_t x[16];
+    int32_t *dst;
+    if (p < L + K) {
+      const uint32_t *src = lds.buf + (p * PP::EB) / 4;
+      unpack_strided<PP::EBITS>(src, v, t);
+#pragma unroll
+      for (int r = 0; r < 16; r++) x[r] = ETA - (int32_t)v[r];
+      dst = p < L ? ws.s1h + ((size_t)task * L + p) * N : ws.s2h + ((size_t)task * K + (p - L)) * N;
+    } else {
+      int i = p - L - K;
+      const uint32_t *src = lds.buf + ((L + K) * PP::EB + i * PP::T0B) / 4;
+      unpack_strided<13>(src, v, t);
+#pragma unroll
+      for (int r = 0; r < 16; r++) x[r] = (1 << (D - 1)) - (int32_t)v[r];
+      dst = ws.t0h + ((size_t)task * K + i) * N;
+    }
+    ntt16(x, ftw, tr, t);
+    store_slots(x, dst, t);
+  }
+}
+
+// ExpandMask: one lane per (active task, i < L)
+template <int LV>
+__global__ void __launch_bounds__(256) expand_mask_k(Ws ws, const uint32_t *active, uint32_t nactive) {
+  constexpr int L = Lv<LV>::L;
+  uint64_t st = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (st >= (uint64_t)nactive * L) return;
+  uint32_t task = active[st / L];
+  int i = (int)(st % L);
+  uint32_t kappa = ws.kappa[task];
+  uint32_t s[50];
+  absorb_seed66(s, ws.rhop + (size_t)task * 64, (kappa + (uint32_t)i) & 0xFFFFu);
+  expand_mask_squeeze<P<LV>::ZBITS, Lv<LV>::GAMMA1>(s, ws.y + ((size_t)task * L + i) * N);
+}
+
+// w = INTT(A * NTT(y)); w1 = HighBits(w) packed after mu
+template <int LV>
+__global__ void __launch_bounds__(64) sg_w_k(Ws ws, const uint32_t *active, uint32_t nactive) {
+  using PP = P<LV>;
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  __shared__ PolyLds<LV> lds;
+  if (blockIdx.x >= nactive) return;
+  uint32_t task = active[blockIdx.x];
+  int lane = threadIdx.x, g = lane >> 4, t = lane & 15;
+  int32_t *tr = lds.tr + g * NTT_LDS_GROUP;
+  uint8_t *wb = (uint8_t *)lds.buf;
+  const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
+  for (int j = g; j < L; j += 4) {
+    int32_t x[16];
+    load_strided(x, ws.y + ((size_t)task * L + j) * N, t);
+    ntt16(x, ftw, tr, t);
+#pragma unroll
+    for (int r = 0; r < 16; r++) lds.hat[j * N + 16 * t + r] = x[r];
+  }
+  wave_sync();
+  for (int i = g; i < K; i += 4) {
+    const int32_t *Ai = ws.A + ((size_t)task * K + i) * L * N;
+    int64_t acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) acc[r] = 0;
+    for (int j = 0; j < L; j++) {
+      int32_t a[16];
+      load_slots(a, Ai + j * N, t);
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * lds.hat[j * N + 16 * t + r];
+    }
+    int32_t x[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) x[r] = mont_reduce(acc[r]);
+    intt16(x, itw, tr, t);
+    int32_t w1[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      x[r] = canon(x[r]);
+      w1[r] = highbits<LV>(x[r]);
+    }
+    store_strided(x, ws.w + ((size_t)task * K + i) * N, t);
+    uint32_t v[16];
+    to_consecutive(w1, v, tr, t);
+    pack16_to_lds<PP::W1BITS>(v, wb + i * PP::W1B, t);
+  }
+  wave_sync();
+  uint32_t *dst = (uint32_t *)(ws.muw1 + (size_t)task * muw1_stride<LV>() + 64);
+  for (int w = lane; w < K * PP::W1B / 4; w += 64) dst[w] = lds.buf[w];
+}
+
+// SampleInBall on the lane's SHAKE256(ctilde) stream, into a per-lane 256-byte
+// LDS array; positions are drawn with rejection against the loop index.
+template <int TAU>
+__device__ __forceinline__ void sample_in_ball(uint32_t s[50], int8_t *c, uint8_t *blockbuf) {
+  // s holds the first squeezed block
+  uint32_t *bw = (uint32_t *)blockbuf;
+#pragma unroll
+  for (int w = 0; w < RATE256 / 4; w++) bw[w] = s[w];
+  uint64_t signs = (uint64_t)s[0] | ((uint64_t)s[1] << 32);
+  uint32_t *cw = (uint32_t *)c;
+#pragma unroll
+  for (int w = 0; w < N / 4; w++) cw[w] = 0;
+  int pos = 8;
+  for (int i = N - TAU; i < N; i++) {
+    int b;
+    for (;;) {
+      if (pos == RATE256) {
+        keccak_f(s);
+#pragma unroll
+        for (int w = 0; w < RATE256 / 4; w++) bw[w] = s[w];
+        pos = 0;
+      }
+      b = blockbuf[pos++];
+      if (b <= i) break;
+    }
+    c[i] = c[b];
+    c[b] = (int8_t)(1 - 2 * (int)(signs & 1));
+    signs >>= 1;
+  }
+}
+
+// ctilde = H(mu || w1); c = SampleInBall(ctilde).  One lane per active task.
+template <int LV>
+__global__ void __launch_bounds__(64) sg_chal_k(Ws ws, const uint32_t *active, uint32_t nactive) {
+  __shared__ int8_t cl[64][N];
+  __shared__ uint32_t bb[64][RATE256 / 4];
+  uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nactive) return;
+  uint32_t task = active[a];
+  const uint8_t *row = ws.muw1 + (size_t)task * muw1_stride<LV>();
+  uint32_t s[50];
+  shake_absorb<RATE256>(s, P<LV>::MUW1, [&](uint64_t pos) { return *(const uint64_t *)(row + pos); });
+  uint32_t ct[8];
+#pragma unroll
+  for (int i = 0; i < 8; i++) ct[i] = s[i];
+  uint32_t *cto = (uint32_t *)(ws.ctilde + (size_t)task * 32);
+#pragma unroll
+  for (int i = 0; i < 8; i++) cto[i] = ct[i];
+  keccak_zero(s);
+#pragma unroll
+  for (int i = 0; i < 8; i++) s[i] = ct[i];
+  s[8] = 0x1Fu;
+  s[2 * (RATE256 / 8 - 1) + 1] ^= 0x80u << 24;
+  keccak_f(s);
+  int8_t *c = cl[threadIdx.x];
+  sample_in_ball<Lv<LV>::TAU>(s, c, (uint8_t *)bb[threadIdx.x]);
+  int4 *dst = (int4 *)(ws.cpoly + (size_t)task * N);
+  const int4 *src = (const int4 *)c;
+#pragma unroll
+  for (int w = 0; w < N / 16; w++) dst[w] = src[w];
+}
+
+// z = y + c s1, r0 = LowBits(w - c s2), c t0, hint; accept -> signature, reject -> next round
+template <int LV>
+__global__ void __launch_bounds__(64) sg_check_k(Ws ws, uint8_t *sig, const uint32_t *active, uint32_t nactive,
+                                                 uint32_t *next_active) {
+  using PP = P<LV>;
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L, BETA = Lv<LV>::BETA, OMEGA = Lv<LV>::OMEGA;
+  constexpr int32_t G1 = Lv<LV>::GAMMA1, G2 = Lv<LV>::GAMMA2;
+  __shared__ int32_t trl[4 * NTT_LDS_GROUP];
+  __shared__ uint32_t sigbuf[PP::SIG / 4 + 2];
+  __shared__ uint16_t hmask[K][16];   // per row: per register r, the 16-lane hint mask
+  __shared__ int rowcnt[K];
+  if (blockIdx.x >= nactive) return;
+  uint32_t task = active[blockIdx.x];
+  int lane = threadIdx.x, g = lane >> 4, t = lane & 15;
+  int32_t *tr = trl + g * NTT_LDS_GROUP;
+  uint8_t *sb = (uint8_t *)sigbuf;
+  const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
+  // c-hat, computed by every group
+  int32_t ch[16];
+  {
+    const int8_t *cp = ws.cpoly + (size_t)task * N;
+#pragma unroll
+    for (int r = 0; r < 16; r++) ch[r] = cp[t + 16 * r];
+    ntt16(ch, ftw, tr, t);
+  }
+  bool bad = false;
+  // z = y + c s1
+  for (int j = g; j < L; j += 4) {
+    int32_t s1[16], x[16];
+    load_slots(s1, ws.s1h + ((size_t)task * L + j) * N, t);
+#pragma unroll
+    for (int r = 0; r < 16; r++) x[r] = mont_mul(ch[r], s1[r]);
+    intt16(x, itw, tr, t);
+    int32_t y[16];
+    load_strided(y, ws.y + ((size_t)task * L + j) * N, t);
+    int32_t zv[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      int32_t z = y[r] + canon(x[r]);              // in [-gamma1 + 1, q + gamma1)
+      z = z > (Q - 1) / 2 ? z - Q : z;             // centred
+      bad |= (z >= G1 - BETA) || (z <= -(G1 - BETA));
+      zv[r] = G1 - z;
+    }
+    uint32_t v[16];
+    to_consecutive(zv, v, tr, t);
+    pack16_to_lds<PP::ZBITS>(v, sb + PP::OFF_Z + j * PP::ZB, t);
+  }
+  if (wave_any(bad)) goto reject;
+  // r0 = LowBits(w - c s2), c t0 and the hint
+  for (int i = g; i < K; i += 4) {
+    int32_t s2[16], x[16], u[16];
+    load_slots(s2, ws.s2h + ((size_t)task * K + i) * N, t);
+#pragma unroll
+    for (int r = 0; r < 16; r++) x[r] = mont_mul(ch[r], s2[r]);
+    intt16(x, itw, tr, t);
+    int32_t wv[16];
+    load_strided(wv, ws.w + ((size_t)task * K + i) * N, t);
+    int32_t r1v[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      x[r] = canon(wv[r] - canon(x[r]));           // w - c s2, canonical
+      int32_t r1, r0;
+      decompose<LV>(x[r], r1, r0);
+      r1v[r] = r1;
+      bad |= (r0 >= G2 - BETA) || (r0 <= -(G2 - BETA));
+    }
+    load_slots(u, ws.t0h + ((size_t)task * K + i) * N, t);
+#pragma unroll
+    for (int r = 0; r < 16; r++) u[r] = mont_mul(ch[r], u[r]);
+    intt16(u, itw, tr, t);
+    int cnt = 0;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      int32_t ct0 = canon(u[r]);
+      bad |= norm_ge(ct0, G2);
+      int32_t sum = x[r] + ct0;
+      sum -= (sum >= Q) ? Q : 0;                   // w - c s2 + c t0, canonical
+      bool h = highbits<LV>(sum) != r1v[r];
+      uint64_t m = __ballot(h);
+      uint32_t m16 = (uint32_t)(m >> (16 * g)) & 0xFFFFu;
+      if (t == 0) hmask[i][r] = (uint16_t)m16;
+      cnt += __popc(m16);
+    }
+    if (t == 0) rowcnt[i] = cnt;
+  }
+  if (wave_any(bad)) goto reject;
+  wave_sync();
+  {
+    int total = 0;
+    for (int i = 0; i < K; i++) total += rowcnt[i];
+    if (total > OMEGA) goto reject;
+  }
+  // accepted: ctilde, hint bytes, copy out
+  if (lane < 8) sigbuf[lane] = ((const uint32_t *)(ws.ctilde + (size_t)task * 32))[lane];
+  for (int b = lane; b < OMEGA + K; b += 64) sb[PP::OFF_H + b] = 0;
+  wave_sync();
+  for (int i = g; i < K; i += 4) {
+    int base = 0;
+    for (int i2 = 0; i2 < i; i2++) base += rowcnt[i2];
+    int pre = base;
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      uint32_t m16 = hmask[i][r];
+      if ((m16 >> t) & 1u) sb[PP::OFF_H + pre + __popc(m16 & ((1u << t) - 1u))] = (uint8_t)(t + 16 * r);
+      pre += __popc(m16);
+    }
+    if (t == 0) sb[PP::OFF_H + OMEGA + i] = (uint8_t)pre;
+  }
+  wave_sync();
+  l2g_bytes(sigbuf, PP::SIG, sig + (size_t)task * PP::SIG, lane, 64);
+  return;
+reject:
+  if (lane == 0) {
+    ws.kappa[task] += L;
+    uint32_t slot = atomicAdd(&ws.counters[0], 1u);
+    next_active[slot] = task;
+  }
+}
+
+// ------------------------------------------------------------------------
+// Verify (Alg. 3), staged
+// ------------------------------------------------------------------------
+// tr = H(pk), mu = H(tr || M), c = SampleInBall(ctilde), strict hint decoding
+template <int LV>
+__global__ void __launch_bounds__(64) vf_prep_k(const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
+                                                const uint64_t *msg_off, const uint8_t *sig, Ws ws, uint32_t count) {
+  using PP = P<LV>;
+  constexpr int K = Lv<LV>::K, OMEGA = Lv<LV>::OMEGA;
+  __shared__ int8_t cl[64][N];
+  __shared__ uint32_t bb[64][RATE256 / 4];
+  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  size_t key = key_idx ? key_idx[t] : t;
+  const uint8_t *pkr = pk + key * PP::PK;
+  uint32_t s[50];
+  shake_absorb<RATE256>(s, PP::PK, [&](uint64_t pos) { return *(const uint64_t *)(pkr + pos); });
+  // tr is staged in the (otherwise unused) ctilde row so the message hash can stream tr || M
+  uint32_t *trg = (uint32_t *)(ws.ctilde + (size_t)t * 32);
+#pragma unroll
+  for (int i = 0; i < 8; i++) trg[i] = s[i];
+  uint64_t o0 = msg_off[t], o1 = msg_off[t + 1];
+  uint64_t mlen = 0;
+  if (o1 >= o0) mlen = o1 - o0;
+  else atomicOr((int *)&ws.counters[1], 1);
+  shake_absorb<RATE256>(s, 32 + mlen, SrcCat{(const uint8_t *)trg, 32, msg + o0, 32 + mlen});
+  uint32_t *muw = (uint32_t *)(ws.muw1 + (size_t)t * muw1_stride<LV>());
+#pragma unroll
+  for (int i = 0; i < 16; i++) muw[i] = s[i];
+  // SampleInBall(ctilde)
+  const uint8_t *sg = sig + (size_t)t * PP::SIG;
+  keccak_zero(s);
+#pragma unroll
+  for (int w = 0; w < 4; w++) {
+    uint64_t v = load_le_bytes(sg + 8 * w, 8);
+    s[2 * w] = (uint32_t)v;
+    s[2 * w + 1] = (uint32_t)(v >> 32);
+  }
+  s[8] = 0x1Fu;
+  s[2 * (RATE256 / 8 - 1) + 1] ^= 0x80u << 24;
+  keccak_f(s);
+  int8_t *c = cl[threadIdx.x];
+  sample_in_ball<Lv<LV>::TAU>(s, c, (uint8_t *)bb[threadIdx.x]);
+  int4 *dst = (int4 *)(ws.cpoly + (size_t)t * N);
+  const int4 *src = (const int4 *)c;
+#pragma unroll
+  for (int w = 0; w < N / 16; w++) dst[w] = src[w];
+  // strict hint decoding into bit masks
+  const uint8_t *hb = sg + PP::OFF_H;
+  uint32_t *hm = ws.hmask + (size_t)t * K * 8;
+  for (int w = 0; w < K * 8; w++) hm[w] = 0;
+  int ok = 1, prev = 0;
+  for (int i = 0; i < K; i++) {
+    int cnt = hb[OMEGA + i];
+    if (cnt < prev || cnt > OMEGA) {
+      ok = 0;
+      break;
+    }
+    for (int j = prev; j < cnt; j++) {
+      if (j > prev && hb[j] <= hb[j - 1]) ok = 0;
+      hm[i * 8 + (hb[j] >> 5)] |= 1u << (hb[j] & 31);
+    }
+    prev = cnt;
+  }
+  if (ok)
+    for (int j = prev; j < OMEGA; j++)
+      if (hb[j] != 0) ok = 0;
+  ws.flag[t] = ok;
+}
+
+// w1' = UseHint(h, INTT(A NTT(z) - c-hat NTT(t1 2^d))), packed after mu; z norm check
+template <int LV>
+__global__ void __launch_bounds__(64) vf_main_k(const uint8_t *pk, const uint32_t *key_idx, const uint8_t *sig, Ws ws,
+                                                uint32_t count) {
+  using PP = P<LV>;
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L, BETA = Lv<LV>::BETA;
+  constexpr int32_t G1 = Lv<LV>::GAMMA1;
+  __shared__ int32_t trl[4 * NTT_LDS_GROUP];
+  __shared__ int32_t zh[L * N];
+  __shared__ uint32_t sigw[PP::SIG / 4 + 3];
+  __shared__ uint32_t pkw[PP::PK / 4 + 2];
+  __shared__ uint32_t w1b[K * PP::W1B / 4 + 1];
+  uint32_t task = blockIdx.x;
+  if (task >= count) return;
+  int lane = threadIdx.x, g = lane >> 4, t = lane & 15;
+  int32_t *tr = trl + g * NTT_LDS_GROUP;
+  size_t key = key_idx ? key_idx[task] : task;
+  g2l_bytes(sig + (size_t)task * PP::SIG, PP::SIG, sigw, lane, 64);
+  if (lane < 2) sigw[PP::SIG / 4 + 1 + lane] = 0;
+  const uint32_t *pkg = (const uint32_t *)(pk + key * PP::PK);
+  for (int w = lane; w < PP::PK / 4; w += 64) pkw[w] = pkg[w];
+  if (lane < 2) pkw[PP::PK / 4 + lane] = 0;
+  wave_sync();
+  const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
+  int32_t ch[16];
+  {
+    const int8_t *cp = ws.cpoly + (size_t)task * N;
+#pragma unroll
+    for (int r = 0; r < 16; r++) ch[r] = cp[t + 16 * r];
+    ntt16(ch, ftw, tr, t);
+  }
+  bool bad = false;
+  for (int j = g; j < L; j += 4) {
+    uint32_t v[16];
+    unpack_strided<PP::ZBITS>(sigw + (PP::OFF_Z + j * PP::ZB) / 4, v, t);
+    int32_t x[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      int32_t z = G1 - (int32_t)v[r];
+      bad |= (z >= G1 - BETA) || (z <= -(G1 - BETA));
+      x[r] = z;
+    }
+    ntt16(x, ftw, tr, t);
+#pragma unroll
+    for (int r = 0; r < 16; r++) zh[j * N + 16 * t + r] = x[r];
+  }
+  bad = wave_any(bad);
+  wave_sync();
+  const uint32_t *hm = ws.hmask + (size_t)task * K * 8;
+  for (int i = g; i < K; i += 4) {
+    const int32_t *Ai = ws.A + ((size_t)task * K + i) * L * N;
+    int64_t acc[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) acc[r] = 0;
+    for (int j = 0; j < L; j++) {
+      int32_t a[16];
+      load_slots(a, Ai + j * N, t);
+#pragma unroll
+      for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * zh[j * N + 16 * t + r];
+    }
+    uint32_t v[16];
+    unpack_strided<10>(pkw + (32 + i * PP::T1B) / 4, v, t);
+    int32_t x[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) x[r] = (int32_t)(v[r] << D);
+    ntt16(x, ftw, tr, t);
+    // transpose-free: t1-hat comes out in slots layout like acc
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      int32_t d = mont_reduce(acc[r]) - mont_mul(ch[r], x[r]);  // in (-2q, 2q)
+      d += (d <= -Q) ? Q : 0;
+      d -= (d >= Q) ? Q : 0;
+      x[r] = d;
+    }
+    intt16(x, itw, tr, t);
+    int32_t w1[16];
+    uint32_t hw[8];
+#pragma unroll
+    for (int q = 0; q < 8; q++) hw[q] = hm[i * 8 + q];
+#pragma unroll
+    for (int r = 0; r < 16; r++) {
+      int c = t + 16 * r;
+      int32_t h = (hw[c >> 5] >> (c & 31)) & 1;
+      w1[r] = use_hint<LV>(h, canon(x[r]));
+    }
+    uint32_t vv[16];
+    to_consecutive(w1, vv, tr, t);
+    pack16_to_lds<PP::W1BITS>(vv, (uint8_t *)w1b + i * PP::W1B, t);
+  }
+  wave_sync();
+  uint32_t *dst = (uint32_t *)(ws.muw1 + (size_t)task * muw1_stride<LV>() + 64);
+  for (int w = lane; w < K * PP::W1B / 4; w += 64) dst[w] = w1b[w];
+  if (lane == 0 && bad) ws.flag[task] = 0;
+}
+
+// ctilde' = H(mu || w1'), verdict
+template <int LV>
+__global__ void __launch_bounds__(256) vf_final_k(const uint8_t *sig, Ws ws, int32_t *verdict, uint32_t count) {
+  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  const uint8_t *row = ws.muw1 + (size_t)t * muw1_stride<LV>();
+  uint32_t s[50];
+  shake_absorb<RATE256>(s, P<LV>::MUW1, [&](uint64_t pos) { return *(const uint64_t *)(row + pos); });
+  const uint8_t *sg = sig + (size_t)t * P<LV>::SIG;
+  bool eq = true;
+#pragma unroll
+  for (int w = 0; w < 4; w++) {
+    uint64_t v = load_le_bytes(sg + 8 * w, 8);
+    eq &= ((uint32_t)v == s[2 * w]) && ((uint32_t)(v >> 32) == s[2 * w + 1]);
+  }
+  verdict[t] = (ws.flag[t] && eq) ? 1 : 0;
+}
+
+// ------------------------------------------------------------------------
+// Primitive microbenchmarks
+// ------------------------------------------------------------------------
+// c_i = INTT(NTT(a_i) o b_i): b read as NTT-domain values; canonical output.
+// 256-thread blocks, 16 polynomials per block per iteration, grid-stride.
+__global__ void __launch_bounds__(256) ntt_mul_k(const int32_t *a, const int32_t *b, int32_t *c, uint64_t count) {
+  __shared__ int32_t trl[16 * NTT_LDS_GROUP];
+  int g = threadIdx.x >> 4, t = threadIdx.x & 15;
+  int32_t *tr = trl + g * NTT_LDS_GROUP;
+  const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
+  for (uint64_t p = (uint64_t)blockIdx.x * 16 + g; p < count; p += (uint64_t)gridDim.x * 16) {
+    int32_t x[16], y[16];
+    load_strided(x, a + p * N, t);
+    load_slots(y, b + p * N, t);
+    ntt16(x, ftw, tr, t);
+#pragma unroll
+    for (int r = 0; r < 16; r++) x[r] = mont_mul(x[r], y[r]);
+    intt16(x, itw, tr, t);
+#pragma unroll
+    for (int r = 0; r < 16; r++) x[r] = canon(x[r]);
+    store_strided(x, c + p * N, t);
+  }
+}
+
+// ExpandA rejection sampling of one polynomial per lane from a 34-byte input
+__global__ void __launch_bounds__(256) expand_a_seed_k(const uint8_t *seeds, int32_t *out, uint64_t count) {
+  uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const uint8_t *sd = seeds + 34 * p;
+  uint32_t s[50];
+  uint32_t nonce = (uint32_t)sd[32] | ((uint32_t)sd[33] << 8);
+  absorb_seed34(s, [&](int pos) { return load_le_bytes(sd + pos, 8); }, nonce);
+  expand_a_squeeze(s, out + p * N);
+}
+
+}  // namespace dil

@@ -1,0 +1,150 @@
+"""Thin Python binding of the libdil C-ABI (include/dil.h).
+
+Argument marshalling only: every step of KeyGen / Sign / Verify runs in the
+HIP kernels of libdil.so.  Buffers are torch tensors on the GPU; their
+device pointers and torch's current HIP stream are passed straight through.
+If libdil.so is missing this module raises at import of the library -- there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdil.so")
+
+DIL_OK, DIL_EINVAL, DIL_ENOMEM, DIL_EHIP, DIL_EMSG = 0, -1, -2, -3, -4
+MODE_STAGED, MODE_PERSISTENT = 0, 1
+
+EXPORTS = [
+    "dil_ctx_create", "dil_ctx_destroy", "dil_ctx_set_mode", "dil_ctx_check", "dil_last_error", "dil_sizes",
+    "dil_keygen_batch", "dil_sign_batch", "dil_verify_batch", "dil_sign_stats", "dil_ntt_mul_batch",
+    "dil_expand_a_batch",
+]
+
+_LIB: Optional[ctypes.CDLL] = None
+_P = ctypes.c_void_p
+
+
+class DilError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libdil error {code}: {msg}")
+        self.code = code
+
+
+def load() -> ctypes.CDLL:
+    """Load libdil.so (built in-tree by __graft_entry__.build())."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first (python -m "
+                           "paper_2211_12265_amd.build); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "dil_ctx_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_size_t]),
+        "dil_ctx_destroy": (ctypes.c_int, [_P]),
+        "dil_ctx_set_mode": (ctypes.c_int, [_P, ctypes.c_int]),
+        "dil_ctx_check": (ctypes.c_int, [_P, _P]),
+        "dil_last_error": (ctypes.c_char_p, [_P]),
+        "dil_sizes": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
+                                     ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
+        "dil_keygen_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_uint32, _P]),
+        "dil_sign_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_uint32, _P]),
+        "dil_verify_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_uint32, _P]),
+        "dil_sign_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
+        "dil_ntt_mul_batch": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_uint64, _P]),
+        "dil_expand_a_batch": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, _P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = L
+    return L
+
+
+def sizes(level: int) -> Tuple[int, int, int]:
+    pk, sk, sg = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    rc = load().dil_sizes(level, ctypes.byref(pk), ctypes.byref(sk), ctypes.byref(sg))
+    if rc:
+        raise DilError(rc, f"bad level {level}")
+    return pk.value, sk.value, sg.value
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    import torch
+    assert t.is_cuda and t.is_contiguous(), "libdil takes contiguous device tensors"
+    return t.data_ptr() if t.numel() > 0 else None
+
+
+def _stream(stream) -> Optional[int]:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream or None
+
+
+class Context:
+    """One libdil context (workspace pool) on one device."""
+
+    def __init__(self, device: int = 0, workspace_bytes: int = 0, mode: int = MODE_STAGED):
+        self.lib = load()
+        h = _P()
+        rc = self.lib.dil_ctx_create(ctypes.byref(h), device, workspace_bytes)
+        if rc:
+            raise DilError(rc, "context creation failed")
+        self.h = h
+        self.device = device
+        if mode != MODE_STAGED:
+            self.set_mode(mode)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dil_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != DIL_OK:
+            raise DilError(rc, self.lib.dil_last_error(self.h).decode(errors="replace"))
+
+    def set_mode(self, mode: int):
+        self._check(self.lib.dil_ctx_set_mode(self.h, mode))
+
+    def check(self, stream=None):
+        self._check(self.lib.dil_ctx_check(self.h, _stream(stream)))
+
+    def keygen(self, level: int, seeds, pk, sk, stream=None):
+        n = seeds.shape[0]
+        self._check(self.lib.dil_keygen_batch(self.h, level, _ptr(seeds), _ptr(pk), _ptr(sk), n, _stream(stream)))
+
+    def sign(self, level: int, sk, msg, msg_off, sig, key_idx=None, stream=None):
+        n = msg_off.shape[0] - 1
+        self._check(self.lib.dil_sign_batch(self.h, level, _ptr(sk), _ptr(key_idx), _ptr(msg) or _ptr(msg_off),
+                                            _ptr(msg_off), _ptr(sig), n, _stream(stream)))
+
+    def verify(self, level: int, pk, msg, msg_off, sig, verdict, key_idx=None, stream=None):
+        n = msg_off.shape[0] - 1
+        self._check(self.lib.dil_verify_batch(self.h, level, _ptr(pk), _ptr(key_idx), _ptr(msg) or _ptr(msg_off),
+                                              _ptr(msg_off), _ptr(sig), _ptr(verdict), n, _stream(stream)))
+
+    def sign_stats(self) -> Tuple[int, int]:
+        ev, sq = ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self.lib.dil_sign_stats(self.h, ctypes.byref(ev), ctypes.byref(sq)))
+        return ev.value, sq.value
+
+    def ntt_mul(self, a, b, c, stream=None):
+        self._check(self.lib.dil_ntt_mul_batch(self.h, _ptr(a), _ptr(b), _ptr(c), a.shape[0], _stream(stream)))
+
+    def expand_a(self, seeds34, out, stream=None):
+        self._check(self.lib.dil_expand_a_batch(self.h, _ptr(seeds34), _ptr(out), seeds34.shape[0],
+                                                _stream(stream)))

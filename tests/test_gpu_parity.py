@@ -1,0 +1,176 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle, element by
+element on the same seeded inputs.  All outputs are integers/bytes: bit-exact."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_12265_amd import workload
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    c = dl.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("count", [1, 17, 4096 + 13])
+def test_ntt_mul_parity(ctx, count):
+    a = workload.uniform_polys(count, seed=count)
+    b = workload.uniform_polys(count, seed=count, tag="dil/poly2")
+    c = torch.zeros((count, 256), dtype=torch.int32, device="cuda")
+    ctx.ntt_mul(dev(a), dev(b), c)
+    torch.cuda.synchronize()
+    assert np.array_equal(c.cpu().numpy(), oracle.ntt_mul_batch(a, b))
+
+
+def test_ntt_mul_edge_values(ctx):
+    q = oracle.Q
+    a = np.stack([np.zeros(256, np.int32), np.full(256, q - 1, np.int32), np.eye(1, 256, 255, dtype=np.int32)[0],
+                  np.eye(1, 256, 0, dtype=np.int32)[0]])
+    b = np.stack([np.full(256, q - 1, np.int32), np.full(256, q - 1, np.int32), np.full(256, 1, np.int32),
+                  np.arange(256, dtype=np.int32)])
+    c = torch.zeros((4, 256), dtype=torch.int32, device="cuda")
+    ctx.ntt_mul(dev(a), dev(b), c)
+    torch.cuda.synchronize()
+    assert np.array_equal(c.cpu().numpy(), oracle.ntt_mul_batch(a, b))
+
+
+@pytest.mark.parametrize("count", [1, 64, 4096 + 5])
+def test_expand_a_parity(ctx, count):
+    seeds = workload.expand_a_inputs(count, seed=count)
+    out = torch.zeros((count, 256), dtype=torch.int32, device="cuda")
+    ctx.expand_a(dev(seeds), out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.expand_a_polys(seeds))
+
+
+def _keygen(ctx, level, seeds):
+    from paper_2211_12265_amd import dilithium as dl
+    pkl, skl, _ = dl.sizes(level)
+    n = seeds.shape[0]
+    pk = torch.zeros((n, pkl), dtype=torch.uint8, device="cuda")
+    sk = torch.zeros((n, skl), dtype=torch.uint8, device="cuda")
+    ctx.keygen(level, dev(seeds), pk, sk)
+    torch.cuda.synchronize()
+    return pk, sk
+
+
+@pytest.mark.parametrize("level", [2, 3, 5])
+def test_keygen_parity(ctx, level):
+    seeds = workload.keygen_seeds(64, seed=level)
+    pk, sk = _keygen(ctx, level, seeds)
+    opk, osk = oracle.keygen_batch(level, seeds)
+    assert np.array_equal(pk.cpu().numpy(), opk)
+    assert np.array_equal(sk.cpu().numpy(), osk)
+
+
+def _sign(ctx, level, sk, msg, off, key_idx=None):
+    from paper_2211_12265_amd import dilithium as dl
+    n = off.size - 1
+    sig = torch.zeros((n, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
+    ctx.sign(level, sk, dev(msg), dev(off.astype(np.int64)), sig,
+             key_idx=None if key_idx is None else dev(key_idx.astype(np.int32)))
+    torch.cuda.synchronize()
+    return sig
+
+
+def _verify(ctx, level, pk, msg, off, sig, key_idx=None):
+    n = off.size - 1
+    v = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+    ctx.verify(level, pk, dev(msg), dev(off.astype(np.int64)), sig, v,
+               key_idx=None if key_idx is None else dev(key_idx.astype(np.int32)))
+    torch.cuda.synchronize()
+    return v.cpu().numpy()
+
+
+@pytest.mark.parametrize("level", [2, 3, 5])
+def test_sign_verify_parity(ctx, level):
+    n = 64
+    seeds = workload.keygen_seeds(n, seed=10 + level)
+    pk, sk = _keygen(ctx, level, seeds)
+    # ragged lengths including 0, 1, rate boundaries and unaligned offsets
+    lens = workload.uniform_lengths(n, 0, 600, seed=level)
+    lens[:6] = [0, 1, 103, 104, 105, 239]
+    msg, off = workload.messages(lens, seed=level)
+    sig = _sign(ctx, level, sk, msg, off)
+    osig, iters = oracle.sign_batch(level, sk.cpu().numpy(), msg, off)
+    got = sig.cpu().numpy()
+    bad = [i for i in range(n) if not np.array_equal(got[i], osig[i])]
+    assert not bad, f"signature mismatch for tasks {bad[:8]} (iters {iters[bad[:8]]})"
+    assert _verify(ctx, level, pk, msg, off, sig).tolist() == [1] * n
+    assert oracle.verify_batch(level, pk.cpu().numpy(), msg, off, got).tolist() == [1] * n
+
+
+@pytest.mark.parametrize("level", [2, 3, 5])
+def test_sign_key_idx(ctx, level):
+    seeds = workload.keygen_seeds(4, seed=30 + level)
+    pk, sk = _keygen(ctx, level, seeds)
+    kidx = np.array([3, 0, 3, 1, 2, 2, 0], dtype=np.uint32)
+    msg, off = workload.messages(workload.fixed_lengths(7, 32), seed=31)
+    sig = _sign(ctx, level, sk, msg, off, key_idx=kidx)
+    osig, _ = oracle.sign_batch(level, sk.cpu().numpy(), msg, off, key_idx=kidx)
+    assert np.array_equal(sig.cpu().numpy(), osig)
+    assert _verify(ctx, level, pk, msg, off, sig, key_idx=kidx).tolist() == [1] * 7
+    wrong = np.array([0, 1, 0, 0, 0, 0, 1], dtype=np.uint32)
+    assert _verify(ctx, level, pk, msg, off, sig, key_idx=wrong).tolist() == [0] * 7
+
+
+def test_verify_every_bit_flip_level2(ctx):
+    level = 2
+    seeds = workload.keygen_seeds(1, seed=41)
+    pk, sk = _keygen(ctx, level, seeds)
+    msg, off = workload.messages(workload.fixed_lengths(1, 32), seed=41)
+    sig = _sign(ctx, level, sk, msg, off).cpu().numpy()
+    nbits = sig.shape[1] * 8
+    flipped = np.repeat(sig, nbits, axis=0)
+    bit = np.arange(nbits)
+    flipped[bit, bit // 8] ^= (1 << (bit % 8)).astype(np.uint8)
+    msgs = np.tile(msg[:32], nbits)
+    offs = np.arange(nbits + 1, dtype=np.uint64) * 32
+    kidx = np.zeros(nbits, np.uint32)
+    v = _verify(ctx, level, pk, msgs, offs, dev(flipped), key_idx=kidx)
+    assert v.sum() == 0
+    ov = oracle.verify_batch(level, pk.cpu().numpy(), msgs, offs, flipped, key_idx=kidx)
+    assert np.array_equal(v, ov)
+
+
+@pytest.mark.parametrize("level", [3, 5])
+def test_verify_bit_flips_and_message_flips(ctx, level):
+    seeds = workload.keygen_seeds(1, seed=50 + level)
+    pk, sk = _keygen(ctx, level, seeds)
+    msg, off = workload.messages(workload.fixed_lengths(1, 40), seed=50)
+    sig = _sign(ctx, level, sk, msg, off).cpu().numpy()
+    nbits = sig.shape[1] * 8
+    bits = np.unique(np.concatenate([np.arange(0, nbits, 5), np.arange(nbits - 8 * 90, nbits)]))
+    flipped = np.repeat(sig, bits.size, axis=0)
+    flipped[np.arange(bits.size), bits // 8] ^= (1 << (bits % 8)).astype(np.uint8)
+    v = _verify(ctx, level, pk, np.tile(msg, bits.size), np.arange(bits.size + 1, dtype=np.uint64) * 40,
+                dev(flipped), key_idx=np.zeros(bits.size, np.uint32))
+    assert v.sum() == 0
+    nb = 40 * 8
+    msgs = np.tile(msg, (nb, 1))
+    msgs[np.arange(nb), np.arange(nb) // 8] ^= (1 << (np.arange(nb) % 8)).astype(np.uint8)
+    v = _verify(ctx, level, pk, msgs.reshape(-1), np.arange(nb + 1, dtype=np.uint64) * 40,
+                dev(np.repeat(sig, nb, axis=0)), key_idx=np.zeros(nb, np.uint32))
+    assert v.sum() == 0
+
+
+def test_empty_batch_and_bad_level(ctx):
+    from paper_2211_12265_amd import dilithium as dl
+    z = torch.zeros(1, dtype=torch.uint8, device="cuda")
+    off = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ctx.sign(2, z, z, off, z)   # count 0: no-op
+    with pytest.raises(dl.DilError):
+        ctx.sign(4, z, z, torch.zeros(2, dtype=torch.int64, device="cuda"), z)
