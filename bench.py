@@ -1,0 +1,220 @@
+"""Benchmark: Dilithium2 batch of 10,000 Sign + 10,000 Verify on one MI355X.
+
+One step = dil_sign_batch over 10,000 tasks (32-byte messages, one key per
+task) followed by dil_verify_batch over the 10,000 signatures just produced,
+all buffers resident in HBM.  Keys are generated on the GPU before timing.
+Prints ONE JSON line (rank 0).  See the design doc for the roofline conventions.
+
+  python bench.py [--steps K] [--warmup W] [--mode persistent|staged]
+                  [--count N] [--level 2|3|5] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per operation in int32 lane-ops (a 64-bit logical op or
+# rotation counts as two 32-bit ops): Keccak-f[1600] 7440 per permutation,
+# one NTT or INTT 7168 (1024 butterflies x (4 mul + 3 add/sub)), one pointwise
+# product 1536 (256 x 6).  Per-level counts of permutations / transforms /
+# pointwise products per Sign iteration and per fixed part of each operation:
+PERM_OPS, XFORM_OPS, PW_OPS = 7440, 7168, 1536
+PER_LEVEL = {
+    # level: (k, l)
+    2: (4, 4), 3: (6, 5), 5: (8, 7),
+}
+# SHAKE blocks: rate 136 (SHAKE256), 168 (SHAKE128)
+W1_BYTES = {2: 4 * 192, 3: 6 * 128, 5: 8 * 128}
+PK_BYTES = {2: 1312, 3: 1952, 5: 2592}
+SK_BYTES = {2: 2528, 3: 4000, 5: 4864}
+SIG_BYTES = {2: 2420, 3: 3293, 5: 4595}
+PEAK_INT32_OPS = 256 * 4 * 32 * 2.4e9   # 78.6 T int32 lane-ops/s
+
+
+def perms_shake(inlen: int, outlen: int, rate: int) -> int:
+    return inlen // rate + 1 + max(0, -(-outlen // rate) - 1)
+
+
+def sign_iteration_ops(level: int) -> float:
+    """Algorithmic int32 ops of one Sign loop iteration (Alg. 2 loop body)."""
+    k, l = PER_LEVEL[level]
+    it_perms = l * perms_shake(66, 576 if level == 2 else 640, 136) + perms_shake(64 + W1_BYTES[level], 32, 136) + 1
+    it_x = l + k + 1 + l + 2 * k          # NTT(y), INTT(w), NTT(c), INTT(c s1), INTT(c s2), INTT(c t0)
+    it_pw = k * l + l + 2 * k             # A y, c s1, c s2, c t0
+    return it_perms * PERM_OPS + it_x * XFORM_OPS + it_pw * PW_OPS
+
+
+def sign_setup_ops(level: int, msg_lens: np.ndarray) -> float:
+    """Algorithmic int32 ops of the per-task part before the loop (mu, rho', ExpandA, NTT of s1, s2, t0)."""
+    k, l = PER_LEVEL[level]
+    perms = sum(perms_shake(32 + int(m), 64, 136) for m in msg_lens)
+    perms += len(msg_lens) * (perms_shake(96, 64, 136) + k * l * 5)
+    return perms * PERM_OPS + len(msg_lens) * (l + 2 * k) * XFORM_OPS
+
+
+def sign_work(level: int, msg_lens: np.ndarray, iterations: int) -> float:
+    """Algorithmic int32 ops for a Sign batch with the given total (sequential) loop iterations."""
+    return sign_setup_ops(level, msg_lens) + iterations * sign_iteration_ops(level)
+
+
+def verify_work(level: int, msg_lens: np.ndarray) -> float:
+    k, l = PER_LEVEL[level]
+    n = len(msg_lens)
+    perms = n * (perms_shake(PK_BYTES[level], 32, 136) + k * l * 5 + 1 + perms_shake(64 + W1_BYTES[level], 32, 136))
+    perms += sum(perms_shake(32 + int(m), 64, 136) for m in msg_lens)
+    xf = n * (l + k + 1 + k)
+    pw = n * (k * l + k)
+    return perms * PERM_OPS + xf * XFORM_OPS + pw * PW_OPS
+
+
+def cpu_baseline(level: int, sample: int) -> dict:
+    import oracle
+    from paper_2211_12265_amd import workload
+    threads = oracle.default_threads()
+    pk, sk = oracle.keygen_batch(level, workload.keygen_seeds(sample, seed=99), nthreads=threads)
+    msg, off = workload.messages(workload.fixed_lengths(sample, 32), seed=99)
+    t0 = time.perf_counter()
+    sig, _ = oracle.sign_batch(level, sk, msg, off, nthreads=threads)
+    t1 = time.perf_counter()
+    v = oracle.verify_batch(level, pk, msg, off, sig, nthreads=threads)
+    t2 = time.perf_counter()
+    assert int(v.sum()) == sample
+    sign_s, ver_s = t1 - t0, t2 - t1
+    return {"value": sample / (sign_s + ver_s), "unit": "sign+verify pairs/s", "cores": threads, "kind": "oracle",
+            "sign_per_s": sample / sign_s, "verify_per_s": sample / ver_s,
+            "sample": f"{sample} Dilithium{level} sign + {sample} verify, 32-byte messages, plain C oracle on "
+                      f"{threads} host threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--count", type=int, default=10000)
+    ap.add_argument("--level", type=int, default=2, choices=[2, 3, 5])
+    ap.add_argument("--mode", default="persistent", choices=["persistent", "staged"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": src.numel() * 4, "launches": 5}), flush=True)
+        return
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only: the batched path runs on a single MI355X "
+              f"(--gpus {args.gpus} is not supported; see DESIGN.md for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import oracle
+    from paper_2211_12265_amd import dilithium as dl
+    from paper_2211_12265_amd import workload
+
+    dev = torch.device("cuda:0")
+    level, n = args.level, args.count
+    pkl, skl, sgl = dl.sizes(level)
+    ctx = dl.Context(0, mode=dl.MODE_PERSISTENT if args.mode == "persistent" else dl.MODE_STAGED)
+    seeds = workload.keygen_seeds(n, seed=0)
+    lens = workload.fixed_lengths(n, 32)
+    msg, off = workload.messages(lens, seed=0)
+    g_seeds = torch.from_numpy(seeds).to(dev)
+    pk = torch.zeros((n, pkl), dtype=torch.uint8, device=dev)
+    sk = torch.zeros((n, skl), dtype=torch.uint8, device=dev)
+    ctx.keygen(level, g_seeds, pk, sk)
+    g_msg = torch.from_numpy(msg).to(dev)
+    g_off = torch.from_numpy(off.astype(np.int64)).to(dev)
+    sig = torch.zeros((n, sgl), dtype=torch.uint8, device=dev)
+    ver = torch.zeros(n, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        ctx.sign(level, sk, g_msg, g_off, sig)
+        if ev is not None:
+            ev[1].record(stream)
+        ctx.verify(level, pk, g_msg, g_off, sig, ver)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if args.mode == "persistent":
+        ctx.set_param("timing", 1)
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sign_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    ver_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    evaluated, sequential = ctx.sign_stats()
+
+    # parity on sampled outputs of the timed configuration
+    idx = np.random.default_rng(5).choice(n, size=32, replace=False)
+    sk_h = sk.cpu().numpy()
+    sub_msg = np.concatenate([msg[int(off[i]):int(off[i + 1])] for i in idx])
+    sub_off = np.concatenate([[0], np.cumsum(lens[idx])]).astype(np.uint64)
+    osig, _ = oracle.sign_batch(level, sk_h[idx], sub_msg, sub_off)
+    parity_ok = bool(np.array_equal(sig.cpu().numpy()[idx], osig)) and bool((ver == 1).all().item())
+
+    ms_per_step = wall * 1e3 / args.steps
+    sign_rate = n / (np.median(sign_ms) * 1e-3)
+    ver_rate = n / (np.median(ver_ms) * 1e-3)
+    if args.mode == "persistent":
+        setup_ms, loop_ms = ctx.sign_timing()
+        loop_med = float(np.median(loop_ms))
+        k_ops = sequential * sign_iteration_ops(level)
+        achieved = k_ops / (loop_med * 1e-3)
+        kname = "sg_persist_k (persistent Sign rejection-loop kernel)"
+        kextra = {"kernel_ms_median": loop_med, "setup_ms_median": float(np.median(setup_ms)),
+                  "timed_launches": len(loop_ms), "ops_per_launch": k_ops}
+    else:
+        achieved = sign_work(level, lens, sequential) / (np.median(sign_ms) * 1e-3)
+        kname = "dil_sign_batch (whole staged Sign call)"
+        kextra = {}
+    out = {
+        "metric": "sign/s and verify/s, Dilithium2 batch 10k on 1 MI355X; p99 latency (serving)",
+        "value": n / (ms_per_step * 1e-3),
+        "unit": "sign+verify pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": f"Dilithium{level} batch {n} sign + {n} verify, 32-byte messages, one key per task, "
+                               f"device-resident buffers", "level": level, "batch": n, "msg_len": 32,
+                   "sign_mode": args.mode},
+        "sign_per_s": sign_rate, "verify_per_s": ver_rate,
+        "sign_ms_median": float(np.median(sign_ms)), "verify_ms_median": float(np.median(ver_ms)),
+        "sign_iterations": {"sequential": int(sequential), "evaluated": int(evaluated),
+                            "per_task": sequential / n},
+        "parity_sampled": parity_ok,
+        "roofline": dict({"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
+                          "unit": "T int32-ops/s", "frac": achieved / PEAK_INT32_OPS, "traffic": None,
+                          "kernel": kname}, **kextra),
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(level, args.cpu_sample)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

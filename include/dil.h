@@ -70,6 +70,12 @@ int dil_ctx_create(dil_ctx **out, int device, size_t workspace_bytes);
 int dil_ctx_destroy(dil_ctx *ctx);
 /* Select the Sign execution form (DIL_MODE_*). */
 int dil_ctx_set_mode(dil_ctx *ctx, int mode);
+/* Tuning knobs (0 = automatic):
+ *   "persist.grid"  workgroups launched by the persistent Sign kernel;
+ *   "persist.hmax"  tasks one workgroup holds at a time (1..slots per batch);
+ *   "timing"        1 = record HIP events around the persistent Sign's setup
+ *                   kernels and its loop kernel (read with dil_sign_timing). */
+int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value);
 /* Synchronise `stream` and report a device-detected input error (DIL_EMSG) once. */
 int dil_ctx_check(dil_ctx *ctx, void *stream);
 /* Text of the last error on this context (static storage inside the context). */
@@ -100,6 +106,14 @@ int dil_verify_batch(dil_ctx *ctx, int level, const uint8_t *pk, const uint32_t 
  * on this context evaluated in total, and the number the sequential algorithm
  * needs (sum over tasks of the winning iteration index + 1).  Synchronises. */
 int dil_sign_stats(dil_ctx *ctx, uint64_t *evaluated, uint64_t *sequential);
+
+/* Event-measured durations (ms) of the most recent persistent dil_sign_batch
+ * calls made since the "timing" parameter was set (at most 64 are kept):
+ * setup kernels (mu, rho', ExpandA, secret NTTs) and the persistent
+ * rejection-loop kernel, oldest first.  Fills at most max_calls entries of
+ * each caller-owned array (either may be NULL), stores the number filled in
+ * *n_calls, and synchronises on the recorded events. */
+int dil_sign_timing(dil_ctx *ctx, float *setup_ms, float *loop_ms, int max_calls, int *n_calls);
 
 /* Primitive: c_i = INTT(NTT(a_i) o b_i) for count polynomials of 256
  * coefficients (Sec. 2.2), a and b canonical int32 in [0, q), b read as

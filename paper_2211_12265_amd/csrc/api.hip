@@ -7,7 +7,7 @@
 #include <mutex>
 
 #include "../../include/dil.h"
-#include "kernels.h"
+#include "persist.h"
 
 using namespace dil;
 
@@ -19,7 +19,14 @@ struct dil_ctx {
   uint32_t *host_counters = nullptr;  // pinned, 16 words
   char err[256] = {0};
   uint64_t stat_evaluated = 0, stat_sequential = 0;
-  int pending_msg_error = 0;
+  uint32_t *dev_stats = nullptr;      // 16 words: statistics of the last persistent Sign
+  hipStream_t last_stream = nullptr;
+  int stats_pending = 0;
+  int64_t persist_grid = 0, persist_hmax = 0;  // 0 = automatic
+  int timing = 0;                              // record HIP events around the persistent Sign phases
+  static constexpr int RING = 64;
+  hipEvent_t ev[RING][3] = {};                 // per timed call: before setup, before loop, after loop
+  int ev_count = 0;                            // timed calls recorded since timing was (re)enabled
 };
 
 namespace {
@@ -56,8 +63,15 @@ size_t ws_need(size_t cap) {
 }
 
 template <int LV>
-int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws) {
-  size_t need = ws_need<LV>(cap);
+size_t pscr_need(size_t grid) {
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfg<LV>::G;
+  size_t w1s = ((size_t)K * P<LV>::W1B + 255) & ~(size_t)255;
+  return grid * G * ((size_t)(L + K) * 1024 + w1s) + 3 * 256;
+}
+
+template <int LV>
+int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws, size_t grid = 0, PScr *sc = nullptr) {
+  size_t need = ws_need<LV>(cap) + (sc ? pscr_need<LV>(grid) : 0);
   if (need > ctx->ws_bytes) {
     if (ctx->ws_mem) {
       hipDeviceSynchronize();
@@ -97,7 +111,28 @@ int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws) {
   ws.flag = (int32_t *)take(cap * 4);
   ws.active0 = (uint32_t *)take(cap * 4);
   ws.active1 = (uint32_t *)take(cap * 4);
+  if (sc) {
+    constexpr int G = PCfg<LV>::G;
+    size_t w1s = ((size_t)K * P<LV>::W1B + 255) & ~(size_t)255;
+    sc->y = (int32_t *)take(grid * G * L * 1024);
+    sc->w = (int32_t *)take(grid * G * K * 1024);
+    sc->w1 = take(grid * G * w1s);
+  }
   if ((size_t)(p - (uint8_t *)ctx->ws_mem) > ctx->ws_bytes) return fail(ctx, DIL_ENOMEM, "workspace layout overflow");
+  return DIL_OK;
+}
+
+// read and clear the device-side message-offset error flag (synchronises `st`)
+int take_msg_error(dil_ctx *ctx, hipStream_t st) {
+  uint32_t flag = 0;
+  HIPCHK(ctx, hipMemcpyAsync(ctx->host_counters + 8, ctx->dev_stats + 8, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  flag = ctx->host_counters[8];
+  if (flag) {
+    HIPCHK(ctx, hipMemsetAsync(ctx->dev_stats + 8, 0, 4, st));
+    HIPCHK(ctx, hipStreamSynchronize(st));
+    return fail(ctx, DIL_EMSG, "decreasing msg_off entry (those messages were treated as empty)");
+  }
   return DIL_OK;
 }
 
@@ -126,7 +161,7 @@ int sign_staged(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const 
   int rc = ws_carve<LV>(ctx, count, ws);
   if (rc) return rc;
   HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
-  sg_prep_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, ws, count);
+  sg_prep_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, ws, count, ctx->dev_stats + 8);
   expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(sk, P<LV>::SK, key_idx, ws.A, count);
   sg_secret_k<LV><<<count, 64, 0, st>>>(sk, key_idx, ws, count);
   LAUNCHCHK(ctx);
@@ -143,18 +178,49 @@ int sign_staged(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const 
     sg_chal_k<LV><<<blocks_for(nactive, 64), 64, 0, st>>>(ws, cur, nactive);
     sg_check_k<LV><<<nactive, 64, 0, st>>>(ws, sig, cur, nactive, nxt);
     LAUNCHCHK(ctx);
-    HIPCHK(ctx, hipMemcpyAsync(ctx->host_counters, ws.counters, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->host_counters, ws.counters, 4, hipMemcpyDeviceToHost, st));
     HIPCHK(ctx, hipStreamSynchronize(st));
     nactive = ctx->host_counters[0];
-    if (ctx->host_counters[1]) ctx->pending_msg_error = 1;
     std::swap(cur, nxt);
   }
   ctx->stat_evaluated = evaluated;
   ctx->stat_sequential = evaluated;
-  if (ctx->pending_msg_error) {
-    ctx->pending_msg_error = 0;
-    return fail(ctx, DIL_EMSG, "decreasing msg_off entry");
+  return take_msg_error(ctx, st);
+}
+
+template <int LV>
+int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                    const uint64_t *msg_off, uint8_t *sig, uint32_t count, hipStream_t st) {
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfg<LV>::G;
+  int per_cu = 0;
+  HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sg_persist_k<LV>, 64, 0));
+  hipDeviceProp_t prop;
+  HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
+  uint64_t pmax = (uint64_t)std::max(per_cu, 1) * prop.multiProcessorCount;
+  uint64_t hmax = ctx->persist_hmax > 0 ? (uint64_t)ctx->persist_hmax : (count + pmax - 1) / pmax;
+  hmax = std::min<uint64_t>(std::max<uint64_t>(hmax, 1), G);
+  uint64_t grid = ctx->persist_grid > 0 ? (uint64_t)ctx->persist_grid : std::min<uint64_t>(pmax, (count + hmax - 1) / hmax);
+  grid = std::max<uint64_t>(grid, 1);
+  Ws ws;
+  PScr sc;
+  int rc = ws_carve<LV>(ctx, count, ws, grid, &sc);
+  if (rc) return rc;
+  HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
+  HIPCHK(ctx, hipMemsetAsync(ctx->dev_stats, 0, 8 * 4, st));
+  hipEvent_t *evs = ctx->timing ? ctx->ev[ctx->ev_count % dil_ctx::RING] : nullptr;
+  if (evs) HIPCHK(ctx, hipEventRecord(evs[0], st));
+  sg_prep_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, ws, count, ctx->dev_stats + 8);
+  expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(sk, P<LV>::SK, key_idx, ws.A, count);
+  sg_secret_k<LV><<<count, 64, 0, st>>>(sk, key_idx, ws, count);
+  if (evs) HIPCHK(ctx, hipEventRecord(evs[1], st));
+  sg_persist_k<LV><<<(unsigned)grid, 64, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+  if (evs) {
+    HIPCHK(ctx, hipEventRecord(evs[2], st));
+    ctx->ev_count++;
   }
+  LAUNCHCHK(ctx);
+  ctx->last_stream = st;
+  ctx->stats_pending = 1;
   return DIL_OK;
 }
 
@@ -166,7 +232,7 @@ int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const 
   int rc = ws_carve<LV>(ctx, count, ws);
   if (rc) return rc;
   HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
-  vf_prep_k<LV><<<blocks_for(count, 64), 64, 0, st>>>(pk, key_idx, msg, msg_off, sig, ws, count);
+  vf_prep_k<LV><<<blocks_for(count, 64), 64, 0, st>>>(pk, key_idx, msg, msg_off, sig, ws, count, ctx->dev_stats + 8);
   expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(pk, P<LV>::PK, key_idx, ws.A, count);
   vf_main_k<LV><<<count, 64, 0, st>>>(pk, key_idx, sig, ws, count);
   vf_final_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sig, ws, verdict, count);
@@ -204,6 +270,13 @@ int dil_ctx_create(dil_ctx **out, int device, size_t workspace_bytes) {
     return DIL_ENOMEM;
   }
   memset(c->host_counters, 0, 64);
+  e = hipMalloc((void **)&c->dev_stats, 64);
+  if (e == hipSuccess) e = hipMemset(c->dev_stats, 0, 64);
+  if (e != hipSuccess) {
+    hipHostFree(c->host_counters);
+    delete c;
+    return DIL_ENOMEM;
+  }
   if (workspace_bytes) {
     e = hipMalloc(&c->ws_mem, workspace_bytes);
     if (e != hipSuccess) {
@@ -223,28 +296,42 @@ int dil_ctx_destroy(dil_ctx *ctx) {
   hipDeviceSynchronize();
   if (ctx->ws_mem) hipFree(ctx->ws_mem);
   if (ctx->host_counters) hipHostFree(ctx->host_counters);
+  if (ctx->dev_stats) hipFree(ctx->dev_stats);
+  for (int r = 0; r < dil_ctx::RING; r++)
+    for (int i = 0; i < 3; i++)
+      if (ctx->ev[r][i]) hipEventDestroy(ctx->ev[r][i]);
   delete ctx;
   return DIL_OK;
 }
 
 int dil_ctx_set_mode(dil_ctx *ctx, int mode) {
   if (!ctx) return DIL_EINVAL;
-  if (mode != DIL_MODE_STAGED) return fail(ctx, DIL_EINVAL, "unsupported mode");
+  if (mode != DIL_MODE_STAGED && mode != DIL_MODE_PERSISTENT) return fail(ctx, DIL_EINVAL, "unsupported mode");
   ctx->mode = mode;
   return DIL_OK;
 }
 
 int dil_ctx_check(dil_ctx *ctx, void *stream) {
   if (!ctx) return DIL_EINVAL;
-  HIPCHK(ctx, hipStreamSynchronize((hipStream_t)stream));
-  if (ctx->pending_msg_error) {
-    ctx->pending_msg_error = 0;
-    return fail(ctx, DIL_EMSG, "decreasing msg_off entry");
-  }
-  return DIL_OK;
+  hipSetDevice(ctx->device);
+  return take_msg_error(ctx, (hipStream_t)stream);
 }
 
 const char *dil_last_error(dil_ctx *ctx) { return ctx ? ctx->err : "null context"; }
+
+int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value) {
+  if (!ctx || !name) return DIL_EINVAL;
+  if (!strcmp(name, "timing")) {
+    if (value && !ctx->ev[0][0])
+      for (int r = 0; r < dil_ctx::RING; r++)
+        for (int i = 0; i < 3; i++) HIPCHK(ctx, hipEventCreate(&ctx->ev[r][i]));
+    ctx->timing = value != 0;
+    ctx->ev_count = 0;
+  } else if (!strcmp(name, "persist.grid")) ctx->persist_grid = value;
+  else if (!strcmp(name, "persist.hmax")) ctx->persist_hmax = value;
+  else return fail(ctx, DIL_EINVAL, "unknown parameter");
+  return DIL_OK;
+}
 
 int dil_sizes(int level, size_t *pk, size_t *sk, size_t *sig) {
   return by_level(level, [&](auto lv) {
@@ -273,7 +360,10 @@ int dil_sign_batch(dil_ctx *ctx, int level, const uint8_t *sk, const uint32_t *k
   if (count == 0) return DIL_OK;
   if (!sk || !msg || !msg_off || !sig) return fail(ctx, DIL_EINVAL, "null buffer");
   hipSetDevice(ctx->device);
+  ctx->stats_pending = 0;
   return by_level(level, [&](auto lv) {
+    if (ctx->mode == DIL_MODE_PERSISTENT)
+      return sign_persistent<decltype(lv)::value>(ctx, sk, key_idx, msg, msg_off, sig, count, (hipStream_t)stream);
     return sign_staged<decltype(lv)::value>(ctx, sk, key_idx, msg, msg_off, sig, count, (hipStream_t)stream);
   });
 }
@@ -290,8 +380,33 @@ int dil_verify_batch(dil_ctx *ctx, int level, const uint8_t *pk, const uint32_t 
   });
 }
 
+int dil_sign_timing(dil_ctx *ctx, float *setup_ms, float *loop_ms, int max_calls, int *n_calls) {
+  if (!ctx) return DIL_EINVAL;
+  int n = std::min(ctx->ev_count, dil_ctx::RING);
+  if (max_calls < n) n = max_calls;
+  if (n_calls) *n_calls = n;
+  for (int k = 0; k < n; k++) {
+    hipEvent_t *e = ctx->ev[(ctx->ev_count - n + k) % dil_ctx::RING];
+    HIPCHK(ctx, hipEventSynchronize(e[2]));
+    float a = 0, b = 0;
+    HIPCHK(ctx, hipEventElapsedTime(&a, e[0], e[1]));
+    HIPCHK(ctx, hipEventElapsedTime(&b, e[1], e[2]));
+    if (setup_ms) setup_ms[k] = a;
+    if (loop_ms) loop_ms[k] = b;
+  }
+  return DIL_OK;
+}
+
 int dil_sign_stats(dil_ctx *ctx, uint64_t *evaluated, uint64_t *sequential) {
   if (!ctx) return DIL_EINVAL;
+  if (ctx->stats_pending) {
+    HIPCHK(ctx, hipStreamSynchronize(ctx->last_stream));
+    HIPCHK(ctx, hipMemcpy(ctx->host_counters, ctx->dev_stats, 32, hipMemcpyDeviceToHost));
+    ctx->stat_evaluated = (uint64_t)ctx->host_counters[2] | ((uint64_t)ctx->host_counters[3] << 32);
+    ctx->stat_sequential = (uint64_t)ctx->host_counters[6] | ((uint64_t)ctx->host_counters[7] << 32);
+    ctx->stats_pending = 0;
+    if (ctx->host_counters[5]) return fail(ctx, DIL_EHIP, "a task exceeded the iteration limit");
+  }
   if (evaluated) *evaluated = ctx->stat_evaluated;
   if (sequential) *sequential = ctx->stat_sequential;
   return DIL_OK;

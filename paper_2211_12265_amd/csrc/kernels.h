@@ -210,7 +210,7 @@ __global__ void __launch_bounds__(256) kg_tr_k(const uint8_t *pk, uint8_t *sk, u
 // mu = H(tr || M), rho' = H(K || mu); initialises kappa and the active list
 template <int LV>
 __global__ void __launch_bounds__(256) sg_prep_k(const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
-                                                 const uint64_t *msg_off, Ws ws, uint32_t count) {
+                                                 const uint64_t *msg_off, Ws ws, uint32_t count, uint32_t *err) {
   uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   size_t key = key_idx ? key_idx[t] : t;
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(256) sg_prep_k(const uint8_t *sk, const uint32
   uint64_t o0 = msg_off[t], o1 = msg_off[t + 1];
   uint64_t mlen = 0;
   if (o1 >= o0) mlen = o1 - o0;
-  else atomicOr((int *)&ws.counters[1], 1);
+  else atomicOr(err, 1u);  // decreasing msg_off: message treated as empty
   uint32_t s[50];
   shake_absorb<RATE256>(s, 32 + mlen, SrcCat{skr + 64, 32, msg + o0, 32 + mlen});
   uint32_t mu[16];
@@ -286,42 +286,37 @@ __global__ void __launch_bounds__(64) sg_secret_k(const uint8_t *sk, const uint3
   }
 }
 
-// ExpandMask: one lane per (active task, i < L)
+// ---- Sign iteration building blocks, shared by the staged kernels and the
+// ---- persistent kernel (same arithmetic in both execution forms)
+
+// ExpandMask stream i of iteration kappa (one lane)
 template <int LV>
-__global__ void __launch_bounds__(256) expand_mask_k(Ws ws, const uint32_t *active, uint32_t nactive) {
-  constexpr int L = Lv<LV>::L;
-  uint64_t st = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (st >= (uint64_t)nactive * L) return;
-  uint32_t task = active[st / L];
-  int i = (int)(st % L);
-  uint32_t kappa = ws.kappa[task];
+__device__ __forceinline__ void dev_expand_mask(const uint8_t *rhop, uint32_t kappa, int i, int32_t *y_out) {
   uint32_t s[50];
-  absorb_seed66(s, ws.rhop + (size_t)task * 64, (kappa + (uint32_t)i) & 0xFFFFu);
-  expand_mask_squeeze<P<LV>::ZBITS, Lv<LV>::GAMMA1>(s, ws.y + ((size_t)task * L + i) * N);
+  absorb_seed66(s, rhop, (kappa + (uint32_t)i) & 0xFFFFu);
+  expand_mask_squeeze<P<LV>::ZBITS, Lv<LV>::GAMMA1>(s, y_out);
 }
 
-// w = INTT(A * NTT(y)); w1 = HighBits(w) packed after mu
+// w = INTT(A-hat * NTT(y)) for one task by one wavefront: w (canonical) to
+// w_out, HighBits(w) packed into w1_out (4-byte aligned, K * W1B bytes).
+// hat: L*256 words of LDS; tr: this group's transpose region; w1buf: LDS staging.
 template <int LV>
-__global__ void __launch_bounds__(64) sg_w_k(Ws ws, const uint32_t *active, uint32_t nactive) {
+__device__ __forceinline__ void dev_compute_w(const int32_t *y, const int32_t *A, int32_t *w_out, uint8_t *w1_out,
+                                              int32_t *hat, int32_t *tr, uint32_t *w1buf, const Tw &ftw,
+                                              const Tw &itw, int lane) {
   using PP = P<LV>;
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
-  __shared__ PolyLds<LV> lds;
-  if (blockIdx.x >= nactive) return;
-  uint32_t task = active[blockIdx.x];
-  int lane = threadIdx.x, g = lane >> 4, t = lane & 15;
-  int32_t *tr = lds.tr + g * NTT_LDS_GROUP;
-  uint8_t *wb = (uint8_t *)lds.buf;
-  const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
+  int g = lane >> 4, t = lane & 15;
   for (int j = g; j < L; j += 4) {
     int32_t x[16];
-    load_strided(x, ws.y + ((size_t)task * L + j) * N, t);
+    load_strided(x, y + j * N, t);
     ntt16(x, ftw, tr, t);
 #pragma unroll
-    for (int r = 0; r < 16; r++) lds.hat[j * N + 16 * t + r] = x[r];
+    for (int r = 0; r < 16; r++) hat[j * N + 16 * t + r] = x[r];
   }
   wave_sync();
   for (int i = g; i < K; i += 4) {
-    const int32_t *Ai = ws.A + ((size_t)task * K + i) * L * N;
+    const int32_t *Ai = A + (size_t)i * L * N;
     int64_t acc[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) acc[r] = 0;
@@ -329,7 +324,7 @@ __global__ void __launch_bounds__(64) sg_w_k(Ws ws, const uint32_t *active, uint
       int32_t a[16];
       load_slots(a, Ai + j * N, t);
 #pragma unroll
-      for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * lds.hat[j * N + 16 * t + r];
+      for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * hat[j * N + 16 * t + r];
     }
     int32_t x[16];
 #pragma unroll
@@ -341,14 +336,14 @@ __global__ void __launch_bounds__(64) sg_w_k(Ws ws, const uint32_t *active, uint
       x[r] = canon(x[r]);
       w1[r] = highbits<LV>(x[r]);
     }
-    store_strided(x, ws.w + ((size_t)task * K + i) * N, t);
+    store_strided(x, w_out + i * N, t);
     uint32_t v[16];
     to_consecutive(w1, v, tr, t);
-    pack16_to_lds<PP::W1BITS>(v, wb + i * PP::W1B, t);
+    pack16_to_lds<PP::W1BITS>(v, (uint8_t *)w1buf + i * PP::W1B, t);
   }
   wave_sync();
-  uint32_t *dst = (uint32_t *)(ws.muw1 + (size_t)task * muw1_stride<LV>() + 64);
-  for (int w = lane; w < K * PP::W1B / 4; w += 64) dst[w] = lds.buf[w];
+  uint32_t *dst = (uint32_t *)w1_out;
+  for (int w = lane; w < K * PP::W1B / 4; w += 64) dst[w] = w1buf[w];
 }
 
 // SampleInBall on the lane's SHAKE256(ctilde) stream, into a per-lane 256-byte
@@ -382,76 +377,72 @@ __device__ __forceinline__ void sample_in_ball(uint32_t s[50], int8_t *c, uint8_
   }
 }
 
-// ctilde = H(mu || w1); c = SampleInBall(ctilde).  One lane per active task.
+// ctilde = H(mu || w1) (mu and packed w1 8-byte aligned); c = SampleInBall(ctilde) (one lane)
 template <int LV>
-__global__ void __launch_bounds__(64) sg_chal_k(Ws ws, const uint32_t *active, uint32_t nactive) {
-  __shared__ int8_t cl[64][N];
-  __shared__ uint32_t bb[64][RATE256 / 4];
-  uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= nactive) return;
-  uint32_t task = active[a];
-  const uint8_t *row = ws.muw1 + (size_t)task * muw1_stride<LV>();
+__device__ __forceinline__ void dev_challenge(const uint8_t *mu, const uint8_t *w1, uint32_t *ctilde_out, int8_t *c,
+                                              uint8_t *blockbuf) {
   uint32_t s[50];
-  shake_absorb<RATE256>(s, P<LV>::MUW1, [&](uint64_t pos) { return *(const uint64_t *)(row + pos); });
+  shake_absorb<RATE256>(s, P<LV>::MUW1, [&](uint64_t pos) {
+    return pos < 64 ? *(const uint64_t *)(mu + pos) : *(const uint64_t *)(w1 + (pos - 64));
+  });
   uint32_t ct[8];
 #pragma unroll
-  for (int i = 0; i < 8; i++) ct[i] = s[i];
-  uint32_t *cto = (uint32_t *)(ws.ctilde + (size_t)task * 32);
-#pragma unroll
-  for (int i = 0; i < 8; i++) cto[i] = ct[i];
+  for (int i = 0; i < 8; i++) {
+    ct[i] = s[i];
+    ctilde_out[i] = s[i];
+  }
   keccak_zero(s);
 #pragma unroll
   for (int i = 0; i < 8; i++) s[i] = ct[i];
   s[8] = 0x1Fu;
   s[2 * (RATE256 / 8 - 1) + 1] ^= 0x80u << 24;
   keccak_f(s);
-  int8_t *c = cl[threadIdx.x];
-  sample_in_ball<Lv<LV>::TAU>(s, c, (uint8_t *)bb[threadIdx.x]);
-  int4 *dst = (int4 *)(ws.cpoly + (size_t)task * N);
-  const int4 *src = (const int4 *)c;
-#pragma unroll
-  for (int w = 0; w < N / 16; w++) dst[w] = src[w];
+  sample_in_ball<Lv<LV>::TAU>(s, c, blockbuf);
 }
 
-// z = y + c s1, r0 = LowBits(w - c s2), c t0, hint; accept -> signature, reject -> next round
 template <int LV>
-__global__ void __launch_bounds__(64) sg_check_k(Ws ws, uint8_t *sig, const uint32_t *active, uint32_t nactive,
-                                                 uint32_t *next_active) {
+struct CheckLds {
+  int32_t tr[4 * NTT_LDS_GROUP];
+  uint32_t sigbuf[P<LV>::SIG / 4 + 2];
+  uint16_t hmask[Lv<LV>::K][16];
+  int rowcnt[Lv<LV>::K];
+};
+
+// The rejection checks of Alg. 2 for one candidate (one wavefront):
+// z = y + c s1, r0 = LowBits(w - c s2), c t0 and the hint.  c is the dense
+// challenge (int8, natural order).  Returns true (wave-uniform) if the
+// candidate passes all four checks; the packed signature (ctilde, z, h) is
+// then in lds.sigbuf.  Polynomials whose norm already fails stop the
+// evaluation early.
+template <int LV>
+__device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctilde, const int32_t *y, const int32_t *w,
+                                          const int32_t *s1h, const int32_t *s2h, const int32_t *t0h,
+                                          CheckLds<LV> &lds, const Tw &ftw, const Tw &itw, int lane) {
   using PP = P<LV>;
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L, BETA = Lv<LV>::BETA, OMEGA = Lv<LV>::OMEGA;
   constexpr int32_t G1 = Lv<LV>::GAMMA1, G2 = Lv<LV>::GAMMA2;
-  __shared__ int32_t trl[4 * NTT_LDS_GROUP];
-  __shared__ uint32_t sigbuf[PP::SIG / 4 + 2];
-  __shared__ uint16_t hmask[K][16];   // per row: per register r, the 16-lane hint mask
-  __shared__ int rowcnt[K];
-  if (blockIdx.x >= nactive) return;
-  uint32_t task = active[blockIdx.x];
-  int lane = threadIdx.x, g = lane >> 4, t = lane & 15;
-  int32_t *tr = trl + g * NTT_LDS_GROUP;
-  uint8_t *sb = (uint8_t *)sigbuf;
-  const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
+  int g = lane >> 4, t = lane & 15;
+  int32_t *tr = lds.tr + g * NTT_LDS_GROUP;
+  uint8_t *sb = (uint8_t *)lds.sigbuf;
   // c-hat, computed by every group
   int32_t ch[16];
-  {
-    const int8_t *cp = ws.cpoly + (size_t)task * N;
 #pragma unroll
-    for (int r = 0; r < 16; r++) ch[r] = cp[t + 16 * r];
-    ntt16(ch, ftw, tr, t);
-  }
+  for (int r = 0; r < 16; r++) ch[r] = c[t + 16 * r];
+  ntt16(ch, ftw, tr, t);
   bool bad = false;
   // z = y + c s1
   for (int j = g; j < L; j += 4) {
     int32_t s1[16], x[16];
-    load_slots(s1, ws.s1h + ((size_t)task * L + j) * N, t);
+    load_slots(s1, s1h + j * N, t);
 #pragma unroll
     for (int r = 0; r < 16; r++) x[r] = mont_mul(ch[r], s1[r]);
     intt16(x, itw, tr, t);
-    int32_t y[16];
-    load_strided(y, ws.y + ((size_t)task * L + j) * N, t);
+    int32_t yv[16];
+    load_strided(yv, y + j * N, t);
     int32_t zv[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) {
-      int32_t z = y[r] + canon(x[r]);              // in [-gamma1 + 1, q + gamma1)
+      int32_t z = yv[r] + canon(x[r]);             // in [-gamma1 + 1, q + gamma1)
       z = z > (Q - 1) / 2 ? z - Q : z;             // centred
       bad |= (z >= G1 - BETA) || (z <= -(G1 - BETA));
       zv[r] = G1 - z;
@@ -460,16 +451,16 @@ __global__ void __launch_bounds__(64) sg_check_k(Ws ws, uint8_t *sig, const uint
     to_consecutive(zv, v, tr, t);
     pack16_to_lds<PP::ZBITS>(v, sb + PP::OFF_Z + j * PP::ZB, t);
   }
-  if (wave_any(bad)) goto reject;
+  if (wave_any(bad)) return false;
   // r0 = LowBits(w - c s2), c t0 and the hint
   for (int i = g; i < K; i += 4) {
     int32_t s2[16], x[16], u[16];
-    load_slots(s2, ws.s2h + ((size_t)task * K + i) * N, t);
+    load_slots(s2, s2h + i * N, t);
 #pragma unroll
     for (int r = 0; r < 16; r++) x[r] = mont_mul(ch[r], s2[r]);
     intt16(x, itw, tr, t);
     int32_t wv[16];
-    load_strided(wv, ws.w + ((size_t)task * K + i) * N, t);
+    load_strided(wv, w + i * N, t);
     int32_t r1v[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) {
@@ -479,7 +470,7 @@ __global__ void __launch_bounds__(64) sg_check_k(Ws ws, uint8_t *sig, const uint
       r1v[r] = r1;
       bad |= (r0 >= G2 - BETA) || (r0 <= -(G2 - BETA));
     }
-    load_slots(u, ws.t0h + ((size_t)task * K + i) * N, t);
+    load_slots(u, t0h + i * N, t);
 #pragma unroll
     for (int r = 0; r < 16; r++) u[r] = mont_mul(ch[r], u[r]);
     intt16(u, itw, tr, t);
@@ -493,39 +484,96 @@ __global__ void __launch_bounds__(64) sg_check_k(Ws ws, uint8_t *sig, const uint
       bool h = highbits<LV>(sum) != r1v[r];
       uint64_t m = __ballot(h);
       uint32_t m16 = (uint32_t)(m >> (16 * g)) & 0xFFFFu;
-      if (t == 0) hmask[i][r] = (uint16_t)m16;
+      if (t == 0) lds.hmask[i][r] = (uint16_t)m16;
       cnt += __popc(m16);
     }
-    if (t == 0) rowcnt[i] = cnt;
+    if (t == 0) lds.rowcnt[i] = cnt;
   }
-  if (wave_any(bad)) goto reject;
+  if (wave_any(bad)) return false;
   wave_sync();
-  {
-    int total = 0;
-    for (int i = 0; i < K; i++) total += rowcnt[i];
-    if (total > OMEGA) goto reject;
-  }
-  // accepted: ctilde, hint bytes, copy out
-  if (lane < 8) sigbuf[lane] = ((const uint32_t *)(ws.ctilde + (size_t)task * 32))[lane];
+  int total = 0;
+  for (int i = 0; i < K; i++) total += lds.rowcnt[i];
+  if (total > OMEGA) return false;
+  // accepted: ctilde and the hint bytes
+  if (lane < 8) lds.sigbuf[lane] = ctilde[lane];
   for (int b = lane; b < OMEGA + K; b += 64) sb[PP::OFF_H + b] = 0;
   wave_sync();
   for (int i = g; i < K; i += 4) {
-    int base = 0;
-    for (int i2 = 0; i2 < i; i2++) base += rowcnt[i2];
-    int pre = base;
+    int pre = 0;
+    for (int i2 = 0; i2 < i; i2++) pre += lds.rowcnt[i2];
 #pragma unroll
     for (int r = 0; r < 16; r++) {
-      uint32_t m16 = hmask[i][r];
+      uint32_t m16 = lds.hmask[i][r];
       if ((m16 >> t) & 1u) sb[PP::OFF_H + pre + __popc(m16 & ((1u << t) - 1u))] = (uint8_t)(t + 16 * r);
       pre += __popc(m16);
     }
     if (t == 0) sb[PP::OFF_H + OMEGA + i] = (uint8_t)pre;
   }
   wave_sync();
-  l2g_bytes(sigbuf, PP::SIG, sig + (size_t)task * PP::SIG, lane, 64);
-  return;
-reject:
-  if (lane == 0) {
+  return true;
+}
+
+// ---- staged kernels ----
+// ExpandMask: one lane per (active task, i < L)
+template <int LV>
+__global__ void __launch_bounds__(256) expand_mask_k(Ws ws, const uint32_t *active, uint32_t nactive) {
+  constexpr int L = Lv<LV>::L;
+  uint64_t st = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (st >= (uint64_t)nactive * L) return;
+  uint32_t task = active[st / L];
+  int i = (int)(st % L);
+  dev_expand_mask<LV>(ws.rhop + (size_t)task * 64, ws.kappa[task], i, ws.y + ((size_t)task * L + i) * N);
+}
+
+// w = INTT(A * NTT(y)); w1 = HighBits(w) packed after mu
+template <int LV>
+__global__ void __launch_bounds__(64) sg_w_k(Ws ws, const uint32_t *active, uint32_t nactive) {
+  using PP = P<LV>;
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  __shared__ PolyLds<LV> lds;
+  if (blockIdx.x >= nactive) return;
+  uint32_t task = active[blockIdx.x];
+  int lane = threadIdx.x, t = lane & 15;
+  const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
+  dev_compute_w<LV>(ws.y + (size_t)task * L * N, ws.A + (size_t)task * K * L * N, ws.w + (size_t)task * K * N,
+                    ws.muw1 + (size_t)task * muw1_stride<LV>() + 64, lds.hat, lds.tr + (lane >> 4) * NTT_LDS_GROUP,
+                    lds.buf, ftw, itw, lane);
+  (void)PP::K;
+}
+
+// ctilde = H(mu || w1); c = SampleInBall(ctilde).  One lane per active task.
+template <int LV>
+__global__ void __launch_bounds__(64) sg_chal_k(Ws ws, const uint32_t *active, uint32_t nactive) {
+  __shared__ int8_t cl[64][N];
+  __shared__ uint32_t bb[64][RATE256 / 4];
+  uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= nactive) return;
+  uint32_t task = active[a];
+  int8_t *c = cl[threadIdx.x];
+  const uint8_t *row = ws.muw1 + (size_t)task * muw1_stride<LV>();
+  dev_challenge<LV>(row, row + 64, (uint32_t *)(ws.ctilde + (size_t)task * 32), c, (uint8_t *)bb[threadIdx.x]);
+  int4 *dst = (int4 *)(ws.cpoly + (size_t)task * N);
+  const int4 *src = (const int4 *)c;
+#pragma unroll
+  for (int w = 0; w < N / 16; w++) dst[w] = src[w];
+}
+
+// checks; accept -> signature row of the task, reject -> kappa += l and next round
+template <int LV>
+__global__ void __launch_bounds__(64) sg_check_k(Ws ws, uint8_t *sig, const uint32_t *active, uint32_t nactive,
+                                                 uint32_t *next_active) {
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  __shared__ CheckLds<LV> lds;
+  if (blockIdx.x >= nactive) return;
+  uint32_t task = active[blockIdx.x];
+  int lane = threadIdx.x, t = lane & 15;
+  const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
+  bool ok = dev_check<LV>(ws.cpoly + (size_t)task * N, (const uint32_t *)(ws.ctilde + (size_t)task * 32),
+                          ws.y + (size_t)task * L * N, ws.w + (size_t)task * K * N, ws.s1h + (size_t)task * L * N,
+                          ws.s2h + (size_t)task * K * N, ws.t0h + (size_t)task * K * N, lds, ftw, itw, lane);
+  if (ok) {
+    l2g_bytes(lds.sigbuf, P<LV>::SIG, sig + (size_t)task * P<LV>::SIG, lane, 64);
+  } else if (lane == 0) {
     ws.kappa[task] += L;
     uint32_t slot = atomicAdd(&ws.counters[0], 1u);
     next_active[slot] = task;
@@ -538,7 +586,8 @@ reject:
 // tr = H(pk), mu = H(tr || M), c = SampleInBall(ctilde), strict hint decoding
 template <int LV>
 __global__ void __launch_bounds__(64) vf_prep_k(const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
-                                                const uint64_t *msg_off, const uint8_t *sig, Ws ws, uint32_t count) {
+                                                const uint64_t *msg_off, const uint8_t *sig, Ws ws, uint32_t count,
+                                                uint32_t *err) {
   using PP = P<LV>;
   constexpr int K = Lv<LV>::K, OMEGA = Lv<LV>::OMEGA;
   __shared__ int8_t cl[64][N];
@@ -556,7 +605,7 @@ __global__ void __launch_bounds__(64) vf_prep_k(const uint8_t *pk, const uint32_
   uint64_t o0 = msg_off[t], o1 = msg_off[t + 1];
   uint64_t mlen = 0;
   if (o1 >= o0) mlen = o1 - o0;
-  else atomicOr((int *)&ws.counters[1], 1);
+  else atomicOr(err, 1u);  // decreasing msg_off: message treated as empty
   shake_absorb<RATE256>(s, 32 + mlen, SrcCat{(const uint8_t *)trg, 32, msg + o0, 32 + mlen});
   uint32_t *muw = (uint32_t *)(ws.muw1 + (size_t)t * muw1_stride<LV>());
 #pragma unroll

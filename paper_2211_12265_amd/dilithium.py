@@ -19,8 +19,10 @@ DIL_OK, DIL_EINVAL, DIL_ENOMEM, DIL_EHIP, DIL_EMSG = 0, -1, -2, -3, -4
 MODE_STAGED, MODE_PERSISTENT = 0, 1
 
 EXPORTS = [
-    "dil_ctx_create", "dil_ctx_destroy", "dil_ctx_set_mode", "dil_ctx_check", "dil_last_error", "dil_sizes",
-    "dil_keygen_batch", "dil_sign_batch", "dil_verify_batch", "dil_sign_stats", "dil_ntt_mul_batch",
+    "dil_ctx_create", "dil_ctx_destroy", "dil_ctx_set_mode", "dil_ctx_set_param", "dil_ctx_check",
+    "dil_last_error", "dil_sizes",
+    "dil_keygen_batch", "dil_sign_batch", "dil_verify_batch", "dil_sign_stats", "dil_sign_timing",
+    "dil_ntt_mul_batch",
     "dil_expand_a_batch",
 ]
 
@@ -47,6 +49,7 @@ def load() -> ctypes.CDLL:
         "dil_ctx_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, ctypes.c_size_t]),
         "dil_ctx_destroy": (ctypes.c_int, [_P]),
         "dil_ctx_set_mode": (ctypes.c_int, [_P, ctypes.c_int]),
+        "dil_ctx_set_param": (ctypes.c_int, [_P, ctypes.c_char_p, ctypes.c_int64]),
         "dil_ctx_check": (ctypes.c_int, [_P, _P]),
         "dil_last_error": (ctypes.c_char_p, [_P]),
         "dil_sizes": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_size_t),
@@ -55,6 +58,7 @@ def load() -> ctypes.CDLL:
         "dil_sign_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_uint32, _P]),
         "dil_verify_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_uint32, _P]),
         "dil_sign_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
+        "dil_sign_timing": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "dil_ntt_mul_batch": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_uint64, _P]),
         "dil_expand_a_batch": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, _P]),
     }
@@ -120,6 +124,9 @@ class Context:
     def set_mode(self, mode: int):
         self._check(self.lib.dil_ctx_set_mode(self.h, mode))
 
+    def set_param(self, name: str, value: int):
+        self._check(self.lib.dil_ctx_set_param(self.h, name.encode(), int(value)))
+
     def check(self, stream=None):
         self._check(self.lib.dil_ctx_check(self.h, _stream(stream)))
 
@@ -141,6 +148,15 @@ class Context:
         ev, sq = ctypes.c_uint64(), ctypes.c_uint64()
         self._check(self.lib.dil_sign_stats(self.h, ctypes.byref(ev), ctypes.byref(sq)))
         return ev.value, sq.value
+
+    def sign_timing(self, max_calls: int = 64):
+        """Lists (setup_ms, loop_ms) of the timed persistent Sign calls (set_param("timing", 1) first)."""
+        a = (ctypes.c_float * max_calls)()
+        b = (ctypes.c_float * max_calls)()
+        n = ctypes.c_int()
+        self._check(self.lib.dil_sign_timing(self.h, ctypes.cast(a, _P), ctypes.cast(b, _P), max_calls,
+                                             ctypes.byref(n)))
+        return list(a[:n.value]), list(b[:n.value])
 
     def ntt_mul(self, a, b, c, stream=None):
         self._check(self.lib.dil_ntt_mul_batch(self.h, _ptr(a), _ptr(b), _ptr(c), a.shape[0], _stream(stream)))

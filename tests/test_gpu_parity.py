@@ -21,6 +21,17 @@ def ctx():
     c.close()
 
 
+@pytest.fixture(scope="module", params=["staged", "persistent"])
+def sctx(request):
+    """A context per Sign execution form."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    c = dl.Context(0, mode=dl.MODE_STAGED if request.param == "staged" else dl.MODE_PERSISTENT)
+    yield c
+    c.close()
+
+
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
@@ -96,7 +107,8 @@ def _verify(ctx, level, pk, msg, off, sig, key_idx=None):
 
 
 @pytest.mark.parametrize("level", [2, 3, 5])
-def test_sign_verify_parity(ctx, level):
+def test_sign_verify_parity(sctx, level):
+    ctx = sctx
     n = 64
     seeds = workload.keygen_seeds(n, seed=10 + level)
     pk, sk = _keygen(ctx, level, seeds)
@@ -114,7 +126,8 @@ def test_sign_verify_parity(ctx, level):
 
 
 @pytest.mark.parametrize("level", [2, 3, 5])
-def test_sign_key_idx(ctx, level):
+def test_sign_key_idx(sctx, level):
+    ctx = sctx
     seeds = workload.keygen_seeds(4, seed=30 + level)
     pk, sk = _keygen(ctx, level, seeds)
     kidx = np.array([3, 0, 3, 1, 2, 2, 0], dtype=np.uint32)
@@ -174,3 +187,59 @@ def test_empty_batch_and_bad_level(ctx):
     ctx.sign(2, z, z, off, z)   # count 0: no-op
     with pytest.raises(dl.DilError):
         ctx.sign(4, z, z, torch.zeros(2, dtype=torch.int64, device="cuda"), z)
+
+
+@pytest.mark.parametrize("level", [2, 5])
+@pytest.mark.parametrize("grid,hmax", [(1, 1), (3, 2), (7, 16), (0, 0)])
+def test_persistent_schedules_match_oracle(level, grid, hmax):
+    """Every grid size / tasks-per-workgroup setting gives the sequential signatures:
+    with hmax < slots the spare slots evaluate speculative later iterations."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    c = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    c.set_param("persist.grid", grid)
+    c.set_param("persist.hmax", hmax)
+    n = 37
+    seeds = workload.keygen_seeds(n, seed=60 + level)
+    pk, sk = _keygen(c, level, seeds)
+    msg, off = workload.messages(workload.uniform_lengths(n, 0, 300, seed=61), seed=61)
+    sig = _sign(c, level, sk, msg, off)
+    ev, seq = c.sign_stats()
+    osig, iters = oracle.sign_batch(level, sk.cpu().numpy(), msg, off)
+    assert np.array_equal(sig.cpu().numpy(), osig)
+    assert seq == int(iters.sum())
+    assert ev >= seq
+    c.close()
+
+
+def test_staged_stats_count_sequential_iterations(ctx):
+    level = 2
+    n = 50
+    seeds = workload.keygen_seeds(n, seed=70)
+    pk, sk = _keygen(ctx, level, seeds)
+    msg, off = workload.messages(workload.fixed_lengths(n, 32), seed=70)
+    _sign(ctx, level, sk, msg, off)
+    ev, seq = ctx.sign_stats()
+    _, iters = oracle.sign_batch(level, sk.cpu().numpy(), msg, off)
+    assert ev == seq == int(iters.sum())
+
+
+def test_decreasing_msg_off_reported(sctx):
+    from paper_2211_12265_amd import dilithium as dl
+    level = 2
+    seeds = workload.keygen_seeds(3, seed=80)
+    pk, sk = _keygen(sctx, level, seeds)
+    msg = workload.random_bytes("test/m", 80, (64,))
+    off = np.array([0, 40, 20, 64], dtype=np.int64)   # task 1 has a negative length
+    sig = torch.zeros((3, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
+    with pytest.raises(dl.DilError) as ei:
+        sctx.sign(level, sk, dev(msg), dev(off), sig)
+        sctx.check()
+    assert ei.value.code == dl.DIL_EMSG
+    sctx.check()   # the flag is cleared once reported
+    v = torch.zeros(3, dtype=torch.int32, device="cuda")
+    sctx.verify(level, pk, dev(msg), dev(off), sig, v)
+    with pytest.raises(dl.DilError) as ei:
+        sctx.check()
+    assert ei.value.code == dl.DIL_EMSG
