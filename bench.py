@@ -94,6 +94,51 @@ def cpu_baseline(level: int, sample: int) -> dict:
                       f"{threads} host threads"}
 
 
+def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -> dict:
+    """Serving loop on 1024 resident key pairs (512 / 307 / 205 at levels 2 / 3 / 5): first a
+    saturation probe (all requests at t = 0), then a Poisson stream at half that rate."""
+    import torch
+    from paper_2211_12265_amd import dilithium as dl
+    from paper_2211_12265_amd import serving as sv
+    from paper_2211_12265_amd import workload
+    ctx = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    keys = {2: 512, 3: 307, 5: 205}
+    keysets = {}
+    for lv, nk in keys.items():
+        pkl, skl, _ = dl.sizes(lv)
+        pk = torch.zeros((nk, pkl), dtype=torch.uint8, device="cuda")
+        sk = torch.zeros((nk, skl), dtype=torch.uint8, device="cuda")
+        ctx.keygen(lv, torch.from_numpy(workload.keygen_seeds(nk, seed=300 + lv)).cuda(), pk, sk)
+        keysets[lv] = dl.KeySet(ctx, lv, pk=pk, sk=sk)
+    resident = sum(ks.device_bytes() for ks in keysets.values())
+    server = sv.Server(keysets, n_streams=streams, max_batch=max_batch, mem_budget=8 << 30)
+    # warm-up and saturation probe
+    warm = sv.build_requests(4000, lam=0.0, keys_per_level=keys, seed=11)
+    sv.attach_signatures(warm, ctx, keysets, seed=11)
+    server.serve(warm)
+    sat_reqs = sv.build_requests(n_requests, lam=0.0, keys_per_level=keys, seed=12)
+    sv.attach_signatures(sat_reqs, ctx, keysets, seed=12)
+    sat = server.serve(sat_reqs)
+    sat_rate = len(sat_reqs) / sat.wall
+    lam = 0.5 * sat_rate
+    count = int(min(max(n_requests, lam * seconds), 2_000_000))
+    reqs = sv.build_requests(count, lam=lam, keys_per_level=keys, seed=13)
+    flipped = sv.attach_signatures(reqs, ctx, keysets, seed=13)
+    res = server.serve(reqs)
+    summ = sv.latency_summary(res, reqs)
+    verify = reqs.op == sv.VERIFY
+    summ.update({"lambda_per_s": lam, "saturated_ops_per_s": sat_rate, "streams": streams, "max_batch": max_batch,
+                 "resident_key_bytes": resident, "flipped_rejected": bool((res.verdict[verify & flipped] == 0).all()),
+                 "valid_accepted": bool((res.verdict[verify & ~flipped] == 1).all()),
+                 "mix": "70% verify / 30% sign, levels 2/3/5 at 50/30/20%, lognormal messages (median 256 B, "
+                        "cap 16 KiB), 1024 resident key pairs"})
+    server.close()
+    for ks in keysets.values():
+        ks.close()
+    ctx.close()
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -104,6 +149,12 @@ def main():
     ap.add_argument("--mode", default="persistent", choices=["persistent", "staged"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--serving", action="store_true", help="also run the serving loop and report p50/p99")
+    ap.add_argument("--serving-only", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=100000)
+    ap.add_argument("--serving-seconds", type=float, default=5.0)
+    ap.add_argument("--serving-streams", type=int, default=4)
+    ap.add_argument("--serving-batch", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -120,6 +171,11 @@ def main():
         print(f"bench.py measures one GPU only: the batched path runs on a single MI355X "
               f"(--gpus {args.gpus} is not supported; see DESIGN.md for how it would shard)", file=sys.stderr)
         sys.exit(2)
+
+    if args.serving_only:
+        print(json.dumps({"serving": serving_run(args.serving_requests, args.serving_seconds, args.serving_streams,
+                                                 args.serving_batch)}), flush=True)
+        return
 
     import torch
     import oracle
@@ -212,6 +268,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(level, args.cpu_sample)
+    if args.serving:
+        out["serving"] = serving_run(args.serving_requests, args.serving_seconds, args.serving_streams,
+                                     args.serving_batch)
     ctx.close()
     print(json.dumps(out), flush=True)
 

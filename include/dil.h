@@ -102,6 +102,30 @@ int dil_sign_batch(dil_ctx *ctx, int level, const uint8_t *sk, const uint32_t *k
 int dil_verify_batch(dil_ctx *ctx, int level, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
                      const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count, void *stream);
 
+/* ---- Resident key tables (serving) ----
+ * A key table keeps n_keys key rows of one level on the device together with
+ * what Sign and Verify would otherwise recompute per call: A-hat = ExpandA(rho)
+ * (Alg. 1-3), NTT(s1), NTT(s2), NTT(t0) (Alg. 2) when secret keys are given,
+ * NTT(t1 2^d) and tr = H(pk) (Alg. 3) when public keys are given.  pk and sk
+ * are device arrays of n_keys rows (either may be NULL, not both; when both are
+ * given row i of each must be one key pair).  The table owns copies of the rows
+ * and may be used from any context on the same device, concurrently for
+ * reads.  Creation is enqueued on `stream`. */
+typedef struct dil_keyset dil_keyset;
+int dil_keyset_create(dil_ctx *ctx, int level, const uint8_t *pk, const uint8_t *sk, uint32_t n_keys,
+                      dil_keyset **out, void *stream);
+/* Waits for the device, then frees the table. */
+int dil_keyset_destroy(dil_keyset *ks);
+/* Level, number of keys and device bytes held by the table (any pointer may be NULL). */
+int dil_keyset_info(const dil_keyset *ks, int *level, uint32_t *n_keys, size_t *device_bytes);
+/* dil_sign_batch / dil_verify_batch against a key table: task i uses key row
+ * key_idx[i] (device array), or row i when key_idx is NULL.  Outputs are
+ * identical to the batch entry points given the same key rows. */
+int dil_sign_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx, const uint8_t *msg,
+                    const uint64_t *msg_off, uint8_t *sig, uint32_t count, void *stream);
+int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx, const uint8_t *msg,
+                      const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count, void *stream);
+
 /* Number of Sign loop iterations (candidate signatures) the last dil_sign_batch
  * on this context evaluated in total, and the number the sequential algorithm
  * needs (sum over tasks of the winning iteration index + 1).  Synchronises. */

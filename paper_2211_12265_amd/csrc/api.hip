@@ -29,6 +29,15 @@ struct dil_ctx {
   int ev_count = 0;                            // timed calls recorded since timing was (re)enabled
 };
 
+struct dil_keyset {
+  int level = 0;
+  uint32_t nkeys = 0;
+  int device = 0;
+  void *mem = nullptr;
+  uint8_t *pk = nullptr, *sk = nullptr, *tr = nullptr;   // key rows (copies) and tr = H(pk)
+  int32_t *A = nullptr, *s1h = nullptr, *s2h = nullptr, *t0h = nullptr, *t1h = nullptr;
+};
+
 namespace {
 
 int fail(dil_ctx *ctx, int code, const char *what, hipError_t e = hipSuccess) {
@@ -94,6 +103,9 @@ int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws, size_t grid = 0, PScr *sc = nullp
     return r;
   };
   ws.cap = cap;
+  ws.kmap = nullptr;
+  ws.t1h = nullptr;
+  ws.tr = nullptr;
   ws.muw1_stride = ((size_t)P<LV>::MUW1 + 255) & ~(size_t)255;
   ws.counters = (uint32_t *)take(16 * 4);
   ws.muw1 = take(cap * ws.muw1_stride);
@@ -153,17 +165,38 @@ int keygen_impl(dil_ctx *ctx, const uint8_t *seeds, uint8_t *pk, uint8_t *sk, ui
   return DIL_OK;
 }
 
+// Resident key tables replace the per-task A-hat / NTT(s) arrays (no ExpandA, no secret NTTs)
+void use_keyset(Ws &ws, const dil_keyset *ks, const uint32_t *key_idx) {
+  ws.A = ks->A;
+  ws.s1h = ks->s1h;
+  ws.s2h = ks->s2h;
+  ws.t0h = ks->t0h;
+  ws.t1h = ks->t1h;
+  ws.tr = ks->tr;
+  ws.kmap = key_idx;
+}
+
+template <int LV>
+void sign_setup(Ws &ws, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg, const uint64_t *msg_off,
+                uint32_t count, hipStream_t st, const dil_keyset *ks, uint32_t *err) {
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  sg_prep_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, ws, count, err);
+  if (!ks) {
+    expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(sk, P<LV>::SK, key_idx, ws.A, count);
+    sg_secret_k<LV><<<count, 64, 0, st>>>(sk, key_idx, ws, count);
+  }
+}
+
 template <int LV>
 int sign_staged(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg, const uint64_t *msg_off,
-                uint8_t *sig, uint32_t count, hipStream_t st) {
-  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+                uint8_t *sig, uint32_t count, hipStream_t st, const dil_keyset *ks = nullptr) {
+  constexpr int L = Lv<LV>::L;
   Ws ws;
   int rc = ws_carve<LV>(ctx, count, ws);
   if (rc) return rc;
+  if (ks) use_keyset(ws, ks, key_idx);
   HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
-  sg_prep_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, ws, count, ctx->dev_stats + 8);
-  expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(sk, P<LV>::SK, key_idx, ws.A, count);
-  sg_secret_k<LV><<<count, 64, 0, st>>>(sk, key_idx, ws, count);
+  sign_setup<LV>(ws, sk, key_idx, msg, msg_off, count, st, ks, ctx->dev_stats + 8);
   LAUNCHCHK(ctx);
   uint32_t nactive = count;
   uint32_t *cur = ws.active0, *nxt = ws.active1;
@@ -190,8 +223,9 @@ int sign_staged(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const 
 
 template <int LV>
 int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
-                    const uint64_t *msg_off, uint8_t *sig, uint32_t count, hipStream_t st) {
-  constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfg<LV>::G;
+                    const uint64_t *msg_off, uint8_t *sig, uint32_t count, hipStream_t st,
+                    const dil_keyset *ks = nullptr) {
+  constexpr int G = PCfg<LV>::G;
   int per_cu = 0;
   HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sg_persist_k<LV>, 64, 0));
   hipDeviceProp_t prop;
@@ -205,13 +239,12 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   PScr sc;
   int rc = ws_carve<LV>(ctx, count, ws, grid, &sc);
   if (rc) return rc;
+  if (ks) use_keyset(ws, ks, key_idx);
   HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
   HIPCHK(ctx, hipMemsetAsync(ctx->dev_stats, 0, 8 * 4, st));
   hipEvent_t *evs = ctx->timing ? ctx->ev[ctx->ev_count % dil_ctx::RING] : nullptr;
   if (evs) HIPCHK(ctx, hipEventRecord(evs[0], st));
-  sg_prep_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, ws, count, ctx->dev_stats + 8);
-  expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(sk, P<LV>::SK, key_idx, ws.A, count);
-  sg_secret_k<LV><<<count, 64, 0, st>>>(sk, key_idx, ws, count);
+  sign_setup<LV>(ws, sk, key_idx, msg, msg_off, count, st, ks, ctx->dev_stats + 8);
   if (evs) HIPCHK(ctx, hipEventRecord(evs[1], st));
   sg_persist_k<LV><<<(unsigned)grid, 64, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
   if (evs) {
@@ -226,16 +259,76 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
 
 template <int LV>
 int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg, const uint64_t *msg_off,
-                const uint8_t *sig, int32_t *verdict, uint32_t count, hipStream_t st) {
+                const uint8_t *sig, int32_t *verdict, uint32_t count, hipStream_t st,
+                const dil_keyset *ks = nullptr) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
   Ws ws;
   int rc = ws_carve<LV>(ctx, count, ws);
   if (rc) return rc;
+  if (ks) use_keyset(ws, ks, key_idx);
   HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
   vf_prep_k<LV><<<blocks_for(count, 64), 64, 0, st>>>(pk, key_idx, msg, msg_off, sig, ws, count, ctx->dev_stats + 8);
-  expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(pk, P<LV>::PK, key_idx, ws.A, count);
+  if (!ks)
+    expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(pk, P<LV>::PK, key_idx, ws.A, count);
   vf_main_k<LV><<<count, 64, 0, st>>>(pk, key_idx, sig, ws, count);
   vf_final_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sig, ws, verdict, count);
+  LAUNCHCHK(ctx);
+  return DIL_OK;
+}
+
+template <int LV>
+int keyset_build(dil_ctx *ctx, dil_keyset *ks, const uint8_t *pk, const uint8_t *sk, hipStream_t st) {
+  using PP = P<LV>;
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  size_t n = ks->nkeys;
+  size_t bytes = 0;
+  auto rnd = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  bytes += rnd(n * K * L * 1024);
+  if (sk) bytes += rnd(n * PP::SK) + rnd(n * L * 1024) + 2 * rnd(n * K * 1024);
+  if (pk) bytes += rnd(n * PP::PK) + rnd(n * K * 1024);
+  bytes += rnd(n * 32);
+  hipError_t e = hipMalloc(&ks->mem, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, DIL_ENOMEM, "key table allocation", e);
+  }
+  uint8_t *p = (uint8_t *)ks->mem;
+  auto take = [&](size_t b) {
+    uint8_t *r = p;
+    p += rnd(b);
+    return r;
+  };
+  ks->A = (int32_t *)take(n * K * L * 1024);
+  ks->tr = take(n * 32);
+  if (sk) {
+    ks->sk = take(n * PP::SK);
+    ks->s1h = (int32_t *)take(n * L * 1024);
+    ks->s2h = (int32_t *)take(n * K * 1024);
+    ks->t0h = (int32_t *)take(n * K * 1024);
+    HIPCHK(ctx, hipMemcpyAsync(ks->sk, sk, n * PP::SK, hipMemcpyDeviceToDevice, st));
+  }
+  if (pk) {
+    ks->pk = take(n * PP::PK);
+    ks->t1h = (int32_t *)take(n * K * 1024);
+    HIPCHK(ctx, hipMemcpyAsync(ks->pk, pk, n * PP::PK, hipMemcpyDeviceToDevice, st));
+  }
+  unsigned nb = blocks_for(n * K * L, 256);
+  if (sk) {
+    expand_a_k<LV><<<nb, 256, 0, st>>>(ks->sk, PP::SK, nullptr, ks->A, ks->nkeys);
+    Ws w{};
+    w.s1h = ks->s1h;
+    w.s2h = ks->s2h;
+    w.t0h = ks->t0h;
+    sg_secret_k<LV><<<ks->nkeys, 64, 0, st>>>(ks->sk, nullptr, w, ks->nkeys);
+  } else {
+    expand_a_k<LV><<<nb, 256, 0, st>>>(ks->pk, PP::PK, nullptr, ks->A, ks->nkeys);
+  }
+  if (pk) {
+    ks_pk_k<LV><<<ks->nkeys, 64, 0, st>>>(ks->pk, ks->t1h, ks->nkeys);
+    ks_tr_k<LV><<<blocks_for(n, 256), 256, 0, st>>>(ks->pk, ks->tr, ks->nkeys);
+  } else {
+    HIPCHK(ctx, hipMemcpy2DAsync(ks->tr, 32, ks->sk + 64, PP::SK, 32, n, hipMemcpyDeviceToDevice, st));
+  }
   LAUNCHCHK(ctx);
   return DIL_OK;
 }
@@ -377,6 +470,80 @@ int dil_verify_batch(dil_ctx *ctx, int level, const uint8_t *pk, const uint32_t 
   return by_level(level, [&](auto lv) {
     return verify_impl<decltype(lv)::value>(ctx, pk, key_idx, msg, msg_off, sig, verdict, count,
                                             (hipStream_t)stream);
+  });
+}
+
+int dil_keyset_create(dil_ctx *ctx, int level, const uint8_t *pk, const uint8_t *sk, uint32_t n_keys,
+                      dil_keyset **out, void *stream) {
+  if (!ctx || !out || !valid_level(level) || n_keys == 0 || (!pk && !sk))
+    return fail(ctx, DIL_EINVAL, "bad key table arguments");
+  *out = nullptr;
+  hipSetDevice(ctx->device);
+  dil_keyset *ks = new dil_keyset();
+  ks->level = level;
+  ks->nkeys = n_keys;
+  ks->device = ctx->device;
+  int rc = by_level(level, [&](auto lv) {
+    return keyset_build<decltype(lv)::value>(ctx, ks, pk, sk, (hipStream_t)stream);
+  });
+  if (rc) {
+    if (ks->mem) hipFree(ks->mem);
+    delete ks;
+    return rc;
+  }
+  *out = ks;
+  return DIL_OK;
+}
+
+int dil_keyset_destroy(dil_keyset *ks) {
+  if (!ks) return DIL_EINVAL;
+  hipSetDevice(ks->device);
+  hipDeviceSynchronize();
+  if (ks->mem) hipFree(ks->mem);
+  delete ks;
+  return DIL_OK;
+}
+
+int dil_keyset_info(const dil_keyset *ks, int *level, uint32_t *n_keys, size_t *device_bytes) {
+  if (!ks) return DIL_EINVAL;
+  if (level) *level = ks->level;
+  if (n_keys) *n_keys = ks->nkeys;
+  if (device_bytes) {
+    int32_t K = ks->level == 2 ? 4 : ks->level == 3 ? 6 : 8, L = ks->level == 2 ? 4 : ks->level == 3 ? 5 : 7;
+    size_t n = ks->nkeys;
+    *device_bytes = n * (K * L * 1024 + 32) + (ks->sk ? n * ((L + 2 * K) * 1024) : 0) + (ks->pk ? n * K * 1024 : 0);
+  }
+  return DIL_OK;
+}
+
+int dil_sign_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx, const uint8_t *msg,
+                    const uint64_t *msg_off, uint8_t *sig, uint32_t count, void *stream) {
+  if (!ctx || !ks) return fail(ctx, DIL_EINVAL, "bad context or key table");
+  if (!ks->sk) return fail(ctx, DIL_EINVAL, "key table holds no secret keys");
+  if (count == 0) return DIL_OK;
+  if (!msg || !msg_off || !sig) return fail(ctx, DIL_EINVAL, "null buffer");
+  if (!key_idx && count > ks->nkeys) return fail(ctx, DIL_EINVAL, "more tasks than keys without key_idx");
+  hipSetDevice(ctx->device);
+  ctx->stats_pending = 0;
+  return by_level(ks->level, [&](auto lv) {
+    constexpr int LV = decltype(lv)::value;
+    if (ctx->mode == DIL_MODE_PERSISTENT)
+      return sign_persistent<LV>(ctx, ks->sk, key_idx, msg, msg_off, sig, count, (hipStream_t)stream, ks);
+    return sign_staged<LV>(ctx, ks->sk, key_idx, msg, msg_off, sig, count, (hipStream_t)stream, ks);
+  });
+}
+
+int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx, const uint8_t *msg,
+                      const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count, void *stream) {
+  if (!ctx || !ks) return fail(ctx, DIL_EINVAL, "bad context or key table");
+  if (!ks->pk) return fail(ctx, DIL_EINVAL, "key table holds no public keys");
+  if (count == 0) return DIL_OK;
+  if (!msg || !msg_off || !sig || !verdict) return fail(ctx, DIL_EINVAL, "null buffer");
+  if (!key_idx && count > ks->nkeys) return fail(ctx, DIL_EINVAL, "more tasks than keys without key_idx");
+  hipSetDevice(ctx->device);
+  return by_level(ks->level, [&](auto lv) {
+    return verify_impl<decltype(lv)::value>(ctx, ks->pk, key_idx, msg, msg_off, sig, verdict, count,
+                                            (hipStream_t)stream, ks);
   });
 }
 

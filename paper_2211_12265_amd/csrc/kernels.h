@@ -34,7 +34,15 @@ struct Ws {
   uint32_t *counters;           // [8]: next active count, error flags, attempts
   size_t cap;
   size_t muw1_stride;
+  // Resident key tables: when kmap is set, A, s1h, s2h, t0h (and t1h, tr) are
+  // indexed by key row kmap[task] instead of by task.
+  const uint32_t *kmap;
+  const int32_t *t1h;   // [keys][K][256] NTT(t1 2^d), slots layout (verify), or null
+  const uint8_t *tr;    // [keys][32] tr = H(pk) (verify), or null
 };
+
+// row of the per-key arrays used by task `task`
+__device__ __forceinline__ size_t kix(const Ws &ws, uint32_t task) { return ws.kmap ? ws.kmap[task] : task; }
 
 template <int LV>
 __device__ __forceinline__ size_t muw1_stride() {
@@ -535,7 +543,7 @@ __global__ void __launch_bounds__(64) sg_w_k(Ws ws, const uint32_t *active, uint
   uint32_t task = active[blockIdx.x];
   int lane = threadIdx.x, t = lane & 15;
   const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
-  dev_compute_w<LV>(ws.y + (size_t)task * L * N, ws.A + (size_t)task * K * L * N, ws.w + (size_t)task * K * N,
+  dev_compute_w<LV>(ws.y + (size_t)task * L * N, ws.A + kix(ws, task) * K * L * N, ws.w + (size_t)task * K * N,
                     ws.muw1 + (size_t)task * muw1_stride<LV>() + 64, lds.hat, lds.tr + (lane >> 4) * NTT_LDS_GROUP,
                     lds.buf, ftw, itw, lane);
   (void)PP::K;
@@ -569,8 +577,8 @@ __global__ void __launch_bounds__(64) sg_check_k(Ws ws, uint8_t *sig, const uint
   int lane = threadIdx.x, t = lane & 15;
   const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
   bool ok = dev_check<LV>(ws.cpoly + (size_t)task * N, (const uint32_t *)(ws.ctilde + (size_t)task * 32),
-                          ws.y + (size_t)task * L * N, ws.w + (size_t)task * K * N, ws.s1h + (size_t)task * L * N,
-                          ws.s2h + (size_t)task * K * N, ws.t0h + (size_t)task * K * N, lds, ftw, itw, lane);
+                          ws.y + (size_t)task * L * N, ws.w + (size_t)task * K * N, ws.s1h + kix(ws, task) * L * N,
+                          ws.s2h + kix(ws, task) * K * N, ws.t0h + kix(ws, task) * K * N, lds, ftw, itw, lane);
   if (ok) {
     l2g_bytes(lds.sigbuf, P<LV>::SIG, sig + (size_t)task * P<LV>::SIG, lane, 64);
   } else if (lane == 0) {
@@ -595,18 +603,24 @@ __global__ void __launch_bounds__(64) vf_prep_k(const uint8_t *pk, const uint32_
   uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   size_t key = key_idx ? key_idx[t] : t;
-  const uint8_t *pkr = pk + key * PP::PK;
   uint32_t s[50];
-  shake_absorb<RATE256>(s, PP::PK, [&](uint64_t pos) { return *(const uint64_t *)(pkr + pos); });
-  // tr is staged in the (otherwise unused) ctilde row so the message hash can stream tr || M
-  uint32_t *trg = (uint32_t *)(ws.ctilde + (size_t)t * 32);
+  const uint8_t *trsrc;
+  if (ws.tr) {
+    trsrc = ws.tr + key * 32;
+  } else {
+    const uint8_t *pkr = pk + key * PP::PK;
+    shake_absorb<RATE256>(s, PP::PK, [&](uint64_t pos) { return *(const uint64_t *)(pkr + pos); });
+    // tr is staged in the (otherwise unused) ctilde row so the message hash can stream tr || M
+    uint32_t *trg = (uint32_t *)(ws.ctilde + (size_t)t * 32);
 #pragma unroll
-  for (int i = 0; i < 8; i++) trg[i] = s[i];
+    for (int i = 0; i < 8; i++) trg[i] = s[i];
+    trsrc = (const uint8_t *)trg;
+  }
   uint64_t o0 = msg_off[t], o1 = msg_off[t + 1];
   uint64_t mlen = 0;
   if (o1 >= o0) mlen = o1 - o0;
   else atomicOr(err, 1u);  // decreasing msg_off: message treated as empty
-  shake_absorb<RATE256>(s, 32 + mlen, SrcCat{(const uint8_t *)trg, 32, msg + o0, 32 + mlen});
+  shake_absorb<RATE256>(s, 32 + mlen, SrcCat{trsrc, 32, msg + o0, 32 + mlen});
   uint32_t *muw = (uint32_t *)(ws.muw1 + (size_t)t * muw1_stride<LV>());
 #pragma unroll
   for (int i = 0; i < 16; i++) muw[i] = s[i];
@@ -670,9 +684,11 @@ __global__ void __launch_bounds__(64) vf_main_k(const uint8_t *pk, const uint32_
   size_t key = key_idx ? key_idx[task] : task;
   g2l_bytes(sig + (size_t)task * PP::SIG, PP::SIG, sigw, lane, 64);
   if (lane < 2) sigw[PP::SIG / 4 + 1 + lane] = 0;
-  const uint32_t *pkg = (const uint32_t *)(pk + key * PP::PK);
-  for (int w = lane; w < PP::PK / 4; w += 64) pkw[w] = pkg[w];
-  if (lane < 2) pkw[PP::PK / 4 + lane] = 0;
+  if (!ws.t1h) {
+    const uint32_t *pkg = (const uint32_t *)(pk + key * PP::PK);
+    for (int w = lane; w < PP::PK / 4; w += 64) pkw[w] = pkg[w];
+    if (lane < 2) pkw[PP::PK / 4 + lane] = 0;
+  }
   wave_sync();
   const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
   int32_t ch[16];
@@ -701,7 +717,7 @@ __global__ void __launch_bounds__(64) vf_main_k(const uint8_t *pk, const uint32_
   wave_sync();
   const uint32_t *hm = ws.hmask + (size_t)task * K * 8;
   for (int i = g; i < K; i += 4) {
-    const int32_t *Ai = ws.A + ((size_t)task * K + i) * L * N;
+    const int32_t *Ai = ws.A + (kix(ws, task) * K + i) * L * N;
     int64_t acc[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) acc[r] = 0;
@@ -711,12 +727,16 @@ __global__ void __launch_bounds__(64) vf_main_k(const uint8_t *pk, const uint32_
 #pragma unroll
       for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * zh[j * N + 16 * t + r];
     }
-    uint32_t v[16];
-    unpack_strided<10>(pkw + (32 + i * PP::T1B) / 4, v, t);
     int32_t x[16];
+    if (ws.t1h) {
+      load_slots(x, ws.t1h + (kix(ws, task) * K + i) * N, t);
+    } else {
+      uint32_t v[16];
+      unpack_strided<10>(pkw + (32 + i * PP::T1B) / 4, v, t);
 #pragma unroll
-    for (int r = 0; r < 16; r++) x[r] = (int32_t)(v[r] << D);
-    ntt16(x, ftw, tr, t);
+      for (int r = 0; r < 16; r++) x[r] = (int32_t)(v[r] << D);
+      ntt16(x, ftw, tr, t);
+    }
     // transpose-free: t1-hat comes out in slots layout like acc
 #pragma unroll
     for (int r = 0; r < 16; r++) {
@@ -762,6 +782,47 @@ __global__ void __launch_bounds__(256) vf_final_k(const uint8_t *sig, Ws ws, int
     eq &= ((uint32_t)v == s[2 * w]) && ((uint32_t)(v >> 32) == s[2 * w + 1]);
   }
   verdict[t] = (ws.flag[t] && eq) ? 1 : 0;
+}
+
+// ------------------------------------------------------------------------
+// Resident key tables
+// ------------------------------------------------------------------------
+// NTT(t1 2^d) (slots layout) and tr = H(pk) for every key row of a table
+template <int LV>
+__global__ void __launch_bounds__(64) ks_pk_k(const uint8_t *pk, int32_t *t1h, uint32_t nkeys) {
+  using PP = P<LV>;
+  constexpr int K = Lv<LV>::K;
+  __shared__ int32_t trl[4 * NTT_LDS_GROUP];
+  __shared__ uint32_t pkw[PP::PK / 4 + 2];
+  uint32_t key = blockIdx.x;
+  if (key >= nkeys) return;
+  int lane = threadIdx.x, g = lane >> 4, t = lane & 15;
+  const uint32_t *pkg = (const uint32_t *)(pk + (size_t)key * PP::PK);
+  for (int w = lane; w < PP::PK / 4; w += 64) pkw[w] = pkg[w];
+  if (lane < 2) pkw[PP::PK / 4 + lane] = 0;
+  wave_sync();
+  const Tw ftw = ntt_lane_tw(t);
+  for (int i = g; i < K; i += 4) {
+    uint32_t v[16];
+    unpack_strided<10>(pkw + (32 + i * PP::T1B) / 4, v, t);
+    int32_t x[16];
+#pragma unroll
+    for (int r = 0; r < 16; r++) x[r] = (int32_t)(v[r] << D);
+    ntt16(x, ftw, trl + g * NTT_LDS_GROUP, t);
+    store_slots(x, t1h + ((size_t)key * K + i) * N, t);
+  }
+}
+
+template <int LV>
+__global__ void __launch_bounds__(256) ks_tr_k(const uint8_t *pk, uint8_t *tr, uint32_t nkeys) {
+  uint32_t key = blockIdx.x * blockDim.x + threadIdx.x;
+  if (key >= nkeys) return;
+  const uint8_t *p = pk + (size_t)key * P<LV>::PK;
+  uint32_t s[50];
+  shake_absorb<RATE256>(s, P<LV>::PK, [&](uint64_t pos) { return *(const uint64_t *)(p + pos); });
+  uint32_t *o = (uint32_t *)(tr + (size_t)key * 32);
+#pragma unroll
+  for (int w = 0; w < 8; w++) o[w] = s[w];
 }
 
 // ------------------------------------------------------------------------

@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
     // ---- w = INTT(A NTT(y)) per slot ----
     for (int s = 0; s < ns; s++) {
       uint32_t task = lds.h_task[lds.s_h[s]];
-      dev_compute_w<LV>(yb + (size_t)s * L * N, ws.A + (size_t)task * K * L * N, wb + (size_t)s * K * N,
+      dev_compute_w<LV>(yb + (size_t)s * L * N, ws.A + kix(ws, task) * K * L * N, wb + (size_t)s * K * N,
                         w1b + s * w1_stride<LV>(), lds.u.wp.hat, lds.u.wp.tr + (lane >> 4) * NTT_LDS_GROUP,
                         lds.u.wp.w1buf, ftw, itw, lane);
       wave_sync();
@@ -141,8 +141,8 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
       if (lds.h_win[h] != 0xFFFFFFFFu) continue;
       uint32_t task = lds.h_task[h];
       bool ok = dev_check<LV>(lds.c[s], lds.ct[s], yb + (size_t)s * L * N, wb + (size_t)s * K * N,
-                              ws.s1h + (size_t)task * L * N, ws.s2h + (size_t)task * K * N,
-                              ws.t0h + (size_t)task * K * N, lds.u.ck, ftw, itw, lane);
+                              ws.s1h + kix(ws, task) * L * N, ws.s2h + kix(ws, task) * K * N,
+                              ws.t0h + kix(ws, task) * K * N, lds.u.ck, ftw, itw, lane);
       if (ok) {
         l2g_bytes(lds.u.ck.sigbuf, P<LV>::SIG, sig + (size_t)task * P<LV>::SIG, lane, 64);
         if (lane == 0) lds.h_win[h] = lds.s_att[s];

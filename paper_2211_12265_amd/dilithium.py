@@ -23,7 +23,8 @@ EXPORTS = [
     "dil_last_error", "dil_sizes",
     "dil_keygen_batch", "dil_sign_batch", "dil_verify_batch", "dil_sign_stats", "dil_sign_timing",
     "dil_ntt_mul_batch",
-    "dil_expand_a_batch",
+    "dil_expand_a_batch", "dil_keyset_create", "dil_keyset_destroy", "dil_keyset_info", "dil_sign_keyset",
+    "dil_verify_keyset",
 ]
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -61,6 +62,12 @@ def load() -> ctypes.CDLL:
         "dil_sign_timing": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "dil_ntt_mul_batch": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_uint64, _P]),
         "dil_expand_a_batch": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, _P]),
+        "dil_keyset_create": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P), _P]),
+        "dil_keyset_destroy": (ctypes.c_int, [_P]),
+        "dil_keyset_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint32),
+                                           ctypes.POINTER(ctypes.c_size_t)]),
+        "dil_sign_keyset": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_uint32, _P]),
+        "dil_verify_keyset": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_uint32, _P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -164,3 +171,43 @@ class Context:
     def expand_a(self, seeds34, out, stream=None):
         self._check(self.lib.dil_expand_a_batch(self.h, _ptr(seeds34), _ptr(out), seeds34.shape[0],
                                                 _stream(stream)))
+
+
+class KeySet:
+    """Device-resident key table of one level (A-hat, NTT'd secrets, NTT(t1 2^d), tr kept on the GPU)."""
+
+    def __init__(self, ctx: Context, level: int, pk=None, sk=None, stream=None):
+        self.lib = ctx.lib
+        rows = (pk if pk is not None else sk).shape[0]
+        h = _P()
+        ctx._check(self.lib.dil_keyset_create(ctx.h, level, _ptr(pk), _ptr(sk), rows, ctypes.byref(h),
+                                              _stream(stream)))
+        self.h = h
+        self.level = level
+        self.n_keys = rows
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_size_t()
+        self.lib.dil_keyset_info(self.h, None, None, ctypes.byref(b))
+        return b.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dil_keyset_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sign(self, ctx: Context, key_idx, msg, msg_off, sig, stream=None):
+        n = msg_off.shape[0] - 1
+        ctx._check(self.lib.dil_sign_keyset(ctx.h, self.h, _ptr(key_idx), _ptr(msg) or _ptr(msg_off), _ptr(msg_off),
+                                            _ptr(sig), n, _stream(stream)))
+
+    def verify(self, ctx: Context, key_idx, msg, msg_off, sig, verdict, stream=None):
+        n = msg_off.shape[0] - 1
+        ctx._check(self.lib.dil_verify_keyset(ctx.h, self.h, _ptr(key_idx), _ptr(msg) or _ptr(msg_off),
+                                              _ptr(msg_off), _ptr(sig), _ptr(verdict), n, _stream(stream)))

@@ -1,0 +1,308 @@
+"""Continuous-batching request loop over libdil on one GPU.
+
+Requests (mixed level 2/3/5 Sign and Verify, each against one key of a
+resident key table) arrive over time.  The loop keeps up to `n_streams`
+batches in flight, each on its own HIP stream with its own libdil context
+(workspace): whenever a stream is free, every request that has arrived and
+fits the device-memory budget is admitted as the next batch, split by
+(level, op) into key-table calls (dil_sign_keyset / dil_verify_keyset).
+Requests that arrive while earlier batches run are admitted as soon as a
+stream and memory free up, so their work overlaps on the device.
+
+Host <-> device traffic goes through pinned staging buffers per stream
+(messages, key indices and input signatures up; signatures and verdicts
+down), so a request's latency -- completion time minus its scheduled
+arrival -- includes queueing, both copies and the kernels.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import dilithium as dl
+
+SIGN, VERIFY = 0, 1
+LEVELS = (2, 3, 5)
+# device bytes one admitted task holds while in flight (workspace rows + I/O), per level;
+# the workspace layout is in csrc/api.hip (ws_need) plus the persistent kernel's scratch share
+TASK_BYTES = {2: 48 << 10, 3: 80 << 10, 5: 120 << 10}
+
+
+@dataclass
+class Requests:
+    """A request stream in arrival order (all arrays indexed by request)."""
+    t_arrival: np.ndarray      # float64 seconds from stream start
+    op: np.ndarray             # int8: 0 sign, 1 verify
+    level: np.ndarray          # int8
+    key: np.ndarray            # int32 row in the level's key table
+    msg: np.ndarray            # uint8, concatenated messages
+    msg_off: np.ndarray        # int64, n + 1 CSR offsets
+    sig_in: np.ndarray = None  # uint8, concatenated input signatures of verify requests
+    sig_off: np.ndarray = None # int64 per request: offset into sig_in (verify) or -1
+
+    def __len__(self):
+        return self.t_arrival.size
+
+
+@dataclass
+class Results:
+    sig: Dict[int, np.ndarray] = field(default_factory=dict)   # request -> signature bytes (sign)
+    verdict: np.ndarray = None                                  # int32 per request (-1 for sign)
+    t_done: np.ndarray = None                                   # completion time per request
+    sig_buf: np.ndarray = None
+    sig_pos: np.ndarray = None                                  # offset of request's signature in sig_buf
+
+
+def sig_size(level: int) -> int:
+    return dl.sizes(level)[2]
+
+
+def _gather(buf: np.ndarray, starts: np.ndarray, lens: np.ndarray) -> np.ndarray:
+    """Concatenate buf[starts[i] : starts[i] + lens[i]] without a Python loop."""
+    total = int(lens.sum())
+    if total == 0:
+        return np.zeros(0, dtype=buf.dtype)
+    first = np.concatenate([[0], np.cumsum(lens)[:-1]])
+    idx = np.repeat(starts - first, lens) + np.arange(total)
+    return buf[idx]
+
+
+class _Lane:
+    """One stream with its context and pinned staging buffers."""
+
+    def __init__(self, torch, device, max_msg: int, max_tasks: int, max_sig: int, persistent: bool):
+        self.torch = torch
+        self.stream = torch.cuda.Stream(device=device)
+        self.ctx = dl.Context(device.index or 0, mode=dl.MODE_PERSISTENT if persistent else dl.MODE_STAGED)
+        pin = dict(pin_memory=True)
+        self.h_msg = torch.empty(max_msg, dtype=torch.uint8, **pin)
+        self.h_off = torch.empty(max_tasks + 8, dtype=torch.int64, **pin)
+        self.h_key = torch.empty(max_tasks, dtype=torch.int32, **pin)
+        self.h_sig = torch.empty(max_sig, dtype=torch.uint8, **pin)
+        self.h_ver = torch.empty(max_tasks, dtype=torch.int32, **pin)
+        self.d_msg = torch.empty(max_msg, dtype=torch.uint8, device=device)
+        self.d_off = torch.empty(max_tasks + 8, dtype=torch.int64, device=device)
+        self.d_key = torch.empty(max_tasks, dtype=torch.int32, device=device)
+        self.d_sig = torch.empty(max_sig, dtype=torch.uint8, device=device)
+        self.d_ver = torch.empty(max_tasks, dtype=torch.int32, device=device)
+        self.event = None
+        self.batch = None
+
+    def close(self):
+        self.ctx.close()
+
+
+class Server:
+    def __init__(self, keysets: Dict[int, "dl.KeySet"], n_streams: int = 4, max_batch: int = 4096,
+                 mem_budget: int = 2 << 30, max_msg_bytes: int = 64 << 20, persistent: bool = True):
+        import torch
+        self.torch = torch
+        self.device = torch.device("cuda", 0)
+        self.keysets = keysets
+        self.max_batch = max_batch
+        self.mem_budget = mem_budget
+        max_sig = max_batch * max(sig_size(lv) for lv in LEVELS)
+        self.lanes = [_Lane(torch, self.device, max_msg_bytes, max_batch, max_sig, persistent)
+                      for _ in range(n_streams)]
+        self.max_msg_bytes = max_msg_bytes
+
+    def close(self):
+        for ln in self.lanes:
+            ln.close()
+
+    # ---- batch launch ----
+    def _launch(self, lane: _Lane, reqs: Requests, idx: np.ndarray):
+        torch = self.torch
+        lens = (reqs.msg_off[idx + 1] - reqs.msg_off[idx]).astype(np.int64)
+        msg_np = lane.h_msg.numpy()
+        off_np = lane.h_off.numpy()
+        key_np = lane.h_key.numpy()
+        sig_np = lane.h_sig.numpy()
+        groups = []
+        m_pos = s_pos = t_pos = 0
+        for lv in LEVELS:
+            for op in (SIGN, VERIFY):
+                sel = idx[(reqs.level[idx] == lv) & (reqs.op[idx] == op)]
+                if sel.size == 0:
+                    continue
+                gl = (reqs.msg_off[sel + 1] - reqs.msg_off[sel]).astype(np.int64)
+                gm = _gather(reqs.msg, reqs.msg_off[sel].astype(np.int64), gl)
+                msg_np[m_pos:m_pos + gm.size] = gm
+                off_np[t_pos + len(groups):t_pos + len(groups) + sel.size + 1] = np.concatenate(
+                    [[0], np.cumsum(gl)])
+                key_np[t_pos:t_pos + sel.size] = reqs.key[sel]
+                ss = sig_size(lv)
+                if op == VERIFY:
+                    gs = _gather(reqs.sig_in, reqs.sig_off[sel].astype(np.int64), np.full(sel.size, ss))
+                    sig_np[s_pos:s_pos + gs.size] = gs
+                groups.append((lv, op, sel, m_pos, gm.size, t_pos, s_pos, ss))
+                m_pos += gm.size
+                s_pos += sel.size * ss
+                t_pos += sel.size
+        n_off = t_pos + len(groups)
+        with torch.cuda.stream(lane.stream):
+            lane.d_msg[:m_pos].copy_(lane.h_msg[:m_pos], non_blocking=True)
+            lane.d_off[:n_off].copy_(lane.h_off[:n_off], non_blocking=True)
+            lane.d_key[:t_pos].copy_(lane.h_key[:t_pos], non_blocking=True)
+            lane.d_sig[:s_pos].copy_(lane.h_sig[:s_pos], non_blocking=True)
+            for gi, (lv, op, sel, mp, ml, tp, sp, ss) in enumerate(groups):
+                n = sel.size
+                d_off = lane.d_off[tp + gi:tp + gi + n + 1]
+                d_msg = lane.d_msg[mp:mp + max(ml, 1)]
+                d_key = lane.d_key[tp:tp + n]
+                d_sig = lane.d_sig[sp:sp + n * ss].view(n, ss)
+                ks = self.keysets[lv]
+                if op == SIGN:
+                    ks.sign(lane.ctx, d_key, d_msg, d_off, d_sig, stream=lane.stream)
+                else:
+                    ks.verify(lane.ctx, d_key, d_msg, d_off, d_sig, lane.d_ver[tp:tp + n], stream=lane.stream)
+            lane.h_sig[:s_pos].copy_(lane.d_sig[:s_pos], non_blocking=True)
+            lane.h_ver[:t_pos].copy_(lane.d_ver[:t_pos], non_blocking=True)
+            ev = torch.cuda.Event()
+            ev.record(lane.stream)
+        lane.event = ev
+        lane.batch = groups
+
+    def _collect(self, lane: _Lane, res: Results, now: float):
+        sig_np = lane.h_sig.numpy()
+        ver_np = lane.h_ver.numpy()
+        for (lv, op, sel, mp, ml, tp, sp, ss) in lane.batch:
+            res.t_done[sel] = now
+            if op == SIGN:
+                rows = sig_np[sp:sp + sel.size * ss].reshape(sel.size, ss)
+                for j, r in enumerate(sel):
+                    res.sig[int(r)] = rows[j].copy()
+            else:
+                res.verdict[sel] = ver_np[tp:tp + sel.size]
+        lane.event = None
+        lane.batch = None
+
+    def _cost(self, reqs: Requests, i: int) -> int:
+        return TASK_BYTES[int(reqs.level[i])] + int(reqs.msg_off[i + 1] - reqs.msg_off[i])
+
+    # ---- the loop ----
+    def serve(self, reqs: Requests, time_scale: float = 1.0) -> Results:
+        """Run the request stream; arrivals are honoured in real time (t_arrival * time_scale)."""
+        n = len(reqs)
+        res = Results(verdict=np.full(n, -1, np.int32), t_done=np.full(n, np.nan))
+        cost = np.array([self._cost(reqs, i) for i in range(n)], dtype=np.int64)
+        lens = np.diff(reqs.msg_off)
+        free = deque(self.lanes)
+        busy: List[_Lane] = []
+        inflight_bytes = {}
+        head = 0
+        done = 0
+        arrivals = reqs.t_arrival * time_scale
+        t0 = time.perf_counter()
+        while done < n:
+            now = time.perf_counter() - t0
+            # completions
+            for lane in list(busy):
+                if lane.event.query():
+                    k = lane.batch
+                    cnt = sum(g[2].size for g in k)
+                    self._collect(lane, res, time.perf_counter() - t0)
+                    inflight_bytes.pop(id(lane), None)
+                    busy.remove(lane)
+                    free.append(lane)
+                    done += cnt
+            # admission
+            arrived = int(np.searchsorted(arrivals, now, side="right"))
+            if free and head < arrived:
+                budget = self.mem_budget - sum(inflight_bytes.values())
+                end = min(arrived, head + self.max_batch)
+                c = np.cumsum(cost[head:end])
+                fit = int(np.searchsorted(c, budget, side="right"))
+                m = np.cumsum(lens[head:end])
+                fit = min(fit, int(np.searchsorted(m, self.max_msg_bytes, side="right")))
+                if fit == 0 and not busy:
+                    fit = 1  # always make progress
+                if fit > 0:
+                    lane = free.popleft()
+                    idx = np.arange(head, head + fit)
+                    self._launch(lane, reqs, idx)
+                    inflight_bytes[id(lane)] = int(c[fit - 1])
+                    busy.append(lane)
+                    head += fit
+                    continue
+            if not busy and head >= arrived and head < n:
+                # idle until the next arrival
+                wait = arrivals[head] - (time.perf_counter() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 0.001))
+        res.wall = time.perf_counter() - t0
+        res.latency = res.t_done - arrivals
+        return res
+
+
+def latency_summary(res: Results, reqs: Requests) -> dict:
+    lat = res.latency * 1e3
+    out = {"requests": int(len(reqs)), "wall_s": res.wall, "ops_per_s": len(reqs) / res.wall,
+           "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+           "mean_ms": float(lat.mean()), "max_ms": float(lat.max())}
+    for op, name in ((SIGN, "sign"), (VERIFY, "verify")):
+        m = reqs.op == op
+        if m.any():
+            out[f"p99_ms_{name}"] = float(np.percentile(lat[m], 99))
+    return out
+
+
+def build_requests(count: int, lam: float, keys_per_level: Dict[int, int], seed: int = 0) -> Requests:
+    """Poisson stream: 70% verify / 30% sign, levels 50/30/20%, lognormal messages (see workload.py).
+    Verify signatures are filled in by `attach_signatures`."""
+    from . import workload
+    rng_t = np.random.default_rng([seed, 1])
+    gaps = rng_t.exponential(1.0 / lam, size=count) if lam > 0 else np.zeros(count)
+    t = np.cumsum(gaps)
+    if lam <= 0:
+        t[:] = 0.0
+    op = (np.random.default_rng([seed, 2]).random(count) < 0.7).astype(np.int8)
+    level = np.random.default_rng([seed, 3]).choice([2, 3, 5], size=count, p=[0.5, 0.3, 0.2]).astype(np.int8)
+    kr = np.random.default_rng([seed, 4]).random(count)
+    key = np.array([int(kr[i] * keys_per_level[int(level[i])]) % keys_per_level[int(level[i])]
+                    for i in range(count)], dtype=np.int32)
+    lens = workload.lognormal_lengths(count, seed=seed)
+    msg, off = workload.messages(lens, seed=seed + 1)
+    return Requests(t, op, level, key, msg, off.astype(np.int64))
+
+
+def attach_signatures(reqs: Requests, ctx: "dl.Context", keysets: Dict[int, "dl.KeySet"], flip_rate: float = 0.01,
+                      seed: int = 0):
+    """Sign every verify request's message on the GPU (untimed set-up), then flip one random bit in a
+    fraction `flip_rate` of them so those must be rejected."""
+    import torch
+    dev = torch.device("cuda", 0)
+    n = len(reqs)
+    sig_off = np.full(n, -1, np.int64)
+    parts = []
+    pos = 0
+    flips = np.random.default_rng([seed, 5]).random(n) < flip_rate
+    fbits = np.random.default_rng([seed, 6]).integers(0, 1 << 30, size=n)
+    flipped = np.zeros(n, bool)
+    for lv in LEVELS:
+        sel = np.nonzero((reqs.level == lv) & (reqs.op == VERIFY))[0]
+        if sel.size == 0:
+            continue
+        ss = sig_size(lv)
+        lens = (reqs.msg_off[sel + 1] - reqs.msg_off[sel])
+        gm = _gather(reqs.msg, reqs.msg_off[sel], lens)
+        goff = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        d_sig = torch.zeros((sel.size, ss), dtype=torch.uint8, device=dev)
+        keysets[lv].sign(ctx, torch.from_numpy(reqs.key[sel]).to(dev), torch.from_numpy(gm).to(dev),
+                         torch.from_numpy(goff).to(dev), d_sig)
+        sigs = d_sig.cpu().numpy()
+        for j, r in enumerate(sel):
+            if flips[r]:
+                b = int(fbits[r] % (ss * 8))
+                sigs[j, b // 8] ^= np.uint8(1 << (b % 8))
+                flipped[r] = True
+        sig_off[sel] = pos + np.arange(sel.size) * ss
+        parts.append(sigs.reshape(-1))
+        pos += sigs.size
+    reqs.sig_in = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+    reqs.sig_off = sig_off
+    return flipped

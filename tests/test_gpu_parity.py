@@ -243,3 +243,37 @@ def test_decreasing_msg_off_reported(sctx):
     with pytest.raises(dl.DilError) as ei:
         sctx.check()
     assert ei.value.code == dl.DIL_EMSG
+
+
+@pytest.mark.parametrize("level", [2, 3, 5])
+def test_keyset_sign_verify_parity(sctx, level):
+    """Sign / Verify against a resident key table equal the oracle (and the plain batch path)."""
+    from paper_2211_12265_amd import dilithium as dl
+    nkeys, n = 9, 40
+    seeds = workload.keygen_seeds(nkeys, seed=90 + level)
+    pk, sk = _keygen(sctx, level, seeds)
+    ks_both = dl.KeySet(sctx, level, pk=pk, sk=sk)
+    ks_pk = dl.KeySet(sctx, level, pk=pk)
+    ks_sk = dl.KeySet(sctx, level, sk=sk)
+    kidx = np.random.default_rng(level).integers(0, nkeys, size=n).astype(np.uint32)
+    msg, off = workload.messages(workload.uniform_lengths(n, 0, 500, seed=level + 90), seed=level + 90)
+    osig, _ = oracle.sign_batch(level, sk.cpu().numpy(), msg, off, key_idx=kidx)
+    for ks in (ks_both, ks_sk):
+        sig = torch.zeros((n, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
+        ks.sign(sctx, dev(kidx.astype(np.int32)), dev(msg), dev(off.astype(np.int64)), sig)
+        torch.cuda.synchronize()
+        assert np.array_equal(sig.cpu().numpy(), osig)
+    bad = osig.copy()
+    bad[::3, 40] ^= 1
+    for ks in (ks_both, ks_pk):
+        v = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        ks.verify(sctx, dev(kidx.astype(np.int32)), dev(msg), dev(off.astype(np.int64)), dev(bad), v)
+        torch.cuda.synchronize()
+        expect = oracle.verify_batch(level, pk.cpu().numpy(), msg, off, bad, key_idx=kidx)
+        assert np.array_equal(v.cpu().numpy(), expect)
+        assert expect.sum() == n - len(range(0, n, 3))
+    with pytest.raises(dl.DilError):
+        ks_pk.sign(sctx, None, dev(msg), dev(off.astype(np.int64)), torch.zeros((n, 8), dtype=torch.uint8,
+                                                                                device="cuda"))
+    for ks in (ks_both, ks_pk, ks_sk):
+        ks.close()

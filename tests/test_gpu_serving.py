@@ -1,0 +1,85 @@
+"""Serving loop: mixed-level Sign/Verify requests through the continuous-batching
+loop give exactly the oracle's outputs, and each result is the same alone and in
+the mix (deterministic signing: tolerance 0 bytes)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_12265_amd import workload
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def setup():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    from paper_2211_12265_amd import serving as sv
+    ctx = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    keys = {2: 12, 3: 7, 5: 5}
+    keysets, host = {}, {}
+    for lv, nk in keys.items():
+        pkl, skl, _ = dl.sizes(lv)
+        seeds = workload.keygen_seeds(nk, seed=200 + lv)
+        pk = torch.zeros((nk, pkl), dtype=torch.uint8, device="cuda")
+        sk = torch.zeros((nk, skl), dtype=torch.uint8, device="cuda")
+        ctx.keygen(lv, torch.from_numpy(seeds).cuda(), pk, sk)
+        keysets[lv] = dl.KeySet(ctx, lv, pk=pk, sk=sk)
+        host[lv] = (pk.cpu().numpy(), sk.cpu().numpy())
+    reqs = sv.build_requests(300, lam=20000.0, keys_per_level=keys, seed=7)
+    flipped = sv.attach_signatures(reqs, ctx, keysets, flip_rate=0.1, seed=7)
+    yield dl, sv, ctx, keysets, host, reqs, flipped
+    for ks in keysets.values():
+        ks.close()
+    ctx.close()
+
+
+def test_serving_matches_oracle(setup):
+    dl, sv, ctx, keysets, host, reqs, flipped = setup
+    server = sv.Server(keysets, n_streams=3, max_batch=64, mem_budget=4 << 20, max_msg_bytes=1 << 20)
+    res = server.serve(reqs)
+    server.close()
+    assert np.isfinite(res.t_done).all()
+    for lv in (2, 3, 5):
+        pk, sk = host[lv]
+        s = np.nonzero((reqs.level == lv) & (reqs.op == sv.SIGN))[0]
+        if s.size:
+            lens = reqs.msg_off[s + 1] - reqs.msg_off[s]
+            msg = sv._gather(reqs.msg, reqs.msg_off[s], lens)
+            off = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+            osig, _ = oracle.sign_batch(lv, sk, msg, off, key_idx=reqs.key[s].astype(np.uint32))
+            got = np.stack([res.sig[int(r)] for r in s])
+            assert np.array_equal(got, osig)
+        v = np.nonzero((reqs.level == lv) & (reqs.op == sv.VERIFY))[0]
+        if v.size:
+            lens = reqs.msg_off[v + 1] - reqs.msg_off[v]
+            msg = sv._gather(reqs.msg, reqs.msg_off[v], lens)
+            off = np.concatenate([[0], np.cumsum(lens)]).astype(np.uint64)
+            ss = sv.sig_size(lv)
+            sigs = sv._gather(reqs.sig_in, reqs.sig_off[v], np.full(v.size, ss)).reshape(-1, ss)
+            ov = oracle.verify_batch(lv, pk, msg, off, sigs, key_idx=reqs.key[v].astype(np.uint32))
+            assert np.array_equal(res.verdict[v], ov)
+            assert np.array_equal(ov == 0, flipped[v])
+
+
+def test_same_alone_and_in_mix(setup):
+    dl, sv, ctx, keysets, host, reqs, flipped = setup
+    server = sv.Server(keysets, n_streams=4, max_batch=128, mem_budget=64 << 20, max_msg_bytes=1 << 20)
+    mixed = server.serve(reqs)
+    rng = np.random.default_rng(3)
+    for r in rng.choice(len(reqs), size=24, replace=False):
+        one = sv.Requests(np.zeros(1), reqs.op[r:r + 1], reqs.level[r:r + 1], reqs.key[r:r + 1],
+                          reqs.msg[reqs.msg_off[r]:reqs.msg_off[r + 1]].copy(),
+                          np.array([0, reqs.msg_off[r + 1] - reqs.msg_off[r]], np.int64))
+        if reqs.op[r] == sv.VERIFY:
+            ss = sv.sig_size(int(reqs.level[r]))
+            one.sig_in = reqs.sig_in[reqs.sig_off[r]:reqs.sig_off[r] + ss].copy()
+            one.sig_off = np.array([0], np.int64)
+        alone = server.serve(one)
+        if reqs.op[r] == sv.SIGN:
+            assert np.array_equal(alone.sig[0], mixed.sig[int(r)])
+        else:
+            assert alone.verdict[0] == mixed.verdict[r]
+    server.close()
