@@ -111,7 +111,7 @@ def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -
         ctx.keygen(lv, torch.from_numpy(workload.keygen_seeds(nk, seed=300 + lv)).cuda(), pk, sk)
         keysets[lv] = dl.KeySet(ctx, lv, pk=pk, sk=sk)
     resident = sum(ks.device_bytes() for ks in keysets.values())
-    server = sv.Server(keysets, n_streams=streams, max_batch=max_batch, mem_budget=8 << 30)
+    server = sv.NativeServer(keysets, n_streams=streams, max_batch=max_batch, mem_budget=8 << 30)
     # warm-up and saturation probe
     warm = sv.build_requests(4000, lam=0.0, keys_per_level=keys, seed=11)
     sv.attach_signatures(warm, ctx, keysets, seed=11)
@@ -127,7 +127,8 @@ def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -
     res = server.serve(reqs)
     summ = sv.latency_summary(res, reqs)
     verify = reqs.op == sv.VERIFY
-    summ.update({"lambda_per_s": lam, "saturated_ops_per_s": sat_rate, "streams": streams, "max_batch": max_batch,
+    summ.update({"engine": "native dil_server", "lambda_per_s": lam, "saturated_ops_per_s": sat_rate,
+                 "streams": streams, "max_batch": max_batch,
                  "resident_key_bytes": resident, "flipped_rejected": bool((res.verdict[verify & flipped] == 0).all()),
                  "valid_accepted": bool((res.verdict[verify & ~flipped] == 1).all()),
                  "mix": "70% verify / 30% sign, levels 2/3/5 at 50/30/20%, lognormal messages (median 256 B, "
@@ -148,6 +149,8 @@ def main():
     ap.add_argument("--level", type=int, default=2, choices=[2, 3, 5])
     ap.add_argument("--mode", default="persistent", choices=["persistent", "staged"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
+    ap.add_argument("--graph", type=int, default=1, help="replay Sign/Verify launch sequences as hipGraphs")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--serving", action="store_true", help="also run the serving loop and report p50/p99")
     ap.add_argument("--serving-only", action="store_true")
@@ -209,6 +212,14 @@ def main():
         if ev is not None:
             ev[2].record(stream)
 
+    tuning = None
+    if args.mode == "persistent" and not args.no_tune:
+        from paper_2211_12265_amd import autotune
+        resident, _ = ctx.persist_capacity(level)
+        tuning = autotune.tune_sign(ctx, level, lambda: ctx.sign(level, sk, g_msg, g_off, sig), resident,
+                                    count=n)
+    if args.graph:
+        ctx.set_param("graph", 1)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -256,12 +267,14 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": f"Dilithium{level} batch {n} sign + {n} verify, 32-byte messages, one key per task, "
                                f"device-resident buffers", "level": level, "batch": n, "msg_len": 32,
-                   "sign_mode": args.mode},
+                   "sign_mode": args.mode, "hipgraph": bool(args.graph),
+                   "schedule": None if tuning is None else {k: tuning["best"][k] for k in ("hmax", "grid")}},
         "sign_per_s": sign_rate, "verify_per_s": ver_rate,
         "sign_ms_median": float(np.median(sign_ms)), "verify_ms_median": float(np.median(ver_ms)),
         "sign_iterations": {"sequential": int(sequential), "evaluated": int(evaluated),
                             "per_task": sequential / n},
         "parity_sampled": parity_ok,
+        "autotune": None if tuning is None else tuning["table"],
         "roofline": dict({"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
                           "unit": "T int32-ops/s", "frac": achieved / PEAK_INT32_OPS, "traffic": None,
                           "kernel": kname}, **kextra),

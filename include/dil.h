@@ -74,8 +74,17 @@ int dil_ctx_set_mode(dil_ctx *ctx, int mode);
  *   "persist.grid"  workgroups launched by the persistent Sign kernel;
  *   "persist.hmax"  tasks one workgroup holds at a time (1..slots per batch);
  *   "timing"        1 = record HIP events around the persistent Sign's setup
- *                   kernels and its loop kernel (read with dil_sign_timing). */
+ *                   kernels and its loop kernel (read with dil_sign_timing);
+ *   "graph"         1 = capture the launch sequence of persistent-mode Sign and
+ *                   of Verify into hipGraphs, replayed when a call repeats
+ *                   the same level, buffers, count and schedule (up to 16
+ *                   graphs per context, least recently used evicted; dropped
+ *                   when the workspace grows). */
 int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value);
+/* Grow the context's workspace (synchronously) so that any call with up to
+ * `count` tasks at `level` runs without allocating -- serving loops reserve the
+ * largest batch they admit up front. */
+int dil_ctx_reserve(dil_ctx *ctx, int level, uint32_t count);
 /* Synchronise `stream` and report a device-detected input error (DIL_EMSG) once. */
 int dil_ctx_check(dil_ctx *ctx, void *stream);
 /* Text of the last error on this context (static storage inside the context). */
@@ -126,10 +135,45 @@ int dil_sign_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx,
 int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx, const uint8_t *msg,
                       const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count, void *stream);
 
+/* ---- Continuous-batching serving engine ----
+ * Host-side dispatcher over key tables (one per level; NULL for a level not
+ * served).  It keeps up to n_streams batches in flight, each on its own HIP
+ * stream with its own context; whenever a stream is free it admits every
+ * request that has arrived and fits mem_budget (device bytes of workspace
+ * plus message bytes per in-flight request) and max_batch, splits it by
+ * (level, op) into dil_sign_keyset / dil_verify_keyset calls, and stages
+ * messages, key indices and signatures through pinned buffers (max_msg_bytes
+ * of message data per batch).  mode is DIL_MODE_STAGED or
+ * DIL_MODE_PERSISTENT for Sign. */
+typedef struct dil_server dil_server;
+int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset *ks3, dil_keyset *ks5,
+                      int n_streams, uint32_t max_batch, size_t max_msg_bytes, size_t mem_budget, int mode);
+/* Waits for the device and frees the engine (not the key tables). */
+int dil_server_destroy(dil_server *s);
+const char *dil_server_last_error(dil_server *s);
+/* Batches launched and host seconds spent forming/launching them in the last run. */
+int dil_server_stats(dil_server *s, uint64_t *batches, double *host_seconds);
+/* Replay a request trace (HOST arrays, n requests in arrival order): request i
+ * (op[i] 0 = Sign, 1 = Verify; level[i] in {2,3,5}; key row key[i]; message
+ * msg[msg_off[i] .. msg_off[i+1])) becomes visible arrival_ns[i] nanoseconds
+ * after the call starts.  Sign writes its signature to sig_out + sig_out_off[i];
+ * Verify reads sig_in + sig_in_off[i] and writes verdict[i] (1/0; -1 for Sign).
+ * done_ns[i] receives the completion time on the same clock.  Blocks until
+ * every request is done; returns DIL_EINVAL for malformed traces and DIL_EHIP
+ * if a batch fails or no batch completes for 60 s. */
+int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *level, const uint32_t *key,
+                   const uint8_t *msg, const uint64_t *msg_off, const uint8_t *sig_in, const uint64_t *sig_in_off,
+                   const uint64_t *arrival_ns, uint8_t *sig_out, const uint64_t *sig_out_off, int32_t *verdict,
+                   uint64_t *done_ns);
+
 /* Number of Sign loop iterations (candidate signatures) the last dil_sign_batch
  * on this context evaluated in total, and the number the sequential algorithm
  * needs (sum over tasks of the winning iteration index + 1).  Synchronises. */
 int dil_sign_stats(dil_ctx *ctx, uint64_t *evaluated, uint64_t *sequential);
+
+/* Workgroups of the persistent Sign kernel the device keeps resident at once,
+ * and candidate slots per workgroup batch (64 / l), for schedule tuning. */
+int dil_persist_capacity(dil_ctx *ctx, int level, int *resident_groups, int *slots_per_batch);
 
 /* Event-measured durations (ms) of the most recent persistent dil_sign_batch
  * calls made since the "timing" parameter was set (at most 64 are kept):

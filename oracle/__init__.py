@@ -26,16 +26,18 @@ Q = 8380417
 N = 256
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C11, -O2, pthreads)."""
-    if force or not os.path.exists(LIBNAME):
+def build(force: bool = True, out: Optional[str] = None, defines: Optional[list] = None) -> str:
+    """Compile the oracle with gcc (plain C11, -O2, pthreads).  `defines` (e.g. ["DIL_PLANT=3"]) and
+    `out` are used only by the planted-mistake tests, which build variants elsewhere."""
+    target = out or LIBNAME
+    if force or not os.path.exists(target):
         srcs = [os.path.join(HERE, s) for s in SOURCES]
-        tmp = LIBNAME + ".tmp"
+        tmp = target + ".tmp"
         cmd = ["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-pthread", "-Wall", "-Wextra",
-               "-Wno-unused-parameter", "-o", tmp] + srcs
+               "-Wno-unused-parameter", "-o", tmp] + ["-D" + d for d in (defines or [])] + srcs
         subprocess.run(cmd, check=True)
-        os.replace(tmp, LIBNAME)
-    return LIBNAME
+        os.replace(tmp, target)
+    return target
 
 
 class _Params(ctypes.Structure):
@@ -57,7 +59,14 @@ def lib() -> ctypes.CDLL:
     if _LIB is None:
         if not os.path.exists(LIBNAME):
             build(force=False)
-        L = ctypes.CDLL(LIBNAME)
+        _LIB = bind(LIBNAME)
+    return _LIB
+
+
+def bind(path: str) -> ctypes.CDLL:
+    """Load an oracle shared library and declare its ctypes signatures."""
+    if True:
+        L = ctypes.CDLL(path)
         sig = {
             "dil_ref_params": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_Params)]),
             "dil_ref_keccak_f1600": (None, [_P]),
@@ -82,6 +91,7 @@ def lib() -> ctypes.CDLL:
             "dil_ref_bitunpack": (None, [_P, _SZ, ctypes.c_int, _P]),
             "dil_ref_keygen": (ctypes.c_int, [ctypes.c_int, _P, _P, _P]),
             "dil_ref_sign": (ctypes.c_int, [ctypes.c_int, _P, _P, _SZ, _P]),
+            "dil_ref_set_sign_cap": (None, [ctypes.c_int]),
             "dil_ref_verify": (ctypes.c_int, [ctypes.c_int, _P, _P, _SZ, _P]),
             "dil_ref_keygen_batch": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, ctypes.c_uint32, ctypes.c_int]),
             "dil_ref_sign_batch": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_uint32,
@@ -93,8 +103,7 @@ def lib() -> ctypes.CDLL:
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
-        _LIB = L
-    return _LIB
+    return L
 
 
 def _ptr(a: np.ndarray) -> int:

@@ -85,7 +85,9 @@ void dil_ref_bitunpack(const uint8_t *in, size_t n, int b, uint32_t *v);
 
 /* scheme (Alg. 1-3), single task */
 int dil_ref_keygen(int level, const uint8_t zeta[32], uint8_t *pk, uint8_t *sk);
-/* returns the number of loop iterations used (>= 1), or -1 on bad level */
+/* returns the number of loop iterations used (>= 1), -1 on bad level, or -2 (all-zero
+   signature) when the loop reaches the iteration cap (default 100000, see set_sign_cap) */
+void dil_ref_set_sign_cap(int cap);
 int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, uint8_t *sig);
 /* returns 1 accept, 0 reject, -1 bad level */
 int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen, const uint8_t *sig);

@@ -49,6 +49,9 @@ static void keccak_init_once(void) {
   int x = 1, y = 0;
   for (int t = 0; t < 24; t++) {
     g_rho[x + 5 * y] = ((t + 1) * (t + 2) / 2) % 64;
+#if defined(DIL_PLANT) && DIL_PLANT == 1
+    if (t == 7) g_rho[x + 5 * y] = (g_rho[x + 5 * y] + 1) % 64; /* planted: one wrong rotation offset */
+#endif
     int nx = y, ny = (2 * x + 3 * y) % 5;
     x = nx; y = ny;
   }
@@ -82,7 +85,11 @@ void dil_ref_keccak_f1600(uint64_t A[25]) {
     /* chi */
     for (int y = 0; y < 5; y++)
       for (int x = 0; x < 5; x++)
+#if defined(DIL_PLANT) && DIL_PLANT == 2
+        A[x + 5 * y] = B[x + 5 * y] ^ (B[(x + 1) % 5 + 5 * y] & (~B[(x + 2) % 5 + 5 * y])); /* planted: chi operands swapped */
+#else
         A[x + 5 * y] = B[x + 5 * y] ^ ((~B[(x + 1) % 5 + 5 * y]) & B[(x + 2) % 5 + 5 * y]);
+#endif
     /* iota */
     A[0] ^= g_rc[ir];
   }

@@ -50,7 +50,11 @@ void dil_ref_ntt(int32_t a[ORN]) {
   for (int len = 128; len >= 1; len >>= 1) {
     for (int start = 0; start < ORN; start += 2 * len) {
       k++;
+#if defined(DIL_PLANT) && DIL_PLANT == 3
+      int64_t zeta = powmod(PSI, k); /* planted: twiddle index not bit-reversed */
+#else
       int64_t zeta = powmod(PSI, brv8(k));
+#endif
       for (int j = start; j < start + len; j++) {
         int64_t t = modq(zeta * a[j + len]);
         int64_t u = a[j];
@@ -73,7 +77,11 @@ void dil_ref_intt(int32_t a[ORN]) {
       }
     }
   }
+#if defined(DIL_PLANT) && DIL_PLANT == 4
+  int64_t ninv = 1; /* planted: 1/n dropped */
+#else
   int64_t ninv = powmod(ORN, ORQ - 2); /* 256^-1 mod q by Fermat */
+#endif
   for (int i = 0; i < ORN; i++) a[i] = (int32_t)modq(a[i] * ninv);
 }
 

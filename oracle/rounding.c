@@ -24,7 +24,11 @@ static int64_t modp(int64_t x, int64_t m) { /* mod+ : [0, m) */
 
 static int64_t modpm(int64_t x, int64_t alpha) { /* mod+- : (-floor((a+1)/2), floor(a/2)] */
   int64_t r = modp(x, alpha);
+#if defined(DIL_PLANT) && DIL_PLANT == 5
+  if (r >= alpha / 2) r -= alpha; /* planted: tie goes to the negative side */
+#else
   if (r > alpha / 2) r -= alpha;
+#endif
   return r;
 }
 
@@ -39,7 +43,11 @@ static void decomp(int64_t r, int64_t gamma2, int32_t *r1, int32_t *r0) {
   int64_t alpha = 2 * gamma2;
   int64_t rp = modp(r, ORQ);
   int64_t lo = modpm(rp, alpha);
+#if defined(DIL_PLANT) && DIL_PLANT == 6
+  if (0) { /* planted: Decompose special case dropped */
+#else
   if (rp - lo == ORQ - 1) {
+#endif
     *r1 = 0;
     *r0 = (int32_t)(lo - 1);
   } else {
@@ -60,7 +68,11 @@ void dil_ref_make_hint(const int32_t *z, const int32_t *r, int32_t *h, size_t n,
   for (size_t i = 0; i < n; i++) {
     int32_t a1, a0, b1, b0;
     decomp(r[i], gamma2, &a1, &a0);
+#if defined(DIL_PLANT) && DIL_PLANT == 7
+    decomp((int64_t)r[i] - z[i], gamma2, &b1, &b0); /* planted: wrong sign of z */
+#else
     decomp((int64_t)r[i] + z[i], gamma2, &b1, &b0);
+#endif
     h[i] = a1 != b1;
   }
 }
@@ -71,7 +83,11 @@ void dil_ref_use_hint(const int32_t *h, const int32_t *r, int32_t *out, size_t n
     int32_t r1, r0;
     decomp(r[i], gamma2, &r1, &r0);
     if (h[i] == 0) out[i] = r1;
+#if defined(DIL_PLANT) && DIL_PLANT == 8
+    else if (r0 >= 0) out[i] = (int32_t)modp((int64_t)r1 + 1, m); /* planted: r0 = 0 takes the + branch */
+#else
     else if (r0 > 0) out[i] = (int32_t)modp((int64_t)r1 + 1, m);
+#endif
     else out[i] = (int32_t)modp((int64_t)r1 - 1, m);
   }
 }

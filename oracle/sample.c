@@ -31,7 +31,11 @@ void dil_ref_bitpack(const uint32_t *v, size_t n, int b, uint8_t *out) {
   for (size_t i = 0; i < n; i++)
     for (int t = 0; t < b; t++) {
       size_t bit = i * b + t;
+#if defined(DIL_PLANT) && DIL_PLANT == 9
+      if ((v[i] >> t) & 1) out[bit / 8] |= (uint8_t)(0x80u >> (bit % 8)); /* planted: MSB-first packing */
+#else
       if ((v[i] >> t) & 1) out[bit / 8] |= (uint8_t)(1u << (bit % 8));
+#endif
     }
 }
 
@@ -194,7 +198,12 @@ void dil_ref_sample_in_ball(int level, const uint8_t ctilde[32], int32_t c[ORN])
     int b;
     do { b = stream_byte(&s); } while (b > i);
     c[i] = c[b];
+#if defined(DIL_PLANT) && DIL_PLANT == 10
     c[b] = (signs & 1) ? -1 : 1;
+    if (i == ORN - 1) c[b] = 0; /* planted: last position dropped */
+#else
+    c[b] = (signs & 1) ? -1 : 1;
+#endif
     signs >>= 1;
   }
   stream_close(&s);

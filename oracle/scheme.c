@@ -99,7 +99,11 @@ static void unpack_eta(const ref_params *P, const uint8_t *in, int32_t *s) {
 }
 static void pack_t0(const int32_t *t0, uint8_t *out) {
   int32_t t[ORN];
+#if defined(DIL_PLANT) && DIL_PLANT == 14
+  for (int i = 0; i < ORN; i++) t[i] = (1 << 12) + t0[i]; /* planted: t0 offset with the wrong sign */
+#else
   for (int i = 0; i < ORN; i++) t[i] = (1 << 12) - t0[i];
+#endif
   pack_vals(t, ORN, 13, out);
 }
 static void unpack_t0(const uint8_t *in, int32_t *t0) {
@@ -187,6 +191,12 @@ static void pack_w1(const ref_params *P, const int32_t *w1, uint8_t *out) {
 }
 
 /* ---- Alg. 2 ---- */
+/* Iteration cap of the rejection loop: a correct signer needs more than a few
+   hundred iterations with negligible probability; the cap turns a broken
+   variant (the planted-mistake tests) into a returned error instead of a hang. */
+static int g_sign_cap = 100000;
+void dil_ref_set_sign_cap(int cap) { g_sign_cap = cap > 0 ? cap : 100000; }
+
 int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, uint8_t *sig) {
   ref_params P;
   if (dil_ref_params(level, &P)) return -1;
@@ -234,6 +244,11 @@ int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, 
   uint32_t kappa = 0;
   int iters = 0;
   for (;;) {
+    if (iters >= g_sign_cap) {
+      memset(sig, 0, P.sig_bytes);
+      iters = -2;
+      break;
+    }
     iters++;
     dil_ref_expand_mask(level, rhop, kappa, y);
     kappa += (uint32_t)l;
@@ -264,7 +279,11 @@ int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, 
       dil_ref_intt(t);
       for (int cidx = 0; cidx < ORN; cidx++) {
         z[j * ORN + cidx] = centred((int64_t)y[j * ORN + cidx] + t[cidx]);
+#if defined(DIL_PLANT) && DIL_PLANT == 11
+        if (iabs(z[j * ORN + cidx]) >= P.gamma1) reject = 1; /* planted: beta dropped from the z bound */
+#else
         if (iabs(z[j * ORN + cidx]) >= P.gamma1 - P.beta) reject = 1;
+#endif
       }
     }
     if (reject) continue;
@@ -289,7 +308,11 @@ int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, 
       for (int cidx = 0; cidx < ORN; cidx++) {
         if (iabs(centred(t[cidx])) >= P.gamma2) reject = 1;
         negct0[cidx] = (int32_t)modq(-(int64_t)t[cidx]);
+#if defined(DIL_PLANT) && DIL_PLANT == 13
+        r[cidx] = (int32_t)modq((int64_t)wcs2[i * ORN + cidx] - t[cidx]); /* planted: wrong sign of c t0 */
+#else
         r[cidx] = (int32_t)modq((int64_t)wcs2[i * ORN + cidx] + t[cidx]);
+#endif
       }
       dil_ref_make_hint(negct0, r, h + i * ORN, ORN, P.gamma2);
       for (int cidx = 0; cidx < ORN; cidx++) hcount += h[i * ORN + cidx];
@@ -344,7 +367,9 @@ int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen
       for (int cidx = 0; cidx < ORN; cidx++) t1[cidx] = (int32_t)modq((int64_t)t1[cidx] << 13);
       dil_ref_ntt(t1);
       pointwise(t, ch, t1);
+#if !(defined(DIL_PLANT) && DIL_PLANT == 12) /* planted (12): the c t1 2^d term dropped */
       for (int cidx = 0; cidx < ORN; cidx++) acc[cidx] = (int32_t)modq((int64_t)acc[cidx] - t[cidx]);
+#endif
       dil_ref_intt(acc);
       dil_ref_use_hint(h + i * ORN, acc, w1 + i * ORN, ORN, P.gamma2);
     }

@@ -14,7 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdil.so")
-SOURCES = ["api.hip"]
+SOURCES = ["api.hip", "server.hip"]
 HEADERS = ["common.h", "keccak.h", "ntt.h", "poly.h", "sponge.h", "kernels.h", "persist.h"]
 
 

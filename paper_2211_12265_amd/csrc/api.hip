@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <mutex>
+#include <vector>
 
 #include "../../include/dil.h"
 #include "persist.h"
@@ -27,6 +28,19 @@ struct dil_ctx {
   static constexpr int RING = 64;
   hipEvent_t ev[RING][3] = {};                 // per timed call: before setup, before loop, after loop
   int ev_count = 0;                            // timed calls recorded since timing was (re)enabled
+  int cu_count = 0;                            // cached device properties
+  int occ[6] = {0, 0, 0, 0, 0, 0};             // cached persistent-kernel occupancy per level
+  // hipGraph replay of identical calls (same level, buffers, count and schedule)
+  int use_graph = 0;
+  hipStream_t cap_stream = nullptr;            // private stream the graphs are captured on
+  struct Graph {
+    uint64_t key[16];
+    hipGraphExec_t exec;
+    uint64_t last_use;
+  };
+  std::vector<Graph> graphs;
+  uint64_t clock = 0;
+  int graph_hits = 0, graph_builds = 0;
 };
 
 struct dil_keyset {
@@ -60,6 +74,11 @@ int fail(dil_ctx *ctx, int code, const char *what, hipError_t e = hipSuccess) {
     if (e_ != hipSuccess) return fail(ctx, DIL_EHIP, "kernel launch", e_); \
   } while (0)
 
+void drop_graphs(dil_ctx *ctx) {
+  for (auto &g : ctx->graphs) hipGraphExecDestroy(g.exec);
+  ctx->graphs.clear();
+}
+
 bool valid_level(int lv) { return lv == 2 || lv == 3 || lv == 5; }
 
 template <int LV>
@@ -84,6 +103,7 @@ int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws, size_t grid = 0, PScr *sc = nullp
   if (need > ctx->ws_bytes) {
     if (ctx->ws_mem) {
       hipDeviceSynchronize();
+      drop_graphs(ctx);
       hipFree(ctx->ws_mem);
       ctx->ws_mem = nullptr;
       ctx->ws_bytes = 0;
@@ -145,6 +165,49 @@ int take_msg_error(dil_ctx *ctx, hipStream_t st) {
     HIPCHK(ctx, hipStreamSynchronize(st));
     return fail(ctx, DIL_EMSG, "decreasing msg_off entry (those messages were treated as empty)");
   }
+  return DIL_OK;
+}
+
+// Enqueue fn(stream) on st, or -- with graphs enabled -- replay the graph that
+// captured fn for this exact key (capturing it on first use).
+template <class F>
+int enqueue(dil_ctx *ctx, const uint64_t *key, hipStream_t st, F fn) {
+  if (!ctx->use_graph) return fn(st);
+  ctx->clock++;
+  for (auto &g : ctx->graphs)
+    if (!memcmp(g.key, key, sizeof g.key)) {
+      g.last_use = ctx->clock;
+      ctx->graph_hits++;
+      HIPCHK(ctx, hipGraphLaunch(g.exec, st));
+      return DIL_OK;
+    }
+  if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+  int rc = fn(ctx->cap_stream);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(ctx->cap_stream, &graph);
+  if (rc) {
+    if (graph) hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(ctx, DIL_EHIP, "graph capture", e);
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(ctx, DIL_EHIP, "graph instantiate", e);
+  if (ctx->graphs.size() >= 16) {  // evict the least recently used
+    auto it = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                               [](const dil_ctx::Graph &x, const dil_ctx::Graph &y) { return x.last_use < y.last_use; });
+    hipGraphExecDestroy(it->exec);
+    ctx->graphs.erase(it);
+  }
+  dil_ctx::Graph g;
+  memcpy(g.key, key, sizeof g.key);
+  g.exec = exec;
+  g.last_use = ctx->clock;
+  ctx->graphs.push_back(g);
+  ctx->graph_builds++;
+  HIPCHK(ctx, hipGraphLaunch(exec, st));
   return DIL_OK;
 }
 
@@ -226,11 +289,13 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
                     const uint64_t *msg_off, uint8_t *sig, uint32_t count, hipStream_t st,
                     const dil_keyset *ks = nullptr) {
   constexpr int G = PCfg<LV>::G;
-  int per_cu = 0;
-  HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, sg_persist_k<LV>, 64, 0));
-  hipDeviceProp_t prop;
-  HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
-  uint64_t pmax = (uint64_t)std::max(per_cu, 1) * prop.multiProcessorCount;
+  if (!ctx->cu_count) {
+    hipDeviceProp_t prop;
+    HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
+    ctx->cu_count = prop.multiProcessorCount;
+  }
+  if (!ctx->occ[LV]) HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx->occ[LV], sg_persist_k<LV>, 64, 0));
+  uint64_t pmax = (uint64_t)std::max(ctx->occ[LV], 1) * ctx->cu_count;
   uint64_t hmax = ctx->persist_hmax > 0 ? (uint64_t)ctx->persist_hmax : (count + pmax - 1) / pmax;
   hmax = std::min<uint64_t>(std::max<uint64_t>(hmax, 1), G);
   uint64_t grid = ctx->persist_grid > 0 ? (uint64_t)ctx->persist_grid : std::min<uint64_t>(pmax, (count + hmax - 1) / hmax);
@@ -240,18 +305,29 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   int rc = ws_carve<LV>(ctx, count, ws, grid, &sc);
   if (rc) return rc;
   if (ks) use_keyset(ws, ks, key_idx);
-  HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
-  HIPCHK(ctx, hipMemsetAsync(ctx->dev_stats, 0, 8 * 4, st));
+  uint64_t key[16] = {1, (uint64_t)LV, (uint64_t)sk, (uint64_t)key_idx, (uint64_t)msg, (uint64_t)msg_off,
+                      (uint64_t)sig, count, (uint64_t)ks, grid, hmax, (uint64_t)ctx->ws_mem, 0, 0, 0, 0};
   hipEvent_t *evs = ctx->timing ? ctx->ev[ctx->ev_count % dil_ctx::RING] : nullptr;
   if (evs) HIPCHK(ctx, hipEventRecord(evs[0], st));
-  sign_setup<LV>(ws, sk, key_idx, msg, msg_off, count, st, ks, ctx->dev_stats + 8);
+  rc = enqueue(ctx, key, st, [&](hipStream_t s) {
+    zero_words_k<<<1, 64, 0, s>>>(ws.counters, 16, ctx->dev_stats, 8);
+    sign_setup<LV>(ws, sk, key_idx, msg, msg_off, count, s, ks, ctx->dev_stats + 8);
+    LAUNCHCHK(ctx);
+    return DIL_OK;
+  });
+  if (rc) return rc;
   if (evs) HIPCHK(ctx, hipEventRecord(evs[1], st));
-  sg_persist_k<LV><<<(unsigned)grid, 64, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+  key[12] = 1;  // second graph: the loop kernel
+  rc = enqueue(ctx, key, st, [&](hipStream_t s) {
+    sg_persist_k<LV><<<(unsigned)grid, 64, 0, s>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+    LAUNCHCHK(ctx);
+    return DIL_OK;
+  });
+  if (rc) return rc;
   if (evs) {
     HIPCHK(ctx, hipEventRecord(evs[2], st));
     ctx->ev_count++;
   }
-  LAUNCHCHK(ctx);
   ctx->last_stream = st;
   ctx->stats_pending = 1;
   return DIL_OK;
@@ -266,14 +342,18 @@ int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const 
   int rc = ws_carve<LV>(ctx, count, ws);
   if (rc) return rc;
   if (ks) use_keyset(ws, ks, key_idx);
-  HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
-  vf_prep_k<LV><<<blocks_for(count, 64), 64, 0, st>>>(pk, key_idx, msg, msg_off, sig, ws, count, ctx->dev_stats + 8);
-  if (!ks)
-    expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(pk, P<LV>::PK, key_idx, ws.A, count);
-  vf_main_k<LV><<<count, 64, 0, st>>>(pk, key_idx, sig, ws, count);
-  vf_final_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sig, ws, verdict, count);
-  LAUNCHCHK(ctx);
-  return DIL_OK;
+  uint64_t key[16] = {2, (uint64_t)LV, (uint64_t)pk, (uint64_t)key_idx, (uint64_t)msg, (uint64_t)msg_off,
+                      (uint64_t)sig, (uint64_t)verdict, count, (uint64_t)ks, (uint64_t)ctx->ws_mem, 0, 0, 0, 0, 0};
+  return enqueue(ctx, key, st, [&](hipStream_t s) {
+    zero_words_k<<<1, 64, 0, s>>>(ws.counters, 16, nullptr, 0);
+    vf_prep_k<LV><<<blocks_for(count, 64), 64, 0, s>>>(pk, key_idx, msg, msg_off, sig, ws, count, ctx->dev_stats + 8);
+    if (!ks)
+      expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, s>>>(pk, P<LV>::PK, key_idx, ws.A, count);
+    vf_main_k<LV><<<count, 64, 0, s>>>(pk, key_idx, sig, ws, count);
+    vf_final_k<LV><<<blocks_for(count, 256), 256, 0, s>>>(sig, ws, verdict, count);
+    LAUNCHCHK(ctx);
+    return DIL_OK;
+  });
 }
 
 template <int LV>
@@ -363,8 +443,8 @@ int dil_ctx_create(dil_ctx **out, int device, size_t workspace_bytes) {
     return DIL_ENOMEM;
   }
   memset(c->host_counters, 0, 64);
-  e = hipMalloc((void **)&c->dev_stats, 64);
-  if (e == hipSuccess) e = hipMemset(c->dev_stats, 0, 64);
+  e = hipMalloc((void **)&c->dev_stats, 256);
+  if (e == hipSuccess) e = hipMemset(c->dev_stats, 0, 256);
   if (e != hipSuccess) {
     hipHostFree(c->host_counters);
     delete c;
@@ -390,6 +470,8 @@ int dil_ctx_destroy(dil_ctx *ctx) {
   if (ctx->ws_mem) hipFree(ctx->ws_mem);
   if (ctx->host_counters) hipHostFree(ctx->host_counters);
   if (ctx->dev_stats) hipFree(ctx->dev_stats);
+  drop_graphs(ctx);
+  if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
   for (int r = 0; r < dil_ctx::RING; r++)
     for (int i = 0; i < 3; i++)
       if (ctx->ev[r][i]) hipEventDestroy(ctx->ev[r][i]);
@@ -420,6 +502,9 @@ int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value) {
         for (int i = 0; i < 3; i++) HIPCHK(ctx, hipEventCreate(&ctx->ev[r][i]));
     ctx->timing = value != 0;
     ctx->ev_count = 0;
+  } else if (!strcmp(name, "graph")) {
+    ctx->use_graph = value != 0;
+    if (!ctx->use_graph) drop_graphs(ctx);
   } else if (!strcmp(name, "persist.grid")) ctx->persist_grid = value;
   else if (!strcmp(name, "persist.hmax")) ctx->persist_hmax = value;
   else return fail(ctx, DIL_EINVAL, "unknown parameter");
@@ -547,6 +632,43 @@ int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_id
   });
 }
 
+int dil_ctx_reserve(dil_ctx *ctx, int level, uint32_t count) {
+  if (!ctx || !valid_level(level)) return fail(ctx, DIL_EINVAL, "bad context or level");
+  hipSetDevice(ctx->device);
+  if (!ctx->cu_count) {
+    hipDeviceProp_t prop;
+    HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
+    ctx->cu_count = prop.multiProcessorCount;
+  }
+  return by_level(level, [&](auto lv) {
+    constexpr int LV = decltype(lv)::value;
+    if (!ctx->occ[LV])
+      HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx->occ[LV], sg_persist_k<LV>, 64, 0));
+    size_t grid = std::max<size_t>((size_t)ctx->occ[LV] * ctx->cu_count, (size_t)std::max<int64_t>(ctx->persist_grid, 0));
+    Ws ws;
+    PScr sc;
+    return ws_carve<LV>(ctx, count, ws, grid, &sc);
+  });
+}
+
+int dil_persist_capacity(dil_ctx *ctx, int level, int *resident_groups, int *slots_per_batch) {
+  if (!ctx || !valid_level(level)) return fail(ctx, DIL_EINVAL, "bad context or level");
+  hipSetDevice(ctx->device);
+  if (!ctx->cu_count) {
+    hipDeviceProp_t prop;
+    HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
+    ctx->cu_count = prop.multiProcessorCount;
+  }
+  return by_level(level, [&](auto lv) {
+    constexpr int LV = decltype(lv)::value;
+    if (!ctx->occ[LV])
+      HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx->occ[LV], sg_persist_k<LV>, 64, 0));
+    if (resident_groups) *resident_groups = ctx->occ[LV] * ctx->cu_count;
+    if (slots_per_batch) *slots_per_batch = PCfg<LV>::G;
+    return DIL_OK;
+  });
+}
+
 int dil_sign_timing(dil_ctx *ctx, float *setup_ms, float *loop_ms, int max_calls, int *n_calls) {
   if (!ctx) return DIL_EINVAL;
   int n = std::min(ctx->ev_count, dil_ctx::RING);
@@ -563,6 +685,16 @@ int dil_sign_timing(dil_ctx *ctx, float *setup_ms, float *loop_ms, int max_calls
   }
   return DIL_OK;
 }
+
+#ifdef DIL_PHASE_TIMERS
+// Development aid (phase-timer builds only): raw statistics words (64) of the context.
+extern "C" int dil_debug_stats(dil_ctx *ctx, uint32_t *out64) {
+  if (!ctx || !out64) return DIL_EINVAL;
+  HIPCHK(ctx, hipDeviceSynchronize());
+  HIPCHK(ctx, hipMemcpy(out64, ctx->dev_stats, 256, hipMemcpyDeviceToHost));
+  return DIL_OK;
+}
+#endif
 
 int dil_sign_stats(dil_ctx *ctx, uint64_t *evaluated, uint64_t *sequential) {
   if (!ctx) return DIL_EINVAL;
@@ -584,10 +716,13 @@ int dil_ntt_mul_batch(dil_ctx *ctx, const int32_t *a, const int32_t *b, int32_t 
   if (count == 0) return DIL_OK;
   if (!a || !b || !c) return fail(ctx, DIL_EINVAL, "null buffer");
   hipSetDevice(ctx->device);
-  hipDeviceProp_t prop;
-  HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
+  if (!ctx->cu_count) {
+    hipDeviceProp_t prop;
+    HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
+    ctx->cu_count = prop.multiProcessorCount;
+  }
   uint64_t need = (count + 15) / 16;
-  uint64_t grid = std::min<uint64_t>(need, (uint64_t)prop.multiProcessorCount * 16);
+  uint64_t grid = std::min<uint64_t>(need, (uint64_t)ctx->cu_count * 16);
   ntt_mul_k<<<(unsigned)grid, 256, 0, (hipStream_t)stream>>>(a, b, c, count);
   LAUNCHCHK(ctx);
   return DIL_OK;

@@ -49,6 +49,14 @@ __device__ __forceinline__ size_t muw1_stride() {
   return ((size_t)P<LV>::MUW1 + 255) & ~(size_t)255;
 }
 
+// zero two small word arrays (used instead of hipMemsetAsync so that the
+// launch sequence can be captured into a hipGraph)
+__global__ void zero_words_k(uint32_t *a, int na, uint32_t *b, int nb) {
+  int i = threadIdx.x;
+  if (i < na) a[i] = 0;
+  if (b && i < nb) b[i] = 0;
+}
+
 // ------------------------------------------------------------------------
 // KeyGen (Alg. 1)
 // ------------------------------------------------------------------------

@@ -36,6 +36,21 @@ __device__ __forceinline__ size_t w1_stride() {
   return ((size_t)Lv<LV>::K * P<LV>::W1B + 255) & ~(size_t)255;
 }
 
+// Optional per-phase cycle accounting (compile with -DDIL_PHASE_TIMERS): lane 0 of
+// every workgroup adds the s_memtime cycles of each batch phase to stats[8 + p].
+#ifdef DIL_PHASE_TIMERS
+#define PHASE_MARK(p)                                                              \
+  do {                                                                             \
+    uint64_t now_ = __builtin_amdgcn_s_memtime();                                  \
+    if (lane == 0) atomicAdd((unsigned long long *)&stats[16 + 2 * (p)], now_ - ph_t); \
+    ph_t = now_;                                                                   \
+  } while (0)
+#else
+#define PHASE_MARK(p) \
+  do {                \
+  } while (0)
+#endif
+
 __device__ __forceinline__ void wave_sync_global() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
@@ -81,6 +96,9 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
     lds.queue_empty = 0;
   }
   wave_sync();
+#ifdef DIL_PHASE_TIMERS
+  uint64_t ph_t = __builtin_amdgcn_s_memtime();
+#endif
   for (;;) {
     // ---- claim tasks and assign the batch's slots ----
     if (lane == 0) {
@@ -112,6 +130,7 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
     wave_sync();
     const int ns = lds.nslots;
     if (ns == 0) break;
+    PHASE_MARK(0);
     // ---- ExpandMask: one lane per (slot, i) ----
     if (lane < ns * L) {
       int s = lane / L, i = lane % L;
@@ -119,6 +138,7 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
       dev_expand_mask<LV>(ws.rhop + (size_t)task * 64, lds.s_att[s] * (uint32_t)L, i, yb + ((size_t)s * L + i) * N);
     }
     wave_sync_global();
+    PHASE_MARK(1);
     // ---- w = INTT(A NTT(y)) per slot ----
     for (int s = 0; s < ns; s++) {
       uint32_t task = lds.h_task[lds.s_h[s]];
@@ -128,6 +148,7 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
       wave_sync();
     }
     wave_sync_global();
+    PHASE_MARK(2);
     // ---- ctilde and SampleInBall: one lane per slot ----
     if (lane < ns) {
       uint32_t task = lds.h_task[lds.s_h[lane]];
@@ -135,6 +156,7 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
                         lds.c[lane], (uint8_t *)lds.bb[lane]);
     }
     wave_sync();
+    PHASE_MARK(3);
     // ---- checks, in slot order; the first pass of a task is its signature ----
     for (int s = 0; s < ns; s++) {
       int h = lds.s_h[s];
@@ -149,6 +171,7 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
       }
       wave_sync();
     }
+    PHASE_MARK(4);
     // ---- retire signed tasks ----
     if (lane == 0) {
       int nh = lds.nheld, o = 0;

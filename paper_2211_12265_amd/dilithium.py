@@ -24,7 +24,8 @@ EXPORTS = [
     "dil_keygen_batch", "dil_sign_batch", "dil_verify_batch", "dil_sign_stats", "dil_sign_timing",
     "dil_ntt_mul_batch",
     "dil_expand_a_batch", "dil_keyset_create", "dil_keyset_destroy", "dil_keyset_info", "dil_sign_keyset",
-    "dil_verify_keyset",
+    "dil_verify_keyset", "dil_persist_capacity", "dil_ctx_reserve", "dil_server_create", "dil_server_destroy",
+    "dil_server_last_error", "dil_server_stats", "dil_server_run",
 ]
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -68,6 +69,15 @@ def load() -> ctypes.CDLL:
                                            ctypes.POINTER(ctypes.c_size_t)]),
         "dil_sign_keyset": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, ctypes.c_uint32, _P]),
         "dil_verify_keyset": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_uint32, _P]),
+        "dil_persist_capacity": (ctypes.c_int, [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(ctypes.c_int)]),
+        "dil_ctx_reserve": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32]),
+        "dil_server_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, _P, _P, ctypes.c_int,
+                                             ctypes.c_uint32, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int]),
+        "dil_server_destroy": (ctypes.c_int, [_P]),
+        "dil_server_last_error": (ctypes.c_char_p, [_P]),
+        "dil_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
+        "dil_server_run": (ctypes.c_int, [_P, ctypes.c_uint32] + [_P] * 12),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -134,6 +144,9 @@ class Context:
     def set_param(self, name: str, value: int):
         self._check(self.lib.dil_ctx_set_param(self.h, name.encode(), int(value)))
 
+    def reserve(self, level: int, count: int):
+        self._check(self.lib.dil_ctx_reserve(self.h, level, count))
+
     def check(self, stream=None):
         self._check(self.lib.dil_ctx_check(self.h, _stream(stream)))
 
@@ -164,6 +177,12 @@ class Context:
         self._check(self.lib.dil_sign_timing(self.h, ctypes.cast(a, _P), ctypes.cast(b, _P), max_calls,
                                              ctypes.byref(n)))
         return list(a[:n.value]), list(b[:n.value])
+
+    def persist_capacity(self, level: int) -> Tuple[int, int]:
+        """(resident workgroups, candidate slots per batch) of the persistent Sign kernel."""
+        r, s = ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.dil_persist_capacity(self.h, level, ctypes.byref(r), ctypes.byref(s)))
+        return r.value, s.value
 
     def ntt_mul(self, a, b, c, stream=None):
         self._check(self.lib.dil_ntt_mul_batch(self.h, _ptr(a), _ptr(b), _ptr(c), a.shape[0], _stream(stream)))

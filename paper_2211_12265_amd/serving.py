@@ -78,6 +78,8 @@ class _Lane:
         self.torch = torch
         self.stream = torch.cuda.Stream(device=device)
         self.ctx = dl.Context(device.index or 0, mode=dl.MODE_PERSISTENT if persistent else dl.MODE_STAGED)
+        for lv in LEVELS:   # allocate the workspace for the largest admitted batch once
+            self.ctx.reserve(lv, max_tasks)
         pin = dict(pin_memory=True)
         self.h_msg = torch.empty(max_msg, dtype=torch.uint8, **pin)
         self.h_off = torch.empty(max_tasks + 8, dtype=torch.int64, **pin)
@@ -196,6 +198,8 @@ class Server:
         inflight_bytes = {}
         head = 0
         done = 0
+        launch_s: List[float] = []
+        sizes: List[int] = []
         arrivals = reqs.t_arrival * time_scale
         t0 = time.perf_counter()
         while done < n:
@@ -224,7 +228,10 @@ class Server:
                 if fit > 0:
                     lane = free.popleft()
                     idx = np.arange(head, head + fit)
+                    tl = time.perf_counter()
                     self._launch(lane, reqs, idx)
+                    launch_s.append(time.perf_counter() - tl)
+                    sizes.append(fit)
                     inflight_bytes[id(lane)] = int(c[fit - 1])
                     busy.append(lane)
                     head += fit
@@ -236,12 +243,78 @@ class Server:
                     time.sleep(min(wait, 0.001))
         res.wall = time.perf_counter() - t0
         res.latency = res.t_done - arrivals
+        res.batches = len(sizes)
+        res.mean_batch = float(np.mean(sizes)) if sizes else 0.0
+        res.host_launch_s = float(np.sum(launch_s))
+        return res
+
+
+class NativeServer:
+    """The C++ serving engine of libdil (dil_server_*): same admission policy as `Server`, with batch
+    formation, staging and harvesting in native code.  Requests are replayed from a trace with their
+    arrival times (`serve`)."""
+
+    def __init__(self, keysets: Dict[int, "dl.KeySet"], n_streams: int = 4, max_batch: int = 4096,
+                 mem_budget: int = 2 << 30, max_msg_bytes: int = 64 << 20, persistent: bool = True):
+        import ctypes
+        self.lib = dl.load()
+        self.keysets = keysets
+        h = ctypes.c_void_p()
+        ks = [keysets[lv].h if lv in keysets else None for lv in LEVELS]
+        rc = self.lib.dil_server_create(ctypes.byref(h), 0, ks[0], ks[1], ks[2], n_streams, max_batch,
+                                        max_msg_bytes, mem_budget,
+                                        dl.MODE_PERSISTENT if persistent else dl.MODE_STAGED)
+        if rc:
+            raise dl.DilError(rc, "server creation failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dil_server_destroy(self.h)
+            self.h = None
+
+    def serve(self, reqs: Requests, time_scale: float = 1.0) -> Results:
+        import ctypes
+        n = len(reqs)
+        P = lambda a: a.ctypes.data if a is not None and a.size else None
+        op = np.ascontiguousarray(reqs.op, dtype=np.uint8)
+        level = np.ascontiguousarray(reqs.level, dtype=np.uint8)
+        key = np.ascontiguousarray(reqs.key, dtype=np.uint32)
+        msg = np.ascontiguousarray(reqs.msg if reqs.msg.size else np.zeros(1, np.uint8), dtype=np.uint8)
+        moff = np.ascontiguousarray(reqs.msg_off, dtype=np.uint64)
+        arr = np.ascontiguousarray(np.round(reqs.t_arrival * time_scale * 1e9), dtype=np.uint64)
+        sig_in = np.ascontiguousarray(reqs.sig_in if reqs.sig_in is not None and reqs.sig_in.size
+                                      else np.zeros(1, np.uint8), dtype=np.uint8)
+        sig_in_off = np.ascontiguousarray(np.maximum(reqs.sig_off, 0) if reqs.sig_off is not None
+                                          else np.zeros(n, np.int64), dtype=np.uint64)
+        sizes = np.array([sig_size(int(lv)) for lv in LEVELS])
+        ss = np.where(reqs.op == SIGN, sizes[np.searchsorted(LEVELS, reqs.level)], 0).astype(np.uint64)
+        sig_out_off = np.concatenate([[0], np.cumsum(ss)[:-1]]).astype(np.uint64)
+        sig_out = np.zeros(max(int(ss.sum()), 1), np.uint8)
+        verdict = np.full(n, -1, np.int32)
+        done = np.zeros(n, np.uint64)
+        rc = self.lib.dil_server_run(self.h, n, P(op), P(level), P(key), P(msg), P(moff), P(sig_in), P(sig_in_off),
+                                     P(arr), P(sig_out), P(sig_out_off), P(verdict), P(done))
+        if rc:
+            raise dl.DilError(rc, self.lib.dil_server_last_error(self.h).decode(errors="replace"))
+        b, hs = ctypes.c_uint64(), ctypes.c_double()
+        self.lib.dil_server_stats(self.h, ctypes.byref(b), ctypes.byref(hs))
+        res = Results(verdict=verdict, t_done=done.astype(np.float64) * 1e-9)
+        for r in np.nonzero(reqs.op == SIGN)[0]:
+            o = int(sig_out_off[r])
+            res.sig[int(r)] = sig_out[o:o + int(ss[r])]
+        res.wall = float(done.max()) * 1e-9
+        res.latency = res.t_done - arr.astype(np.float64) * 1e-9
+        res.batches = int(b.value)
+        res.mean_batch = n / max(int(b.value), 1)
+        res.host_launch_s = hs.value
         return res
 
 
 def latency_summary(res: Results, reqs: Requests) -> dict:
     lat = res.latency * 1e3
     out = {"requests": int(len(reqs)), "wall_s": res.wall, "ops_per_s": len(reqs) / res.wall,
+           "batches": res.batches, "mean_batch": res.mean_batch, "host_launch_s": res.host_launch_s,
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "mean_ms": float(lat.mean()), "max_ms": float(lat.max())}
     for op, name in ((SIGN, "sign"), (VERIFY, "verify")):

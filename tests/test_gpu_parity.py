@@ -277,3 +277,70 @@ def test_keyset_sign_verify_parity(sctx, level):
                                                                                 device="cuda"))
     for ks in (ks_both, ks_pk, ks_sk):
         ks.close()
+
+
+@pytest.mark.parametrize("level", [2, 5])
+def test_graph_replays_match_eager(level):
+    """hipGraph replays of persistent Sign and of Verify, with eager work and synchronisation
+    between replays, reproduce the eager results on every replay."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    eager = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    g = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    g.set_param("graph", 1)
+    n = 48
+    seeds = workload.keygen_seeds(n, seed=110 + level)
+    pk, sk = _keygen(eager, level, seeds)
+    msg, off = workload.messages(workload.uniform_lengths(n, 0, 300, seed=111), seed=111)
+    dmsg, doff = dev(msg), dev(off.astype(np.int64))
+    ref = torch.zeros((n, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
+    eager.sign(level, sk, dmsg, doff, ref)
+    torch.cuda.synchronize()
+    ref_h = ref.cpu().numpy()
+    ev0, seq0 = eager.sign_stats()
+    bad = ref_h.copy()
+    bad[::4, 100] ^= 0x10
+    dbad = dev(bad)
+    vref = torch.zeros(n, dtype=torch.int32, device="cuda")
+    eager.verify(level, pk, dmsg, doff, dbad, vref)
+    torch.cuda.synchronize()
+    vref_h = vref.cpu().numpy()
+    out = torch.zeros_like(ref)
+    ver = torch.zeros(n, dtype=torch.int32, device="cuda")
+    for rep in range(4):
+        out.zero_()
+        ver.fill_(-1)
+        g.sign(level, sk, dmsg, doff, out)
+        g.verify(level, pk, dmsg, doff, dbad, ver)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref_h), rep
+        assert np.array_equal(ver.cpu().numpy(), vref_h), rep
+        assert g.sign_stats() == (ev0, seq0)
+        # eager work on other buffers between replays
+        tmp = torch.zeros_like(ref)
+        eager.sign(level, sk, dmsg, doff, tmp)
+        torch.cuda.synchronize()
+    assert vref_h.sum() == n - len(range(0, n, 4))
+    eager.close()
+    g.close()
+
+
+def test_autotuner_picks_a_measured_candidate(ctx):
+    from paper_2211_12265_amd import autotune
+    from paper_2211_12265_amd import dilithium as dl
+    c = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    level, n = 2, 200
+    pk, sk = _keygen(c, level, workload.keygen_seeds(n, seed=120))
+    msg, off = workload.messages(workload.fixed_lengths(n, 32), seed=120)
+    dmsg, doff = dev(msg), dev(off.astype(np.int64))
+    sig = torch.zeros((n, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
+    resident, slots = c.persist_capacity(level)
+    assert resident > 0 and slots == 16
+    res = autotune.tune_sign(c, level, lambda: c.sign(level, sk, dmsg, doff, sig), resident, reps=1, count=n)
+    assert res["best"] in res["table"]
+    c.sign(level, sk, dmsg, doff, sig)
+    torch.cuda.synchronize()
+    osig, _ = oracle.sign_batch(level, sk.cpu().numpy(), msg, off)
+    assert np.array_equal(sig.cpu().numpy(), osig)
+    c.close()

@@ -36,9 +36,11 @@ def setup():
     ctx.close()
 
 
-def test_serving_matches_oracle(setup):
+@pytest.mark.parametrize("engine", ["python", "native"])
+def test_serving_matches_oracle(setup, engine):
     dl, sv, ctx, keysets, host, reqs, flipped = setup
-    server = sv.Server(keysets, n_streams=3, max_batch=64, mem_budget=4 << 20, max_msg_bytes=1 << 20)
+    cls = sv.Server if engine == "python" else sv.NativeServer
+    server = cls(keysets, n_streams=3, max_batch=64, mem_budget=4 << 20, max_msg_bytes=1 << 20)
     res = server.serve(reqs)
     server.close()
     assert np.isfinite(res.t_done).all()
@@ -64,9 +66,11 @@ def test_serving_matches_oracle(setup):
             assert np.array_equal(ov == 0, flipped[v])
 
 
-def test_same_alone_and_in_mix(setup):
+@pytest.mark.parametrize("engine", ["python", "native"])
+def test_same_alone_and_in_mix(setup, engine):
     dl, sv, ctx, keysets, host, reqs, flipped = setup
-    server = sv.Server(keysets, n_streams=4, max_batch=128, mem_budget=64 << 20, max_msg_bytes=1 << 20)
+    cls = sv.Server if engine == "python" else sv.NativeServer
+    server = cls(keysets, n_streams=4, max_batch=128, mem_budget=64 << 20, max_msg_bytes=1 << 20)
     mixed = server.serve(reqs)
     rng = np.random.default_rng(3)
     for r in rng.choice(len(reqs), size=24, replace=False):
