@@ -3,7 +3,9 @@
 One step = dil_sign_batch over 10,000 tasks (32-byte messages, one key per
 task) followed by dil_verify_batch over the 10,000 signatures just produced,
 all buffers resident in HBM.  Keys are generated on the GPU before timing.
-Prints ONE JSON line (rank 0).  See the design doc for the roofline conventions.
+Prints ONE JSON line (rank 0) with the roofline of the Sign loop kernel
+(algorithmic int32 lane-ops per launch over its HIP-event time, against the
+chip's 32-bit integer issue rate) and the CPU oracle's rate on a sample.
 
   python bench.py [--steps K] [--warmup W] [--mode persistent|staged]
                   [--count N] [--level 2|3|5] [--no-cpu-baseline]
@@ -36,7 +38,8 @@ W1_BYTES = {2: 4 * 192, 3: 6 * 128, 5: 8 * 128}
 PK_BYTES = {2: 1312, 3: 1952, 5: 2592}
 SK_BYTES = {2: 2528, 3: 4000, 5: 4864}
 SIG_BYTES = {2: 2420, 3: 3293, 5: 4595}
-PEAK_INT32_OPS = 256 * 4 * 32 * 2.4e9   # 78.6 T int32 lane-ops/s (see DESIGN.md)
+# 256 CUs x 4 SIMDs x 32 lanes of simple 32-bit integer ops per clock x 2.4 GHz
+PEAK_INT32_OPS = 256 * 4 * 32 * 2.4e9   # 78.6 T int32 lane-ops/s
 
 
 def perms_shake(inlen: int, outlen: int, rate: int) -> int:
@@ -90,8 +93,9 @@ def cpu_baseline(level: int, sample: int) -> dict:
     sign_s, ver_s = t1 - t0, t2 - t1
     return {"value": sample / (sign_s + ver_s), "unit": "sign+verify pairs/s", "cores": threads, "kind": "oracle",
             "sign_per_s": sample / sign_s, "verify_per_s": sample / ver_s,
+            "wall_s": sign_s + ver_s,
             "sample": f"{sample} Dilithium{level} sign + {sample} verify, 32-byte messages, plain C oracle on "
-                      f"{threads} host threads"}
+                      f"{threads} host threads ({sign_s + ver_s:.2f} s wall)"}
 
 
 def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -> dict:
@@ -140,6 +144,55 @@ def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -
     return summ
 
 
+def e2e_run(level: int, n: int, msg_dist: str, stream_counts, chunks_per_stream: int = 2, reps: int = 5) -> dict:
+    """PCIe-inclusive rates: keys, messages, signatures and verdicts live in pinned host memory and
+    every call moves them through the multi-stream chunked pipeline.  Reported beside the bench
+    line, never as its value."""
+    import torch
+    from paper_2211_12265_amd import dilithium as dl
+    from paper_2211_12265_amd import workload
+    from paper_2211_12265_amd.pipeline import HostPipeline, pinned
+    pkl, skl, sgl = dl.sizes(level)
+    ctx = dl.Context(0)
+    pk = torch.zeros((n, pkl), dtype=torch.uint8, device="cuda")
+    sk = torch.zeros((n, skl), dtype=torch.uint8, device="cuda")
+    ctx.keygen(level, torch.from_numpy(workload.keygen_seeds(n, seed=0)).cuda(), pk, sk)
+    lens = workload.fixed_lengths(n, 32) if msg_dist == "fixed32" else workload.uniform_lengths(n, 32, 4096)
+    msg, off = workload.messages(lens, seed=0)
+    h_pk, h_sk = pinned((n, pkl)), pinned((n, skl))
+    h_pk.copy_(pk)
+    h_sk.copy_(sk)
+    h_msg = pinned((len(msg),))
+    h_msg.numpy()[:] = msg
+    h_sig, h_ver = pinned((n, sgl)), pinned((n,), torch.int32)
+    rows = []
+    for S in stream_counts:
+        chunk = -(-n // (S * chunks_per_stream))
+        p = HostPipeline(level, n_streams=S, chunk=chunk)
+        p.sign(h_sk, h_msg, off, h_sig)
+        p.verify(h_pk, h_msg, off, h_sig, h_ver)
+        torch.cuda.synchronize()
+        ts, tv = [], []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            p.sign(h_sk, h_msg, off, h_sig)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            p.verify(h_pk, h_msg, off, h_sig, h_ver)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            ts.append(t1 - t0)
+            tv.append(t2 - t1)
+        p.check()
+        rows.append({"streams": S, "chunk": chunk, "sign_per_s": n / float(np.median(ts)),
+                     "verify_per_s": n / float(np.median(tv)), "all_verified": bool(int(h_ver.sum()) == n)})
+        p.close()
+    ctx.close()
+    best = max(rows, key=lambda r: r["sign_per_s"] * r["verify_per_s"] / (r["sign_per_s"] + r["verify_per_s"]))
+    return {"what": f"Dilithium{level} batch {n}, host-resident pinned buffers, H2D + kernels + D2H per call, "
+                    f"chunked over HIP streams (median of {reps})", "rows": rows, "best": best}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,16 +201,26 @@ def main():
     ap.add_argument("--count", type=int, default=10000)
     ap.add_argument("--level", type=int, default=2, choices=[2, 3, 5])
     ap.add_argument("--mode", default="persistent", choices=["persistent", "staged"])
+    ap.add_argument("--msg-dist", default="fixed32", choices=["fixed32", "uniform"],
+                    help="32-byte messages, or lengths uniform on [32, 4096] (the level-3/5 configuration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
+    ap.add_argument("--waves", type=int, default=0, choices=[0, 1, 4],
+                    help="wavefronts per persistent workgroup (0: let the autotuner choose; 1 without it)")
+    ap.add_argument("--schedule", default="",
+                    help="fixed persistent schedule 'waves,hmax,grid' (skips the autotuner)")
     ap.add_argument("--graph", type=int, default=1, help="replay Sign/Verify launch sequences as hipGraphs")
-    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--cpu-sample", type=int, default=8192,
+                    help="tasks the CPU oracle signs and verifies for the baseline (about 15 thread-seconds at level 2)")
     ap.add_argument("--serving", action="store_true", help="also run the serving loop and report p50/p99")
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=100000)
     ap.add_argument("--serving-seconds", type=float, default=5.0)
     ap.add_argument("--serving-streams", type=int, default=4)
     ap.add_argument("--serving-batch", type=int, default=4096)
+    ap.add_argument("--e2e", action="store_true",
+                    help="also report PCIe-inclusive rates through the multi-stream host pipeline")
+    ap.add_argument("--e2e-streams", default="1,2,4,8,12")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -172,7 +235,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only: the batched path runs on a single MI355X "
-              f"(--gpus {args.gpus} is not supported; see DESIGN.md for how it would shard)", file=sys.stderr)
+              f"(--gpus {args.gpus} is not supported: tasks are independent, so a multi-GPU run would split the "
+              f"batch into one contiguous task range per GPU)", file=sys.stderr)
         sys.exit(2)
 
     if args.serving_only:
@@ -190,7 +254,7 @@ def main():
     pkl, skl, sgl = dl.sizes(level)
     ctx = dl.Context(0, mode=dl.MODE_PERSISTENT if args.mode == "persistent" else dl.MODE_STAGED)
     seeds = workload.keygen_seeds(n, seed=0)
-    lens = workload.fixed_lengths(n, 32)
+    lens = workload.fixed_lengths(n, 32) if args.msg_dist == "fixed32" else workload.uniform_lengths(n, 32, 4096)
     msg, off = workload.messages(lens, seed=0)
     g_seeds = torch.from_numpy(seeds).to(dev)
     pk = torch.zeros((n, pkl), dtype=torch.uint8, device=dev)
@@ -213,11 +277,17 @@ def main():
             ev[2].record(stream)
 
     tuning = None
-    if args.mode == "persistent" and not args.no_tune:
+    if args.schedule:
+        w, h, g = (int(x) for x in args.schedule.split(","))
+        for name, v in (("persist.waves", w), ("persist.hmax", h), ("persist.grid", g)):
+            ctx.set_param(name, v)
+        args.waves = w
+    elif args.mode == "persistent" and not args.no_tune:
         from paper_2211_12265_amd import autotune
-        resident, _ = ctx.persist_capacity(level)
-        tuning = autotune.tune_sign(ctx, level, lambda: ctx.sign(level, sk, g_msg, g_off, sig), resident,
-                                    count=n)
+        tuning = autotune.tune_sign(ctx, level, lambda: ctx.sign(level, sk, g_msg, g_off, sig), count=n,
+                                    waves=(args.waves,) if args.waves else (1, 4))
+    elif args.mode == "persistent" and args.waves:
+        ctx.set_param("persist.waves", args.waves)
     if args.graph:
         ctx.set_param("graph", 1)
     for _ in range(args.warmup):
@@ -252,7 +322,8 @@ def main():
         loop_med = float(np.median(loop_ms))
         k_ops = sequential * sign_iteration_ops(level)
         achieved = k_ops / (loop_med * 1e-3)
-        kname = "sg_persist_k (persistent Sign rejection-loop kernel)"
+        four = tuning["best"]["waves"] == 4 if tuning else args.waves == 4
+        kname = ("sg_persist4_k" if four else "sg_persist_k") + " (persistent Sign rejection-loop kernel)"
         kextra = {"kernel_ms_median": loop_med, "setup_ms_median": float(np.median(setup_ms)),
                   "timed_launches": len(loop_ms), "ops_per_launch": k_ops}
     else:
@@ -265,10 +336,13 @@ def main():
         "unit": "sign+verify pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"Dilithium{level} batch {n} sign + {n} verify, 32-byte messages, one key per task, "
-                               f"device-resident buffers", "level": level, "batch": n, "msg_len": 32,
+        "config": {"workload": f"Dilithium{level} batch {n} sign + {n} verify, "
+                               f"{'32-byte' if args.msg_dist == 'fixed32' else 'uniform 32-4096-byte'} messages, "
+                               f"one key per task, device-resident buffers", "level": level, "batch": n,
+                   "msg_len": 32 if args.msg_dist == "fixed32" else "uniform[32,4096]",
                    "sign_mode": args.mode, "hipgraph": bool(args.graph),
-                   "schedule": None if tuning is None else {k: tuning["best"][k] for k in ("hmax", "grid")}},
+                   "schedule": ({k: tuning["best"][k] for k in ("waves", "hmax", "grid")} if tuning else
+                                args.schedule or None)},
         "sign_per_s": sign_rate, "verify_per_s": ver_rate,
         "sign_ms_median": float(np.median(sign_ms)), "verify_ms_median": float(np.median(ver_ms)),
         "sign_iterations": {"sequential": int(sequential), "evaluated": int(evaluated),
@@ -281,6 +355,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(level, args.cpu_sample)
+    if args.e2e:
+        out["e2e_pcie_inclusive"] = e2e_run(level, n, args.msg_dist,
+                                            [int(x) for x in args.e2e_streams.split(",") if x])
     if args.serving:
         out["serving"] = serving_run(args.serving_requests, args.serving_seconds, args.serving_streams,
                                      args.serving_batch)

@@ -1,9 +1,12 @@
 """Autotuner for the persistent Sign kernel's schedule.
 
-The schedule has two knobs (dil_ctx_set_param):
-  persist.hmax  tasks a workgroup holds at once; with G = 64 / l candidate
-                slots per batch, each held task gets G / hmax consecutive
-                nonces per batch (hmax = G: no speculation until tasks retire);
+The schedule has three knobs (dil_ctx_set_param):
+  persist.waves wavefronts per workgroup: 1 (G = 64 / l candidate slots per
+                batch) or 4 (G = 4 * (64 / l) slots; the challenge hashes of
+                all slots run on one wavefront with its lanes full);
+  persist.hmax  tasks a workgroup holds at once; each held task gets G / hmax
+                consecutive nonces per batch (hmax = G: no speculation until
+                tasks retire);
   persist.grid  workgroups launched (at most the number the GPU keeps
                 resident; fewer concentrate tasks into fewer, fuller groups).
 Small hmax fills the GPU with speculative nonces and shortens the tail but
@@ -15,18 +18,20 @@ same signatures) and the fastest median wins.
 """
 from __future__ import annotations
 
-from typing import Dict, List, Optional
+from typing import Dict, List, Optional, Sequence
 
 import numpy as np
 
 
-def slots_per_batch(level: int) -> int:
-    return 64 // {2: 4, 3: 5, 5: 7}[level]
+def slots_per_batch(level: int, waves: int = 1) -> int:
+    return waves * (64 // {2: 4, 3: 5, 5: 7}[level])
 
 
-def candidates(level: int, count: int, resident_groups: int) -> List[tuple]:
-    g = slots_per_batch(level)
-    hm = sorted({h for h in (1, 2, 3, 4, 6, 8, 12, 16) if h <= g} | {g})
+def candidates(level: int, count: int, resident_groups: int, waves: int = 1) -> List[tuple]:
+    """(hmax, grid) pairs for one workgroup shape."""
+    g = slots_per_batch(level, waves)
+    base = (1, 2, 3, 4, 6, 8, 12, 16) if waves == 1 else (1, 2, 4, 6, 8, 12, 16, 24, 32, 48, 64)
+    hm = sorted({h for h in base if h <= g} | {g})
     out = []
     for h in hm:
         need = -(-count // h)
@@ -37,17 +42,26 @@ def candidates(level: int, count: int, resident_groups: int) -> List[tuple]:
     return out
 
 
-def tune_sign(ctx, level: int, run, resident_groups: int, reps: int = 3,
-              cands: Optional[List[tuple]] = None, count: Optional[int] = None) -> Dict:
-    """Time `run()` (one Sign call on ctx) for each (hmax, grid) candidate; leave the best set on ctx.
+def tune_sign(ctx, level: int, run, resident_groups: Optional[int] = None, reps: int = 3,
+              cands: Optional[List[tuple]] = None, count: Optional[int] = None,
+              waves: Sequence[int] = (1, 4)) -> Dict:
+    """Time `run()` (one Sign call on ctx) for each schedule; leave the best set on ctx.
 
     run: callable issuing the Sign batch on the current stream.
-    resident_groups: workgroups the GPU keeps resident for the persistent kernel.
+    cands: explicit (waves, hmax, grid) triples; otherwise candidates() for each
+      workgroup shape in `waves`, sized by the resident workgroups the context
+      reports for that shape (resident_groups, if given, overrides it).
     """
     import torch
-    cands = cands or candidates(level, count, resident_groups)
+    if cands is None:
+        cands = []
+        for w in waves:
+            ctx.set_param("persist.waves", w)
+            res = resident_groups or ctx.persist_capacity(level)[0]
+            cands += [(w, h, grid) for h, grid in candidates(level, count, res, w)]
     table = []
-    for h, grid in cands:
+    for w, h, grid in cands:
+        ctx.set_param("persist.waves", w)
         ctx.set_param("persist.hmax", h)
         ctx.set_param("persist.grid", grid)
         run()
@@ -62,8 +76,10 @@ def tune_sign(ctx, level: int, run, resident_groups: int, reps: int = 3,
             torch.cuda.synchronize()
             ts.append(a.elapsed_time(b))
         ev, seq = ctx.sign_stats()
-        table.append({"hmax": h, "grid": grid, "ms": float(np.median(ts)), "evaluated": ev, "sequential": seq})
+        table.append({"waves": w, "hmax": h, "grid": grid, "ms": float(np.median(ts)), "evaluated": ev,
+                      "sequential": seq})
     best = min(table, key=lambda r: r["ms"])
+    ctx.set_param("persist.waves", best["waves"])
     ctx.set_param("persist.hmax", best["hmax"])
     ctx.set_param("persist.grid", best["grid"])
     return {"best": best, "table": table}

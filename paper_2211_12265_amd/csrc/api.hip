@@ -24,12 +24,14 @@ struct dil_ctx {
   hipStream_t last_stream = nullptr;
   int stats_pending = 0;
   int64_t persist_grid = 0, persist_hmax = 0;  // 0 = automatic
+  int persist_waves = 1;                       // wavefronts per persistent workgroup: 1 or 4
   int timing = 0;                              // record HIP events around the persistent Sign phases
   static constexpr int RING = 64;
   hipEvent_t ev[RING][3] = {};                 // per timed call: before setup, before loop, after loop
   int ev_count = 0;                            // timed calls recorded since timing was (re)enabled
   int cu_count = 0;                            // cached device properties
   int occ[6] = {0, 0, 0, 0, 0, 0};             // cached persistent-kernel occupancy per level
+  int occ4[6] = {0, 0, 0, 0, 0, 0};            // same for the four-wave kernel
   // hipGraph replay of identical calls (same level, buffers, count and schedule)
   int use_graph = 0;
   hipStream_t cap_stream = nullptr;            // private stream the graphs are captured on
@@ -41,6 +43,9 @@ struct dil_ctx {
   std::vector<Graph> graphs;
   uint64_t clock = 0;
   int graph_hits = 0, graph_builds = 0;
+  // side streams for independent setup stages (fork/join through events)
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
 };
 
 struct dil_keyset {
@@ -91,15 +96,22 @@ size_t ws_need(size_t cap) {
 }
 
 template <int LV>
-size_t pscr_need(size_t grid) {
-  constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfg<LV>::G;
-  size_t w1s = ((size_t)K * P<LV>::W1B + 255) & ~(size_t)255;
-  return grid * G * ((size_t)(L + K) * 1024 + w1s) + 3 * 256;
+constexpr int persist_slots(int waves) {
+  return waves == 4 ? PCfg4<LV>::G : PCfg<LV>::G;
 }
 
 template <int LV>
-int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws, size_t grid = 0, PScr *sc = nullptr) {
-  size_t need = ws_need<LV>(cap) + (sc ? pscr_need<LV>(grid) : 0);
+size_t pscr_need(size_t grid, int waves) {
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  size_t G = persist_slots<LV>(waves);
+  size_t w1s = ((size_t)K * P<LV>::W1B + 255) & ~(size_t)255;
+  size_t stage = waves == 4 ? sig_stride<LV>() : 0;
+  return grid * G * ((size_t)(L + K) * 1024 + w1s + stage) + 4 * 256;
+}
+
+template <int LV>
+int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws, size_t grid = 0, PScr *sc = nullptr, int waves = 1) {
+  size_t need = ws_need<LV>(cap) + (sc ? pscr_need<LV>(grid, waves) : 0);
   if (need > ctx->ws_bytes) {
     if (ctx->ws_mem) {
       hipDeviceSynchronize();
@@ -144,11 +156,12 @@ int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws, size_t grid = 0, PScr *sc = nullp
   ws.active0 = (uint32_t *)take(cap * 4);
   ws.active1 = (uint32_t *)take(cap * 4);
   if (sc) {
-    constexpr int G = PCfg<LV>::G;
+    size_t G = persist_slots<LV>(waves);
     size_t w1s = ((size_t)K * P<LV>::W1B + 255) & ~(size_t)255;
     sc->y = (int32_t *)take(grid * G * L * 1024);
     sc->w = (int32_t *)take(grid * G * K * 1024);
     sc->w1 = take(grid * G * w1s);
+    sc->stage = waves == 4 ? take(grid * G * sig_stride<LV>()) : nullptr;
   }
   if ((size_t)(p - (uint8_t *)ctx->ws_mem) > ctx->ws_bytes) return fail(ctx, DIL_ENOMEM, "workspace layout overflow");
   return DIL_OK;
@@ -211,6 +224,28 @@ int enqueue(dil_ctx *ctx, const uint64_t *key, hipStream_t st, F fn) {
   return DIL_OK;
 }
 
+// Fork: side streams wait for everything enqueued on st so far.
+int fork_side(dil_ctx *ctx, hipStream_t st) {
+  if (!ctx->side[0]) {
+    for (int i = 0; i < 2; i++) {
+      HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->side[i], hipStreamNonBlocking));
+      HIPCHK(ctx, hipEventCreateWithFlags(&ctx->join_ev[i], hipEventDisableTiming));
+    }
+    HIPCHK(ctx, hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming));
+  }
+  HIPCHK(ctx, hipEventRecord(ctx->fork_ev, st));
+  for (int i = 0; i < 2; i++) HIPCHK(ctx, hipStreamWaitEvent(ctx->side[i], ctx->fork_ev, 0));
+  return DIL_OK;
+}
+// Join: st waits for the side streams' work.
+int join_side(dil_ctx *ctx, hipStream_t st) {
+  for (int i = 0; i < 2; i++) {
+    HIPCHK(ctx, hipEventRecord(ctx->join_ev[i], ctx->side[i]));
+    HIPCHK(ctx, hipStreamWaitEvent(st, ctx->join_ev[i], 0));
+  }
+  return DIL_OK;
+}
+
 inline unsigned blocks_for(uint64_t n, unsigned per) { return (unsigned)((n + per - 1) / per); }
 
 template <int LV>
@@ -239,15 +274,28 @@ void use_keyset(Ws &ws, const dil_keyset *ks, const uint32_t *key_idx) {
   ws.kmap = key_idx;
 }
 
+// The setup stages are independent of each other: mu/rho' hash chains (one lane
+// per task, latency-bound for small batches), ExpandA (one lane per stream) and
+// the secret NTTs (one wave per task).  With `concurrent` they run on the
+// context's side streams so the long chains overlap the bulk work.
 template <int LV>
-void sign_setup(Ws &ws, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg, const uint64_t *msg_off,
-                uint32_t count, hipStream_t st, const dil_keyset *ks, uint32_t *err) {
+int sign_setup(dil_ctx *ctx, Ws &ws, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+               const uint64_t *msg_off, uint32_t count, hipStream_t st, const dil_keyset *ks, uint32_t *err,
+               bool concurrent) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
+  concurrent = concurrent && !ks;
+  if (concurrent) {
+    int rc = fork_side(ctx, st);
+    if (rc) return rc;
+  }
   sg_prep_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, ws, count, err);
   if (!ks) {
-    expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(sk, P<LV>::SK, key_idx, ws.A, count);
-    sg_secret_k<LV><<<count, 64, 0, st>>>(sk, key_idx, ws, count);
+    hipStream_t s1 = concurrent ? ctx->side[0] : st, s2 = concurrent ? ctx->side[1] : st;
+    expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, s1>>>(sk, P<LV>::SK, key_idx, ws.A, count);
+    sg_secret_k<LV><<<count, 64, 0, s2>>>(sk, key_idx, ws, count);
   }
+  if (concurrent) return join_side(ctx, st);
+  return DIL_OK;
 }
 
 template <int LV>
@@ -259,7 +307,8 @@ int sign_staged(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const 
   if (rc) return rc;
   if (ks) use_keyset(ws, ks, key_idx);
   HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
-  sign_setup<LV>(ws, sk, key_idx, msg, msg_off, count, st, ks, ctx->dev_stats + 8);
+  rc = sign_setup<LV>(ctx, ws, sk, key_idx, msg, msg_off, count, st, ks, ctx->dev_stats + 8, false);
+  if (rc) return rc;
   LAUNCHCHK(ctx);
   uint32_t nactive = count;
   uint32_t *cur = ws.active0, *nxt = ws.active1;
@@ -284,34 +333,53 @@ int sign_staged(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const 
   return take_msg_error(ctx, st);
 }
 
+// resident workgroups per CU of the persistent kernel in the context's shape (cached)
 template <int LV>
-int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
-                    const uint64_t *msg_off, uint8_t *sig, uint32_t count, hipStream_t st,
-                    const dil_keyset *ks = nullptr) {
-  constexpr int G = PCfg<LV>::G;
+int persist_occupancy(dil_ctx *ctx, int *occ) {
   if (!ctx->cu_count) {
     hipDeviceProp_t prop;
     HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
     ctx->cu_count = prop.multiProcessorCount;
   }
-  if (!ctx->occ[LV]) HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx->occ[LV], sg_persist_k<LV>, 64, 0));
-  uint64_t pmax = (uint64_t)std::max(ctx->occ[LV], 1) * ctx->cu_count;
+  if (ctx->persist_waves == 4) {
+    if (!ctx->occ4[LV])
+      HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx->occ4[LV], sg_persist4_k<LV>, 256, 0));
+    *occ = std::max(ctx->occ4[LV], 1);
+  } else {
+    if (!ctx->occ[LV])
+      HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx->occ[LV], sg_persist_k<LV>, 64, 0));
+    *occ = std::max(ctx->occ[LV], 1);
+  }
+  return DIL_OK;
+}
+
+template <int LV>
+int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                    const uint64_t *msg_off, uint8_t *sig, uint32_t count, hipStream_t st,
+                    const dil_keyset *ks = nullptr) {
+  const int waves = ctx->persist_waves;
+  const int G = persist_slots<LV>(waves);
+  int occ = 1;
+  int rc = persist_occupancy<LV>(ctx, &occ);
+  if (rc) return rc;
+  uint64_t pmax = (uint64_t)occ * ctx->cu_count;
   uint64_t hmax = ctx->persist_hmax > 0 ? (uint64_t)ctx->persist_hmax : (count + pmax - 1) / pmax;
   hmax = std::min<uint64_t>(std::max<uint64_t>(hmax, 1), G);
   uint64_t grid = ctx->persist_grid > 0 ? (uint64_t)ctx->persist_grid : std::min<uint64_t>(pmax, (count + hmax - 1) / hmax);
   grid = std::max<uint64_t>(grid, 1);
   Ws ws;
   PScr sc;
-  int rc = ws_carve<LV>(ctx, count, ws, grid, &sc);
+  rc = ws_carve<LV>(ctx, count, ws, grid, &sc, waves);
   if (rc) return rc;
   if (ks) use_keyset(ws, ks, key_idx);
   uint64_t key[16] = {1, (uint64_t)LV, (uint64_t)sk, (uint64_t)key_idx, (uint64_t)msg, (uint64_t)msg_off,
-                      (uint64_t)sig, count, (uint64_t)ks, grid, hmax, (uint64_t)ctx->ws_mem, 0, 0, 0, 0};
+                      (uint64_t)sig, count, (uint64_t)ks, grid, hmax, (uint64_t)ctx->ws_mem, 0, (uint64_t)waves, 0, 0};
   hipEvent_t *evs = ctx->timing ? ctx->ev[ctx->ev_count % dil_ctx::RING] : nullptr;
   if (evs) HIPCHK(ctx, hipEventRecord(evs[0], st));
   rc = enqueue(ctx, key, st, [&](hipStream_t s) {
     zero_words_k<<<1, 64, 0, s>>>(ws.counters, 16, ctx->dev_stats, 8);
-    sign_setup<LV>(ws, sk, key_idx, msg, msg_off, count, s, ks, ctx->dev_stats + 8);
+    int r2 = sign_setup<LV>(ctx, ws, sk, key_idx, msg, msg_off, count, s, ks, ctx->dev_stats + 8, true);
+    if (r2) return r2;
     LAUNCHCHK(ctx);
     return DIL_OK;
   });
@@ -319,7 +387,10 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   if (evs) HIPCHK(ctx, hipEventRecord(evs[1], st));
   key[12] = 1;  // second graph: the loop kernel
   rc = enqueue(ctx, key, st, [&](hipStream_t s) {
-    sg_persist_k<LV><<<(unsigned)grid, 64, 0, s>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+    if (waves == 4)
+      sg_persist4_k<LV><<<(unsigned)grid, 256, 0, s>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+    else
+      sg_persist_k<LV><<<(unsigned)grid, 64, 0, s>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
     LAUNCHCHK(ctx);
     return DIL_OK;
   });
@@ -346,9 +417,21 @@ int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const 
                       (uint64_t)sig, (uint64_t)verdict, count, (uint64_t)ks, (uint64_t)ctx->ws_mem, 0, 0, 0, 0, 0};
   return enqueue(ctx, key, st, [&](hipStream_t s) {
     zero_words_k<<<1, 64, 0, s>>>(ws.counters, 16, nullptr, 0);
+    // the hash chains (tr, mu, SampleInBall) and ExpandA are independent: outside the
+    // staged form they run concurrently on a side stream
+    bool conc = ctx->mode != DIL_MODE_STAGED && !ks;
+    if (conc) {
+      int r2 = fork_side(ctx, s);
+      if (r2) return r2;
+    }
     vf_prep_k<LV><<<blocks_for(count, 64), 64, 0, s>>>(pk, key_idx, msg, msg_off, sig, ws, count, ctx->dev_stats + 8);
     if (!ks)
-      expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, s>>>(pk, P<LV>::PK, key_idx, ws.A, count);
+      expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, conc ? ctx->side[0] : s>>>(
+          pk, P<LV>::PK, key_idx, ws.A, count);
+    if (conc) {
+      int r2 = join_side(ctx, s);
+      if (r2) return r2;
+    }
     vf_main_k<LV><<<count, 64, 0, s>>>(pk, key_idx, sig, ws, count);
     vf_final_k<LV><<<blocks_for(count, 256), 256, 0, s>>>(sig, ws, verdict, count);
     LAUNCHCHK(ctx);
@@ -472,6 +555,11 @@ int dil_ctx_destroy(dil_ctx *ctx) {
   if (ctx->dev_stats) hipFree(ctx->dev_stats);
   drop_graphs(ctx);
   if (ctx->cap_stream) hipStreamDestroy(ctx->cap_stream);
+  for (int i = 0; i < 2; i++) {
+    if (ctx->side[i]) hipStreamDestroy(ctx->side[i]);
+    if (ctx->join_ev[i]) hipEventDestroy(ctx->join_ev[i]);
+  }
+  if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
   for (int r = 0; r < dil_ctx::RING; r++)
     for (int i = 0; i < 3; i++)
       if (ctx->ev[r][i]) hipEventDestroy(ctx->ev[r][i]);
@@ -507,6 +595,10 @@ int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value) {
     if (!ctx->use_graph) drop_graphs(ctx);
   } else if (!strcmp(name, "persist.grid")) ctx->persist_grid = value;
   else if (!strcmp(name, "persist.hmax")) ctx->persist_hmax = value;
+  else if (!strcmp(name, "persist.waves")) {
+    if (value != 1 && value != 4) return fail(ctx, DIL_EINVAL, "persist.waves must be 1 or 4");
+    ctx->persist_waves = (int)value;
+  }
   else return fail(ctx, DIL_EINVAL, "unknown parameter");
   return DIL_OK;
 }
@@ -635,36 +727,28 @@ int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_id
 int dil_ctx_reserve(dil_ctx *ctx, int level, uint32_t count) {
   if (!ctx || !valid_level(level)) return fail(ctx, DIL_EINVAL, "bad context or level");
   hipSetDevice(ctx->device);
-  if (!ctx->cu_count) {
-    hipDeviceProp_t prop;
-    HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
-    ctx->cu_count = prop.multiProcessorCount;
-  }
   return by_level(level, [&](auto lv) {
     constexpr int LV = decltype(lv)::value;
-    if (!ctx->occ[LV])
-      HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx->occ[LV], sg_persist_k<LV>, 64, 0));
-    size_t grid = std::max<size_t>((size_t)ctx->occ[LV] * ctx->cu_count, (size_t)std::max<int64_t>(ctx->persist_grid, 0));
+    int occ = 1;
+    int rc = persist_occupancy<LV>(ctx, &occ);
+    if (rc) return rc;
+    size_t grid = std::max<size_t>((size_t)occ * ctx->cu_count, (size_t)std::max<int64_t>(ctx->persist_grid, 0));
     Ws ws;
     PScr sc;
-    return ws_carve<LV>(ctx, count, ws, grid, &sc);
+    return ws_carve<LV>(ctx, count, ws, grid, &sc, ctx->persist_waves);
   });
 }
 
 int dil_persist_capacity(dil_ctx *ctx, int level, int *resident_groups, int *slots_per_batch) {
   if (!ctx || !valid_level(level)) return fail(ctx, DIL_EINVAL, "bad context or level");
   hipSetDevice(ctx->device);
-  if (!ctx->cu_count) {
-    hipDeviceProp_t prop;
-    HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
-    ctx->cu_count = prop.multiProcessorCount;
-  }
   return by_level(level, [&](auto lv) {
     constexpr int LV = decltype(lv)::value;
-    if (!ctx->occ[LV])
-      HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx->occ[LV], sg_persist_k<LV>, 64, 0));
-    if (resident_groups) *resident_groups = ctx->occ[LV] * ctx->cu_count;
-    if (slots_per_batch) *slots_per_batch = PCfg<LV>::G;
+    int occ = 1;
+    int rc = persist_occupancy<LV>(ctx, &occ);
+    if (rc) return rc;
+    if (resident_groups) *resident_groups = occ * ctx->cu_count;
+    if (slots_per_batch) *slots_per_batch = persist_slots<LV>(ctx->persist_waves);
     return DIL_OK;
   });
 }

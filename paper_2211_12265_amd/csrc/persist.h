@@ -29,6 +29,7 @@ struct PScr {
   int32_t *y;    // [P][G][L][256]
   int32_t *w;    // [P][G][K][256]
   uint8_t *w1;   // [P][G][K * W1B rounded to 256]
+  uint8_t *stage; // four-wave kernel only: [P][G][SIG rounded to 256]
 };
 
 template <int LV>
@@ -191,6 +192,174 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
       lds.nheld = o;
     }
     wave_sync();
+  }
+}
+
+}  // namespace dil
+
+namespace dil {
+
+// ---------------------------------------------------------------------------
+// Four-wavefront variant.  A 256-thread workgroup holds 4 * (64 / l) slots per
+// batch.  ExpandMask uses one thread per stream over all four waves; w and the
+// checks run per slot, wave w taking slots w, w + 4, ...; the challenge hashes
+// of all slots (at most 64) run on ONE wave, so that phase keeps its lanes busy
+// (the single-wave kernel hashes 64/l challenges on 64 lanes).  Which wave
+// hashes rotates with the workgroup and batch index so the SIMDs stay
+// balanced.  Passing candidates are staged per slot and the smallest passing
+// nonce of each task is copied to the output after a barrier.
+// ---------------------------------------------------------------------------
+template <int LV>
+struct PCfg4 {
+  static constexpr int W = 4;
+  static constexpr int GW = 64 / Lv<LV>::L;  // slots per wave
+  static constexpr int G = W * GW;           // 64 / 48 / 36
+};
+
+template <int LV>
+struct Persist4Lds {
+  union {
+    struct {
+      int32_t hat[Lv<LV>::L * N];
+      int32_t tr[4 * NTT_LDS_GROUP];
+      uint32_t w1buf[Lv<LV>::K * P<LV>::W1B / 4 + 1];
+    } wp;
+    CheckLds<LV> ck;
+  } u[4];
+  int8_t c[PCfg4<LV>::G][N];
+  uint32_t ct[PCfg4<LV>::G][8];
+  uint32_t bb[PCfg4<LV>::G][RATE256 / 4];
+  uint32_t h_task[PCfg4<LV>::G], h_next[PCfg4<LV>::G], h_win[PCfg4<LV>::G];
+  uint32_t s_att[PCfg4<LV>::G];
+  uint8_t s_h[PCfg4<LV>::G];
+  int nheld, nslots, queue_empty;
+};
+
+template <int LV>
+__host__ __device__ __forceinline__ size_t sig_stride() {
+  return ((size_t)P<LV>::SIG + 255) & ~(size_t)255;
+}
+
+template <int LV>
+__global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *sig, uint32_t count,
+                                                     uint32_t hmax, uint32_t *stats) {
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfg4<LV>::G, W = PCfg4<LV>::W;
+  __shared__ Persist4Lds<LV> lds;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, t = lane & 15;
+  const size_t wg = blockIdx.x;
+  int32_t *yb = sc.y + wg * G * L * N;
+  int32_t *wb = sc.w + wg * G * K * N;
+  uint8_t *w1b = sc.w1 + wg * G * w1_stride<LV>();
+  uint8_t *stg = sc.stage + wg * G * sig_stride<LV>();
+  const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
+  if (tid == 0) {
+    lds.nheld = 0;
+    lds.queue_empty = 0;
+  }
+  __syncthreads();
+  for (uint32_t batch = 0;; batch++) {
+    if (tid == 0) {
+      int nh = lds.nheld;
+      while (!lds.queue_empty && nh < (int)hmax) {
+        uint32_t tk = atomicAdd(&ws.counters[0], 1u);
+        if (tk >= count) {
+          lds.queue_empty = 1;
+          break;
+        }
+        lds.h_task[nh] = tk;
+        lds.h_next[nh] = 0;
+        nh++;
+      }
+      lds.nheld = nh;
+      int ns = nh ? G : 0;
+      for (int s = 0; s < ns; s++) {
+        int h = s % nh;
+        lds.s_h[s] = (uint8_t)h;
+        lds.s_att[s] = lds.h_next[h] + (uint32_t)(s / nh);
+      }
+      for (int h = 0; h < nh; h++) {
+        lds.h_next[h] += (uint32_t)(ns / nh + (h < ns % nh ? 1 : 0));
+        lds.h_win[h] = 0xFFFFFFFFu;
+      }
+      lds.nslots = ns;
+      if (ns) atomicAdd((unsigned long long *)&stats[2], (unsigned long long)ns);
+    }
+    __syncthreads();
+    const int ns = lds.nslots;
+    if (ns == 0) break;
+    // ExpandMask: one thread per (slot, i)
+    if (tid < ns * L) {
+      int s = tid / L, i = tid % L;
+      uint32_t task = lds.h_task[lds.s_h[s]];
+      dev_expand_mask<LV>(ws.rhop + (size_t)task * 64, lds.s_att[s] * (uint32_t)L, i, yb + ((size_t)s * L + i) * N);
+    }
+    __threadfence_block();
+    __syncthreads();
+    // w per slot, wave w takes slots w, w + 4, ...
+    for (int s = wave; s < ns; s += W) {
+      uint32_t task = lds.h_task[lds.s_h[s]];
+      dev_compute_w<LV>(yb + (size_t)s * L * N, ws.A + kix(ws, task) * K * L * N, wb + (size_t)s * K * N,
+                        w1b + s * w1_stride<LV>(), lds.u[wave].wp.hat,
+                        lds.u[wave].wp.tr + (lane >> 4) * NTT_LDS_GROUP, lds.u[wave].wp.w1buf, ftw, itw, lane);
+      wave_sync();
+    }
+    __threadfence_block();
+    __syncthreads();
+    // challenges of all slots on one (rotating) wave
+    if (wave == (int)((wg + batch) % W) && lane < ns) {
+      uint32_t task = lds.h_task[lds.s_h[lane]];
+      dev_challenge<LV>(ws.muw1 + (size_t)task * muw1_stride<LV>(), w1b + lane * w1_stride<LV>(), lds.ct[lane],
+                        lds.c[lane], (uint8_t *)lds.bb[lane]);
+    }
+    __syncthreads();
+    // checks; a slot is skipped once a smaller nonce of its task has passed
+    for (int s = wave; s < ns; s += W) {
+      int h = lds.s_h[s];
+      // another wave may lower h_win meanwhile: read it once, wave-uniformly
+      if (__builtin_amdgcn_readfirstlane(lds.h_win[h]) < lds.s_att[s]) continue;
+      uint32_t task = lds.h_task[h];
+      bool ok = dev_check<LV>(lds.c[s], lds.ct[s], yb + (size_t)s * L * N, wb + (size_t)s * K * N,
+                              ws.s1h + kix(ws, task) * L * N, ws.s2h + kix(ws, task) * K * N,
+                              ws.t0h + kix(ws, task) * K * N, lds.u[wave].ck, ftw, itw, lane);
+      if (ok) {
+        const uint32_t *sb = lds.u[wave].ck.sigbuf;
+        uint32_t *dst = (uint32_t *)(stg + s * sig_stride<LV>());
+        for (int w = lane; w < (P<LV>::SIG + 3) / 4; w += 64) dst[w] = sb[w];
+        if (lane == 0) atomicMin(&lds.h_win[h], lds.s_att[s]);
+      }
+      wave_sync();
+    }
+    __threadfence_block();
+    __syncthreads();
+    // copy each signed task's smallest passing candidate out; wave w handles held tasks w, w + 4, ...
+    for (int h = wave; h < lds.nheld; h += W) {
+      uint32_t win = lds.h_win[h];
+      if (win == 0xFFFFFFFFu) continue;
+      int s = -1;
+      for (int q = 0; q < ns; q++)
+        if (lds.s_h[q] == h && lds.s_att[q] == win) s = q;
+      l2g_bytes((const uint32_t *)(stg + s * sig_stride<LV>()), P<LV>::SIG,
+                sig + (size_t)lds.h_task[h] * P<LV>::SIG, lane, 64);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int nh = lds.nheld, o = 0;
+      for (int h = 0; h < nh; h++) {
+        if (lds.h_win[h] != 0xFFFFFFFFu) {
+          atomicAdd((unsigned long long *)&stats[6], (unsigned long long)(lds.h_win[h] + 1));
+          continue;
+        }
+        if (lds.h_next[h] >= (uint32_t)PCfg<LV>::MAX_ATTEMPTS) {
+          atomicAdd(&stats[5], 1u);
+          continue;
+        }
+        lds.h_task[o] = lds.h_task[h];
+        lds.h_next[o] = lds.h_next[h];
+        o++;
+      }
+      lds.nheld = o;
+    }
+    __syncthreads();
   }
 }
 

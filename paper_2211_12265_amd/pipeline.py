@@ -1,0 +1,143 @@
+"""End-to-end host path: Sign / Verify of host-resident batches.
+
+The paper's throughput figures include the host<->device copies and hide them
+behind computation with several CUDA streams, one chunk of tasks per stream
+(Sec. 4.4, multi-stream execution).  This module is the same pipeline on HIP:
+the caller's pinned host buffers are cut into contiguous chunks of tasks;
+chunk c goes to stream c mod S, where its rows are copied to device buffers
+owned by that stream, signed or verified by the C-ABI on that stream (each
+stream has its own libdil context, so workspaces never alias), and its
+results copied back.  Copies and kernels of different streams overlap;
+operations of one stream stay in order, so a stream's device buffers are
+reused by its next chunk without further synchronisation.
+
+Every step of Sign / Verify runs in libdil's kernels; this module only moves
+bytes (torch copies on pinned memory) and rebases each chunk's message
+offsets, which is host marshalling done once per batch before the copies
+start.
+"""
+from __future__ import annotations
+
+from typing import List, Optional
+
+import numpy as np
+
+from . import dilithium as dl
+
+
+def pinned(shape, dtype=None):
+    """A new page-locked host tensor (hipHostMalloc through torch)."""
+    import torch
+    return torch.empty(shape, dtype=dtype or torch.uint8, pin_memory=True)
+
+
+class _Chunk:
+    __slots__ = ("a", "b", "o0", "o1", "off")
+
+    def __init__(self, a, b, o0, o1, off):
+        self.a, self.b, self.o0, self.o1, self.off = a, b, o0, o1, off
+
+
+class HostPipeline:
+    """Chunked, multi-stream Sign / Verify of host-resident batches at one level.
+
+    n_streams: HIP streams (and libdil contexts) used; chunk: tasks per chunk.
+    mode: Sign execution form of every context (dl.MODE_*).
+    """
+
+    def __init__(self, level: int, n_streams: int = 4, chunk: int = 1250, mode: int = dl.MODE_PERSISTENT,
+                 device: int = 0):
+        import torch
+        if n_streams < 1 or chunk < 1:
+            raise ValueError("n_streams and chunk must be positive")
+        self.level, self.S, self.chunk = level, n_streams, chunk
+        self.pkl, self.skl, self.sgl = dl.sizes(level)
+        self.dev = torch.device("cuda", device)
+        self.ctx = [dl.Context(device, mode=mode) for _ in range(n_streams)]
+        for c in self.ctx:
+            c.reserve(level, chunk)
+        self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_streams)]
+        # flat, so that [m, PK] and [m, SK] views of it are both contiguous
+        self.d_key = [torch.empty(chunk * max(self.pkl, self.skl), dtype=torch.uint8, device=self.dev)
+                      for _ in range(n_streams)]
+        self.d_sig = [torch.empty((chunk, self.sgl), dtype=torch.uint8, device=self.dev) for _ in range(n_streams)]
+        self.d_ver = [torch.empty(chunk, dtype=torch.int32, device=self.dev) for _ in range(n_streams)]
+        self.d_off = [torch.empty(chunk + 1, dtype=torch.int64, device=self.dev) for _ in range(n_streams)]
+        self.d_msg: List = [None] * n_streams
+        self._plan: Optional[List[_Chunk]] = None
+        self._plan_key = None
+
+    def close(self):
+        for c in self.ctx:
+            c.close()
+        self.ctx = []
+
+    def plan(self, off: np.ndarray) -> List[_Chunk]:
+        """Cut the batch into chunks and rebase each chunk's CSR offsets (pinned, reused)."""
+        import torch
+        off = np.asarray(off, dtype=np.int64)
+        if np.any(np.diff(off) < 0) or off[0] != 0:
+            raise ValueError("msg_off must start at 0 and be non-decreasing")
+        key = (off.shape[0], int(off[-1]), hash(off.tobytes()))
+        if self._plan_key == key:
+            return self._plan
+        n = off.shape[0] - 1
+        plan = []
+        for a in range(0, n, self.chunk):
+            b = min(n, a + self.chunk)
+            o = pinned((b - a + 1,), torch.int64)
+            o.numpy()[:] = off[a:b + 1] - off[a]
+            plan.append(_Chunk(a, b, int(off[a]), int(off[b]), o))
+        longest = max((c.o1 - c.o0 for c in plan), default=0)
+        for s in range(self.S):
+            if self.d_msg[s] is None or self.d_msg[s].numel() < max(longest, 1):
+                self.d_msg[s] = torch.empty(max(longest, 1), dtype=torch.uint8, device=self.dev)
+        self._plan, self._plan_key = plan, key
+        return plan
+
+    def _run(self, op: str, keys, msg, off, sig, out):
+        import torch
+        plan = self.plan(off)
+        cur = torch.cuda.current_stream(self.dev)
+        for s in self.streams:
+            s.wait_stream(cur)
+        kl = self.skl if op == "sign" else self.pkl
+        for i, c in enumerate(plan):
+            s = i % self.S
+            st, ctx = self.streams[s], self.ctx[s]
+            m = c.b - c.a
+            with torch.cuda.stream(st):
+                dk = self.d_key[s][:m * kl].view(m, kl)
+                dk.copy_(keys[c.a:c.b], non_blocking=True)
+                dm = self.d_msg[s][:c.o1 - c.o0]
+                if c.o1 > c.o0:
+                    dm.copy_(msg[c.o0:c.o1], non_blocking=True)
+                do = self.d_off[s][:m + 1]
+                do.copy_(c.off, non_blocking=True)
+                if op == "sign":
+                    ds = self.d_sig[s][:m]
+                    ctx.sign(self.level, dk, dm, do, ds, stream=st)
+                    out[c.a:c.b].copy_(ds, non_blocking=True)
+                else:
+                    ds = self.d_sig[s][:m]
+                    ds.copy_(sig[c.a:c.b], non_blocking=True)
+                    dv = self.d_ver[s][:m]
+                    ctx.verify(self.level, dk, dm, do, ds, dv, stream=st)
+                    out[c.a:c.b].copy_(dv, non_blocking=True)
+        for s in self.streams:
+            cur.wait_stream(s)
+
+    def sign(self, sk, msg, off, sig_out):
+        """sk: pinned uint8 [n, SK]; msg: pinned uint8 bytes; off: int64 [n + 1]; sig_out: pinned uint8 [n, SIG].
+        Asynchronous with respect to the host; synchronise the current stream before reading sig_out."""
+        self._run("sign", sk, msg, off, None, sig_out)
+
+    def verify(self, pk, msg, off, sig, verdict_out):
+        """pk: pinned uint8 [n, PK]; sig: pinned uint8 [n, SIG]; verdict_out: pinned int32 [n]."""
+        self._run("verify", pk, msg, off, sig, verdict_out)
+
+    def check(self):
+        """Synchronise every stream and report a device-detected input error once."""
+        for st, ctx in zip(self.streams, self.ctx):
+            ctx.check(st)
+

@@ -4,16 +4,18 @@ from paper_2211_12265_amd import autotune
 
 def test_candidates_cover_speculation_range():
     for level, g in ((2, 16), (3, 12), (5, 9)):
-        assert autotune.slots_per_batch(level) == g
-        c = autotune.candidates(level, 10000, 2048)
-        hm = {h for h, _ in c}
-        assert 1 in hm and g in hm and max(hm) == g
-        for h, grid in c:
-            assert 1 <= grid <= 2048
-            assert grid <= -(-10000 // h)
+        for waves in (1, 4):
+            assert autotune.slots_per_batch(level, waves) == waves * g
+            c = autotune.candidates(level, 10000, 2048, waves)
+            hm = {h for h, _ in c}
+            assert 1 in hm and waves * g in hm and max(hm) == waves * g
+            for h, grid in c:
+                assert 1 <= grid <= 2048
+                assert grid <= -(-10000 // h)
 
 
 def test_candidates_small_batch():
-    c = autotune.candidates(2, 5, 2048)
-    assert all(grid <= 5 for _, grid in c)
-    assert len(set(c)) == len(c)
+    for waves in (1, 4):
+        c = autotune.candidates(2, 5, 2048, waves)
+        assert all(grid <= 5 for _, grid in c)
+        assert len(set(c)) == len(c)

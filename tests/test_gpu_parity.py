@@ -190,14 +190,17 @@ def test_empty_batch_and_bad_level(ctx):
 
 
 @pytest.mark.parametrize("level", [2, 5])
-@pytest.mark.parametrize("grid,hmax", [(1, 1), (3, 2), (7, 16), (0, 0)])
-def test_persistent_schedules_match_oracle(level, grid, hmax):
-    """Every grid size / tasks-per-workgroup setting gives the sequential signatures:
-    with hmax < slots the spare slots evaluate speculative later iterations."""
+@pytest.mark.parametrize("waves,grid,hmax", [(1, 1, 1), (1, 3, 2), (1, 7, 16), (1, 0, 0),
+                                             (4, 1, 1), (4, 3, 5), (4, 2, 64), (4, 0, 0)])
+def test_persistent_schedules_match_oracle(level, waves, grid, hmax):
+    """Every workgroup shape / grid size / tasks-per-workgroup setting gives the
+    sequential signatures: with hmax < slots the spare slots evaluate
+    speculative later iterations, and the smallest passing nonce wins."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2211_12265_amd import dilithium as dl
     c = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    c.set_param("persist.waves", waves)
     c.set_param("persist.grid", grid)
     c.set_param("persist.hmax", hmax)
     n = 37
@@ -337,8 +340,14 @@ def test_autotuner_picks_a_measured_candidate(ctx):
     sig = torch.zeros((n, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
     resident, slots = c.persist_capacity(level)
     assert resident > 0 and slots == 16
-    res = autotune.tune_sign(c, level, lambda: c.sign(level, sk, dmsg, doff, sig), resident, reps=1, count=n)
+    c.set_param("persist.waves", 4)
+    resident4, slots4 = c.persist_capacity(level)
+    assert resident4 > 0 and slots4 == 64
+    with pytest.raises(dl.DilError):
+        c.set_param("persist.waves", 2)
+    res = autotune.tune_sign(c, level, lambda: c.sign(level, sk, dmsg, doff, sig), reps=1, count=n)
     assert res["best"] in res["table"]
+    assert {r["waves"] for r in res["table"]} == {1, 4}
     c.sign(level, sk, dmsg, doff, sig)
     torch.cuda.synchronize()
     osig, _ = oracle.sign_batch(level, sk.cpu().numpy(), msg, off)
