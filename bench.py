@@ -144,6 +144,64 @@ def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -
     return summ
 
 
+def ablation_run(level: int, n: int, msg_dist: str, steps: int = 10) -> list:
+    """Runtime-selectable execution forms timed on the same keys and messages: the staged form
+    (one launch per stage, host-driven loop), the persistent kernel in both workgroup shapes with
+    its autotuned schedule, and hipGraph replay on / off."""
+    import torch
+    from paper_2211_12265_amd import autotune
+    from paper_2211_12265_amd import dilithium as dl
+    from paper_2211_12265_amd import workload
+    pkl, skl, sgl = dl.sizes(level)
+    ctx0 = dl.Context(0)
+    pk = torch.zeros((n, pkl), dtype=torch.uint8, device="cuda")
+    sk = torch.zeros((n, skl), dtype=torch.uint8, device="cuda")
+    ctx0.keygen(level, torch.from_numpy(workload.keygen_seeds(n, seed=0)).cuda(), pk, sk)
+    lens = workload.fixed_lengths(n, 32) if msg_dist == "fixed32" else workload.uniform_lengths(n, 32, 4096)
+    msg, off = workload.messages(lens, seed=0)
+    gm, go = torch.from_numpy(msg).cuda(), torch.from_numpy(off.astype(np.int64)).cuda()
+    ref = None
+    rows = []
+    forms = [("staged", dl.MODE_STAGED, None, 0), ("persistent 1-wave", dl.MODE_PERSISTENT, 1, 1),
+             ("persistent 4-wave", dl.MODE_PERSISTENT, 4, 1), ("persistent 4-wave, no hipGraph",
+                                                                dl.MODE_PERSISTENT, 4, 0)]
+    for name, mode, waves, graph in forms:
+        ctx = dl.Context(0, mode=mode)
+        sig = torch.zeros((n, sgl), dtype=torch.uint8, device="cuda")
+        ver = torch.zeros(n, dtype=torch.int32, device="cuda")
+        sched = None
+        if waves:
+            t = autotune.tune_sign(ctx, level, lambda: ctx.sign(level, sk, gm, go, sig), count=n, waves=(waves,))
+            sched = {k: t["best"][k] for k in ("waves", "hmax", "grid")}
+        ctx.set_param("graph", graph)
+        for _ in range(2):
+            ctx.sign(level, sk, gm, go, sig)
+            ctx.verify(level, pk, gm, go, sig, ver)
+        torch.cuda.synchronize()
+        ts, tv = [], []
+        for _ in range(steps):
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            e[0].record()
+            ctx.sign(level, sk, gm, go, sig)
+            e[1].record()
+            ctx.verify(level, pk, gm, go, sig, ver)
+            e[2].record()
+            torch.cuda.synchronize()
+            ts.append(e[0].elapsed_time(e[1]))
+            tv.append(e[1].elapsed_time(e[2]))
+        out = sig.cpu().numpy()
+        same = True if ref is None else bool(np.array_equal(out, ref))
+        ref = out if ref is None else ref
+        ev, seq = ctx.sign_stats()
+        rows.append({"form": name, "schedule": sched, "sign_ms": float(np.median(ts)),
+                     "verify_ms": float(np.median(tv)), "sign_per_s": n / (float(np.median(ts)) * 1e-3),
+                     "verify_per_s": n / (float(np.median(tv)) * 1e-3), "evaluated": ev, "sequential": seq,
+                     "all_verified": bool(int(ver.sum()) == n), "same_signatures": same})
+        ctx.close()
+    ctx0.close()
+    return rows
+
+
 def e2e_run(level: int, n: int, msg_dist: str, stream_counts, chunks_per_stream: int = 2, reps: int = 5) -> dict:
     """PCIe-inclusive rates: keys, messages, signatures and verdicts live in pinned host memory and
     every call moves them through the multi-stream chunked pipeline.  Reported beside the bench
@@ -218,6 +276,8 @@ def main():
     ap.add_argument("--serving-seconds", type=float, default=5.0)
     ap.add_argument("--serving-streams", type=int, default=4)
     ap.add_argument("--serving-batch", type=int, default=4096)
+    ap.add_argument("--ablation", action="store_true",
+                    help="only time the execution forms (staged, persistent 1/4-wave, graph on/off) at --level")
     ap.add_argument("--e2e", action="store_true",
                     help="also report PCIe-inclusive rates through the multi-stream host pipeline")
     ap.add_argument("--e2e-streams", default="1,2,4,8,12")
@@ -239,6 +299,10 @@ def main():
               f"batch into one contiguous task range per GPU)", file=sys.stderr)
         sys.exit(2)
 
+    if args.ablation:
+        print(json.dumps({"ablation": ablation_run(args.level, args.count, args.msg_dist),
+                          "level": args.level, "batch": args.count, "msg_dist": args.msg_dist}), flush=True)
+        return
     if args.serving_only:
         print(json.dumps({"serving": serving_run(args.serving_requests, args.serving_seconds, args.serving_streams,
                                                  args.serving_batch)}), flush=True)

@@ -237,11 +237,17 @@ int fork_side(dil_ctx *ctx, hipStream_t st) {
   for (int i = 0; i < 2; i++) HIPCHK(ctx, hipStreamWaitEvent(ctx->side[i], ctx->fork_ev, 0));
   return DIL_OK;
 }
-// Join: st waits for the side streams' work.
+// Join: st waits for the work enqueued so far on side stream i.
+int join_one(dil_ctx *ctx, hipStream_t st, int i) {
+  HIPCHK(ctx, hipEventRecord(ctx->join_ev[i], ctx->side[i]));
+  HIPCHK(ctx, hipStreamWaitEvent(st, ctx->join_ev[i], 0));
+  return DIL_OK;
+}
+// Join: st waits for both side streams' work.
 int join_side(dil_ctx *ctx, hipStream_t st) {
   for (int i = 0; i < 2; i++) {
-    HIPCHK(ctx, hipEventRecord(ctx->join_ev[i], ctx->side[i]));
-    HIPCHK(ctx, hipStreamWaitEvent(st, ctx->join_ev[i], 0));
+    int rc = join_one(ctx, st, i);
+    if (rc) return rc;
   }
   return DIL_OK;
 }
@@ -417,22 +423,33 @@ int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const 
                       (uint64_t)sig, (uint64_t)verdict, count, (uint64_t)ks, (uint64_t)ctx->ws_mem, 0, 0, 0, 0, 0};
   return enqueue(ctx, key, st, [&](hipStream_t s) {
     zero_words_k<<<1, 64, 0, s>>>(ws.counters, 16, nullptr, 0);
-    // the hash chains (tr, mu, SampleInBall) and ExpandA are independent: outside the
-    // staged form they run concurrently on a side stream
-    bool conc = ctx->mode != DIL_MODE_STAGED && !ks;
+    // Three independent fronts: the tr / mu hash chain (needed only by the
+    // final hash), ExpandA, and SampleInBall + hint decoding.  Outside the
+    // staged form the first two run on side streams and are joined where
+    // their results are first read.  With a resident key table there is no
+    // ExpandA and tr is stored, so the calls (typically many small ones from
+    // a serving loop) stay on one stream.
+    const bool conc = ctx->mode != DIL_MODE_STAGED && !ks;
     if (conc) {
       int r2 = fork_side(ctx, s);
       if (r2) return r2;
     }
-    vf_prep_k<LV><<<blocks_for(count, 64), 64, 0, s>>>(pk, key_idx, msg, msg_off, sig, ws, count, ctx->dev_stats + 8);
+    hipStream_t s_hash = conc ? ctx->side[1] : s, s_ea = conc ? ctx->side[0] : s;
+    vf_hash_k<LV><<<blocks_for(count, 64), 64, 0, s_hash>>>(pk, key_idx, msg, msg_off, ws, count,
+                                                            ctx->dev_stats + 8);
     if (!ks)
-      expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, conc ? ctx->side[0] : s>>>(
-          pk, P<LV>::PK, key_idx, ws.A, count);
+      expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, s_ea>>>(pk, P<LV>::PK, key_idx, ws.A,
+                                                                                count);
+    vf_prep_k<LV><<<blocks_for(count, 64), 64, 0, s>>>(sig, ws, count);
     if (conc) {
-      int r2 = join_side(ctx, s);
+      int r2 = join_one(ctx, s, 0);
       if (r2) return r2;
     }
     vf_main_k<LV><<<count, 64, 0, s>>>(pk, key_idx, sig, ws, count);
+    if (conc) {
+      int r2 = join_one(ctx, s, 1);
+      if (r2) return r2;
+    }
     vf_final_k<LV><<<blocks_for(count, 256), 256, 0, s>>>(sig, ws, verdict, count);
     LAUNCHCHK(ctx);
     return DIL_OK;

@@ -86,20 +86,69 @@ __global__ void __launch_bounds__(256) kg_seed_k(const uint8_t *seeds, uint8_t *
 }
 
 // ExpandA: one lane per (task, i, j); rho read from rows of `rho_src` (pk or sk)
+// ExpandA (Sec. 2.3 sampling; Alg. 4's rejection sampler) with wave-cooperative
+// compaction: 3 bytes -> 23-bit candidate, kept if < q, in stream order, until
+// 256 are kept.  Every lane squeezes its own
+// SHAKE128 stream; each squeezed block is staged in LDS and the wave then
+// walks the lanes whose polynomial is unfinished, testing that lane's 56
+// candidates on 56 lanes at once: a ballot gives each accepted candidate its
+// position in stream order, so the accepted values of one stream are stored
+// as one contiguous run.  out0 is lane 0's polynomial; lane l writes
+// out0 + l * N.  rows: 64 * EA_ROW words of LDS for this wavefront.  Lanes
+// with valid = false run the permutations but store nothing.
+constexpr int EA_ROW = RATE128 / 4 + 1;  // 43 words: odd stride, conflict-free staging
+
+__device__ __forceinline__ void expand_a_squeeze_wave(uint32_t s[50], int32_t *out0, uint32_t *rows, int lane,
+                                                      bool valid) {
+  int ctr = valid ? 0 : N;
+  uint32_t *row = rows + lane * EA_ROW;
+  for (;;) {
+#pragma unroll
+    for (int w = 0; w < RATE128 / 4; w++) row[w] = s[w];
+    wave_sync();
+    uint64_t pending = __ballot(ctr < N);
+    while (pending) {
+      const int L = __builtin_ctzll(pending);
+      pending &= pending - 1;
+      const int cL = __builtin_amdgcn_readlane(ctr, L);
+      const uint32_t *rL = rows + L * EA_ROW;
+      const int b = 3 * lane;
+      uint32_t tv = 0;
+      bool ok = false;
+      if (lane < RATE128 / 3) {  // word (b >> 2) + 1 is at most 42, the row's pad word
+        tv = __builtin_amdgcn_alignbit(rL[(b >> 2) + 1], rL[b >> 2], 8 * (b & 3)) & 0x7FFFFFu;
+        ok = tv < (uint32_t)Q;
+      }
+      const uint64_t m = __ballot(ok);
+      const int pos =
+          cL + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+      if (ok && pos < N) out0[(size_t)L * N + pos] = (int32_t)tv;
+      const int nL = min(N, cL + (int)__popcll(m));
+      if (lane == L) ctr = nL;
+    }
+    wave_sync();
+    if (__ballot(ctr < N) == 0) break;
+    keccak_f(s);
+  }
+}
+
 template <int LV>
 __global__ void __launch_bounds__(256) expand_a_k(const uint8_t *rho_src, size_t rho_stride, const uint32_t *key_idx,
                                                   int32_t *A, uint32_t count) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
   uint64_t st = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (st >= (uint64_t)count * K * L) return;
-  uint32_t task = (uint32_t)(st / (K * L));
-  int ij = (int)(st % (K * L));
+  __shared__ uint32_t rows[4][64 * EA_ROW];
+  const bool valid = st < (uint64_t)count * K * L;
+  const uint64_t sl = valid ? st : 0;  // spare lanes absorb stream 0 and store nothing
+  uint32_t task = (uint32_t)(sl / (K * L));
+  int ij = (int)(sl % (K * L));
   int i = ij / L, j = ij % L;
   size_t key = key_idx ? key_idx[task] : task;
   const uint64_t *rho = (const uint64_t *)(rho_src + key * rho_stride);
   uint32_t s[50];
   absorb_seed34(s, [&](int pos) { return rho[pos >> 3]; }, (uint32_t)j | ((uint32_t)i << 8));
-  expand_a_squeeze(s, A + (size_t)st * N);
+  const int lane = threadIdx.x & 63;
+  expand_a_squeeze_wave(s, A + (size_t)(st - lane) * N, rows[threadIdx.x >> 6], lane, valid);
 }
 
 // ExpandS: one lane per (task, r < L + K); centred coefficients to ws.s1h
@@ -119,7 +168,7 @@ __global__ void __launch_bounds__(256) expand_s_k(Ws ws, uint32_t count) {
 template <int LV>
 struct PolyLds {
   int32_t tr[4 * NTT_LDS_GROUP];              // transposes, one region per group
-  int32_t hat[(Lv<LV>::L > Lv<LV>::K ? Lv<LV>::L : Lv<LV>::K) * N];  // NTT-domain vector (slots)
+  int32_t hat[(Lv<LV>::L > Lv<LV>::K ? Lv<LV>::L : Lv<LV>::K) * HAT_POLY];  // NTT-domain vector (hat_idx)
   uint32_t buf[(P<LV>::SK + 64) / 4 + 2];     // byte staging (packed rows), + pad words
 };
 
@@ -159,7 +208,7 @@ __global__ void __launch_bounds__(64) kg_main_k(Ws ws, uint8_t *pk, uint8_t *sk,
     pack16_to_lds<PP::EBITS>(v, skb + PP::OFF_S1 + j * PP::EB, t);
     ntt16(x, ftw, tr, t);
 #pragma unroll
-    for (int r = 0; r < 16; r++) lds.hat[j * N + 16 * t + r] = x[r];
+    for (int r = 0; r < 16; r++) lds.hat[hat_idx(j, t, r)] = x[r];
   }
   wave_sync();
   for (int i = g; i < K; i += 4) {
@@ -171,7 +220,7 @@ __global__ void __launch_bounds__(64) kg_main_k(Ws ws, uint8_t *pk, uint8_t *sk,
       int32_t a[16];
       load_slots(a, Ai + j * N, t);
 #pragma unroll
-      for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * lds.hat[j * N + 16 * t + r];
+      for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * lds.hat[hat_idx(j, t, r)];
     }
     int32_t x[16];
 #pragma unroll
@@ -315,11 +364,12 @@ __device__ __forceinline__ void dev_expand_mask(const uint8_t *rhop, uint32_t ka
 
 // w = INTT(A-hat * NTT(y)) for one task by one wavefront: w (canonical) to
 // w_out, HighBits(w) packed into w1_out (4-byte aligned, K * W1B bytes).
-// hat: L*256 words of LDS; tr: this group's transpose region; w1buf: LDS staging.
-template <int LV>
+// hat: L * HAT_POLY words of LDS; tr: this group's transpose region; w1buf: LDS
+// staging; ftw / itw: forward / inverse twiddles.
+template <int LV, class TW>
 __device__ __forceinline__ void dev_compute_w(const int32_t *y, const int32_t *A, int32_t *w_out, uint8_t *w1_out,
-                                              int32_t *hat, int32_t *tr, uint32_t *w1buf, const Tw &ftw,
-                                              const Tw &itw, int lane) {
+                                              int32_t *hat, int32_t *tr, uint32_t *w1buf, const TW &ftw,
+                                              const TW &itw, int lane) {
   using PP = P<LV>;
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
   int g = lane >> 4, t = lane & 15;
@@ -328,7 +378,7 @@ __device__ __forceinline__ void dev_compute_w(const int32_t *y, const int32_t *A
     load_strided(x, y + j * N, t);
     ntt16(x, ftw, tr, t);
 #pragma unroll
-    for (int r = 0; r < 16; r++) hat[j * N + 16 * t + r] = x[r];
+    for (int r = 0; r < 16; r++) hat[hat_idx(j, t, r)] = x[r];
   }
   wave_sync();
   for (int i = g; i < K; i += 4) {
@@ -340,7 +390,7 @@ __device__ __forceinline__ void dev_compute_w(const int32_t *y, const int32_t *A
       int32_t a[16];
       load_slots(a, Ai + j * N, t);
 #pragma unroll
-      for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * hat[j * N + 16 * t + r];
+      for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * hat[hat_idx(j, t, r)];
     }
     int32_t x[16];
 #pragma unroll
@@ -430,10 +480,10 @@ struct CheckLds {
 // candidate passes all four checks; the packed signature (ctilde, z, h) is
 // then in lds.sigbuf.  Polynomials whose norm already fails stop the
 // evaluation early.
-template <int LV>
+template <int LV, class TW>
 __device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctilde, const int32_t *y, const int32_t *w,
                                           const int32_t *s1h, const int32_t *s2h, const int32_t *t0h,
-                                          CheckLds<LV> &lds, const Tw &ftw, const Tw &itw, int lane) {
+                                          CheckLds<LV> &lds, const TW &ftw, const TW &itw, int lane) {
   using PP = P<LV>;
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L, BETA = Lv<LV>::BETA, OMEGA = Lv<LV>::OMEGA;
   constexpr int32_t G1 = Lv<LV>::GAMMA1, G2 = Lv<LV>::GAMMA2;
@@ -599,15 +649,11 @@ __global__ void __launch_bounds__(64) sg_check_k(Ws ws, uint8_t *sig, const uint
 // ------------------------------------------------------------------------
 // Verify (Alg. 3), staged
 // ------------------------------------------------------------------------
-// tr = H(pk), mu = H(tr || M), c = SampleInBall(ctilde), strict hint decoding
+// tr = H(pk) (unless resident) and mu = H(tr || M), one lane per task
 template <int LV>
-__global__ void __launch_bounds__(64) vf_prep_k(const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
-                                                const uint64_t *msg_off, const uint8_t *sig, Ws ws, uint32_t count,
-                                                uint32_t *err) {
+__global__ void __launch_bounds__(64) vf_hash_k(const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
+                                                const uint64_t *msg_off, Ws ws, uint32_t count, uint32_t *err) {
   using PP = P<LV>;
-  constexpr int K = Lv<LV>::K, OMEGA = Lv<LV>::OMEGA;
-  __shared__ int8_t cl[64][N];
-  __shared__ uint32_t bb[64][RATE256 / 4];
   uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   size_t key = key_idx ? key_idx[t] : t;
@@ -632,8 +678,28 @@ __global__ void __launch_bounds__(64) vf_prep_k(const uint8_t *pk, const uint32_
   uint32_t *muw = (uint32_t *)(ws.muw1 + (size_t)t * muw1_stride<LV>());
 #pragma unroll
   for (int i = 0; i < 16; i++) muw[i] = s[i];
-  // SampleInBall(ctilde)
+}
+
+// c = SampleInBall(ctilde) and strict hint decoding, one lane per task
+template <int LV>
+__global__ void __launch_bounds__(64) vf_prep_k(const uint8_t *sig, Ws ws, uint32_t count) {
+  using PP = P<LV>;
+  constexpr int K = Lv<LV>::K, OMEGA = Lv<LV>::OMEGA;
+  constexpr int HB = OMEGA + K;        // hint section bytes
+  constexpr int HMW = K * 8 + 1;       // mask words per lane (+1: odd stride)
+  __shared__ int8_t cl[64][N];
+  __shared__ uint32_t bb[64][RATE256 / 4];
+  __shared__ uint8_t hbl[64][HB];
+  __shared__ uint32_t hml[64][HMW];
+  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
   const uint8_t *sg = sig + (size_t)t * PP::SIG;
+  // the hint bytes are fetched now (independent loads, one wait) and decoded from LDS at the end
+  uint8_t *hb = hbl[threadIdx.x];
+#pragma unroll
+  for (int j = 0; j < HB; j++) hb[j] = sg[PP::OFF_H + j];
+  uint32_t s[50];
+  // SampleInBall(ctilde)
   keccak_zero(s);
 #pragma unroll
   for (int w = 0; w < 4; w++) {
@@ -650,10 +716,10 @@ __global__ void __launch_bounds__(64) vf_prep_k(const uint8_t *pk, const uint32_
   const int4 *src = (const int4 *)c;
 #pragma unroll
   for (int w = 0; w < N / 16; w++) dst[w] = src[w];
-  // strict hint decoding into bit masks
-  const uint8_t *hb = sg + PP::OFF_H;
-  uint32_t *hm = ws.hmask + (size_t)t * K * 8;
-  for (int w = 0; w < K * 8; w++) hm[w] = 0;
+  // strict hint decoding into bit masks (built in LDS, then stored row-wise)
+  uint32_t *hml_t = hml[threadIdx.x];
+#pragma unroll
+  for (int w = 0; w < K * 8; w++) hml_t[w] = 0;
   int ok = 1, prev = 0;
   for (int i = 0; i < K; i++) {
     int cnt = hb[OMEGA + i];
@@ -663,13 +729,16 @@ __global__ void __launch_bounds__(64) vf_prep_k(const uint8_t *pk, const uint32_
     }
     for (int j = prev; j < cnt; j++) {
       if (j > prev && hb[j] <= hb[j - 1]) ok = 0;
-      hm[i * 8 + (hb[j] >> 5)] |= 1u << (hb[j] & 31);
+      hml_t[i * 8 + (hb[j] >> 5)] |= 1u << (hb[j] & 31);
     }
     prev = cnt;
   }
   if (ok)
     for (int j = prev; j < OMEGA; j++)
       if (hb[j] != 0) ok = 0;
+  uint32_t *hm = ws.hmask + (size_t)t * K * 8;
+#pragma unroll
+  for (int w = 0; w < K * 8; w++) hm[w] = hml_t[w];
   ws.flag[t] = ok;
 }
 
@@ -681,7 +750,7 @@ __global__ void __launch_bounds__(64) vf_main_k(const uint8_t *pk, const uint32_
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L, BETA = Lv<LV>::BETA;
   constexpr int32_t G1 = Lv<LV>::GAMMA1;
   __shared__ int32_t trl[4 * NTT_LDS_GROUP];
-  __shared__ int32_t zh[L * N];
+  __shared__ int32_t zh[L * HAT_POLY];
   __shared__ uint32_t sigw[PP::SIG / 4 + 3];
   __shared__ uint32_t pkw[PP::PK / 4 + 2];
   __shared__ uint32_t w1b[K * PP::W1B / 4 + 1];
@@ -719,7 +788,7 @@ __global__ void __launch_bounds__(64) vf_main_k(const uint8_t *pk, const uint32_
     }
     ntt16(x, ftw, tr, t);
 #pragma unroll
-    for (int r = 0; r < 16; r++) zh[j * N + 16 * t + r] = x[r];
+    for (int r = 0; r < 16; r++) zh[hat_idx(j, t, r)] = x[r];
   }
   bad = wave_any(bad);
   wave_sync();
@@ -733,7 +802,7 @@ __global__ void __launch_bounds__(64) vf_main_k(const uint8_t *pk, const uint32_
       int32_t a[16];
       load_slots(a, Ai + j * N, t);
 #pragma unroll
-      for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * zh[j * N + 16 * t + r];
+      for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * zh[hat_idx(j, t, r)];
     }
     int32_t x[16];
     if (ws.t1h) {
@@ -860,12 +929,14 @@ __global__ void __launch_bounds__(256) ntt_mul_k(const int32_t *a, const int32_t
 // ExpandA rejection sampling of one polynomial per lane from a 34-byte input
 __global__ void __launch_bounds__(256) expand_a_seed_k(const uint8_t *seeds, int32_t *out, uint64_t count) {
   uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= count) return;
-  const uint8_t *sd = seeds + 34 * p;
+  __shared__ uint32_t rows[4][64 * EA_ROW];
+  const bool valid = p < count;
+  const uint8_t *sd = seeds + 34 * (valid ? p : 0);
   uint32_t s[50];
   uint32_t nonce = (uint32_t)sd[32] | ((uint32_t)sd[33] << 8);
   absorb_seed34(s, [&](int pos) { return load_le_bytes(sd + pos, 8); }, nonce);
-  expand_a_squeeze(s, out + p * N);
+  const int lane = threadIdx.x & 63;
+  expand_a_squeeze_wave(s, out + (p - lane) * N, rows[threadIdx.x >> 6], lane, valid);
 }
 
 }  // namespace dil

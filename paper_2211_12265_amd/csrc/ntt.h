@@ -44,10 +44,20 @@ constexpr int NTT_LDS_GROUP = 272;  // int32 words per 16-lane group
 
 __device__ __forceinline__ int lds_idx(int i) { return i + (i >> 4); }
 
-// per-lane twiddles for the four lane-dependent levels (15 values)
+// An NTT-domain vector kept in LDS for pointwise products: polynomial j, lane
+// t, register r (slot 16 t + r) lives at j * HAT_POLY + 17 t + r.  With one pad
+// word per 16 slots, the 64 lanes of a wave hit 64 distinct banks both when
+// each 16-lane group writes its own polynomial and when all groups read the
+// same polynomial (then equal addresses broadcast).
+constexpr int HAT_POLY = 272;
+__device__ __forceinline__ int hat_idx(int j, int t, int r) { return j * HAT_POLY + 17 * t + r; }
+
+// per-lane twiddles for the four lane-dependent levels (15 values), held in VGPRs
 struct Tw {
   int32_t w[15];
+  __device__ __forceinline__ int32_t operator()(int k) const { return w[k]; }
 };
+
 __device__ __forceinline__ Tw ntt_lane_tw(int t) {
   Tw tw;
   tw.w[0] = kZT.z[16 + t];
@@ -109,7 +119,8 @@ __device__ __forceinline__ void transpose_c2s(int32_t x[16], int32_t *lds, int t
 }
 
 // Forward NTT: strided input -> slots output.
-__device__ __forceinline__ void ntt16(int32_t x[16], const Tw &tw, int32_t *lds, int t) {
+template <class TW>
+__device__ __forceinline__ void ntt16(int32_t x[16], const TW &tw, int32_t *lds, int t) {
   // levels with distance 128, 64, 32, 16: register distance 8, 4, 2, 1, compile-time twiddles
 #pragma unroll
   for (int r = 0; r < 8; r++) ct_bfly(x[r], x[r + 8], zeta_m(1));
@@ -124,30 +135,31 @@ __device__ __forceinline__ void ntt16(int32_t x[16], const Tw &tw, int32_t *lds,
   transpose_s2c(x, lds, t);
   // distance 8, 4, 2, 1 inside the lane's 16 consecutive slots, lane-dependent twiddles
 #pragma unroll
-  for (int r = 0; r < 8; r++) ct_bfly(x[r], x[r + 8], tw.w[0]);
+  for (int r = 0; r < 8; r++) ct_bfly(x[r], x[r + 8], tw(0));
 #pragma unroll
   for (int r = 0; r < 16; r++)
-    if ((r & 4) == 0) ct_bfly(x[r], x[r + 4], tw.w[1 + r / 8]);
+    if ((r & 4) == 0) ct_bfly(x[r], x[r + 4], tw(1 + r / 8));
 #pragma unroll
   for (int r = 0; r < 16; r++)
-    if ((r & 2) == 0) ct_bfly(x[r], x[r + 2], tw.w[3 + r / 4]);
+    if ((r & 2) == 0) ct_bfly(x[r], x[r + 2], tw(3 + r / 4));
 #pragma unroll
-  for (int r = 0; r < 16; r += 2) ct_bfly(x[r], x[r + 1], tw.w[7 + r / 2]);
+  for (int r = 0; r < 16; r += 2) ct_bfly(x[r], x[r + 1], tw(7 + r / 2));
 }
 
 // Inverse NTT: slots input (|x| < q) -> strided output in (-q, q); removes the
 // 2^-32 of one Montgomery product and divides by 256.
-__device__ __forceinline__ void intt16(int32_t x[16], const Tw &tw, int32_t *lds, int t) {
+template <class TW>
+__device__ __forceinline__ void intt16(int32_t x[16], const TW &tw, int32_t *lds, int t) {
 #pragma unroll
-  for (int r = 0; r < 16; r += 2) gs_bfly(x[r], x[r + 1], tw.w[r / 2]);
-#pragma unroll
-  for (int r = 0; r < 16; r++)
-    if ((r & 2) == 0) gs_bfly(x[r], x[r + 2], tw.w[8 + r / 4]);
+  for (int r = 0; r < 16; r += 2) gs_bfly(x[r], x[r + 1], tw(r / 2));
 #pragma unroll
   for (int r = 0; r < 16; r++)
-    if ((r & 4) == 0) gs_bfly(x[r], x[r + 4], tw.w[12 + r / 8]);
+    if ((r & 2) == 0) gs_bfly(x[r], x[r + 2], tw(8 + r / 4));
 #pragma unroll
-  for (int r = 0; r < 8; r++) gs_bfly(x[r], x[r + 8], tw.w[14]);
+  for (int r = 0; r < 16; r++)
+    if ((r & 4) == 0) gs_bfly(x[r], x[r + 4], tw(12 + r / 8));
+#pragma unroll
+  for (int r = 0; r < 8; r++) gs_bfly(x[r], x[r + 8], tw(14));
   transpose_c2s(x, lds, t);
 #pragma unroll
   for (int r = 0; r < 16; r += 2) gs_bfly(x[r], x[r + 1], zinv_m(8 + r / 2));

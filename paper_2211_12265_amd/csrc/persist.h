@@ -37,17 +37,26 @@ __device__ __forceinline__ size_t w1_stride() {
   return ((size_t)Lv<LV>::K * P<LV>::W1B + 255) & ~(size_t)255;
 }
 
-// Optional per-phase cycle accounting (compile with -DDIL_PHASE_TIMERS): lane 0 of
-// every workgroup adds the s_memtime cycles of each batch phase to stats[8 + p].
+// Optional per-phase cycle accounting (compile with -DDIL_PHASE_TIMERS): lane 0
+// of every workgroup accumulates the s_memtime cycles of each batch phase p and
+// adds them at exit to the 64-bit counter at stats words 16 + 2p.
 #ifdef DIL_PHASE_TIMERS
-#define PHASE_MARK(p)                                                              \
-  do {                                                                             \
-    uint64_t now_ = __builtin_amdgcn_s_memtime();                                  \
-    if (lane == 0) atomicAdd((unsigned long long *)&stats[16 + 2 * (p)], now_ - ph_t); \
-    ph_t = now_;                                                                   \
+#define PHASE_MARK(p)                               \
+  do {                                              \
+    uint64_t now_ = __builtin_amdgcn_s_memtime();   \
+    ph_acc[p] += now_ - ph_t;                       \
+    ph_t = now_;                                    \
+  } while (0)
+#define PHASE_FLUSH()                                                                          \
+  do {                                                                                         \
+    if (lane == 0)                                                                             \
+      for (int p_ = 0; p_ < 5; p_++) atomicAdd((unsigned long long *)&stats[16 + 2 * p_], ph_acc[p_]); \
   } while (0)
 #else
 #define PHASE_MARK(p) \
+  do {                \
+  } while (0)
+#define PHASE_FLUSH() \
   do {                \
   } while (0)
 #endif
@@ -58,11 +67,39 @@ __device__ __forceinline__ void wave_sync_global() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Claim up to `want` tasks from the work queue with one atomic; they are
+// appended to h_task / h_next from index nh.  Sets queue_empty once the queue
+// has run dry.  Returns the new number of held tasks.  (The counter may pass
+// `count`; it is cleared before every launch.)
+__device__ __forceinline__ int claim_tasks(uint32_t *queue, uint32_t count, uint32_t want, int nh, uint32_t *h_task,
+                                           uint32_t *h_next, int &queue_empty) {
+  uint32_t base = atomicAdd(queue, want);
+  uint32_t got = base >= count ? 0u : min(want, count - base);
+  if (got < want) queue_empty = 1;
+  for (uint32_t q = 0; q < got; q++) {
+    h_task[nh] = base + q;
+    h_next[nh] = 0;
+    nh++;
+  }
+  return nh;
+}
+
+// per-workgroup statistics, flushed to the launch's stats words at exit
+struct Tally {
+  uint64_t evaluated = 0, sequential = 0;
+  uint32_t dropped = 0;
+  __device__ void flush(uint32_t *stats) const {
+    if (evaluated) atomicAdd((unsigned long long *)&stats[2], (unsigned long long)evaluated);
+    if (sequential) atomicAdd((unsigned long long *)&stats[6], (unsigned long long)sequential);
+    if (dropped) atomicAdd(&stats[5], dropped);
+  }
+};
+
 template <int LV>
 struct PersistLds {
   union {
     struct {
-      int32_t hat[Lv<LV>::L * N];
+      int32_t hat[Lv<LV>::L * HAT_POLY];
       int32_t tr[4 * NTT_LDS_GROUP];
       uint32_t w1buf[Lv<LV>::K * P<LV>::W1B / 4 + 1];
     } wp;
@@ -92,6 +129,7 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
   int32_t *wb = sc.w + wg * G * K * N;
   uint8_t *w1b = sc.w1 + wg * G * w1_stride<LV>();
   const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
+  Tally tally;  // kept by lane 0, added to stats once at exit
   if (lane == 0) {
     lds.nheld = 0;
     lds.queue_empty = 0;
@@ -99,21 +137,14 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
   wave_sync();
 #ifdef DIL_PHASE_TIMERS
   uint64_t ph_t = __builtin_amdgcn_s_memtime();
+  uint64_t ph_acc[5] = {0, 0, 0, 0, 0};
 #endif
   for (;;) {
     // ---- claim tasks and assign the batch's slots ----
     if (lane == 0) {
       int nh = lds.nheld;
-      while (!lds.queue_empty && nh < (int)hmax) {
-        uint32_t tk = atomicAdd(&ws.counters[0], 1u);
-        if (tk >= count) {
-          lds.queue_empty = 1;
-          break;
-        }
-        lds.h_task[nh] = tk;
-        lds.h_next[nh] = 0;
-        nh++;
-      }
+      if (!lds.queue_empty && nh < (int)hmax) nh = claim_tasks(ws.counters, count, hmax - nh, nh, lds.h_task,
+                                                               lds.h_next, lds.queue_empty);
       lds.nheld = nh;
       int ns = nh ? G : 0;
       for (int s = 0; s < ns; s++) {
@@ -126,7 +157,7 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
         lds.h_win[h] = 0xFFFFFFFFu;
       }
       lds.nslots = ns;
-      if (ns) atomicAdd((unsigned long long *)&stats[2], (unsigned long long)ns);
+      tally.evaluated += (uint64_t)ns;
     }
     wave_sync();
     const int ns = lds.nslots;
@@ -178,11 +209,11 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
       int nh = lds.nheld, o = 0;
       for (int h = 0; h < nh; h++) {
         if (lds.h_win[h] != 0xFFFFFFFFu) {
-          atomicAdd((unsigned long long *)&stats[6], (unsigned long long)(lds.h_win[h] + 1));
+          tally.sequential += (uint64_t)lds.h_win[h] + 1;
           continue;
         }
         if (lds.h_next[h] >= (uint32_t)PCfg<LV>::MAX_ATTEMPTS) {
-          atomicAdd(&stats[5], 1u);
+          tally.dropped++;
           continue;
         }
         lds.h_task[o] = lds.h_task[h];
@@ -193,6 +224,8 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
     }
     wave_sync();
   }
+  if (lane == 0) tally.flush(stats);
+  PHASE_FLUSH();
 }
 
 }  // namespace dil
@@ -220,7 +253,7 @@ template <int LV>
 struct Persist4Lds {
   union {
     struct {
-      int32_t hat[Lv<LV>::L * N];
+      int32_t hat[Lv<LV>::L * HAT_POLY];
       int32_t tr[4 * NTT_LDS_GROUP];
       uint32_t w1buf[Lv<LV>::K * P<LV>::W1B / 4 + 1];
     } wp;
@@ -252,6 +285,7 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
   uint8_t *w1b = sc.w1 + wg * G * w1_stride<LV>();
   uint8_t *stg = sc.stage + wg * G * sig_stride<LV>();
   const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
+  Tally tally;  // kept by thread 0, added to stats once at exit
   if (tid == 0) {
     lds.nheld = 0;
     lds.queue_empty = 0;
@@ -260,16 +294,8 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
   for (uint32_t batch = 0;; batch++) {
     if (tid == 0) {
       int nh = lds.nheld;
-      while (!lds.queue_empty && nh < (int)hmax) {
-        uint32_t tk = atomicAdd(&ws.counters[0], 1u);
-        if (tk >= count) {
-          lds.queue_empty = 1;
-          break;
-        }
-        lds.h_task[nh] = tk;
-        lds.h_next[nh] = 0;
-        nh++;
-      }
+      if (!lds.queue_empty && nh < (int)hmax) nh = claim_tasks(ws.counters, count, hmax - nh, nh, lds.h_task,
+                                                               lds.h_next, lds.queue_empty);
       lds.nheld = nh;
       int ns = nh ? G : 0;
       for (int s = 0; s < ns; s++) {
@@ -282,7 +308,7 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
         lds.h_win[h] = 0xFFFFFFFFu;
       }
       lds.nslots = ns;
-      if (ns) atomicAdd((unsigned long long *)&stats[2], (unsigned long long)ns);
+      tally.evaluated += (uint64_t)ns;
     }
     __syncthreads();
     const int ns = lds.nslots;
@@ -346,11 +372,11 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
       int nh = lds.nheld, o = 0;
       for (int h = 0; h < nh; h++) {
         if (lds.h_win[h] != 0xFFFFFFFFu) {
-          atomicAdd((unsigned long long *)&stats[6], (unsigned long long)(lds.h_win[h] + 1));
+          tally.sequential += (uint64_t)lds.h_win[h] + 1;
           continue;
         }
         if (lds.h_next[h] >= (uint32_t)PCfg<LV>::MAX_ATTEMPTS) {
-          atomicAdd(&stats[5], 1u);
+          tally.dropped++;
           continue;
         }
         lds.h_task[o] = lds.h_task[h];
@@ -361,6 +387,7 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
     }
     __syncthreads();
   }
+  if (tid == 0) tally.flush(stats);
 }
 
 }  // namespace dil

@@ -83,27 +83,6 @@ __device__ __forceinline__ void absorb_seed66(uint32_t s[50], const uint8_t *rho
   keccak_f(s);
 }
 
-// ExpandA rejection sampling on the lane's SHAKE128 stream (state already
-// absorbed and permuted once).  3 bytes -> 23-bit candidate, kept if < q, in
-// stream order, until 256 are kept.  Writes out[0..256).
-__device__ __forceinline__ void expand_a_squeeze(uint32_t s[50], int32_t *out) {
-  int ctr = 0;
-  for (;;) {
-#pragma unroll
-    for (int m = 0; m < RATE128 / 3; m++) {
-      constexpr int dummy = 0;
-      (void)dummy;
-      int h = (3 * m) >> 2, sh = 8 * ((3 * m) & 3);
-      uint32_t tv = __builtin_amdgcn_alignbit(s[h + 1], s[h], sh) & 0x7FFFFFu;
-      bool ok = tv < (uint32_t)Q;
-      if (ok && ctr < N) out[ctr] = (int32_t)tv;
-      ctr += ok;
-    }
-    if (ctr >= N) break;
-    keccak_f(s);
-  }
-}
-
 // ExpandMask: y_i coefficients from the lane's SHAKE256 stream (absorbed and
 // permuted once).  B-bit little-endian values v, coefficient gamma1 - v.
 // Stores the 256 coefficients to out (natural order) four at a time.
