@@ -18,6 +18,10 @@ import os
 import sys
 import time
 
+# The serving engine runs every (level, op) group of a batch on its own HIP stream; HIP gives a
+# process 4 hardware queues by default, which serialises them.  Must be set before HIP starts.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+
 import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
@@ -40,6 +44,37 @@ SK_BYTES = {2: 2528, 3: 4000, 5: 4864}
 SIG_BYTES = {2: 2420, 3: 3293, 5: 4595}
 # 256 CUs x 4 SIMDs x 32 lanes of simple 32-bit integer ops per clock x 2.4 GHz
 PEAK_INT32_OPS = 256 * 4 * 32 * 2.4e9   # 78.6 T int32 lane-ops/s
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources (file names and contents), to tie stored counter results to the
+    kernels they were taken on."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2211_12265_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".h", ".hip")):
+            h.update(name.encode())
+            with open(os.path.join(d, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def stored_traffic(kernel: str, level: int, count: int, msg_dist: str, schedule: str):
+    """HBM bytes per launch (FETCH_SIZE and WRITE_SIZE, copy-calibrated) recorded in
+    profiles/hbm_traffic.json for this kernel and launch configuration, or None when there is no
+    record or the kernels have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        recs = json.load(f)
+    src = kernel_source_hash()
+    for r in recs:
+        if (r["kernel"], r["level"], r["count"], r["msg_dist"], r["schedule"]) == \
+                (kernel, level, count, msg_dist, schedule) and r["source_sha256"] == src:
+            return r
+    return None
 
 
 def perms_shake(inlen: int, outlen: int, rate: int) -> int:
@@ -124,12 +159,22 @@ def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -
     sv.attach_signatures(sat_reqs, ctx, keysets, seed=12)
     sat = server.serve(sat_reqs)
     sat_rate = len(sat_reqs) / sat.wall
+    sweep = []
+    for frac in (0.25, 0.75):     # latency at a lighter and a heavier load, beside the 0.5 point
+        lam_f = frac * sat_rate
+        cnt_f = int(min(max(n_requests // 2, lam_f * seconds / 2), 1_000_000))
+        r_f = sv.build_requests(cnt_f, lam=lam_f, keys_per_level=keys, seed=14)
+        sv.attach_signatures(r_f, ctx, keysets, seed=14)
+        s_f = sv.latency_summary(server.serve(r_f), r_f)
+        sweep.append({"load": frac, "lambda_per_s": lam_f, "ops_per_s": s_f["ops_per_s"], "p50_ms": s_f["p50_ms"],
+                      "p99_ms": s_f["p99_ms"]})
     lam = 0.5 * sat_rate
     count = int(min(max(n_requests, lam * seconds), 2_000_000))
     reqs = sv.build_requests(count, lam=lam, keys_per_level=keys, seed=13)
     flipped = sv.attach_signatures(reqs, ctx, keysets, seed=13)
     res = server.serve(reqs)
     summ = sv.latency_summary(res, reqs)
+    summ["load_sweep"] = sweep
     verify = reqs.op == sv.VERIFY
     summ.update({"engine": "native dil_server", "lambda_per_s": lam, "saturated_ops_per_s": sat_rate,
                  "streams": streams, "max_batch": max_batch,
@@ -263,6 +308,11 @@ def main():
                     help="32-byte messages, or lengths uniform on [32, 4096] (the level-3/5 configuration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the schedule autotuner")
+    ap.add_argument("--tune", action="store_true",
+                    help="re-run the autotuner even if a schedule is recorded for this workload")
+    ap.add_argument("--tune-reps", type=int, default=3)
+    ap.add_argument("--record-schedule", default="",
+                    help="after tuning, record the chosen schedule in this JSON file")
     ap.add_argument("--waves", type=int, default=0, choices=[0, 1, 4],
                     help="wavefronts per persistent workgroup (0: let the autotuner choose; 1 without it)")
     ap.add_argument("--schedule", default="",
@@ -341,15 +391,25 @@ def main():
             ev[2].record(stream)
 
     tuning = None
+    schedule_src = None
+    from paper_2211_12265_amd import autotune
+    cached = autotune.cached_schedule(level, n, args.msg_dist)
     if args.schedule:
         w, h, g = (int(x) for x in args.schedule.split(","))
-        for name, v in (("persist.waves", w), ("persist.hmax", h), ("persist.grid", g)):
-            ctx.set_param(name, v)
+        autotune.apply_schedule(ctx, {"waves": w, "hmax": h, "grid": g})
         args.waves = w
+        schedule_src = "command line"
+    elif args.mode == "persistent" and cached and not args.tune and not args.no_tune and not args.waves:
+        autotune.apply_schedule(ctx, cached)
+        args.waves = cached["waves"]
+        args.schedule = f"{cached['waves']},{cached['hmax']},{cached['grid']}"
+        schedule_src = "autotuner (recorded)"
     elif args.mode == "persistent" and not args.no_tune:
-        from paper_2211_12265_amd import autotune
         tuning = autotune.tune_sign(ctx, level, lambda: ctx.sign(level, sk, g_msg, g_off, sig), count=n,
-                                    waves=(args.waves,) if args.waves else (1, 4))
+                                    reps=args.tune_reps, waves=(args.waves,) if args.waves else (1, 4))
+        schedule_src = "autotuner (this run)"
+        if args.record_schedule:
+            autotune.store_schedule(level, n, args.msg_dist, tuning["best"], args.record_schedule)
     elif args.mode == "persistent" and args.waves:
         ctx.set_param("persist.waves", args.waves)
     if args.graph:
@@ -386,10 +446,18 @@ def main():
         loop_med = float(np.median(loop_ms))
         k_ops = sequential * sign_iteration_ops(level)
         achieved = k_ops / (loop_med * 1e-3)
-        four = tuning["best"]["waves"] == 4 if tuning else args.waves == 4
-        kname = ("sg_persist4_k" if four else "sg_persist_k") + " (persistent Sign rejection-loop kernel)"
         kextra = {"kernel_ms_median": loop_med, "setup_ms_median": float(np.median(setup_ms)),
                   "timed_launches": len(loop_ms), "ops_per_launch": k_ops}
+        four = tuning["best"]["waves"] == 4 if tuning else args.waves == 4
+        kbase = "sg_persist4_k" if four else "sg_persist_k"
+        kname = kbase + " (persistent Sign rejection-loop kernel)"
+        sched_str = args.schedule if not tuning else \
+            f"{tuning['best']['waves']},{tuning['best']['hmax']},{tuning['best']['grid']}"
+        rec = stored_traffic(f"{kbase}<{level}>", level, n, args.msg_dist, sched_str)
+        if rec:
+            kextra["traffic_detail"] = {"fetch_bytes": rec["fetch_bytes"], "write_bytes": rec["write_bytes"],
+                                        "profile": rec["profile"]}
+
     else:
         achieved = sign_work(level, lens, sequential) / (np.median(sign_ms) * 1e-3)
         kname = "dil_sign_batch (whole staged Sign call)"
@@ -406,7 +474,7 @@ def main():
                    "msg_len": 32 if args.msg_dist == "fixed32" else "uniform[32,4096]",
                    "sign_mode": args.mode, "hipgraph": bool(args.graph),
                    "schedule": ({k: tuning["best"][k] for k in ("waves", "hmax", "grid")} if tuning else
-                                args.schedule or None)},
+                                args.schedule or None), "schedule_source": schedule_src},
         "sign_per_s": sign_rate, "verify_per_s": ver_rate,
         "sign_ms_median": float(np.median(sign_ms)), "verify_ms_median": float(np.median(ver_ms)),
         "sign_iterations": {"sequential": int(sequential), "evaluated": int(evaluated),
@@ -414,7 +482,9 @@ def main():
         "parity_sampled": parity_ok,
         "autotune": None if tuning is None else tuning["table"],
         "roofline": dict({"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_INT32_OPS / 1e12,
-                          "unit": "T int32-ops/s", "frac": achieved / PEAK_INT32_OPS, "traffic": None,
+                          "unit": "T int32-ops/s", "frac": achieved / PEAK_INT32_OPS,
+                          "traffic": (kextra["traffic_detail"]["fetch_bytes"] + kextra["traffic_detail"]["write_bytes"])
+                          if "traffic_detail" in kextra else None,
                           "kernel": kname}, **kextra),
     }
     if not args.no_cpu_baseline:

@@ -18,9 +18,45 @@ same signatures) and the fastest median wins.
 """
 from __future__ import annotations
 
+import json
+import os
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
+
+# Schedules the tuner chose, keyed "L<level>/<count>/<message mix>": the
+# benchmark reuses them so that its timed launch configuration is fixed.
+CACHE_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuned_schedules.json")
+
+
+def cache_key(level: int, count: int, mix: str) -> str:
+    return f"L{level}/{count}/{mix}"
+
+
+def load_cache(path: str = CACHE_PATH) -> Dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def cached_schedule(level: int, count: int, mix: str, path: str = CACHE_PATH) -> Optional[Dict]:
+    """{"waves", "hmax", "grid"} recorded for this workload, or None."""
+    return load_cache(path).get(cache_key(level, count, mix))
+
+
+def store_schedule(level: int, count: int, mix: str, best: Dict, path: str = CACHE_PATH) -> None:
+    cache = load_cache(path)
+    cache[cache_key(level, count, mix)] = {k: int(best[k]) for k in ("waves", "hmax", "grid")}
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+        f.write("\n")
+
+
+def apply_schedule(ctx, sched: Dict) -> None:
+    ctx.set_param("persist.waves", sched["waves"])
+    ctx.set_param("persist.hmax", sched["hmax"])
+    ctx.set_param("persist.grid", sched["grid"])
 
 
 def slots_per_batch(level: int, waves: int = 1) -> int:

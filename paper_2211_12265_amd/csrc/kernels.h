@@ -106,25 +106,43 @@ __device__ __forceinline__ void expand_a_squeeze_wave(uint32_t s[50], int32_t *o
 #pragma unroll
     for (int w = 0; w < RATE128 / 4; w++) row[w] = s[w];
     wave_sync();
+    // up to four unfinished streams per step, so that their LDS reads and
+    // ballots overlap instead of forming one dependent chain per stream
     uint64_t pending = __ballot(ctr < N);
+    const int b3 = 3 * lane;
     while (pending) {
-      const int L = __builtin_ctzll(pending);
-      pending &= pending - 1;
-      const int cL = __builtin_amdgcn_readlane(ctr, L);
-      const uint32_t *rL = rows + L * EA_ROW;
-      const int b = 3 * lane;
-      uint32_t tv = 0;
-      bool ok = false;
-      if (lane < RATE128 / 3) {  // word (b >> 2) + 1 is at most 42, the row's pad word
-        tv = __builtin_amdgcn_alignbit(rL[(b >> 2) + 1], rL[b >> 2], 8 * (b & 3)) & 0x7FFFFFu;
-        ok = tv < (uint32_t)Q;
+      int Ls[4];
+      bool act[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        act[u] = pending != 0;
+        Ls[u] = act[u] ? __builtin_ctzll(pending) : 0;
+        pending &= pending - 1;
       }
-      const uint64_t m = __ballot(ok);
-      const int pos =
-          cL + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-      if (ok && pos < N) out0[(size_t)L * N + pos] = (int32_t)tv;
-      const int nL = min(N, cL + (int)__popcll(m));
-      if (lane == L) ctr = nL;
+      uint32_t tv[4];
+      bool ok[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        const uint32_t *rL = rows + Ls[u] * EA_ROW;
+        tv[u] = 0;
+        ok[u] = false;
+        if (act[u] && lane < RATE128 / 3) {  // word (b3 >> 2) + 1 is at most 42, the row's pad word
+          tv[u] = __builtin_amdgcn_alignbit(rL[(b3 >> 2) + 1], rL[b3 >> 2], 8 * (b3 & 3)) & 0x7FFFFFu;
+          ok[u] = tv[u] < (uint32_t)Q;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; u++) {
+        if (!act[u]) continue;  // wave-uniform
+        const int L = Ls[u];
+        const int cL = __builtin_amdgcn_readlane(ctr, L);
+        const uint64_t m = __ballot(ok[u]);
+        const int pos =
+            cL + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (ok[u] && pos < N) out0[(size_t)L * N + pos] = (int32_t)tv[u];
+        const int nL = min(N, cL + (int)__popcll(m));
+        if (lane == L) ctr = nL;
+      }
     }
     wave_sync();
     if (__ballot(ctr < N) == 0) break;
@@ -285,7 +303,11 @@ __global__ void __launch_bounds__(256) sg_prep_k(const uint8_t *sk, const uint32
   if (o1 >= o0) mlen = o1 - o0;
   else atomicOr(err, 1u);  // decreasing msg_off: message treated as empty
   uint32_t s[50];
-  shake_absorb<RATE256>(s, 32 + mlen, SrcCat{skr + 64, 32, msg + o0, 32 + mlen});
+  uint32_t trw[8];
+  const uint32_t *skw = (const uint32_t *)(skr + 64);  // tr inside the 8-byte aligned sk row
+#pragma unroll
+  for (int i = 0; i < 8; i++) trw[i] = skw[i];
+  absorb_tr_msg(s, trw, msg + o0, mlen);
   uint32_t mu[16];
 #pragma unroll
   for (int i = 0; i < 16; i++) mu[i] = s[i];
@@ -658,23 +680,22 @@ __global__ void __launch_bounds__(64) vf_hash_k(const uint8_t *pk, const uint32_
   if (t >= count) return;
   size_t key = key_idx ? key_idx[t] : t;
   uint32_t s[50];
-  const uint8_t *trsrc;
+  uint32_t trw[8];
   if (ws.tr) {
-    trsrc = ws.tr + key * 32;
+    const uint32_t *tg = (const uint32_t *)(ws.tr + key * 32);
+#pragma unroll
+    for (int i = 0; i < 8; i++) trw[i] = tg[i];
   } else {
     const uint8_t *pkr = pk + key * PP::PK;
     shake_absorb<RATE256>(s, PP::PK, [&](uint64_t pos) { return *(const uint64_t *)(pkr + pos); });
-    // tr is staged in the (otherwise unused) ctilde row so the message hash can stream tr || M
-    uint32_t *trg = (uint32_t *)(ws.ctilde + (size_t)t * 32);
 #pragma unroll
-    for (int i = 0; i < 8; i++) trg[i] = s[i];
-    trsrc = (const uint8_t *)trg;
+    for (int i = 0; i < 8; i++) trw[i] = s[i];
   }
   uint64_t o0 = msg_off[t], o1 = msg_off[t + 1];
   uint64_t mlen = 0;
   if (o1 >= o0) mlen = o1 - o0;
   else atomicOr(err, 1u);  // decreasing msg_off: message treated as empty
-  shake_absorb<RATE256>(s, 32 + mlen, SrcCat{trsrc, 32, msg + o0, 32 + mlen});
+  absorb_tr_msg(s, trw, msg + o0, mlen);
   uint32_t *muw = (uint32_t *)(ws.muw1 + (size_t)t * muw1_stride<LV>());
 #pragma unroll
   for (int i = 0; i < 16; i++) muw[i] = s[i];

@@ -291,6 +291,10 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
     lds.queue_empty = 0;
   }
   __syncthreads();
+#ifdef DIL_PHASE_TIMERS
+  uint64_t ph_t = __builtin_amdgcn_s_memtime();  // lane 0 of every wavefront times the barrier-separated phases
+  uint64_t ph_acc[5] = {0, 0, 0, 0, 0};
+#endif
   for (uint32_t batch = 0;; batch++) {
     if (tid == 0) {
       int nh = lds.nheld;
@@ -313,6 +317,7 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
     __syncthreads();
     const int ns = lds.nslots;
     if (ns == 0) break;
+    PHASE_MARK(0);
     // ExpandMask: one thread per (slot, i)
     if (tid < ns * L) {
       int s = tid / L, i = tid % L;
@@ -321,6 +326,7 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
     }
     __threadfence_block();
     __syncthreads();
+    PHASE_MARK(1);
     // w per slot, wave w takes slots w, w + 4, ...
     for (int s = wave; s < ns; s += W) {
       uint32_t task = lds.h_task[lds.s_h[s]];
@@ -331,6 +337,7 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
     }
     __threadfence_block();
     __syncthreads();
+    PHASE_MARK(2);
     // challenges of all slots on one (rotating) wave
     if (wave == (int)((wg + batch) % W) && lane < ns) {
       uint32_t task = lds.h_task[lds.s_h[lane]];
@@ -338,6 +345,7 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
                         lds.c[lane], (uint8_t *)lds.bb[lane]);
     }
     __syncthreads();
+    PHASE_MARK(3);
     // checks; a slot is skipped once a smaller nonce of its task has passed
     for (int s = wave; s < ns; s += W) {
       int h = lds.s_h[s];
@@ -357,6 +365,7 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
     }
     __threadfence_block();
     __syncthreads();
+    PHASE_MARK(4);
     // copy each signed task's smallest passing candidate out; wave w handles held tasks w, w + 4, ...
     for (int h = wave; h < lds.nheld; h += W) {
       uint32_t win = lds.h_win[h];
@@ -388,6 +397,7 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
     __syncthreads();
   }
   if (tid == 0) tally.flush(stats);
+  PHASE_FLUSH();
 }
 
 }  // namespace dil

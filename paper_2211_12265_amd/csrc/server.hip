@@ -8,6 +8,12 @@
 // device-memory budget, splits the batch by (level, op) into
 // dil_sign_keyset / dil_verify_keyset calls, and enqueues the host->device
 // copies, the kernels and the device->host copies followed by an event.
+// The (level, op) groups of a batch are independent: each runs on a stream and
+// context of its own, forked after the batch's copies in and joined before its
+// copies out, so a batch takes about as long as its slowest group.  This
+// needs hardware queues for the lanes' and groups' streams: with HIP's
+// default of 4 per process they serialise, so serving processes should raise
+// GPU_MAX_HW_QUEUES (the benchmark uses 16).
 // Completed batches are harvested by polling the events; a request's
 // completion time is the poll that observed its batch's event.
 #include <hip/hip_runtime.h>
@@ -32,10 +38,14 @@ struct Group {
   size_t m_pos = 0, m_len = 0, t_pos = 0, o_pos = 0, s_pos = 0;
 };
 
+constexpr int NGROUP = 2 * NLV;  // (level, op) groups, index 2 * level index + op
+
 struct Lane {
   hipStream_t st = nullptr;
-  dil_ctx *ctx = nullptr;
-  hipEvent_t ev = nullptr;
+  hipEvent_t ev = nullptr, fork = nullptr;
+  hipStream_t gst[NGROUP] = {};
+  dil_ctx *gctx[NGROUP] = {};
+  hipEvent_t gev[NGROUP] = {};
   uint8_t *h_msg = nullptr, *h_sig = nullptr, *d_msg = nullptr, *d_sig = nullptr;
   uint64_t *h_off = nullptr, *d_off = nullptr;
   uint32_t *h_key = nullptr, *d_key = nullptr;
@@ -100,10 +110,15 @@ int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset 
   for (auto &ln : s->lanes) {
     bool ok = hipStreamCreateWithFlags(&ln.st, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&ln.ev, hipEventDisableTiming) == hipSuccess &&
-              dil_ctx_create(&ln.ctx, device, 0) == DIL_OK &&
-              dil_ctx_set_mode(ln.ctx, mode) == DIL_OK;
-    for (int i = 0; ok && i < NLV; i++)
-      if (s->ks[i]) ok = dil_ctx_reserve(ln.ctx, kLevels[i], max_batch) == DIL_OK;
+              hipEventCreateWithFlags(&ln.fork, hipEventDisableTiming) == hipSuccess;
+    for (int gi = 0; ok && gi < NGROUP; gi++) {
+      int li = gi / 2;
+      if (!s->ks[li]) continue;
+      ok = hipStreamCreateWithFlags(&ln.gst[gi], hipStreamNonBlocking) == hipSuccess &&
+           hipEventCreateWithFlags(&ln.gev[gi], hipEventDisableTiming) == hipSuccess &&
+           dil_ctx_create(&ln.gctx[gi], device, 0) == DIL_OK && dil_ctx_set_mode(ln.gctx[gi], mode) == DIL_OK &&
+           dil_ctx_reserve(ln.gctx[gi], kLevels[li], max_batch) == DIL_OK;
+    }
     ok = ok && hipHostMalloc((void **)&ln.h_msg, max_msg_bytes, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc((void **)&ln.h_sig, max_batch * max_sig, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc((void **)&ln.h_off, (max_batch + 8) * 8, hipHostMallocDefault) == hipSuccess &&
@@ -128,7 +143,12 @@ int dil_server_destroy(dil_server *s) {
   hipSetDevice(s->device);
   hipDeviceSynchronize();
   for (auto &ln : s->lanes) {
-    if (ln.ctx) dil_ctx_destroy(ln.ctx);
+    for (int gi = 0; gi < NGROUP; gi++) {
+      if (ln.gctx[gi]) dil_ctx_destroy(ln.gctx[gi]);
+      if (ln.gev[gi]) hipEventDestroy(ln.gev[gi]);
+      if (ln.gst[gi]) hipStreamDestroy(ln.gst[gi]);
+    }
+    if (ln.fork) hipEventDestroy(ln.fork);
     if (ln.ev) hipEventDestroy(ln.ev);
     if (ln.st) hipStreamDestroy(ln.st);
     hipHostFree(ln.h_msg);
@@ -272,19 +292,26 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
                   (s_pos == 0 ||
                    hipMemcpyAsync(ln.d_sig, ln.h_sig, s_pos, hipMemcpyHostToDevice, ln.st) == hipSuccess);
         if (!ok) return sfail(s, DIL_EHIP, "host-to-device copy");
+        if (hipEventRecord(ln.fork, ln.st) != hipSuccess) return sfail(s, DIL_EHIP, "fork");
         for (auto &g : ln.groups) {
           uint32_t cnt = (uint32_t)g.req.size();
+          const int gi = 2 * g.li + g.op;
+          hipStream_t gs = ln.gst[gi];
+          dil_ctx *gc = ln.gctx[gi];
+          if (hipStreamWaitEvent(gs, ln.fork, 0) != hipSuccess) return sfail(s, DIL_EHIP, "fork wait");
           int rc;
           if (g.op == 0)
-            rc = dil_sign_keyset(ln.ctx, s->ks[g.li], ln.d_key + g.t_pos, ln.d_msg + g.m_pos, ln.d_off + g.o_pos,
-                                 ln.d_sig + g.s_pos, cnt, ln.st);
+            rc = dil_sign_keyset(gc, s->ks[g.li], ln.d_key + g.t_pos, ln.d_msg + g.m_pos, ln.d_off + g.o_pos,
+                                 ln.d_sig + g.s_pos, cnt, gs);
           else
-            rc = dil_verify_keyset(ln.ctx, s->ks[g.li], ln.d_key + g.t_pos, ln.d_msg + g.m_pos, ln.d_off + g.o_pos,
-                                   ln.d_sig + g.s_pos, ln.d_ver + g.t_pos, cnt, ln.st);
+            rc = dil_verify_keyset(gc, s->ks[g.li], ln.d_key + g.t_pos, ln.d_msg + g.m_pos, ln.d_off + g.o_pos,
+                                   ln.d_sig + g.s_pos, ln.d_ver + g.t_pos, cnt, gs);
           if (rc) {
-            snprintf(s->err, sizeof s->err, "batch call: %s", dil_last_error(ln.ctx));
+            snprintf(s->err, sizeof s->err, "batch call: %s", dil_last_error(gc));
             return rc;
           }
+          if (hipEventRecord(ln.gev[gi], gs) != hipSuccess || hipStreamWaitEvent(ln.st, ln.gev[gi], 0) != hipSuccess)
+            return sfail(s, DIL_EHIP, "join");
         }
         ok = (s_pos == 0 || hipMemcpyAsync(ln.h_sig, ln.d_sig, s_pos, hipMemcpyDeviceToHost, ln.st) == hipSuccess) &&
              hipMemcpyAsync(ln.h_ver, ln.d_ver, t_pos * 4, hipMemcpyDeviceToHost, ln.st) == hipSuccess &&

@@ -43,6 +43,11 @@ class HostPipeline:
 
     n_streams: HIP streams (and libdil contexts) used; chunk: tasks per chunk.
     mode: Sign execution form of every context (dl.MODE_*).
+    Persistent Sign calls of different streams run at the same time, so each
+    context gets an equal share of the GPU's resident four-wavefront
+    workgroups (and as many held tasks per workgroup as its chunk needs)
+    instead of the single-call automatic schedule, which would size every
+    launch for the whole GPU.
     """
 
     def __init__(self, level: int, n_streams: int = 4, chunk: int = 1250, mode: int = dl.MODE_PERSISTENT,
@@ -55,6 +60,12 @@ class HostPipeline:
         self.dev = torch.device("cuda", device)
         self.ctx = [dl.Context(device, mode=mode) for _ in range(n_streams)]
         for c in self.ctx:
+            if mode == dl.MODE_PERSISTENT:
+                c.set_param("persist.waves", 4)
+                resident, slots = c.persist_capacity(level)
+                grid = max(1, min(resident // n_streams, -(-chunk // 16)))
+                c.set_param("persist.grid", grid)
+                c.set_param("persist.hmax", min(slots, -(-chunk // grid)))
             c.reserve(level, chunk)
         self.streams = [torch.cuda.Stream(device=self.dev) for _ in range(n_streams)]
         # flat, so that [m, PK] and [m, SK] views of it are both contiguous

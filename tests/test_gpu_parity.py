@@ -353,3 +353,42 @@ def test_autotuner_picks_a_measured_candidate(ctx):
     osig, _ = oracle.sign_batch(level, sk.cpu().numpy(), msg, off)
     assert np.array_equal(sig.cpu().numpy(), osig)
     c.close()
+
+
+@pytest.mark.parametrize("level", [2, 5])
+def test_message_lengths_at_block_boundaries(sctx, level):
+    """mu = H(tr || M) with M ending on and around every SHAKE256 block boundary (the
+    first block holds tr and 104 message bytes, later ones 136) and starting at each of
+    the four byte alignments: Sign and Verify equal the oracle.  One contiguous CSR holds
+    a filler task of 0-3 bytes before every message to set that message's alignment."""
+    from paper_2211_12265_amd import dilithium as dl
+    lens = [0, 1, 2, 3, 4, 5, 7, 103, 104, 105, 239, 240, 241, 375, 376, 377, 2000]
+    task_lens, key_of, real = [], [], []
+    pos = 0
+    for ln in lens:
+        for align in range(4):
+            lead = (align - pos) % 4
+            task_lens.append(lead)         # filler task (key 0)
+            key_of.append(0)
+            real.append(False)
+            pos += lead
+            task_lens.append(ln)           # the message under test, starting at pos % 4 == align
+            key_of.append(len(key_of) // 2 % 8)
+            real.append(True)
+            pos += ln
+    task_lens = np.array(task_lens, dtype=np.int64)
+    n = len(task_lens)
+    msg, off = workload.messages(task_lens, seed=150 + level)
+    kidx = np.array(key_of, dtype=np.uint32)
+    pk, sk = _keygen(sctx, level, workload.keygen_seeds(8, seed=150 + level))
+    osig, _ = oracle.sign_batch(level, sk.cpu().numpy(), msg, off, key_idx=kidx)
+    sig = torch.zeros((n, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
+    sctx.sign(level, sk, dev(msg), dev(off.astype(np.int64)), sig, key_idx=dev(kidx))
+    torch.cuda.synchronize()
+    got = sig.cpu().numpy()
+    assert np.array_equal(got, osig)
+    assert [int(off[i]) % 4 for i in range(1, n, 2)] == [j % 4 for j in range(n // 2)]
+    v = torch.zeros(n, dtype=torch.int32, device="cuda")
+    sctx.verify(level, pk, dev(msg), dev(off.astype(np.int64)), sig, v, key_idx=dev(kidx))
+    torch.cuda.synchronize()
+    assert v.cpu().numpy().tolist() == [1] * n
