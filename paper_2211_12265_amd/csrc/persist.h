@@ -268,6 +268,38 @@ struct Persist4Lds {
   int nheld, nslots, queue_empty;
 };
 
+// Copy an NB-byte signature from a 4-byte aligned global row to a destination
+// row at any byte alignment with one wavefront: each lane requests all the
+// source words it needs before storing anything, then funnel-shifts them into
+// the destination's word grid (head and tail bytes stored singly).
+template <int NB>
+__device__ __forceinline__ void copy_sig_row(const uint32_t *src, uint8_t *dst, int lane) {
+  constexpr int NWS = (NB + 3) / 4;    // source words
+  constexpr int PER = (NWS + 63) / 64;  // destination words per lane (upper bound)
+  const int head = (int)((4 - ((uintptr_t)dst & 3)) & 3);
+  const int body = (NB - head) >> 2;
+  uint32_t lo[PER], hi[PER];
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const int i = lane + 64 * q;
+    lo[q] = i < NWS ? src[i] : 0u;
+    hi[q] = i + 1 < NWS ? src[i + 1] : 0u;
+  }
+  const uint32_t first = src[0];
+  if (lane < head) dst[lane] = (uint8_t)(first >> (8 * lane));
+  uint32_t *dw = (uint32_t *)(dst + head);
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const int i = lane + 64 * q;
+    if (i < body) dw[i] = __builtin_amdgcn_alignbit(hi[q], lo[q], 8 * head);
+  }
+  const int done = head + 4 * body;
+  if (lane < NB - done) {
+    const int b = done + lane;
+    dst[b] = (uint8_t)(src[b >> 2] >> (8 * (b & 3)));
+  }
+}
+
 template <int LV>
 __host__ __device__ __forceinline__ size_t sig_stride() {
   return ((size_t)P<LV>::SIG + 255) & ~(size_t)255;
@@ -373,8 +405,8 @@ __global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *si
       int s = -1;
       for (int q = 0; q < ns; q++)
         if (lds.s_h[q] == h && lds.s_att[q] == win) s = q;
-      l2g_bytes((const uint32_t *)(stg + s * sig_stride<LV>()), P<LV>::SIG,
-                sig + (size_t)lds.h_task[h] * P<LV>::SIG, lane, 64);
+      copy_sig_row<P<LV>::SIG>((const uint32_t *)(stg + s * sig_stride<LV>()),
+                               sig + (size_t)lds.h_task[h] * P<LV>::SIG, lane);
     }
     __syncthreads();
     if (tid == 0) {
