@@ -208,8 +208,8 @@ def ablation_run(level: int, n: int, msg_dist: str, steps: int = 10) -> list:
     ref = None
     rows = []
     forms = [("staged", dl.MODE_STAGED, None, 0), ("persistent 1-wave", dl.MODE_PERSISTENT, 1, 1),
-             ("persistent 4-wave", dl.MODE_PERSISTENT, 4, 1), ("persistent 4-wave, no hipGraph",
-                                                                dl.MODE_PERSISTENT, 4, 0)]
+             ("persistent 2-wave", dl.MODE_PERSISTENT, 2, 1), ("persistent 4-wave", dl.MODE_PERSISTENT, 4, 1),
+             ("persistent 4-wave, no hipGraph", dl.MODE_PERSISTENT, 4, 0)]
     for name, mode, waves, graph in forms:
         ctx = dl.Context(0, mode=mode)
         sig = torch.zeros((n, sgl), dtype=torch.uint8, device="cuda")
@@ -313,7 +313,7 @@ def main():
     ap.add_argument("--tune-reps", type=int, default=3)
     ap.add_argument("--record-schedule", default="",
                     help="after tuning, record the chosen schedule in this JSON file")
-    ap.add_argument("--waves", type=int, default=0, choices=[0, 1, 4],
+    ap.add_argument("--waves", type=int, default=0, choices=[0, 1, 2, 4],
                     help="wavefronts per persistent workgroup (0: let the autotuner choose; 1 without it)")
     ap.add_argument("--schedule", default="",
                     help="fixed persistent schedule 'waves,hmax,grid' (skips the autotuner)")
@@ -406,7 +406,7 @@ def main():
         schedule_src = "autotuner (recorded)"
     elif args.mode == "persistent" and not args.no_tune:
         tuning = autotune.tune_sign(ctx, level, lambda: ctx.sign(level, sk, g_msg, g_off, sig), count=n,
-                                    reps=args.tune_reps, waves=(args.waves,) if args.waves else (1, 4))
+                                    reps=args.tune_reps, waves=(args.waves,) if args.waves else (1, 2, 4))
         schedule_src = "autotuner (this run)"
         if args.record_schedule:
             autotune.store_schedule(level, n, args.msg_dist, tuning["best"], args.record_schedule)
@@ -448,12 +448,12 @@ def main():
         achieved = k_ops / (loop_med * 1e-3)
         kextra = {"kernel_ms_median": loop_med, "setup_ms_median": float(np.median(setup_ms)),
                   "timed_launches": len(loop_ms), "ops_per_launch": k_ops}
-        four = tuning["best"]["waves"] == 4 if tuning else args.waves == 4
-        kbase = "sg_persist4_k" if four else "sg_persist_k"
+        nw = tuning["best"]["waves"] if tuning else (args.waves or 1)
+        kbase = f"sg_persistw_k<{level}, {nw}>" if nw > 1 else f"sg_persist_k<{level}>"
         kname = kbase + " (persistent Sign rejection-loop kernel)"
         sched_str = args.schedule if not tuning else \
             f"{tuning['best']['waves']},{tuning['best']['hmax']},{tuning['best']['grid']}"
-        rec = stored_traffic(f"{kbase}<{level}>", level, n, args.msg_dist, sched_str)
+        rec = stored_traffic(kbase, level, n, args.msg_dist, sched_str)
         if rec:
             kextra["traffic_detail"] = {"fetch_bytes": rec["fetch_bytes"], "write_bytes": rec["write_bytes"],
                                         "profile": rec["profile"]}

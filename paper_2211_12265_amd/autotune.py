@@ -2,8 +2,8 @@
 
 The schedule has three knobs (dil_ctx_set_param):
   persist.waves wavefronts per workgroup: 1 (G = 64 / l candidate slots per
-                batch) or 4 (G = 4 * (64 / l) slots; the challenge hashes of
-                all slots run on one wavefront with its lanes full);
+                batch), 2 or 4 (G = W * (64 / l) slots; the challenge hashes
+                of all slots run on one wavefront);
   persist.hmax  tasks a workgroup holds at once; each held task gets G / hmax
                 consecutive nonces per batch (hmax = G: no speculation until
                 tasks retire);
@@ -66,7 +66,8 @@ def slots_per_batch(level: int, waves: int = 1) -> int:
 def candidates(level: int, count: int, resident_groups: int, waves: int = 1) -> List[tuple]:
     """(hmax, grid) pairs for one workgroup shape."""
     g = slots_per_batch(level, waves)
-    base = (1, 2, 3, 4, 6, 8, 12, 16) if waves == 1 else (1, 2, 4, 6, 8, 12, 16, 24, 32, 48, 64)
+    base = {1: (1, 2, 3, 4, 6, 8, 12, 16), 2: (1, 2, 4, 6, 8, 12, 16, 24, 32),
+            4: (1, 2, 4, 6, 8, 12, 16, 24, 32, 48, 64)}[waves]
     hm = sorted({h for h in base if h <= g} | {g})
     out = []
     for h in hm:
@@ -80,7 +81,7 @@ def candidates(level: int, count: int, resident_groups: int, waves: int = 1) -> 
 
 def tune_sign(ctx, level: int, run, resident_groups: Optional[int] = None, reps: int = 3,
               cands: Optional[List[tuple]] = None, count: Optional[int] = None,
-              waves: Sequence[int] = (1, 4)) -> Dict:
+              waves: Sequence[int] = (1, 2, 4)) -> Dict:
     """Time `run()` (one Sign call on ctx) for each schedule; leave the best set on ctx.
 
     run: callable issuing the Sign batch on the current stream.

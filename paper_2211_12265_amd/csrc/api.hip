@@ -24,14 +24,13 @@ struct dil_ctx {
   hipStream_t last_stream = nullptr;
   int stats_pending = 0;
   int64_t persist_grid = 0, persist_hmax = 0;  // 0 = automatic
-  int persist_waves = 1;                       // wavefronts per persistent workgroup: 1 or 4
+  int persist_waves = 1;                       // wavefronts per persistent workgroup: 1, 2 or 4
   int timing = 0;                              // record HIP events around the persistent Sign phases
   static constexpr int RING = 64;
   hipEvent_t ev[RING][3] = {};                 // per timed call: before setup, before loop, after loop
   int ev_count = 0;                            // timed calls recorded since timing was (re)enabled
   int cu_count = 0;                            // cached device properties
-  int occ[6] = {0, 0, 0, 0, 0, 0};             // cached persistent-kernel occupancy per level
-  int occ4[6] = {0, 0, 0, 0, 0, 0};            // same for the four-wave kernel
+  int occ[3][6] = {};                          // cached persistent-kernel occupancy [shape: 1/2/4 waves][level]
   // hipGraph replay of identical calls (same level, buffers, count and schedule)
   int use_graph = 0;
   hipStream_t cap_stream = nullptr;            // private stream the graphs are captured on
@@ -97,7 +96,7 @@ size_t ws_need(size_t cap) {
 
 template <int LV>
 constexpr int persist_slots(int waves) {
-  return waves == 4 ? PCfg4<LV>::G : PCfg<LV>::G;
+  return waves == 1 ? PCfg<LV>::G : waves * PCfg<LV>::G;
 }
 
 template <int LV>
@@ -105,7 +104,7 @@ size_t pscr_need(size_t grid, int waves) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
   size_t G = persist_slots<LV>(waves);
   size_t w1s = ((size_t)K * P<LV>::W1B + 255) & ~(size_t)255;
-  size_t stage = waves == 4 ? sig_stride<LV>() : 0;
+  size_t stage = waves > 1 ? sig_stride<LV>() : 0;
   return grid * G * ((size_t)(L + K) * 1024 + w1s + stage) + 4 * 256;
 }
 
@@ -161,7 +160,7 @@ int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws, size_t grid = 0, PScr *sc = nullp
     sc->y = (int32_t *)take(grid * G * L * 1024);
     sc->w = (int32_t *)take(grid * G * K * 1024);
     sc->w1 = take(grid * G * w1s);
-    sc->stage = waves == 4 ? take(grid * G * sig_stride<LV>()) : nullptr;
+    sc->stage = waves > 1 ? take(grid * G * sig_stride<LV>()) : nullptr;
   }
   if ((size_t)(p - (uint8_t *)ctx->ws_mem) > ctx->ws_bytes) return fail(ctx, DIL_ENOMEM, "workspace layout overflow");
   return DIL_OK;
@@ -347,15 +346,14 @@ int persist_occupancy(dil_ctx *ctx, int *occ) {
     HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
     ctx->cu_count = prop.multiProcessorCount;
   }
-  if (ctx->persist_waves == 4) {
-    if (!ctx->occ4[LV])
-      HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx->occ4[LV], sg_persist4_k<LV>, 256, 0));
-    *occ = std::max(ctx->occ4[LV], 1);
-  } else {
-    if (!ctx->occ[LV])
-      HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&ctx->occ[LV], sg_persist_k<LV>, 64, 0));
-    *occ = std::max(ctx->occ[LV], 1);
+  const int w = ctx->persist_waves, si = w == 4 ? 2 : w == 2 ? 1 : 0;
+  int &o = ctx->occ[si][LV];
+  if (!o) {
+    if (w == 4) HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_persistw_k<LV, 4>, 256, 0));
+    else if (w == 2) HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_persistw_k<LV, 2>, 128, 0));
+    else HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_persist_k<LV>, 64, 0));
   }
+  *occ = std::max(o, 1);
   return DIL_OK;
 }
 
@@ -394,7 +392,9 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   key[12] = 1;  // second graph: the loop kernel
   rc = enqueue(ctx, key, st, [&](hipStream_t s) {
     if (waves == 4)
-      sg_persist4_k<LV><<<(unsigned)grid, 256, 0, s>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+      sg_persistw_k<LV, 4><<<(unsigned)grid, 256, 0, s>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+    else if (waves == 2)
+      sg_persistw_k<LV, 2><<<(unsigned)grid, 128, 0, s>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
     else
       sg_persist_k<LV><<<(unsigned)grid, 64, 0, s>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
     LAUNCHCHK(ctx);
@@ -613,7 +613,7 @@ int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value) {
   } else if (!strcmp(name, "persist.grid")) ctx->persist_grid = value;
   else if (!strcmp(name, "persist.hmax")) ctx->persist_hmax = value;
   else if (!strcmp(name, "persist.waves")) {
-    if (value != 1 && value != 4) return fail(ctx, DIL_EINVAL, "persist.waves must be 1 or 4");
+    if (value != 1 && value != 2 && value != 4) return fail(ctx, DIL_EINVAL, "persist.waves must be 1, 2 or 4");
     ctx->persist_waves = (int)value;
   }
   else return fail(ctx, DIL_EINVAL, "unknown parameter");

@@ -29,7 +29,7 @@ struct PScr {
   int32_t *y;    // [P][G][L][256]
   int32_t *w;    // [P][G][K][256]
   uint8_t *w1;   // [P][G][K * W1B rounded to 256]
-  uint8_t *stage; // four-wave kernel only: [P][G][SIG rounded to 256]
+  uint8_t *stage; // multi-wave kernels only: [P][G][SIG rounded to 256]
 };
 
 template <int LV>
@@ -233,24 +233,25 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
 namespace dil {
 
 // ---------------------------------------------------------------------------
-// Four-wavefront variant.  A 256-thread workgroup holds 4 * (64 / l) slots per
-// batch.  ExpandMask uses one thread per stream over all four waves; w and the
-// checks run per slot, wave w taking slots w, w + 4, ...; the challenge hashes
-// of all slots (at most 64) run on ONE wave, so that phase keeps its lanes busy
-// (the single-wave kernel hashes 64/l challenges on 64 lanes).  Which wave
-// hashes rotates with the workgroup and batch index so the SIMDs stay
-// balanced.  Passing candidates are staged per slot and the smallest passing
-// nonce of each task is copied to the output after a barrier.
+// Multi-wavefront variant (W = 2 or 4 wavefronts per workgroup).  A workgroup
+// holds W * (64 / l) slots per batch.  ExpandMask uses one thread per stream
+// over all W waves; w and the checks run per slot, wave w taking slots w,
+// w + W, ...; the challenge hashes of all slots (at most 64) run on ONE wave,
+// so that phase keeps its lanes busy (the single-wave kernel hashes 64/l
+// challenges on 64 lanes) while the other W - 1 waves wait at the barrier.
+// Which wave hashes rotates with the workgroup and batch index so the SIMDs
+// stay balanced.  Passing candidates are staged per slot and the smallest
+// passing nonce of each task is copied to the output after a barrier.
 // ---------------------------------------------------------------------------
-template <int LV>
-struct PCfg4 {
-  static constexpr int W = 4;
+template <int LV, int NW>
+struct PCfgW {
+  static constexpr int W = NW;
   static constexpr int GW = 64 / Lv<LV>::L;  // slots per wave
-  static constexpr int G = W * GW;           // 64 / 48 / 36
+  static constexpr int G = W * GW;           // 4 waves: 64 / 48 / 36
 };
 
-template <int LV>
-struct Persist4Lds {
+template <int LV, int NW>
+struct PersistWLds {
   union {
     struct {
       int32_t hat[Lv<LV>::L * HAT_POLY];
@@ -258,13 +259,13 @@ struct Persist4Lds {
       uint32_t w1buf[Lv<LV>::K * P<LV>::W1B / 4 + 1];
     } wp;
     CheckLds<LV> ck;
-  } u[4];
-  int8_t c[PCfg4<LV>::G][N];
-  uint32_t ct[PCfg4<LV>::G][8];
-  uint32_t bb[PCfg4<LV>::G][RATE256 / 4];
-  uint32_t h_task[PCfg4<LV>::G], h_next[PCfg4<LV>::G], h_win[PCfg4<LV>::G];
-  uint32_t s_att[PCfg4<LV>::G];
-  uint8_t s_h[PCfg4<LV>::G];
+  } u[NW];
+  int8_t c[PCfgW<LV, NW>::G][N];
+  uint32_t ct[PCfgW<LV, NW>::G][8];
+  uint32_t bb[PCfgW<LV, NW>::G][RATE256 / 4];
+  uint32_t h_task[PCfgW<LV, NW>::G], h_next[PCfgW<LV, NW>::G], h_win[PCfgW<LV, NW>::G];
+  uint32_t s_att[PCfgW<LV, NW>::G];
+  uint8_t s_h[PCfgW<LV, NW>::G];
   int nheld, nslots, queue_empty;
 };
 
@@ -305,11 +306,11 @@ __host__ __device__ __forceinline__ size_t sig_stride() {
   return ((size_t)P<LV>::SIG + 255) & ~(size_t)255;
 }
 
-template <int LV>
-__global__ void __launch_bounds__(256) sg_persist4_k(Ws ws, PScr sc, uint8_t *sig, uint32_t count,
+template <int LV, int NW>
+__global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t *sig, uint32_t count,
                                                      uint32_t hmax, uint32_t *stats) {
-  constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfg4<LV>::G, W = PCfg4<LV>::W;
-  __shared__ Persist4Lds<LV> lds;
+  constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfgW<LV, NW>::G, W = NW;
+  __shared__ PersistWLds<LV, NW> lds;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, t = lane & 15;
   const size_t wg = blockIdx.x;
   int32_t *yb = sc.y + wg * G * L * N;

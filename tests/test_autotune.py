@@ -4,7 +4,7 @@ from paper_2211_12265_amd import autotune
 
 def test_candidates_cover_speculation_range():
     for level, g in ((2, 16), (3, 12), (5, 9)):
-        for waves in (1, 4):
+        for waves in (1, 2, 4):
             assert autotune.slots_per_batch(level, waves) == waves * g
             c = autotune.candidates(level, 10000, 2048, waves)
             hm = {h for h, _ in c}
@@ -15,7 +15,7 @@ def test_candidates_cover_speculation_range():
 
 
 def test_candidates_small_batch():
-    for waves in (1, 4):
+    for waves in (1, 2, 4):
         c = autotune.candidates(2, 5, 2048, waves)
         assert all(grid <= 5 for _, grid in c)
         assert len(set(c)) == len(c)

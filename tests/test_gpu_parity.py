@@ -191,6 +191,7 @@ def test_empty_batch_and_bad_level(ctx):
 
 @pytest.mark.parametrize("level", [2, 5])
 @pytest.mark.parametrize("waves,grid,hmax", [(1, 1, 1), (1, 3, 2), (1, 7, 16), (1, 0, 0),
+                                             (2, 1, 1), (2, 5, 3), (2, 0, 0),
                                              (4, 1, 1), (4, 3, 5), (4, 2, 64), (4, 0, 0)])
 def test_persistent_schedules_match_oracle(level, waves, grid, hmax):
     """Every workgroup shape / grid size / tasks-per-workgroup setting gives the
@@ -344,10 +345,10 @@ def test_autotuner_picks_a_measured_candidate(ctx):
     resident4, slots4 = c.persist_capacity(level)
     assert resident4 > 0 and slots4 == 64
     with pytest.raises(dl.DilError):
-        c.set_param("persist.waves", 2)
+        c.set_param("persist.waves", 3)
     res = autotune.tune_sign(c, level, lambda: c.sign(level, sk, dmsg, doff, sig), reps=1, count=n)
     assert res["best"] in res["table"]
-    assert {r["waves"] for r in res["table"]} == {1, 4}
+    assert {r["waves"] for r in res["table"]} == {1, 2, 4}
     c.sign(level, sk, dmsg, doff, sig)
     torch.cuda.synchronize()
     osig, _ = oracle.sign_batch(level, sk.cpu().numpy(), msg, off)
