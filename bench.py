@@ -311,6 +311,7 @@ def main():
     ap.add_argument("--tune", action="store_true",
                     help="re-run the autotuner even if a schedule is recorded for this workload")
     ap.add_argument("--tune-reps", type=int, default=3)
+    ap.add_argument("--tune-rounds", type=int, default=1)
     ap.add_argument("--record-schedule", default="",
                     help="after tuning, record the chosen schedule in this JSON file")
     ap.add_argument("--waves", type=int, default=0, choices=[0, 1, 2, 4],
@@ -406,7 +407,8 @@ def main():
         schedule_src = "autotuner (recorded)"
     elif args.mode == "persistent" and not args.no_tune:
         tuning = autotune.tune_sign(ctx, level, lambda: ctx.sign(level, sk, g_msg, g_off, sig), count=n,
-                                    reps=args.tune_reps, waves=(args.waves,) if args.waves else (1, 2, 4))
+                                    reps=args.tune_reps, rounds=args.tune_rounds,
+                                    waves=(args.waves,) if args.waves else (1, 2, 4))
         schedule_src = "autotuner (this run)"
         if args.record_schedule:
             autotune.store_schedule(level, n, args.msg_dist, tuning["best"], args.record_schedule)

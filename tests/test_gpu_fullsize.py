@@ -54,3 +54,79 @@ def test_ten_thousand_tasks(level, lengths, waves):
         torch.cuda.synchronize()
         assert int(ver.sum()) == 0
     ctx.close()
+
+
+@pytest.mark.parametrize("mode", ["staged", "persistent"])
+@pytest.mark.parametrize("level", [2, 3, 5])
+def test_single_task(mode, level):
+    """count = 1 in every execution form (a persistent launch with one workgroup holding one task)."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    ctx = dl.Context(0, mode=dl.MODE_STAGED if mode == "staged" else dl.MODE_PERSISTENT)
+    seeds = workload.keygen_seeds(1, seed=170 + level)
+    opk, osk = oracle.keygen_batch(level, seeds)
+    msg, off = workload.messages(workload.fixed_lengths(1, 77), seed=171)
+    osig, _ = oracle.sign_batch(level, osk, msg, off)
+    sig = torch.zeros((1, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
+    gm, go = torch.from_numpy(msg).cuda(), torch.from_numpy(off.astype(np.int64)).cuda()
+    ctx.sign(level, torch.from_numpy(osk).cuda(), gm, go, sig)
+    v = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.verify(level, torch.from_numpy(opk).cuda(), gm, go, sig, v)
+    torch.cuda.synchronize()
+    assert np.array_equal(sig.cpu().numpy(), osig) and int(v.item()) == 1
+    ctx.close()
+
+
+def test_long_messages():
+    """64 KiB messages (482 SHAKE256 blocks for mu) next to empty ones, at level 3."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    level = 3
+    ctx = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    seeds = workload.keygen_seeds(4, seed=180)
+    opk, osk = oracle.keygen_batch(level, seeds)
+    lens = np.array([65536, 0, 65535, 1], dtype=np.int64)
+    msg, off = workload.messages(lens, seed=181)
+    osig, _ = oracle.sign_batch(level, osk, msg, off)
+    sig = torch.zeros((4, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
+    gm, go = torch.from_numpy(msg).cuda(), torch.from_numpy(off.astype(np.int64)).cuda()
+    ctx.sign(level, torch.from_numpy(osk).cuda(), gm, go, sig)
+    v = torch.zeros(4, dtype=torch.int32, device="cuda")
+    ctx.verify(level, torch.from_numpy(opk).cuda(), gm, go, sig, v)
+    torch.cuda.synchronize()
+    assert np.array_equal(sig.cpu().numpy(), osig)
+    assert v.cpu().tolist() == [1, 1, 1, 1]
+    ctx.close()
+
+
+def test_hundred_thousand_tasks():
+    """A batch ten times the benchmark's (workspace growth, queue and grid limits): sampled
+    outputs equal the oracle's and every signature verifies."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    level, n = 2, 100000
+    ctx = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    pkl, skl, sgl = dl.sizes(level)
+    seeds = workload.keygen_seeds(n, seed=190)
+    pk = torch.zeros((n, pkl), dtype=torch.uint8, device="cuda")
+    sk = torch.zeros((n, skl), dtype=torch.uint8, device="cuda")
+    ctx.keygen(level, torch.from_numpy(seeds).cuda(), pk, sk)
+    lens = workload.fixed_lengths(n, 32)
+    msg, off = workload.messages(lens, seed=190)
+    gm, go = torch.from_numpy(msg).cuda(), torch.from_numpy(off.astype(np.int64)).cuda()
+    sig = torch.zeros((n, sgl), dtype=torch.uint8, device="cuda")
+    ctx.sign(level, sk, gm, go, sig)
+    v = torch.zeros(n, dtype=torch.int32, device="cuda")
+    ctx.verify(level, pk, gm, go, sig, v)
+    torch.cuda.synchronize()
+    assert int(v.sum()) == n
+    idx = np.sort(np.random.default_rng(191).choice(n, size=24, replace=False))
+    osk = oracle.keygen_batch(level, seeds[idx])[1]
+    sub_msg = np.concatenate([msg[int(off[i]):int(off[i + 1])] for i in idx])
+    sub_off = np.concatenate([[0], np.cumsum(lens[idx])]).astype(np.uint64)
+    osig, _ = oracle.sign_batch(level, osk, sub_msg, sub_off)
+    assert np.array_equal(sig.cpu().numpy()[idx], osig)
+    ctx.close()
