@@ -98,14 +98,4 @@ __device__ __forceinline__ int32_t mont_reduce(int64_t a) {
 __device__ __forceinline__ int32_t mont_mul(int32_t a, int32_t b) { return mont_reduce((int64_t)a * b); }
 // canonical representative in [0, q) of x in (-q, q)
 __device__ __forceinline__ int32_t canon(int32_t x) { return x + ((x >> 31) & Q); }
-// full reduction of any int32 to [0, q): x - q*floor(x/q) via a float estimate refined once
-__device__ __forceinline__ int32_t reduce_full(int32_t x) {
-  int32_t qt = (int32_t)__builtin_floorf((float)x * (1.0f / (float)Q));
-  int32_t r = x - qt * Q;
-  r += (r >> 31) & Q;
-  r -= Q;
-  r += (r >> 31) & Q;
-  return r;
-}
-
 }  // namespace dil

@@ -155,35 +155,4 @@ __device__ __forceinline__ uint64_t load_le_bytes(const uint8_t *p, int n) {
   return v;
 }
 
-// XOR 8 bytes (as a 64-bit little-endian word) into state word `lane`
-__device__ __forceinline__ void xor_lane(uint32_t s[50], int lane, uint64_t v) {
-  // lane index is runtime here: select through an unrolled compare chain
-#pragma unroll
-  for (int i = 0; i < 25; i++) {
-    if (i == lane) {
-      s[2 * i] ^= (uint32_t)v;
-      s[2 * i + 1] ^= (uint32_t)(v >> 32);
-    }
-  }
-}
-
-// Absorb `len` bytes from `src` (any alignment) into a sponge of rate RATE,
-// starting at byte position `pos` (a multiple of 8) of the current block.
-// Returns the new position; permutes whenever a block fills.
-template <int RATE>
-__device__ __forceinline__ int absorb_bytes(uint32_t s[50], int pos, const uint8_t *src, uint64_t len) {
-  uint64_t i = 0;
-  while (i + 8 <= len) {
-    uint64_t v = load_le_bytes(src + i, 8);
-    xor_lane(s, pos >> 3, v);
-    pos += 8;
-    i += 8;
-    if (pos == RATE) {
-      keccak_f(s);
-      pos = 0;
-    }
-  }
-  return pos;  // caller handles the < 8 byte tail via absorb_tail
-}
-
 }  // namespace dil
