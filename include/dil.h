@@ -147,8 +147,11 @@ int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_id
  * plus message bytes per in-flight request) and max_batch, splits it by
  * (level, op) into dil_sign_keyset / dil_verify_keyset calls, and stages
  * messages, key indices and signatures through pinned buffers (max_msg_bytes
- * of message data per batch).  mode is DIL_MODE_STAGED or
- * DIL_MODE_PERSISTENT for Sign. */
+ * of message data per batch).  The (level, op) groups of a batch run
+ * concurrently, each on a stream and context of its own; that needs more
+ * hardware queues than HIP's default of 4 per process, so the process should
+ * set GPU_MAX_HW_QUEUES (e.g. 16) before HIP starts.  mode is
+ * DIL_MODE_STAGED or DIL_MODE_PERSISTENT for Sign. */
 typedef struct dil_server dil_server;
 int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset *ks3, dil_keyset *ks5,
                       int n_streams, uint32_t max_batch, size_t max_msg_bytes, size_t mem_budget, int mode);
@@ -175,8 +178,9 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
  * needs (sum over tasks of the winning iteration index + 1).  Synchronises. */
 int dil_sign_stats(dil_ctx *ctx, uint64_t *evaluated, uint64_t *sequential);
 
-/* Workgroups of the persistent Sign kernel the device keeps resident at once,
- * and candidate slots per workgroup batch (64 / l), for schedule tuning. */
+/* For the context's current "persist.waves" shape W: workgroups of the
+ * persistent Sign kernel the device keeps resident at once, and candidate
+ * slots per workgroup batch (W * (64 / l)), for schedule tuning. */
 int dil_persist_capacity(dil_ctx *ctx, int level, int *resident_groups, int *slots_per_batch);
 
 /* Event-measured durations (ms) of the most recent persistent dil_sign_batch
