@@ -5,7 +5,7 @@ task) followed by dil_verify_batch over the 10,000 signatures just produced,
 all buffers resident in HBM.  Keys are generated on the GPU before timing.
 Prints ONE JSON line (rank 0) with the roofline of the Sign loop kernel
 (algorithmic int32 lane-ops per launch over its HIP-event time, against the
-chip's 32-bit integer issue rate) and the CPU oracle's rate on a sample.
+chip's 32-bit integer issue rate) and the CPU oracle's rate on the same batch.
 
   python bench.py [--steps K] [--warmup W] [--mode persistent|staged]
                   [--count N] [--level 2|3|5] [--no-cpu-baseline]
@@ -113,33 +113,102 @@ def verify_work(level: int, msg_lens: np.ndarray) -> float:
     return perms * PERM_OPS + xf * XFORM_OPS + pw * PW_OPS
 
 
-def cpu_baseline(level: int, sample: int, gpu_check=None) -> dict:
-    """The CPU oracle timed on the host's cores on a bounded sample, and (gpu_check =
-    (sk rows, message bytes, offsets, GPU signatures) of a few tasks of the timed batch)
-    the byte-equality of those GPU signatures with the oracle's.  The only place the
-    benchmark runs the oracle."""
+def cpu_baseline(level: int, seeds, msg, off, msg_desc: str, gpu_sig, min_seconds: float) -> dict:
+    """The CPU oracle on the host's cores over the benchmark's own batch: the same keys (KeyGen from the
+    same seeds, untimed) and the same messages.  Sign and Verify of the whole batch are repeated until
+    min_seconds of wall time have passed and the median repetition gives the rate.  The oracle's
+    signatures are compared byte for byte with the GPU's signatures of the timed batch.  The only place
+    the benchmark runs the oracle."""
     import oracle
-    from paper_2211_12265_amd import workload
     threads = oracle.default_threads()
-    parity = None
-    if gpu_check is not None:
-        c_sk, c_msg, c_off, c_sig = gpu_check
-        osig, _ = oracle.sign_batch(level, c_sk, c_msg, c_off, nthreads=threads)
-        parity = bool(np.array_equal(c_sig, osig))
-    pk, sk = oracle.keygen_batch(level, workload.keygen_seeds(sample, seed=99), nthreads=threads)
-    msg, off = workload.messages(workload.fixed_lengths(sample, 32), seed=99)
-    t0 = time.perf_counter()
-    sig, _ = oracle.sign_batch(level, sk, msg, off, nthreads=threads)
-    t1 = time.perf_counter()
-    v = oracle.verify_batch(level, pk, msg, off, sig, nthreads=threads)
-    t2 = time.perf_counter()
-    assert int(v.sum()) == sample
-    sign_s, ver_s = t1 - t0, t2 - t1
-    return {"value": sample / (sign_s + ver_s), "unit": "sign+verify pairs/s", "cores": threads, "kind": "oracle",
-            "sign_per_s": sample / sign_s, "verify_per_s": sample / ver_s,
-            "wall_s": sign_s + ver_s, "timed_batch_parity_sampled": parity,
-            "sample": f"{sample} Dilithium{level} sign + {sample} verify, 32-byte messages, plain C oracle on "
-                      f"{threads} host threads ({sign_s + ver_s:.2f} s wall)"}
+    n = seeds.shape[0]
+    pk, sk = oracle.keygen_batch(level, seeds, nthreads=threads)
+    sign_t, ver_t, parity = [], [], None
+    start = time.perf_counter()
+    while True:
+        t0 = time.perf_counter()
+        sig, _ = oracle.sign_batch(level, sk, msg, off, nthreads=threads)
+        t1 = time.perf_counter()
+        v = oracle.verify_batch(level, pk, msg, off, sig, nthreads=threads)
+        t2 = time.perf_counter()
+        assert int(v.sum()) == n
+        if parity is None:
+            parity = bool(np.array_equal(sig, gpu_sig))
+        sign_t.append(t1 - t0)
+        ver_t.append(t2 - t1)
+        if t2 - start >= min_seconds:
+            break
+    sign_s, ver_s, wall = float(np.median(sign_t)), float(np.median(ver_t)), time.perf_counter() - start
+    return {"value": n / (sign_s + ver_s), "unit": "sign+verify pairs/s", "cores": threads, "kind": "oracle",
+            "sign_per_s": n / sign_s, "verify_per_s": n / ver_s, "repetitions": len(sign_t), "wall_s": wall,
+            "timed_batch_parity": parity,
+            "sample": f"the benchmark's whole batch ({n} Dilithium{level} sign + {n} verify, {msg_desc}, the same "
+                      f"keys and messages as the GPU run), repeated {len(sign_t)} times ({wall:.1f} s wall, median "
+                      f"repetition); plain C oracle on {threads} host threads"}
+
+
+NTT_FORMS = [(3, "unfused: NTT, pointwise, INTT as three launches through HBM"),
+             (2, "fused, one LDS round trip per butterfly level"),
+             (1, "fused, levels merged in registers, unpadded LDS transpose"),
+             (0, "fused, levels merged in registers, padded LDS transpose (production)")]
+
+
+def micro_run(steps: int, warmup: int) -> dict:
+    """The primitive workloads at 2^20 polynomials: c = INTT(NTT(a) o b) in each form of the
+    NTT optimisation ablation, ExpandA from 34-byte inputs, and a plain device copy of the
+    same size as the HBM ceiling actually reachable.  Median HIP-event time per call."""
+    import torch
+    from paper_2211_12265_amd import dilithium as dl
+    from paper_2211_12265_amd import workload
+    n = 1 << 20
+    ctx = dl.Context(0)
+    ga = torch.from_numpy(workload.uniform_polys(n, seed=0)).cuda()
+    gb = torch.from_numpy(workload.uniform_polys(n, seed=0, tag="dil/poly2")).cuda()
+    out = torch.empty((n, 256), dtype=torch.int32, device="cuda")
+    ref = torch.empty_like(out)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        ts = []
+        for _ in range(steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    res = {"polys": n}
+    copy_ms = timed(lambda: out.copy_(ga))
+    res["device_copy"] = {"ms": copy_ms, "GB_per_s": 2 * ga.numel() * 4 / copy_ms / 1e6}
+    ntt_bytes = 3 * 1024        # a and b read, c written: 1 KiB each per polynomial
+    ntt_ops = 2 * XFORM_OPS + PW_OPS
+    forms = []
+    for variant, name in NTT_FORMS:
+        ctx.set_param("ntt.variant", variant)
+        ms = timed(lambda: ctx.ntt_mul(ga, gb, out))
+        torch.cuda.synchronize()
+        if variant == 3:
+            ref.copy_(out)
+        forms.append({"variant": variant, "form": name, "ms": ms, "polys_per_s": n / ms * 1e3,
+                      "GB_per_s": n * ntt_bytes / ms / 1e6, "hbm_frac": n * ntt_bytes / ms / 1e6 / 8000.0,
+                      "alu_frac": n * ntt_ops / (ms / 1e3) / PEAK_INT32_OPS,
+                      "same_words_as_unfused": bool(torch.equal(out, ref))})
+    ctx.set_param("ntt.variant", 0)
+    res["ntt_mul"] = {"algorithmic_bytes_per_poly": ntt_bytes, "algorithmic_ops_per_poly": ntt_ops,
+                      "forms": forms}
+    del ga, gb, ref
+    seeds = torch.from_numpy(workload.expand_a_inputs(n, seed=0)).cuda()
+    ms = timed(lambda: ctx.expand_a(seeds, out))
+    ea_ops, ea_bytes = 5 * PERM_OPS, 34 + 1024
+    res["expand_a"] = {"ms": ms, "polys_per_s": n / ms * 1e3, "GB_per_s": n * ea_bytes / ms / 1e6,
+                       "hbm_frac": n * ea_bytes / ms / 1e6 / 8000.0,
+                       "alu_frac": n * ea_ops / (ms / 1e3) / PEAK_INT32_OPS,
+                       "algorithmic_bytes_per_poly": ea_bytes, "algorithmic_ops_per_poly": ea_ops}
+    ctx.close()
+    return res
 
 
 def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -> dict:
@@ -328,8 +397,8 @@ def main():
     ap.add_argument("--schedule", default="",
                     help="fixed persistent schedule 'waves,hmax,grid' (skips the autotuner)")
     ap.add_argument("--graph", type=int, default=1, help="replay Sign/Verify launch sequences as hipGraphs")
-    ap.add_argument("--cpu-sample", type=int, default=8192,
-                    help="tasks the CPU oracle signs and verifies for the baseline (about 15 thread-seconds at level 2)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="wall time over which the CPU oracle repeats Sign + Verify of the whole batch")
     ap.add_argument("--serving", action="store_true", help="also run the serving loop and report p50/p99")
     ap.add_argument("--serving-only", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=100000)
@@ -341,6 +410,9 @@ def main():
     ap.add_argument("--e2e", action="store_true",
                     help="also report PCIe-inclusive rates through the multi-stream host pipeline")
     ap.add_argument("--e2e-streams", default="1,2,4,8,12")
+    ap.add_argument("--micro", action="store_true",
+                    help="only time the primitive workloads (2^20-polynomial NTT product in each ablation form, "
+                         "ExpandA) and print them as one JSON line")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -359,6 +431,9 @@ def main():
               f"batch into one contiguous task range per GPU)", file=sys.stderr)
         sys.exit(2)
 
+    if args.micro:
+        print(json.dumps({"micro": micro_run(args.steps, args.warmup)}), flush=True)
+        return
     if args.ablation:
         print(json.dumps({"ablation": ablation_run(args.level, args.count, args.msg_dist),
                           "level": args.level, "batch": args.count, "msg_dist": args.msg_dist}), flush=True)
@@ -440,12 +515,9 @@ def main():
     ver_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
     evaluated, sequential = ctx.sign_stats()
 
-    # every signature of the timed batch verifies on the GPU; a sample of them is also compared
-    # byte for byte with the oracle's, in the CPU-baseline leg below
+    # every signature of the timed batch verifies on the GPU; the CPU-baseline leg below also
+    # compares all of them byte for byte with the oracle's
     all_verified = bool((ver == 1).all().item())
-    idx = np.random.default_rng(5).choice(n, size=32, replace=False)
-    gpu_check = (sk.cpu().numpy()[idx], np.concatenate([msg[int(off[i]):int(off[i + 1])] for i in idx]),
-                 np.concatenate([[0], np.cumsum(lens[idx])]).astype(np.uint64), sig.cpu().numpy()[idx])
 
     ms_per_step = wall * 1e3 / args.steps
     sign_rate = n / (np.median(sign_ms) * 1e-3)
@@ -471,14 +543,14 @@ def main():
         achieved = sign_work(level, lens, sequential) / (np.median(sign_ms) * 1e-3)
         kname = "dil_sign_batch (whole staged Sign call)"
         kextra = {}
+    msg_desc = "32-byte messages" if args.msg_dist == "fixed32" else "uniform 32-4096-byte messages"
     out = {
         "metric": "sign/s and verify/s, Dilithium2 batch 10k on 1 MI355X; p99 latency (serving)",
         "value": n / (ms_per_step * 1e-3),
         "unit": "sign+verify pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"Dilithium{level} batch {n} sign + {n} verify, "
-                               f"{'32-byte' if args.msg_dist == 'fixed32' else 'uniform 32-4096-byte'} messages, "
+        "config": {"workload": f"Dilithium{level} batch {n} sign + {n} verify, {msg_desc}, "
                                f"one key per task, device-resident buffers", "level": level, "batch": n,
                    "msg_len": 32 if args.msg_dist == "fixed32" else "uniform[32,4096]",
                    "sign_mode": args.mode, "hipgraph": bool(args.graph),
@@ -497,7 +569,8 @@ def main():
                           "kernel": kname}, **kextra),
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(level, args.cpu_sample, gpu_check)
+        out["cpu_baseline"] = cpu_baseline(level, seeds, msg, off, msg_desc,
+                                           sig.cpu().numpy(), args.cpu_seconds)
     if args.e2e:
         out["e2e_pcie_inclusive"] = e2e_run(level, n, args.msg_dist,
                                             [int(x) for x in args.e2e_streams.split(",") if x])

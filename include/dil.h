@@ -83,7 +83,16 @@ int dil_ctx_set_mode(dil_ctx *ctx, int mode);
  *                   of Verify into hipGraphs, replayed when a call repeats
  *                   the same level, buffers, count and schedule (up to 16
  *                   graphs per context, least recently used evicted; dropped
- *                   when the workspace grows). */
+ *                   when the workspace grows);
+ *   "ntt.variant"   form of dil_ntt_mul_batch, for the optimisation ablation
+ *                   of the NTT primitive (Sec. 3.2, Sec. 4.2); every form
+ *                   returns the same words: 0 (default) levels merged in
+ *                   registers with one padded LDS transpose per transform,
+ *                   1 the same transpose unpadded (bank conflicts), 2 one LDS
+ *                   round trip per butterfly level, 3 unfused (forward NTT,
+ *                   pointwise product and inverse NTT as three launches
+ *                   through HBM, c used as the intermediate); other values
+ *                   are DIL_EINVAL. */
 int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value);
 /* Grow the context's workspace (synchronously) so that any call with up to
  * `count` tasks at `level` runs without allocating -- serving loops reserve the
@@ -194,7 +203,8 @@ int dil_sign_timing(dil_ctx *ctx, float *setup_ms, float *loop_ms, int max_calls
 /* Primitive: c_i = INTT(NTT(a_i) o b_i) for count polynomials of 256
  * coefficients (Sec. 2.2), a and b canonical int32 in [0, q), b read as
  * NTT-domain values (slot j = evaluation at psi^(2 brv8(j)+1), psi = 1753);
- * c canonical.  Uses Montgomery arithmetic internally. */
+ * c canonical.  Uses Montgomery arithmetic internally.  a, b and c must be
+ * 16-byte aligned (DIL_EINVAL otherwise) and c must not overlap a or b. */
 int dil_ntt_mul_batch(dil_ctx *ctx, const int32_t *a, const int32_t *b, int32_t *c, uint64_t count, void *stream);
 
 /* Primitive: ExpandA rejection sampling (Sec. 2.3, Sec. 3.4) of count

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "../../include/dil.h"
+#include "ntt_ablation.h"
 #include "persist.h"
 
 using namespace dil;
@@ -26,6 +27,7 @@ struct dil_ctx {
   int64_t persist_grid = 0, persist_hmax = 0;  // 0 = automatic
   int persist_waves = 1;                       // wavefronts per persistent workgroup: 1, 2 or 4
   int timing = 0;                              // record HIP events around the persistent Sign phases
+  int ntt_variant = 0;                         // form of dil_ntt_mul_batch (0 = production kernel)
   static constexpr int RING = 64;
   hipEvent_t ev[RING][3] = {};                 // per timed call: before setup, before loop, after loop
   int ev_count = 0;                            // timed calls recorded since timing was (re)enabled
@@ -615,6 +617,9 @@ int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value) {
   else if (!strcmp(name, "persist.waves")) {
     if (value != 1 && value != 2 && value != 4) return fail(ctx, DIL_EINVAL, "persist.waves must be 1, 2 or 4");
     ctx->persist_waves = (int)value;
+  } else if (!strcmp(name, "ntt.variant")) {
+    if (value < 0 || value > 3) return fail(ctx, DIL_EINVAL, "ntt.variant must be 0..3");
+    ctx->ntt_variant = (int)value;
   }
   else return fail(ctx, DIL_EINVAL, "unknown parameter");
   return DIL_OK;
@@ -816,15 +821,29 @@ int dil_ntt_mul_batch(dil_ctx *ctx, const int32_t *a, const int32_t *b, int32_t 
   if (!ctx) return DIL_EINVAL;
   if (count == 0) return DIL_OK;
   if (!a || !b || !c) return fail(ctx, DIL_EINVAL, "null buffer");
+  if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) return fail(ctx, DIL_EINVAL, "buffers must be 16-byte aligned");
   hipSetDevice(ctx->device);
   if (!ctx->cu_count) {
     hipDeviceProp_t prop;
     HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
     ctx->cu_count = prop.multiProcessorCount;
   }
-  uint64_t need = (count + 15) / 16;
-  uint64_t grid = std::min<uint64_t>(need, (uint64_t)ctx->cu_count * 16);
-  ntt_mul_k<<<(unsigned)grid, 256, 0, (hipStream_t)stream>>>(a, b, c, count);
+  // 16 polynomials per 256-lane workgroup, grid-strided over at most 16 workgroups per CU
+  const uint64_t need = (count + 15) / 16;
+  const unsigned grid = (unsigned)std::min<uint64_t>(need, (uint64_t)ctx->cu_count * 16);
+  const hipStream_t st = (hipStream_t)stream;
+  switch (ctx->ntt_variant) {
+    case 0: ntt_mul_k<true><<<grid, 256, 0, st>>>(a, b, c, count); break;
+    case 1: ntt_mul_k<false><<<grid, 256, 0, st>>>(a, b, c, count); break;
+    case 2: ntt_mul_perlevel_k<<<grid, 256, 0, st>>>(a, b, c, count); break;
+    default: {
+      ntt_fwd_k<<<grid, 256, 0, st>>>(a, c, count);
+      const uint64_t words4 = count * (N / 4);
+      const unsigned pgrid = (unsigned)std::min<uint64_t>((words4 + 255) / 256, (uint64_t)ctx->cu_count * 16);
+      ntt_pointwise_k<<<pgrid, 256, 0, st>>>(c, b, words4);
+      ntt_inv_k<<<grid, 256, 0, st>>>(c, count);
+    }
+  }
   LAUNCHCHK(ctx);
   return DIL_OK;
 }

@@ -928,6 +928,8 @@ __global__ void __launch_bounds__(256) ks_tr_k(const uint8_t *pk, uint8_t *tr, u
 // ------------------------------------------------------------------------
 // c_i = INTT(NTT(a_i) o b_i): b read as NTT-domain values; canonical output.
 // 256-thread blocks, 16 polynomials per block per iteration, grid-stride.
+// PAD = false is the bank-conflicted transpose of the optimisation ablation.
+template <bool PAD>
 __global__ void __launch_bounds__(256) ntt_mul_k(const int32_t *a, const int32_t *b, int32_t *c, uint64_t count) {
   __shared__ int32_t trl[16 * NTT_LDS_GROUP];
   int g = threadIdx.x >> 4, t = threadIdx.x & 15;
@@ -937,10 +939,10 @@ __global__ void __launch_bounds__(256) ntt_mul_k(const int32_t *a, const int32_t
     int32_t x[16], y[16];
     load_strided(x, a + p * N, t);
     load_slots(y, b + p * N, t);
-    ntt16(x, ftw, tr, t);
+    ntt16<Tw, PAD>(x, ftw, tr, t);
 #pragma unroll
     for (int r = 0; r < 16; r++) x[r] = mont_mul(x[r], y[r]);
-    intt16(x, itw, tr, t);
+    intt16<Tw, PAD>(x, itw, tr, t);
 #pragma unroll
     for (int r = 0; r < 16; r++) x[r] = canon(x[r]);
     store_strided(x, c + p * N, t);

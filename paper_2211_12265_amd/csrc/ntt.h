@@ -42,7 +42,10 @@ __constant__ constexpr ZTab kZT = ZTab();
 
 constexpr int NTT_LDS_GROUP = 272;  // int32 words per 16-lane group
 
-__device__ __forceinline__ int lds_idx(int i) { return i + (i >> 4); }
+// PAD = false drops the pad word (the bank-conflicted layout, kept for the
+// optimisation ablation of the NTT primitive)
+template <bool PAD = true>
+__device__ __forceinline__ int lds_idx(int i) { return PAD ? i + (i >> 4) : i; }
 
 // An NTT-domain vector kept in LDS for pointwise products: polynomial j, lane
 // t, register r (slot 16 t + r) lives at j * HAT_POLY + 17 t + r.  With one pad
@@ -93,33 +96,35 @@ __device__ __forceinline__ void gs_bfly(int32_t &a, int32_t &b, int32_t zi) {
 }
 
 // strided -> slots within a group (lds points at the group's 272-word region)
+template <bool PAD = true>
 __device__ __forceinline__ void transpose_s2c(int32_t x[16], int32_t *lds, int t) {
 #pragma unroll
-  for (int r = 0; r < 16; r++) lds[lds_idx(t + 16 * r)] = x[r];
+  for (int r = 0; r < 16; r++) lds[lds_idx<PAD>(t + 16 * r)] = x[r];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-  for (int r = 0; r < 16; r++) x[r] = lds[lds_idx(16 * t + r)];
+  for (int r = 0; r < 16; r++) x[r] = lds[lds_idx<PAD>(16 * t + r)];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+template <bool PAD = true>
 __device__ __forceinline__ void transpose_c2s(int32_t x[16], int32_t *lds, int t) {
 #pragma unroll
-  for (int r = 0; r < 16; r++) lds[lds_idx(16 * t + r)] = x[r];
+  for (int r = 0; r < 16; r++) lds[lds_idx<PAD>(16 * t + r)] = x[r];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 #pragma unroll
-  for (int r = 0; r < 16; r++) x[r] = lds[lds_idx(t + 16 * r)];
+  for (int r = 0; r < 16; r++) x[r] = lds[lds_idx<PAD>(t + 16 * r)];
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Forward NTT: strided input -> slots output.
-template <class TW>
+template <class TW, bool PAD = true>
 __device__ __forceinline__ void ntt16(int32_t x[16], const TW &tw, int32_t *lds, int t) {
   // levels with distance 128, 64, 32, 16: register distance 8, 4, 2, 1, compile-time twiddles
 #pragma unroll
@@ -132,7 +137,7 @@ __device__ __forceinline__ void ntt16(int32_t x[16], const TW &tw, int32_t *lds,
     if ((r & 2) == 0) ct_bfly(x[r], x[r + 2], zeta_m(4 + r / 4));
 #pragma unroll
   for (int r = 0; r < 16; r += 2) ct_bfly(x[r], x[r + 1], zeta_m(8 + r / 2));
-  transpose_s2c(x, lds, t);
+  transpose_s2c<PAD>(x, lds, t);
   // distance 8, 4, 2, 1 inside the lane's 16 consecutive slots, lane-dependent twiddles
 #pragma unroll
   for (int r = 0; r < 8; r++) ct_bfly(x[r], x[r + 8], tw(0));
@@ -148,7 +153,7 @@ __device__ __forceinline__ void ntt16(int32_t x[16], const TW &tw, int32_t *lds,
 
 // Inverse NTT: slots input (|x| < q) -> strided output in (-q, q); removes the
 // 2^-32 of one Montgomery product and divides by 256.
-template <class TW>
+template <class TW, bool PAD = true>
 __device__ __forceinline__ void intt16(int32_t x[16], const TW &tw, int32_t *lds, int t) {
 #pragma unroll
   for (int r = 0; r < 16; r += 2) gs_bfly(x[r], x[r + 1], tw(r / 2));
@@ -160,7 +165,7 @@ __device__ __forceinline__ void intt16(int32_t x[16], const TW &tw, int32_t *lds
     if ((r & 4) == 0) gs_bfly(x[r], x[r + 4], tw(12 + r / 8));
 #pragma unroll
   for (int r = 0; r < 8; r++) gs_bfly(x[r], x[r + 8], tw(14));
-  transpose_c2s(x, lds, t);
+  transpose_c2s<PAD>(x, lds, t);
 #pragma unroll
   for (int r = 0; r < 16; r += 2) gs_bfly(x[r], x[r + 1], zinv_m(8 + r / 2));
 #pragma unroll

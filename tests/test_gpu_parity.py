@@ -46,6 +46,34 @@ def test_ntt_mul_parity(ctx, count):
     assert np.array_equal(c.cpu().numpy(), oracle.ntt_mul_batch(a, b))
 
 
+@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("count", [1, 17, 4096 + 13])
+def test_ntt_mul_ablation_forms(ctx, count, variant):
+    """The ablation forms of the NTT primitive (unpadded transpose, one LDS round trip per
+    level, unfused launches) against the oracle, including a ragged last workgroup."""
+    a = workload.uniform_polys(count, seed=count + 7)
+    b = workload.uniform_polys(count, seed=count + 7, tag="dil/poly2")
+    c = torch.zeros((count, 256), dtype=torch.int32, device="cuda")
+    ctx.set_param("ntt.variant", variant)
+    try:
+        ctx.ntt_mul(dev(a), dev(b), c)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_param("ntt.variant", 0)
+    assert np.array_equal(c.cpu().numpy(), oracle.ntt_mul_batch(a, b))
+
+
+def test_ntt_mul_rejects_bad_arguments(ctx):
+    from paper_2211_12265_amd import dilithium as dl
+    a = torch.zeros((9, 256), dtype=torch.int32, device="cuda")
+    c = torch.zeros((9, 256), dtype=torch.int32, device="cuda")
+    with pytest.raises(dl.DilError):
+        ctx.set_param("ntt.variant", 4)
+    with pytest.raises(dl.DilError):
+        ctx.ntt_mul(a.view(-1)[1:1 + 8 * 256].view(8, 256), a[:8], c[:8])   # 4-byte offset: misaligned
+    torch.cuda.synchronize()
+
+
 def test_ntt_mul_edge_values(ctx):
     q = oracle.Q
     a = np.stack([np.zeros(256, np.int32), np.full(256, q - 1, np.int32), np.eye(1, 256, 255, dtype=np.int32)[0],
