@@ -262,7 +262,7 @@ int keygen_impl(dil_ctx *ctx, const uint8_t *seeds, uint8_t *pk, uint8_t *sk, ui
   int rc = ws_carve<LV>(ctx, count, ws);
   if (rc) return rc;
   kg_seed_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(seeds, pk, sk, ws, count);
-  expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, st>>>(pk, P<LV>::PK, nullptr, ws.A, count);
+  expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, EA_WG), EA_WG, 0, st>>>(pk, P<LV>::PK, nullptr, ws.A, count);
   expand_s_k<LV><<<blocks_for((uint64_t)count * (K + L), 256), 256, 0, st>>>(ws, count);
   kg_main_k<LV><<<count, 64, 0, st>>>(ws, pk, sk, count);
   kg_tr_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(pk, sk, count);
@@ -298,7 +298,7 @@ int sign_setup(dil_ctx *ctx, Ws &ws, const uint8_t *sk, const uint32_t *key_idx,
   sg_prep_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, ws, count, err);
   if (!ks) {
     hipStream_t s1 = concurrent ? ctx->side[0] : st, s2 = concurrent ? ctx->side[1] : st;
-    expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, s1>>>(sk, P<LV>::SK, key_idx, ws.A, count);
+    expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, EA_WG), EA_WG, 0, s1>>>(sk, P<LV>::SK, key_idx, ws.A, count);
     sg_secret_k<LV><<<count, 64, 0, s2>>>(sk, key_idx, ws, count);
   }
   if (concurrent) return join_side(ctx, st);
@@ -440,7 +440,7 @@ int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const 
     vf_hash_k<LV><<<blocks_for(count, 64), 64, 0, s_hash>>>(pk, key_idx, msg, msg_off, ws, count,
                                                             ctx->dev_stats + 8);
     if (!ks)
-      expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, 256), 256, 0, s_ea>>>(pk, P<LV>::PK, key_idx, ws.A,
+      expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, EA_WG), EA_WG, 0, s_ea>>>(pk, P<LV>::PK, key_idx, ws.A,
                                                                                 count);
     vf_prep_k<LV><<<blocks_for(count, 64), 64, 0, s>>>(sig, ws, count);
     if (conc) {
@@ -452,7 +452,7 @@ int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const 
       int r2 = join_one(ctx, s, 1);
       if (r2) return r2;
     }
-    vf_final_k<LV><<<blocks_for(count, 256), 256, 0, s>>>(sig, ws, verdict, count);
+    vf_final_k<LV><<<blocks_for(2 * (uint64_t)count, 256), 256, 0, s>>>(sig, ws, verdict, count);
     LAUNCHCHK(ctx);
     return DIL_OK;
   });
@@ -494,16 +494,16 @@ int keyset_build(dil_ctx *ctx, dil_keyset *ks, const uint8_t *pk, const uint8_t 
     ks->t1h = (int32_t *)take(n * K * 1024);
     HIPCHK(ctx, hipMemcpyAsync(ks->pk, pk, n * PP::PK, hipMemcpyDeviceToDevice, st));
   }
-  unsigned nb = blocks_for(n * K * L, 256);
+  unsigned nb = blocks_for(n * K * L, EA_WG);
   if (sk) {
-    expand_a_k<LV><<<nb, 256, 0, st>>>(ks->sk, PP::SK, nullptr, ks->A, ks->nkeys);
+    expand_a_k<LV><<<nb, EA_WG, 0, st>>>(ks->sk, PP::SK, nullptr, ks->A, ks->nkeys);
     Ws w{};
     w.s1h = ks->s1h;
     w.s2h = ks->s2h;
     w.t0h = ks->t0h;
     sg_secret_k<LV><<<ks->nkeys, 64, 0, st>>>(ks->sk, nullptr, w, ks->nkeys);
   } else {
-    expand_a_k<LV><<<nb, 256, 0, st>>>(ks->pk, PP::PK, nullptr, ks->A, ks->nkeys);
+    expand_a_k<LV><<<nb, EA_WG, 0, st>>>(ks->pk, PP::PK, nullptr, ks->A, ks->nkeys);
   }
   if (pk) {
     ks_pk_k<LV><<<ks->nkeys, 64, 0, st>>>(ks->pk, ks->t1h, ks->nkeys);
@@ -853,7 +853,7 @@ int dil_expand_a_batch(dil_ctx *ctx, const uint8_t *seeds34, int32_t *out, uint6
   if (count == 0) return DIL_OK;
   if (!seeds34 || !out) return fail(ctx, DIL_EINVAL, "null buffer");
   hipSetDevice(ctx->device);
-  expand_a_seed_k<<<blocks_for(count, 256), 256, 0, (hipStream_t)stream>>>(seeds34, out, count);
+  expand_a_seed_k<<<blocks_for(count, EA_WG), EA_WG, 0, (hipStream_t)stream>>>(seeds34, out, count);
   LAUNCHCHK(ctx);
   return DIL_OK;
 }

@@ -10,6 +10,7 @@
 #include "ntt.h"
 #include "poly.h"
 #include "sponge.h"
+#include "keccak_pair.h"
 
 namespace dil {
 
@@ -97,51 +98,52 @@ __global__ void __launch_bounds__(256) kg_seed_k(const uint8_t *seeds, uint8_t *
 // out0 + l * N.  rows: 64 * EA_ROW words of LDS for this wavefront.  Lanes
 // with valid = false run the permutations but store nothing.
 constexpr int EA_ROW = RATE128 / 4 + 1;  // 43 words: odd stride, conflict-free staging
+constexpr int EA_STEP = 4;                // unfinished streams tested per step
+constexpr int EA_WG = 64;                 // one wavefront per workgroup (11 KiB of LDS)
 
 __device__ __forceinline__ void expand_a_squeeze_wave(uint32_t s[50], int32_t *out0, uint32_t *rows, int lane,
                                                       bool valid) {
   int ctr = valid ? 0 : N;
   uint32_t *row = rows + lane * EA_ROW;
+  // lane l < 56 tests candidate l of a block: bytes 3l .. 3l + 2, inside words
+  // wi and wi + 1 of the staged row; the other lanes read word 0 and test nothing
+  const bool cand = lane < RATE128 / 3;
+  const int wi = cand ? (3 * lane) >> 2 : 0;
+  const uint32_t sh = cand ? 8u * (uint32_t)((3 * lane) & 3) : 0u;
   for (;;) {
 #pragma unroll
     for (int w = 0; w < RATE128 / 4; w++) row[w] = s[w];
     wave_sync();
-    // up to four unfinished streams per step, so that their LDS reads and
-    // ballots overlap instead of forming one dependent chain per stream
+    // up to EA_STEP unfinished streams per step; the step is branch-free up to
+    // the stores, so that its LDS reads, ballots and counter reads overlap
     uint64_t pending = __ballot(ctr < N);
-    const int b3 = 3 * lane;
     while (pending) {
-      int Ls[4];
-      bool act[4];
+      int Ls[EA_STEP];
+      bool act[EA_STEP];
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
+      for (int u = 0; u < EA_STEP; u++) {
         act[u] = pending != 0;
         Ls[u] = act[u] ? __builtin_ctzll(pending) : 0;
         pending &= pending - 1;
       }
-      uint32_t tv[4];
-      bool ok[4];
+      uint32_t tv[EA_STEP];
+      bool ok[EA_STEP];
+      int cL[EA_STEP];
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
+      for (int u = 0; u < EA_STEP; u++) {
         const uint32_t *rL = rows + Ls[u] * EA_ROW;
-        tv[u] = 0;
-        ok[u] = false;
-        if (act[u] && lane < RATE128 / 3) {  // word (b3 >> 2) + 1 is at most 42, the row's pad word
-          tv[u] = __builtin_amdgcn_alignbit(rL[(b3 >> 2) + 1], rL[b3 >> 2], 8 * (b3 & 3)) & 0x7FFFFFu;
-          ok[u] = tv[u] < (uint32_t)Q;
-        }
+        tv[u] = __builtin_amdgcn_alignbit(rL[wi + 1], rL[wi], sh) & 0x7FFFFFu;
+        ok[u] = act[u] && cand && tv[u] < (uint32_t)Q;
+        cL[u] = __builtin_amdgcn_readlane(ctr, Ls[u]);  // the streams' lanes are distinct
       }
 #pragma unroll
-      for (int u = 0; u < 4; u++) {
+      for (int u = 0; u < EA_STEP; u++) {
         if (!act[u]) continue;  // wave-uniform
-        const int L = Ls[u];
-        const int cL = __builtin_amdgcn_readlane(ctr, L);
         const uint64_t m = __ballot(ok[u]);
         const int pos =
-            cL + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if (ok[u] && pos < N) out0[(size_t)L * N + pos] = (int32_t)tv[u];
-        const int nL = min(N, cL + (int)__popcll(m));
-        if (lane == L) ctr = nL;
+            cL[u] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        if (ok[u] && pos < N) out0[(size_t)Ls[u] * N + pos] = (int32_t)tv[u];
+        if (lane == Ls[u]) ctr = min(N, cL[u] + (int)__popcll(m));
       }
     }
     wave_sync();
@@ -151,11 +153,11 @@ __device__ __forceinline__ void expand_a_squeeze_wave(uint32_t s[50], int32_t *o
 }
 
 template <int LV>
-__global__ void __launch_bounds__(256) expand_a_k(const uint8_t *rho_src, size_t rho_stride, const uint32_t *key_idx,
+__global__ void __launch_bounds__(EA_WG) expand_a_k(const uint8_t *rho_src, size_t rho_stride, const uint32_t *key_idx,
                                                   int32_t *A, uint32_t count) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
   uint64_t st = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  __shared__ uint32_t rows[4][64 * EA_ROW];
+  __shared__ uint32_t rows[EA_WG / 64][64 * EA_ROW];
   const bool valid = st < (uint64_t)count * K * L;
   const uint64_t sl = valid ? st : 0;  // spare lanes absorb stream 0 and store nothing
   uint32_t task = (uint32_t)(sl / (K * L));
@@ -864,22 +866,22 @@ __global__ void __launch_bounds__(64) vf_main_k(const uint8_t *pk, const uint32_
   if (lane == 0 && bad) ws.flag[task] = 0;
 }
 
-// ctilde' = H(mu || w1'), verdict
+// ctilde' = H(mu || w1'), verdict; two lanes per task (keccak_pair.h), the
+// even lane writing the verdict
 template <int LV>
 __global__ void __launch_bounds__(256) vf_final_k(const uint8_t *sig, Ws ws, int32_t *verdict, uint32_t count) {
-  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
+  const uint32_t t = (uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1);
+  const int half = threadIdx.x & 1;
+  if (t >= count) return;  // both lanes of a pair
   const uint8_t *row = ws.muw1 + (size_t)t * muw1_stride<LV>();
-  uint32_t s[50];
-  shake_absorb<RATE256>(s, P<LV>::MUW1, [&](uint64_t pos) { return *(const uint64_t *)(row + pos); });
+  uint32_t a[25];
+  shake256_absorb_pair<P<LV>::MUW1>(a, half, [&](int pos) { return *(const uint32_t *)(row + pos + 4 * half); });
   const uint8_t *sg = sig + (size_t)t * P<LV>::SIG;
-  bool eq = true;
+  uint32_t diff = 0;
 #pragma unroll
-  for (int w = 0; w < 4; w++) {
-    uint64_t v = load_le_bytes(sg + 8 * w, 8);
-    eq &= ((uint32_t)v == s[2 * w]) && ((uint32_t)(v >> 32) == s[2 * w + 1]);
-  }
-  verdict[t] = (ws.flag[t] && eq) ? 1 : 0;
+  for (int w = 0; w < 4; w++) diff |= (uint32_t)load_le_bytes(sg + 8 * w + 4 * half, 4) ^ a[w];
+  diff |= pair_swap(diff);
+  if (!half) verdict[t] = (ws.flag[t] && diff == 0) ? 1 : 0;
 }
 
 // ------------------------------------------------------------------------
@@ -950,9 +952,9 @@ __global__ void __launch_bounds__(256) ntt_mul_k(const int32_t *a, const int32_t
 }
 
 // ExpandA rejection sampling of one polynomial per lane from a 34-byte input
-__global__ void __launch_bounds__(256) expand_a_seed_k(const uint8_t *seeds, int32_t *out, uint64_t count) {
+__global__ void __launch_bounds__(EA_WG) expand_a_seed_k(const uint8_t *seeds, int32_t *out, uint64_t count) {
   uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  __shared__ uint32_t rows[4][64 * EA_ROW];
+  __shared__ uint32_t rows[EA_WG / 64][64 * EA_ROW];
   const bool valid = p < count;
   const uint8_t *sd = seeds + 34 * (valid ? p : 0);
   uint32_t s[50];

@@ -105,7 +105,7 @@ struct PersistLds {
     } wp;
     CheckLds<LV> ck;
   } u;
-  int8_t c[PCfg<LV>::G][N];
+  int8_t c[PCfg<LV>::G][N + 4];  // + 4 bytes: the rows start on different banks
   uint32_t ct[PCfg<LV>::G][8];
   uint32_t bb[PCfg<LV>::G][RATE256 / 4];
   uint32_t h_task[PCfg<LV>::G], h_next[PCfg<LV>::G], h_win[PCfg<LV>::G];
@@ -181,11 +181,12 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
     }
     wave_sync_global();
     PHASE_MARK(2);
-    // ---- ctilde and SampleInBall: one lane per slot ----
-    if (lane < ns) {
-      uint32_t task = lds.h_task[lds.s_h[lane]];
-      dev_challenge<LV>(ws.muw1 + (size_t)task * muw1_stride<LV>(), w1b + lane * w1_stride<LV>(), lds.ct[lane],
-                        lds.c[lane], (uint8_t *)lds.bb[lane]);
+    // ---- ctilde and SampleInBall: two lanes per slot ----
+    if ((lane >> 1) < ns) {
+      const int s = lane >> 1;
+      uint32_t task = lds.h_task[lds.s_h[s]];
+      dev_challenge_pair<LV>(ws.muw1 + (size_t)task * muw1_stride<LV>(), w1b + s * w1_stride<LV>(), lane & 1,
+                             lds.ct[s], lds.c[s], lds.bb[s]);
     }
     wave_sync();
     PHASE_MARK(3);
@@ -236,11 +237,10 @@ namespace dil {
 // Multi-wavefront variant (W = 2 or 4 wavefronts per workgroup).  A workgroup
 // holds W * (64 / l) slots per batch.  ExpandMask uses one thread per stream
 // over all W waves; w and the checks run per slot, wave w taking slots w,
-// w + W, ...; the challenge hashes of all slots (at most 64) run on ONE wave,
-// so that phase keeps its lanes busy (the single-wave kernel hashes 64/l
-// challenges on 64 lanes) while the other W - 1 waves wait at the barrier.
-// Which wave hashes rotates with the workgroup and batch index so the SIMDs
-// stay balanced.  Passing candidates are staged per slot and the smallest
+// w + W, ...; the challenge hashes run on two lanes per slot (keccak_pair.h),
+// slots 0..31 on one wave and the rest (at most 32) on the next, while the
+// other waves wait at the barrier.  Which waves hash rotates with the
+// workgroup and batch index so the SIMDs stay balanced.  Passing candidates are staged per slot and the smallest
 // passing nonce of each task is copied to the output after a barrier.
 // ---------------------------------------------------------------------------
 template <int LV, int NW>
@@ -260,7 +260,7 @@ struct PersistWLds {
     } wp;
     CheckLds<LV> ck;
   } u[NW];
-  int8_t c[PCfgW<LV, NW>::G][N];
+  int8_t c[PCfgW<LV, NW>::G][N + 4];  // + 4 bytes: the rows start on different banks
   uint32_t ct[PCfgW<LV, NW>::G][8];
   uint32_t bb[PCfgW<LV, NW>::G][RATE256 / 4];
   uint32_t h_task[PCfgW<LV, NW>::G], h_next[PCfgW<LV, NW>::G], h_win[PCfgW<LV, NW>::G];
@@ -371,11 +371,15 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
     __threadfence_block();
     __syncthreads();
     PHASE_MARK(2);
-    // challenges of all slots on one (rotating) wave
-    if (wave == (int)((wg + batch) % W) && lane < ns) {
-      uint32_t task = lds.h_task[lds.s_h[lane]];
-      dev_challenge<LV>(ws.muw1 + (size_t)task * muw1_stride<LV>(), w1b + lane * w1_stride<LV>(), lds.ct[lane],
-                        lds.c[lane], (uint8_t *)lds.bb[lane]);
+    // challenges, two lanes per slot: slots 0..31 on the batch's first
+    // (rotating) wave, slots 32.. on the next one
+    {
+      const int s = (wave - (int)((wg + batch) % W) + W) % W * 32 + (lane >> 1);
+      if (s < ns) {
+        uint32_t task = lds.h_task[lds.s_h[s]];
+        dev_challenge_pair<LV>(ws.muw1 + (size_t)task * muw1_stride<LV>(), w1b + s * w1_stride<LV>(), lane & 1,
+                               lds.ct[s], lds.c[s], lds.bb[s]);
+      }
     }
     __syncthreads();
     PHASE_MARK(3);
