@@ -348,7 +348,7 @@ __global__ void __launch_bounds__(64) sg_secret_k(const uint8_t *sk, const uint3
   // stage sk bytes 96..SK into LDS (sk rows are 8-byte aligned)
   const uint32_t *skw = (const uint32_t *)(skr + 96);
   constexpr int NW = (PP::SK - 96) / 4;
-  for (int w = lane; w < NW; w += 64) lds.buf[w] = skw[w];
+  g2l_words<NW>(skw, lds.buf, lane);
   if (lane < 2) lds.buf[NW + lane] = 0;
   wave_sync();
   const Tw ftw = ntt_lane_tw(t);
@@ -631,10 +631,21 @@ __global__ void __launch_bounds__(64) sg_w_k(Ws ws, const uint32_t *active, uint
   (void)PP::K;
 }
 
+// One lane's dense challenge in LDS: rows of C_ROW bytes (65 words), so that
+// the lanes of a wavefront writing the same coefficient index hit 64
+// different banks; copied out to a 16-byte aligned global row.
+constexpr int C_ROW = N + 4;
+__device__ __forceinline__ void store_c_row(const int8_t *c, int8_t *dst) {
+  const uint32_t *cw = (const uint32_t *)c;
+  int4 *d = (int4 *)dst;
+#pragma unroll
+  for (int w = 0; w < N / 16; w++) d[w] = make_int4(cw[4 * w], cw[4 * w + 1], cw[4 * w + 2], cw[4 * w + 3]);
+}
+
 // ctilde = H(mu || w1); c = SampleInBall(ctilde).  One lane per active task.
 template <int LV>
 __global__ void __launch_bounds__(64) sg_chal_k(Ws ws, const uint32_t *active, uint32_t nactive) {
-  __shared__ int8_t cl[64][N];
+  __shared__ int8_t cl[64][C_ROW];
   __shared__ uint32_t bb[64][RATE256 / 4];
   uint32_t a = blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= nactive) return;
@@ -642,10 +653,7 @@ __global__ void __launch_bounds__(64) sg_chal_k(Ws ws, const uint32_t *active, u
   int8_t *c = cl[threadIdx.x];
   const uint8_t *row = ws.muw1 + (size_t)task * muw1_stride<LV>();
   dev_challenge<LV>(row, row + 64, (uint32_t *)(ws.ctilde + (size_t)task * 32), c, (uint8_t *)bb[threadIdx.x]);
-  int4 *dst = (int4 *)(ws.cpoly + (size_t)task * N);
-  const int4 *src = (const int4 *)c;
-#pragma unroll
-  for (int w = 0; w < N / 16; w++) dst[w] = src[w];
+  store_c_row(c, ws.cpoly + (size_t)task * N);
 }
 
 // checks; accept -> signature row of the task, reject -> kappa += l and next round
@@ -710,7 +718,7 @@ __global__ void __launch_bounds__(64) vf_prep_k(const uint8_t *sig, Ws ws, uint3
   constexpr int K = Lv<LV>::K, OMEGA = Lv<LV>::OMEGA;
   constexpr int HB = OMEGA + K;        // hint section bytes
   constexpr int HMW = K * 8 + 1;       // mask words per lane (+1: odd stride)
-  __shared__ int8_t cl[64][N];
+  __shared__ int8_t cl[64][C_ROW];
   __shared__ uint32_t bb[64][RATE256 / 4];
   __shared__ uint8_t hbl[64][HB];
   __shared__ uint32_t hml[64][HMW];
@@ -735,10 +743,7 @@ __global__ void __launch_bounds__(64) vf_prep_k(const uint8_t *sig, Ws ws, uint3
   keccak_f(s);
   int8_t *c = cl[threadIdx.x];
   sample_in_ball<Lv<LV>::TAU>(s, c, (uint8_t *)bb[threadIdx.x]);
-  int4 *dst = (int4 *)(ws.cpoly + (size_t)t * N);
-  const int4 *src = (const int4 *)c;
-#pragma unroll
-  for (int w = 0; w < N / 16; w++) dst[w] = src[w];
+  store_c_row(c, ws.cpoly + (size_t)t * N);
   // strict hint decoding into bit masks (built in LDS, then stored row-wise)
   uint32_t *hml_t = hml[threadIdx.x];
 #pragma unroll
@@ -782,11 +787,11 @@ __global__ void __launch_bounds__(64) vf_main_k(const uint8_t *pk, const uint32_
   int lane = threadIdx.x, g = lane >> 4, t = lane & 15;
   int32_t *tr = trl + g * NTT_LDS_GROUP;
   size_t key = key_idx ? key_idx[task] : task;
-  g2l_bytes(sig + (size_t)task * PP::SIG, PP::SIG, sigw, lane, 64);
+  g2l_bytes<PP::SIG>(sig + (size_t)task * PP::SIG, sigw, lane);
   if (lane < 2) sigw[PP::SIG / 4 + 1 + lane] = 0;
   if (!ws.t1h) {
     const uint32_t *pkg = (const uint32_t *)(pk + key * PP::PK);
-    for (int w = lane; w < PP::PK / 4; w += 64) pkw[w] = pkg[w];
+    g2l_words<PP::PK / 4>(pkg, pkw, lane);
     if (lane < 2) pkw[PP::PK / 4 + lane] = 0;
   }
   wave_sync();
@@ -898,7 +903,7 @@ __global__ void __launch_bounds__(64) ks_pk_k(const uint8_t *pk, int32_t *t1h, u
   if (key >= nkeys) return;
   int lane = threadIdx.x, g = lane >> 4, t = lane & 15;
   const uint32_t *pkg = (const uint32_t *)(pk + (size_t)key * PP::PK);
-  for (int w = lane; w < PP::PK / 4; w += 64) pkw[w] = pkg[w];
+  g2l_words<PP::PK / 4>(pkg, pkw, lane);
   if (lane < 2) pkw[PP::PK / 4 + lane] = 0;
   wave_sync();
   const Tw ftw = ntt_lane_tw(t);

@@ -105,7 +105,7 @@ struct PersistLds {
     } wp;
     CheckLds<LV> ck;
   } u;
-  int8_t c[PCfg<LV>::G][N + 4];  // + 4 bytes: the rows start on different banks
+  int8_t c[PCfg<LV>::G][C_ROW];
   uint32_t ct[PCfg<LV>::G][8];
   uint32_t bb[PCfg<LV>::G][RATE256 / 4];
   uint32_t h_task[PCfg<LV>::G], h_next[PCfg<LV>::G], h_win[PCfg<LV>::G];
@@ -260,7 +260,7 @@ struct PersistWLds {
     } wp;
     CheckLds<LV> ck;
   } u[NW];
-  int8_t c[PCfgW<LV, NW>::G][N + 4];  // + 4 bytes: the rows start on different banks
+  int8_t c[PCfgW<LV, NW>::G][C_ROW];
   uint32_t ct[PCfgW<LV, NW>::G][8];
   uint32_t bb[PCfgW<LV, NW>::G][RATE256 / 4];
   uint32_t h_task[PCfgW<LV, NW>::G], h_next[PCfgW<LV, NW>::G], h_win[PCfgW<LV, NW>::G];

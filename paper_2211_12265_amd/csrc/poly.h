@@ -58,26 +58,51 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // ---- byte movement between global memory and LDS ----
-// Copy nbytes from global (any alignment) into LDS words (4-aligned, zero-padded
-// to a whole word).  Only aligned global words that contain a requested byte are read.
-__device__ __forceinline__ void g2l_bytes(const uint8_t *g, int nbytes, uint32_t *lw, int lane, int nlanes) {
-  uintptr_t base = (uintptr_t)g;
-  int mis = (int)(base & 3);
+// Copy NB bytes from global (any alignment) into LDS words (4-aligned,
+// zero-padded to a whole word) with one wavefront.  Only aligned global words
+// that contain a requested byte are read, and every lane issues all of its
+// loads before its first LDS store: one memory round trip for the whole copy.
+template <int NB>
+__device__ __forceinline__ void g2l_bytes(const uint8_t *g, uint32_t *lw, int lane) {
+  constexpr int NWD = (NB + 3) / 4, PER = (NWD + 63) / 64;
+  const uintptr_t base = (uintptr_t)g;
+  const int mis = (int)(base & 3);
   const uint32_t *gw = (const uint32_t *)(base - mis);
-  int nw = (nbytes + 3) >> 2;
-  uintptr_t last_word = (base + nbytes - 1) >> 2;  // aligned word index of the last valid byte
-  for (int i = lane; i < nw; i += nlanes) {
-    uint32_t lo = gw[i];
-    uint32_t v;
-    if (mis == 0) {
-      v = lo;
-    } else {
-      uint32_t hi = (((uintptr_t)(gw + i + 1)) >> 2) <= last_word ? gw[i + 1] : 0u;
-      v = __builtin_amdgcn_alignbit(hi, lo, 8 * mis);
+  const uintptr_t last_word = (base + NB - 1) >> 2;  // aligned word index of the last valid byte
+  uint32_t lo[PER], hi[PER];
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const int i = lane + 64 * q;
+    const bool in = i < NWD;
+    lo[q] = in ? gw[i] : 0u;
+    hi[q] = in && mis && (((uintptr_t)(gw + i + 1)) >> 2) <= last_word ? gw[i + 1] : 0u;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const int i = lane + 64 * q;
+    if (i < NWD) {
+      uint32_t v = mis ? __builtin_amdgcn_alignbit(hi[q], lo[q], 8 * mis) : lo[q];
+      const int rem = NB - 4 * i;
+      if (rem < 4) v &= (1u << (8 * rem)) - 1u;
+      lw[i] = v;
     }
-    int rem = nbytes - 4 * i;
-    if (rem < 4) v &= (1u << (8 * rem)) - 1u;
-    lw[i] = v;
+  }
+}
+// Copy NW aligned 32-bit words from global into LDS with one wavefront, all
+// loads issued before the first store.
+template <int NW>
+__device__ __forceinline__ void g2l_words(const uint32_t *g, uint32_t *l, int lane) {
+  constexpr int PER = (NW + 63) / 64;
+  uint32_t v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const int i = lane + 64 * q;
+    v[q] = i < NW ? g[i] : 0u;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; q++) {
+    const int i = lane + 64 * q;
+    if (i < NW) l[i] = v[q];
   }
 }
 // Copy nbytes of LDS (starting at a 4-aligned LDS byte address) to global (any alignment).
