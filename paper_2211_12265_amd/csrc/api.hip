@@ -295,7 +295,7 @@ int sign_setup(dil_ctx *ctx, Ws &ws, const uint8_t *sk, const uint32_t *key_idx,
     int rc = fork_side(ctx, st);
     if (rc) return rc;
   }
-  sg_prep_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, ws, count, err);
+  sg_prep_k<LV><<<blocks_for(2 * (uint64_t)count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, ws, count, err);
   if (!ks) {
     hipStream_t s1 = concurrent ? ctx->side[0] : st, s2 = concurrent ? ctx->side[1] : st;
     expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, EA_WG), EA_WG, 0, s1>>>(sk, P<LV>::SK, key_idx, ws.A, count);
@@ -437,7 +437,7 @@ int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const 
       if (r2) return r2;
     }
     hipStream_t s_hash = conc ? ctx->side[1] : s, s_ea = conc ? ctx->side[0] : s;
-    vf_hash_k<LV><<<blocks_for(count, 64), 64, 0, s_hash>>>(pk, key_idx, msg, msg_off, ws, count,
+    vf_hash_k<LV><<<blocks_for(2 * (uint64_t)count, 64), 64, 0, s_hash>>>(pk, key_idx, msg, msg_off, ws, count,
                                                             ctx->dev_stats + 8);
     if (!ks)
       expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, EA_WG), EA_WG, 0, s_ea>>>(pk, P<LV>::PK, key_idx, ws.A,

@@ -292,45 +292,51 @@ __global__ void __launch_bounds__(256) kg_tr_k(const uint8_t *pk, uint8_t *sk, u
 // ------------------------------------------------------------------------
 // Sign (Alg. 2), staged
 // ------------------------------------------------------------------------
-// mu = H(tr || M), rho' = H(K || mu); initialises kappa and the active list
+// mu = H(tr || M), rho' = H(K || mu) on two lanes per task (keccak_pair.h);
+// initialises kappa and the active list
 template <int LV>
 __global__ void __launch_bounds__(256) sg_prep_k(const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                                                  const uint64_t *msg_off, Ws ws, uint32_t count, uint32_t *err) {
-  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
+  // the longest dependent chain of the Sign setup (up to ~30 permutations per
+  // task for 4 KiB messages), sharing the CUs with ExpandA and the secret NTTs
+  // launched beside it: its waves issue first
+  __builtin_amdgcn_s_setprio(3);
+  const uint32_t t = (uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1);
+  const int half = threadIdx.x & 1;
+  if (t >= count) return;  // both lanes of a pair
   size_t key = key_idx ? key_idx[t] : t;
   const uint8_t *skr = sk + key * P<LV>::SK;
   uint64_t o0 = msg_off[t], o1 = msg_off[t + 1];
   uint64_t mlen = 0;
   if (o1 >= o0) mlen = o1 - o0;
-  else atomicOr(err, 1u);  // decreasing msg_off: message treated as empty
-  uint32_t s[50];
+  else if (!half) atomicOr(err, 1u);  // decreasing msg_off: message treated as empty
+  uint32_t a[25];
   uint32_t trw[8];
   const uint32_t *skw = (const uint32_t *)(skr + 64);  // tr inside the 8-byte aligned sk row
 #pragma unroll
   for (int i = 0; i < 8; i++) trw[i] = skw[i];
-  absorb_tr_msg(s, trw, msg + o0, mlen);
-  uint32_t mu[16];
-#pragma unroll
-  for (int i = 0; i < 16; i++) mu[i] = s[i];
+  absorb_tr_msg(a, half, trw, msg + o0, mlen);
+  uint32_t mu[8];  // this lane's halves of mu's eight 8-byte words
   uint32_t *muw = (uint32_t *)(ws.muw1 + (size_t)t * muw1_stride<LV>());
 #pragma unroll
-  for (int i = 0; i < 16; i++) muw[i] = mu[i];
+  for (int i = 0; i < 8; i++) {
+    mu[i] = a[i];
+    muw[2 * i + half] = a[i];
+  }
   // rho' = H(K || mu): 96 bytes, one block
-  keccak_zero(s);
   const uint32_t *Kw = (const uint32_t *)(skr + 32);
 #pragma unroll
-  for (int i = 0; i < 8; i++) s[i] = Kw[i];
-#pragma unroll
-  for (int i = 0; i < 16; i++) s[8 + i] = mu[i];
-  s[24] ^= 0x1Fu;
-  s[2 * (RATE256 / 8 - 1) + 1] ^= 0x80u << 24;
-  keccak_f(s);
+  for (int i = 0; i < 25; i++) a[i] = i < 4 ? Kw[2 * i + half] : i < 12 ? mu[i - 4] : 0u;
+  if (!half) a[12] ^= 0x1Fu;
+  else a[RATE256 / 8 - 1] ^= 0x80u << 24;
+  keccak_f_pair(a, half);
   uint32_t *rp = (uint32_t *)(ws.rhop + (size_t)t * 64);
 #pragma unroll
-  for (int i = 0; i < 16; i++) rp[i] = s[i];
-  ws.kappa[t] = 0;
-  ws.active0[t] = t;
+  for (int i = 0; i < 8; i++) rp[2 * i + half] = a[i];
+  if (!half) {
+    ws.kappa[t] = 0;
+    ws.active0[t] = t;
+  }
 }
 
 // NTT of the secret vectors s1, s2, t0 unpacked from sk
@@ -681,34 +687,42 @@ __global__ void __launch_bounds__(64) sg_check_k(Ws ws, uint8_t *sig, const uint
 // ------------------------------------------------------------------------
 // Verify (Alg. 3), staged
 // ------------------------------------------------------------------------
-// tr = H(pk) (unless resident) and mu = H(tr || M), one lane per task
+// tr = H(pk) (unless resident) and mu = H(tr || M), two lanes per task
+// (keccak_pair.h)
 template <int LV>
 __global__ void __launch_bounds__(64) vf_hash_k(const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
                                                 const uint64_t *msg_off, Ws ws, uint32_t count, uint32_t *err) {
   using PP = P<LV>;
-  uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= count) return;
+  __builtin_amdgcn_s_setprio(3);  // the long hash chain of Verify, beside ExpandA: its waves issue first
+  const uint32_t t = (uint32_t)(((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 1);
+  const int half = threadIdx.x & 1;
+  if (t >= count) return;  // both lanes of a pair
   size_t key = key_idx ? key_idx[t] : t;
-  uint32_t s[50];
+  uint32_t a[25];
   uint32_t trw[8];
   if (ws.tr) {
     const uint32_t *tg = (const uint32_t *)(ws.tr + key * 32);
 #pragma unroll
     for (int i = 0; i < 8; i++) trw[i] = tg[i];
   } else {
-    const uint8_t *pkr = pk + key * PP::PK;
-    shake_absorb<RATE256>(s, PP::PK, [&](uint64_t pos) { return *(const uint64_t *)(pkr + pos); });
+    const uint32_t *pkr = (const uint32_t *)(pk + key * PP::PK);
+    shake256_absorb_pair<PP::PK>(a, half, [&](int pos) { return pkr[pos / 4 + half]; });
+    // both lanes need all of tr: the partner's halves come over the DPP swap
 #pragma unroll
-    for (int i = 0; i < 8; i++) trw[i] = s[i];
+    for (int i = 0; i < 4; i++) {
+      const uint32_t other = pair_swap(a[i]);
+      trw[2 * i] = half ? other : a[i];
+      trw[2 * i + 1] = half ? a[i] : other;
+    }
   }
   uint64_t o0 = msg_off[t], o1 = msg_off[t + 1];
   uint64_t mlen = 0;
   if (o1 >= o0) mlen = o1 - o0;
-  else atomicOr(err, 1u);  // decreasing msg_off: message treated as empty
-  absorb_tr_msg(s, trw, msg + o0, mlen);
+  else if (!half) atomicOr(err, 1u);  // decreasing msg_off: message treated as empty
+  absorb_tr_msg(a, half, trw, msg + o0, mlen);
   uint32_t *muw = (uint32_t *)(ws.muw1 + (size_t)t * muw1_stride<LV>());
 #pragma unroll
-  for (int i = 0; i < 16; i++) muw[i] = s[i];
+  for (int i = 0; i < 8; i++) muw[2 * i + half] = a[i];
 }
 
 // c = SampleInBall(ctilde) and strict hint decoding, one lane per task

@@ -31,75 +31,6 @@ __device__ __forceinline__ void shake_absorb(uint32_t s[50], uint64_t len, W wor
   }
 }
 
-// tr || M absorption, one SHAKE256 block at a time: PRE leading words of tr
-// (8 in the first block, 0 after), then message words from message byte m0 on.
-// A block's message part is fetched as the aligned dwords that cover it (NW + 1
-// for NW message words), with addresses clamped to M's last dword (no dword
-// outside [M's first, M's last] is read; none at all when M is empty).
-template <int NW>
-__device__ __forceinline__ void tr_msg_fetch(uint32_t D[NW + 1], const uint32_t *base, int64_t last, uint32_t sh,
-                                             int64_t m0) {
-  const int64_t d0 = (int64_t)((sh + (uint64_t)m0) >> 2);
-#pragma unroll
-  for (int i = 0; i < NW + 1; i++) {
-    int64_t di = d0 + i;
-    di = di > last ? last : di;
-    D[i] = last >= 0 ? base[di] : 0u;
-  }
-}
-// The fetched dwords are funnel-shifted by the byte misalignment sh, bytes past
-// the end of M masked, the padding added arithmetically, and the block
-// permuted.  All indices are compile-time so the words stay in registers.
-template <int PRE>
-__device__ __forceinline__ void tr_msg_mix(uint32_t s[50], const uint32_t tr[8], const uint32_t D[RATE256 / 4 - PRE + 1],
-                                           uint32_t sh, int64_t m0, uint64_t mlen, bool final_block) {
-  constexpr int WPB = RATE256 / 4;  // 34 words per block
-#pragma unroll
-  for (int j = 0; j < WPB; j++) {
-    uint32_t v;
-    if (j < PRE) {
-      v = tr[j];
-    } else {
-      const int k = j - PRE;
-      v = __builtin_amdgcn_alignbit(D[k + 1], D[k], 8 * sh);
-      const int64_t rem = (int64_t)mlen - (m0 + 4 * k);  // message bytes left from this word on
-      v = rem <= 0 ? 0u : rem < 4 ? v & ((1u << (8 * rem)) - 1u) : v;
-      if (rem >= 0 && rem < 4) v ^= 0x1Fu << (8 * rem);   // SHAKE suffix right after M
-    }
-    if (j == WPB - 1 && final_block) v ^= 0x80u << 24;    // final bit of the 10*1 padding
-    s[j] ^= v;
-  }
-  keccak_f(s);
-}
-
-// SHAKE256 absorption of tr || M, for mu = H(tr || M): tr is 32 bytes given as
-// eight little-endian words, M is mlen bytes at any alignment.  Lanes hash
-// messages of different lengths, so nothing per word depends on a branch.
-// Block b >= 1 carries message bytes from 136 b - 32 on, a multiple of 4, so
-// one funnel shift serves every block; the next block's dwords are requested
-// before the current block is permuted, so their latency overlaps it.  On
-// return the first output block is in s[0 .. RATE256/4).
-__device__ __forceinline__ void absorb_tr_msg(uint32_t s[50], const uint32_t tr[8], const uint8_t *msg,
-                                              uint64_t mlen) {
-  constexpr int WPB = RATE256 / 4;
-  keccak_zero(s);
-  const uint32_t sh = (uint32_t)((uintptr_t)msg & 3u);
-  const uint32_t *base = (const uint32_t *)(msg - sh);
-  const int64_t last = mlen ? (int64_t)((sh + mlen - 1) >> 2) : -1;  // last dword holding message bytes
-  const uint64_t nblk = (32 + mlen) / RATE256 + 1;
-  uint32_t D0[WPB - 8 + 1], Dn[WPB + 1];
-  tr_msg_fetch<WPB - 8>(D0, base, last, sh, 0);
-  if (nblk > 1) tr_msg_fetch<WPB>(Dn, base, last, sh, RATE256 - 32);
-  tr_msg_mix<8>(s, tr, D0, sh, 0, mlen, nblk == 1);
-  for (uint64_t b = 1; b < nblk; b++) {
-    uint32_t Dc[WPB + 1];
-#pragma unroll
-    for (int i = 0; i < WPB + 1; i++) Dc[i] = Dn[i];
-    if (b + 1 < nblk) tr_msg_fetch<WPB>(Dn, base, last, sh, (int64_t)(b + 1) * RATE256 - 32);
-    tr_msg_mix<0>(s, tr, Dc, sh, (int64_t)b * RATE256 - 32, mlen, b == nblk - 1);
-  }
-}
-
 // word source for one contiguous byte string (any alignment)
 struct SrcBytes {
   const uint8_t *p;
