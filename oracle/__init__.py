@@ -96,6 +96,8 @@ def bind(path: str) -> ctypes.CDLL:
             "dil_ref_keygen_batch": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, ctypes.c_uint32, ctypes.c_int]),
             "dil_ref_sign_batch": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_uint32,
                                                   ctypes.c_int, _P]),
+            "dil_ref_sign_batch_rnd": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_uint32,
+                                                      ctypes.c_int, _P]),
             "dil_ref_verify_batch": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_uint32,
                                                     ctypes.c_int]),
         }
@@ -313,8 +315,10 @@ def _msg_arrays(msg: np.ndarray, msg_off: np.ndarray):
 
 
 def sign_batch(level: int, sk: np.ndarray, msg: np.ndarray, msg_off: np.ndarray,
-               key_idx: Optional[np.ndarray] = None, nthreads: Optional[int] = None):
-    """Returns (sig [count, SIG] uint8, iterations [count] int32)."""
+               key_idx: Optional[np.ndarray] = None, nthreads: Optional[int] = None,
+               rnd: Optional[np.ndarray] = None):
+    """Returns (sig [count, SIG] uint8, iterations [count] int32).  rnd: optional [count, 64] uint8,
+    the rho' of each task for the randomized variant (None: deterministic Sign)."""
     p = params(level)
     sk = np.ascontiguousarray(sk, dtype=np.uint8)
     msg, msg_off = _msg_arrays(msg, msg_off)
@@ -322,8 +326,13 @@ def sign_batch(level: int, sk: np.ndarray, msg: np.ndarray, msg_off: np.ndarray,
     sig = np.zeros((n, p["sig_bytes"]), dtype=np.uint8)
     iters = np.zeros(max(n, 1), dtype=np.int32)
     ki = None if key_idx is None else np.ascontiguousarray(key_idx, dtype=np.uint32)
-    rc = lib().dil_ref_sign_batch(level, _ptr(sk), None if ki is None else _ptr(ki), _ptr(msg), _ptr(msg_off),
-                                  _ptr(sig), n, nthreads or default_threads(), _ptr(iters))
+    if rnd is not None:
+        rnd = np.ascontiguousarray(rnd, dtype=np.uint8)
+        if rnd.shape != (n, 64):
+            raise ValueError("rnd must be [count, 64] bytes")
+    rc = lib().dil_ref_sign_batch_rnd(level, _ptr(sk), None if ki is None else _ptr(ki), _ptr(msg), _ptr(msg_off),
+                                      None if rnd is None else _ptr(rnd), _ptr(sig), n,
+                                      nthreads or default_threads(), _ptr(iters))
     if rc:
         raise ValueError("bad arguments")
     return sig, iters[:n]

@@ -89,6 +89,10 @@ int dil_ref_keygen(int level, const uint8_t zeta[32], uint8_t *pk, uint8_t *sk);
    signature) when the loop reaches the iteration cap (default 100000, see set_sign_cap) */
 void dil_ref_set_sign_cap(int cap);
 int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, uint8_t *sig);
+/* the randomized variant of round-3 Sign: rho' is the 64 caller-supplied bytes rnd
+   instead of H(K || mu); same return values */
+int dil_ref_sign_rnd(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, const uint8_t rnd[64],
+                     uint8_t *sig);
 /* returns 1 accept, 0 reject, -1 bad level */
 int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen, const uint8_t *sig);
 
@@ -98,6 +102,10 @@ int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen
 int dil_ref_keygen_batch(int level, const uint8_t *seeds, uint8_t *pk, uint8_t *sk, uint32_t count, int nthreads);
 int dil_ref_sign_batch(int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                        const uint64_t *msg_off, uint8_t *sig, uint32_t count, int nthreads, int32_t *iters);
+/* as dil_ref_sign_batch, task t signing with rho' = rnd[64 t .. 64 t + 64) (rnd NULL: deterministic) */
+int dil_ref_sign_batch_rnd(int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                           const uint64_t *msg_off, const uint8_t *rnd, uint8_t *sig, uint32_t count, int nthreads,
+                           int32_t *iters);
 int dil_ref_verify_batch(int level, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
                          const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count,
                          int nthreads);

@@ -197,7 +197,11 @@ static void pack_w1(const ref_params *P, const int32_t *w1, uint8_t *out) {
 static int g_sign_cap = 100000;
 void dil_ref_set_sign_cap(int cap) { g_sign_cap = cap > 0 ? cap : 100000; }
 
-int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, uint8_t *sig) {
+/* rnd == NULL: deterministic Sign, rho' = H(K || mu) (Alg. 2 as printed).
+   rnd != NULL: the randomized variant of the round-3 scheme, rho' = the 64
+   caller-supplied bytes; every other step is unchanged. */
+static int sign_core(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, const uint8_t *rnd,
+                     uint8_t *sig) {
   ref_params P;
   if (dil_ref_params(level, &P)) return -1;
   const int k = P.k, l = P.l;
@@ -220,9 +224,13 @@ int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, 
   memcpy(buf, tr, 32);
   memcpy(buf + 32, msg, mlen);
   dil_ref_shake256(buf, 32 + mlen, mu, 64);
-  memcpy(buf, K, 32);
-  memcpy(buf + 32, mu, 64);
-  dil_ref_shake256(buf, 96, rhop, 64);
+  if (rnd) {
+    memcpy(rhop, rnd, 64);
+  } else {
+    memcpy(buf, K, 32);
+    memcpy(buf + 32, mu, 64);
+    dil_ref_shake256(buf, 96, rhop, 64);
+  }
 
   dil_ref_expand_a(level, rho, A);
   for (int j = 0; j < l; j++) {
@@ -329,6 +337,15 @@ int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, 
   return iters;
 }
 
+int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, uint8_t *sig) {
+  return sign_core(level, sk, msg, mlen, NULL, sig);
+}
+
+int dil_ref_sign_rnd(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, const uint8_t rnd[64],
+                     uint8_t *sig) {
+  return sign_core(level, sk, msg, mlen, rnd, sig);
+}
+
 /* ---- Alg. 3 ---- */
 int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen, const uint8_t *sig) {
   ref_params P;
@@ -386,7 +403,7 @@ int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen
 /* ---- threaded batch drivers (tasks are independent) ---- */
 typedef struct {
   int op, level;
-  const uint8_t *in_key, *msg, *sig_in, *seeds;
+  const uint8_t *in_key, *msg, *sig_in, *seeds, *rnd;
   const uint32_t *key_idx;
   const uint64_t *msg_off;
   uint8_t *pk, *sk, *sig;
@@ -405,7 +422,8 @@ static void *batch_worker(void *arg) {
       const uint8_t *m = j->msg + j->msg_off[t];
       size_t mlen = (size_t)(j->msg_off[t + 1] - j->msg_off[t]);
       if (j->op == 1) {
-        int it = dil_ref_sign(j->level, j->in_key + j->P.sk_bytes * key, m, mlen, j->sig + j->P.sig_bytes * t);
+        int it = sign_core(j->level, j->in_key + j->P.sk_bytes * key, m, mlen, j->rnd ? j->rnd + 64 * (size_t)t : NULL,
+                           j->sig + j->P.sig_bytes * t);
         if (j->iters) j->iters[t] = it;
       } else {
         j->verdict[t] = dil_ref_verify(j->level, j->in_key + j->P.pk_bytes * key, m, mlen,
@@ -441,16 +459,22 @@ int dil_ref_keygen_batch(int level, const uint8_t *seeds, uint8_t *pk, uint8_t *
   return run_batch(&j, count, nthreads);
 }
 
-int dil_ref_sign_batch(int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
-                       const uint64_t *msg_off, uint8_t *sig, uint32_t count, int nthreads, int32_t *iters) {
+int dil_ref_sign_batch_rnd(int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                           const uint64_t *msg_off, const uint8_t *rnd, uint8_t *sig, uint32_t count, int nthreads,
+                           int32_t *iters) {
   batch_job j;
   memset(&j, 0, sizeof j);
   if (dil_ref_params(level, &j.P)) return -1;
   for (uint32_t t = 0; t < count; t++)
     if (msg_off[t + 1] < msg_off[t]) return -1;
   j.op = 1; j.level = level; j.in_key = sk; j.key_idx = key_idx; j.msg = msg; j.msg_off = msg_off;
-  j.sig = sig; j.iters = iters;
+  j.sig = sig; j.iters = iters; j.rnd = rnd;
   return run_batch(&j, count, nthreads);
+}
+
+int dil_ref_sign_batch(int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                       const uint64_t *msg_off, uint8_t *sig, uint32_t count, int nthreads, int32_t *iters) {
+  return dil_ref_sign_batch_rnd(level, sk, key_idx, msg, msg_off, NULL, sig, count, nthreads, iters);
 }
 
 int dil_ref_verify_batch(int level, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
