@@ -119,6 +119,15 @@ int dil_keygen_batch(dil_ctx *ctx, int level, const uint8_t *seeds, uint8_t *pk,
 int dil_sign_batch(dil_ctx *ctx, int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                    const uint64_t *msg_off, uint8_t *sig, uint32_t count, void *stream);
 
+/* The randomized variant of round-3 Sign: as dil_sign_batch, but task i uses
+ * rho' = rnd[64 i .. 64 i + 64) (caller-supplied random bytes, a device
+ * buffer of count x 64 bytes, 4-byte aligned) instead of H(K || mu) (Alg. 2
+ * computes rho' deterministically; every other step is the same).  rnd NULL
+ * is deterministic Sign.  DIL_EINVAL for a misaligned rnd.  The caller owns
+ * the randomness: the output is a deterministic function of (sk, M, rnd). */
+int dil_sign_batch_rnd(dil_ctx *ctx, int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                       const uint64_t *msg_off, const uint8_t *rnd, uint8_t *sig, uint32_t count, void *stream);
+
 /* Dilithium.Verify (Alg. 3) with strict signature decoding:
  * verdict[count] int32 = 1 accept, 0 reject. */
 int dil_verify_batch(dil_ctx *ctx, int level, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,

@@ -288,14 +288,14 @@ void use_keyset(Ws &ws, const dil_keyset *ks, const uint32_t *key_idx) {
 template <int LV>
 int sign_setup(dil_ctx *ctx, Ws &ws, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                const uint64_t *msg_off, uint32_t count, hipStream_t st, const dil_keyset *ks, uint32_t *err,
-               bool concurrent) {
+               bool concurrent, const uint8_t *rnd) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
   concurrent = concurrent && !ks;
   if (concurrent) {
     int rc = fork_side(ctx, st);
     if (rc) return rc;
   }
-  sg_prep_k<LV><<<blocks_for(2 * (uint64_t)count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, ws, count, err);
+  sg_prep_k<LV><<<blocks_for(2 * (uint64_t)count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, rnd, ws, count, err);
   if (!ks) {
     hipStream_t s1 = concurrent ? ctx->side[0] : st, s2 = concurrent ? ctx->side[1] : st;
     expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, EA_WG), EA_WG, 0, s1>>>(sk, P<LV>::SK, key_idx, ws.A, count);
@@ -307,14 +307,15 @@ int sign_setup(dil_ctx *ctx, Ws &ws, const uint8_t *sk, const uint32_t *key_idx,
 
 template <int LV>
 int sign_staged(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg, const uint64_t *msg_off,
-                uint8_t *sig, uint32_t count, hipStream_t st, const dil_keyset *ks = nullptr) {
+                uint8_t *sig, uint32_t count, hipStream_t st, const dil_keyset *ks = nullptr,
+                const uint8_t *rnd = nullptr) {
   constexpr int L = Lv<LV>::L;
   Ws ws;
   int rc = ws_carve<LV>(ctx, count, ws);
   if (rc) return rc;
   if (ks) use_keyset(ws, ks, key_idx);
   HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
-  rc = sign_setup<LV>(ctx, ws, sk, key_idx, msg, msg_off, count, st, ks, ctx->dev_stats + 8, false);
+  rc = sign_setup<LV>(ctx, ws, sk, key_idx, msg, msg_off, count, st, ks, ctx->dev_stats + 8, false, rnd);
   if (rc) return rc;
   LAUNCHCHK(ctx);
   uint32_t nactive = count;
@@ -362,7 +363,7 @@ int persist_occupancy(dil_ctx *ctx, int *occ) {
 template <int LV>
 int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                     const uint64_t *msg_off, uint8_t *sig, uint32_t count, hipStream_t st,
-                    const dil_keyset *ks = nullptr) {
+                    const dil_keyset *ks = nullptr, const uint8_t *rnd = nullptr) {
   const int waves = ctx->persist_waves;
   const int G = persist_slots<LV>(waves);
   int occ = 1;
@@ -379,12 +380,13 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   if (rc) return rc;
   if (ks) use_keyset(ws, ks, key_idx);
   uint64_t key[16] = {1, (uint64_t)LV, (uint64_t)sk, (uint64_t)key_idx, (uint64_t)msg, (uint64_t)msg_off,
-                      (uint64_t)sig, count, (uint64_t)ks, grid, hmax, (uint64_t)ctx->ws_mem, 0, (uint64_t)waves, 0, 0};
+                      (uint64_t)sig, count, (uint64_t)ks, grid, hmax, (uint64_t)ctx->ws_mem, 0, (uint64_t)waves,
+                      (uint64_t)rnd, 0};
   hipEvent_t *evs = ctx->timing ? ctx->ev[ctx->ev_count % dil_ctx::RING] : nullptr;
   if (evs) HIPCHK(ctx, hipEventRecord(evs[0], st));
   rc = enqueue(ctx, key, st, [&](hipStream_t s) {
     zero_words_k<<<1, 64, 0, s>>>(ws.counters, 16, ctx->dev_stats, 8);
-    int r2 = sign_setup<LV>(ctx, ws, sk, key_idx, msg, msg_off, count, s, ks, ctx->dev_stats + 8, true);
+    int r2 = sign_setup<LV>(ctx, ws, sk, key_idx, msg, msg_off, count, s, ks, ctx->dev_stats + 8, true, rnd);
     if (r2) return r2;
     LAUNCHCHK(ctx);
     return DIL_OK;
@@ -648,15 +650,23 @@ int dil_keygen_batch(dil_ctx *ctx, int level, const uint8_t *seeds, uint8_t *pk,
 
 int dil_sign_batch(dil_ctx *ctx, int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                    const uint64_t *msg_off, uint8_t *sig, uint32_t count, void *stream) {
+  return dil_sign_batch_rnd(ctx, level, sk, key_idx, msg, msg_off, nullptr, sig, count, stream);
+}
+
+int dil_sign_batch_rnd(dil_ctx *ctx, int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                       const uint64_t *msg_off, const uint8_t *rnd, uint8_t *sig, uint32_t count, void *stream) {
   if (!ctx || !valid_level(level)) return fail(ctx, DIL_EINVAL, "bad context or level");
   if (count == 0) return DIL_OK;
   if (!sk || !msg || !msg_off || !sig) return fail(ctx, DIL_EINVAL, "null buffer");
+  if ((uintptr_t)rnd & 3) return fail(ctx, DIL_EINVAL, "rnd must be 4-byte aligned");
   hipSetDevice(ctx->device);
   ctx->stats_pending = 0;
   return by_level(level, [&](auto lv) {
     if (ctx->mode == DIL_MODE_PERSISTENT)
-      return sign_persistent<decltype(lv)::value>(ctx, sk, key_idx, msg, msg_off, sig, count, (hipStream_t)stream);
-    return sign_staged<decltype(lv)::value>(ctx, sk, key_idx, msg, msg_off, sig, count, (hipStream_t)stream);
+      return sign_persistent<decltype(lv)::value>(ctx, sk, key_idx, msg, msg_off, sig, count, (hipStream_t)stream,
+                                                  nullptr, rnd);
+    return sign_staged<decltype(lv)::value>(ctx, sk, key_idx, msg, msg_off, sig, count, (hipStream_t)stream, nullptr,
+                                            rnd);
   });
 }
 

@@ -293,10 +293,12 @@ __global__ void __launch_bounds__(256) kg_tr_k(const uint8_t *pk, uint8_t *sk, u
 // Sign (Alg. 2), staged
 // ------------------------------------------------------------------------
 // mu = H(tr || M), rho' = H(K || mu) on two lanes per task (keccak_pair.h);
-// initialises kappa and the active list
+// initialises kappa and the active list.  rnd (randomized signing, 64 bytes
+// per task, 4-byte aligned) replaces H(K || mu) as rho' when it is not null.
 template <int LV>
 __global__ void __launch_bounds__(256) sg_prep_k(const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
-                                                 const uint64_t *msg_off, Ws ws, uint32_t count, uint32_t *err) {
+                                                 const uint64_t *msg_off, const uint8_t *rnd, Ws ws, uint32_t count,
+                                                 uint32_t *err) {
   // the longest dependent chain of the Sign setup (up to ~30 permutations per
   // task for 4 KiB messages), sharing the CUs with ExpandA and the secret NTTs
   // launched beside it: its waves issue first
@@ -323,16 +325,22 @@ __global__ void __launch_bounds__(256) sg_prep_k(const uint8_t *sk, const uint32
     mu[i] = a[i];
     muw[2 * i + half] = a[i];
   }
-  // rho' = H(K || mu): 96 bytes, one block
-  const uint32_t *Kw = (const uint32_t *)(skr + 32);
-#pragma unroll
-  for (int i = 0; i < 25; i++) a[i] = i < 4 ? Kw[2 * i + half] : i < 12 ? mu[i - 4] : 0u;
-  if (!half) a[12] ^= 0x1Fu;
-  else a[RATE256 / 8 - 1] ^= 0x80u << 24;
-  keccak_f_pair(a, half);
   uint32_t *rp = (uint32_t *)(ws.rhop + (size_t)t * 64);
+  if (rnd) {
+    const uint32_t *rw = (const uint32_t *)(rnd + (size_t)t * 64);
 #pragma unroll
-  for (int i = 0; i < 8; i++) rp[2 * i + half] = a[i];
+    for (int i = 0; i < 8; i++) rp[2 * i + half] = rw[2 * i + half];
+  } else {
+    // rho' = H(K || mu): 96 bytes, one block
+    const uint32_t *Kw = (const uint32_t *)(skr + 32);
+#pragma unroll
+    for (int i = 0; i < 25; i++) a[i] = i < 4 ? Kw[2 * i + half] : i < 12 ? mu[i - 4] : 0u;
+    if (!half) a[12] ^= 0x1Fu;
+    else a[RATE256 / 8 - 1] ^= 0x80u << 24;
+    keccak_f_pair(a, half);
+#pragma unroll
+    for (int i = 0; i < 8; i++) rp[2 * i + half] = a[i];
+  }
   if (!half) {
     ws.kappa[t] = 0;
     ws.active0[t] = t;

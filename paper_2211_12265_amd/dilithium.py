@@ -21,7 +21,7 @@ MODE_STAGED, MODE_PERSISTENT = 0, 1
 EXPORTS = [
     "dil_ctx_create", "dil_ctx_destroy", "dil_ctx_set_mode", "dil_ctx_set_param", "dil_ctx_check",
     "dil_last_error", "dil_sizes",
-    "dil_keygen_batch", "dil_sign_batch", "dil_verify_batch", "dil_sign_stats", "dil_sign_timing",
+    "dil_keygen_batch", "dil_sign_batch", "dil_sign_batch_rnd", "dil_verify_batch", "dil_sign_stats", "dil_sign_timing",
     "dil_ntt_mul_batch",
     "dil_expand_a_batch", "dil_keyset_create", "dil_keyset_destroy", "dil_keyset_info", "dil_sign_keyset",
     "dil_verify_keyset", "dil_persist_capacity", "dil_ctx_reserve", "dil_server_create", "dil_server_destroy",
@@ -58,6 +58,7 @@ def load() -> ctypes.CDLL:
                                      ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)]),
         "dil_keygen_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, ctypes.c_uint32, _P]),
         "dil_sign_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_uint32, _P]),
+        "dil_sign_batch_rnd": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_uint32, _P]),
         "dil_verify_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_uint32, _P]),
         "dil_sign_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]),
         "dil_sign_timing": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
@@ -154,10 +155,18 @@ class Context:
         n = seeds.shape[0]
         self._check(self.lib.dil_keygen_batch(self.h, level, _ptr(seeds), _ptr(pk), _ptr(sk), n, _stream(stream)))
 
-    def sign(self, level: int, sk, msg, msg_off, sig, key_idx=None, stream=None):
+    def sign(self, level: int, sk, msg, msg_off, sig, key_idx=None, stream=None, rnd=None):
+        """rnd: optional uint8 device tensor [count, 64], the rho' of each task (randomized signing)."""
         n = msg_off.shape[0] - 1
-        self._check(self.lib.dil_sign_batch(self.h, level, _ptr(sk), _ptr(key_idx), _ptr(msg) or _ptr(msg_off),
-                                            _ptr(msg_off), _ptr(sig), n, _stream(stream)))
+        if rnd is None:
+            self._check(self.lib.dil_sign_batch(self.h, level, _ptr(sk), _ptr(key_idx), _ptr(msg) or _ptr(msg_off),
+                                                _ptr(msg_off), _ptr(sig), n, _stream(stream)))
+        else:
+            if tuple(rnd.shape) != (n, 64):
+                raise ValueError("rnd must be [count, 64] bytes")
+            self._check(self.lib.dil_sign_batch_rnd(self.h, level, _ptr(sk), _ptr(key_idx),
+                                                    _ptr(msg) or _ptr(msg_off), _ptr(msg_off), _ptr(rnd), _ptr(sig),
+                                                    n, _stream(stream)))
 
     def verify(self, level: int, pk, msg, msg_off, sig, verdict, key_idx=None, stream=None):
         n = msg_off.shape[0] - 1

@@ -115,12 +115,13 @@ def test_keygen_parity(ctx, level):
     assert np.array_equal(sk.cpu().numpy(), osk)
 
 
-def _sign(ctx, level, sk, msg, off, key_idx=None):
+def _sign(ctx, level, sk, msg, off, key_idx=None, rnd=None):
     from paper_2211_12265_amd import dilithium as dl
     n = off.size - 1
     sig = torch.zeros((n, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
     ctx.sign(level, sk, dev(msg), dev(off.astype(np.int64)), sig,
-             key_idx=None if key_idx is None else dev(key_idx.astype(np.int32)))
+             key_idx=None if key_idx is None else dev(key_idx.astype(np.int32)),
+             rnd=None if rnd is None else dev(rnd))
     torch.cuda.synchronize()
     return sig
 
@@ -151,6 +152,44 @@ def test_sign_verify_parity(sctx, level):
     assert not bad, f"signature mismatch for tasks {bad[:8]} (iters {iters[bad[:8]]})"
     assert _verify(ctx, level, pk, msg, off, sig).tolist() == [1] * n
     assert oracle.verify_batch(level, pk.cpu().numpy(), msg, off, got).tolist() == [1] * n
+
+
+@pytest.mark.parametrize("level", [2, 3, 5])
+def test_randomized_sign_parity(sctx, level):
+    """Randomized Sign with caller-supplied rho': GPU signatures equal the oracle's for the same
+    rho' and verify; rho' = SHAKE256(K || mu) computed by hashlib reproduces deterministic Sign."""
+    import hashlib
+    ctx = sctx
+    n = 40
+    seeds = workload.keygen_seeds(n, seed=70 + level)
+    pk, sk = _keygen(ctx, level, seeds)
+    lens = workload.uniform_lengths(n, 0, 300, seed=71 + level)
+    lens[:3] = [0, 1, 104]
+    msg, off = workload.messages(lens, seed=71 + level)
+    rnd = workload.random_bytes("dil/rnd", level, (n, 64))
+    sig = _sign(ctx, level, sk, msg, off, rnd=rnd)
+    osig, _ = oracle.sign_batch(level, sk.cpu().numpy(), msg, off, rnd=rnd)
+    assert np.array_equal(sig.cpu().numpy(), osig)
+    assert _verify(ctx, level, pk, msg, off, sig).tolist() == [1] * n
+    sk_h = sk.cpu().numpy()
+    det_rnd = np.stack([np.frombuffer(hashlib.shake_256(
+        sk_h[i, 32:64].tobytes() + hashlib.shake_256(sk_h[i, 64:96].tobytes() +
+                                                      msg[int(off[i]):int(off[i + 1])].tobytes()).digest(64)
+    ).digest(64), np.uint8) for i in range(n)])
+    assert np.array_equal(_sign(ctx, level, sk, msg, off, rnd=det_rnd).cpu().numpy(),
+                          _sign(ctx, level, sk, msg, off).cpu().numpy())
+
+
+def test_randomized_sign_rejects_misaligned_rnd(ctx):
+    from paper_2211_12265_amd import dilithium as dl
+    level = 2
+    pk, sk = _keygen(ctx, level, workload.keygen_seeds(2, seed=75))
+    msg, off = workload.messages(workload.fixed_lengths(2, 32), seed=75)
+    buf = torch.zeros(2 * 64 + 4, dtype=torch.uint8, device="cuda")
+    sig = torch.zeros((2, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
+    with pytest.raises(dl.DilError):
+        ctx.sign(level, sk, dev(msg), dev(off.astype(np.int64)), sig, rnd=buf[1:1 + 128].view(2, 64))
+    torch.cuda.synchronize()
 
 
 @pytest.mark.parametrize("level", [2, 3, 5])
