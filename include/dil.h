@@ -169,7 +169,8 @@ int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_id
  * concurrently, each on a stream and context of its own; that needs more
  * hardware queues than HIP's default of 4 per process, so the process should
  * set GPU_MAX_HW_QUEUES (e.g. 16) before HIP starts.  mode is
- * DIL_MODE_STAGED or DIL_MODE_PERSISTENT for Sign. */
+ * DIL_MODE_STAGED or DIL_MODE_PERSISTENT for Sign; the persistent Sign calls
+ * use four-wavefront workgroups ("persist.waves" = 4). */
 typedef struct dil_server dil_server;
 int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset *ks3, dil_keyset *ks5,
                       int n_streams, uint32_t max_batch, size_t max_msg_bytes, size_t mem_budget, int mode);

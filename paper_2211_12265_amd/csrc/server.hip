@@ -117,6 +117,10 @@ int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset 
       ok = hipStreamCreateWithFlags(&ln.gst[gi], hipStreamNonBlocking) == hipSuccess &&
            hipEventCreateWithFlags(&ln.gev[gi], hipEventDisableTiming) == hipSuccess &&
            dil_ctx_create(&ln.gctx[gi], device, 0) == DIL_OK && dil_ctx_set_mode(ln.gctx[gi], mode) == DIL_OK &&
+           // a group call holds few tasks: four-wavefront workgroups give each
+           // task 4 x 64 / l nonces per batch, so almost every task passes in
+           // the first batch instead of needing a second or third
+           (gi % 2 == 1 || dil_ctx_set_param(ln.gctx[gi], "persist.waves", 4) == DIL_OK) &&
            dil_ctx_reserve(ln.gctx[gi], kLevels[li], max_batch) == DIL_OK;
     }
     ok = ok && hipHostMalloc((void **)&ln.h_msg, max_msg_bytes, hipHostMallocDefault) == hipSuccess &&
