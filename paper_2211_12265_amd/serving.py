@@ -78,6 +78,9 @@ class _Lane:
         self.torch = torch
         self.stream = torch.cuda.Stream(device=device)
         self.ctx = dl.Context(device.index or 0, mode=dl.MODE_PERSISTENT if persistent else dl.MODE_STAGED)
+        if persistent:
+            # few tasks per call: four-wavefront workgroups give each task 4 x 64 / l nonces per batch
+            self.ctx.set_param("persist.waves", 4)
         for lv in LEVELS:   # allocate the workspace for the largest admitted batch once
             self.ctx.reserve(lv, max_tasks)
         pin = dict(pin_memory=True)
