@@ -394,7 +394,7 @@ def main():
     ap.add_argument("--record-schedule", default="",
                     help="after tuning, record the chosen schedule in this JSON file")
     ap.add_argument("--waves", type=int, default=0, choices=[0, 1, 2, 4],
-                    help="wavefronts per persistent workgroup (0: let the autotuner choose; 1 without it)")
+                    help="wavefronts per persistent workgroup (0: let the autotuner choose; the library default 4 without it)")
     ap.add_argument("--schedule", default="",
                     help="fixed persistent schedule 'waves,hmax,grid' (skips the autotuner)")
     ap.add_argument("--graph", type=int, default=1, help="replay Sign/Verify launch sequences as hipGraphs")
@@ -530,7 +530,7 @@ def main():
         achieved = k_ops / (loop_med * 1e-3)
         kextra = {"kernel_ms_median": loop_med, "setup_ms_median": float(np.median(setup_ms)),
                   "timed_launches": len(loop_ms), "ops_per_launch": k_ops}
-        nw = tuning["best"]["waves"] if tuning else (args.waves or 1)
+        nw = tuning["best"]["waves"] if tuning else (args.waves or 4)
         kbase = f"sg_persistw_k<{level}, {nw}>" if nw > 1 else f"sg_persist_k<{level}>"
         kname = kbase + " (persistent Sign rejection-loop kernel)"
         sched_str = args.schedule if not tuning else \

@@ -73,10 +73,10 @@ int dil_ctx_set_mode(dil_ctx *ctx, int mode);
 /* Tuning knobs (0 = automatic):
  *   "persist.grid"  workgroups launched by the persistent Sign kernel;
  *   "persist.hmax"  tasks one workgroup holds at a time (1..slots per batch);
- *   "persist.waves" wavefronts per persistent workgroup: 1 (default; 64 / l
- *                   candidate slots per batch), 2 or 4 (W * (64 / l) slots,
- *                   the challenge hashes of all slots on one wavefront); any
- *                   other value is DIL_EINVAL;
+ *   "persist.waves" wavefronts per persistent workgroup: 1 (64 / l candidate
+ *                   slots per batch), 2 or 4 (default; W * (64 / l) slots,
+ *                   the challenge hashes on two lanes per slot); any other
+ *                   value is DIL_EINVAL;
  *   "timing"        1 = record HIP events around the persistent Sign's setup
  *                   kernels and its loop kernel (read with dil_sign_timing);
  *   "graph"         1 = capture the launch sequence of persistent-mode Sign and

@@ -25,7 +25,7 @@ struct dil_ctx {
   hipStream_t last_stream = nullptr;
   int stats_pending = 0;
   int64_t persist_grid = 0, persist_hmax = 0;  // 0 = automatic
-  int persist_waves = 1;                       // wavefronts per persistent workgroup: 1, 2 or 4
+  int persist_waves = 4;                       // wavefronts per persistent workgroup: 1, 2 or 4
   int timing = 0;                              // record HIP events around the persistent Sign phases
   int ntt_variant = 0;                         // form of dil_ntt_mul_batch (0 = production kernel)
   static constexpr int RING = 64;

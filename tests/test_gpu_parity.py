@@ -406,11 +406,11 @@ def test_autotuner_picks_a_measured_candidate(ctx):
     msg, off = workload.messages(workload.fixed_lengths(n, 32), seed=120)
     dmsg, doff = dev(msg), dev(off.astype(np.int64))
     sig = torch.zeros((n, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
+    resident4, slots4 = c.persist_capacity(level)   # default shape: four wavefronts
+    assert resident4 > 0 and slots4 == 64
+    c.set_param("persist.waves", 1)
     resident, slots = c.persist_capacity(level)
     assert resident > 0 and slots == 16
-    c.set_param("persist.waves", 4)
-    resident4, slots4 = c.persist_capacity(level)
-    assert resident4 > 0 and slots4 == 64
     with pytest.raises(dl.DilError):
         c.set_param("persist.waves", 3)
     res = autotune.tune_sign(c, level, lambda: c.sign(level, sk, dmsg, doff, sig), reps=1, count=n)
