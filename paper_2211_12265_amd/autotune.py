@@ -3,7 +3,7 @@
 The schedule has three knobs (dil_ctx_set_param):
   persist.waves wavefronts per workgroup: 1 (G = 64 / l candidate slots per
                 batch), 2 or 4 (G = W * (64 / l) slots; the challenge hashes
-                of all slots run on one wavefront);
+                run on two lanes per slot, 32 slots per wavefront);
   persist.hmax  tasks a workgroup holds at once; each held task gets G / hmax
                 consecutive nonces per batch (hmax = G: no speculation until
                 tasks retire);

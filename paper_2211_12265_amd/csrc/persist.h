@@ -240,8 +240,9 @@ namespace dil {
 // w + W, ...; the challenge hashes run on two lanes per slot (keccak_pair.h),
 // slots 0..31 on one wave and the rest (at most 32) on the next, while the
 // other waves wait at the barrier.  Which waves hash rotates with the
-// workgroup and batch index so the SIMDs stay balanced.  Passing candidates are staged per slot and the smallest
-// passing nonce of each task is copied to the output after a barrier.
+// workgroup and batch index so the SIMDs stay balanced.  Passing candidates
+// are staged per slot and the smallest passing nonce of each task is copied
+// to the output after a barrier.
 // ---------------------------------------------------------------------------
 template <int LV, int NW>
 struct PCfgW {
