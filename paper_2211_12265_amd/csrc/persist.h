@@ -84,6 +84,23 @@ __device__ __forceinline__ int claim_tasks(uint32_t *queue, uint32_t count, uint
   return nh;
 }
 
+// Slot layout of one batch, run by lanes 0 .. nh - 1 of one wavefront (nh <= 64):
+// slot s evaluates held task s mod nh at that task's nonce index
+// h_next + s / nh, so each task's slots try consecutive nonces.  Lane h writes
+// the slots of task h, advances its h_next past them and clears its h_win.
+__device__ __forceinline__ void assign_slots(int nh, int ns, uint32_t *h_next, uint32_t *h_win, uint8_t *s_h,
+                                             uint32_t *s_att, int lane) {
+  if (lane >= nh) return;
+  const uint32_t base = h_next[lane];
+  uint32_t j = 0;
+  for (int s = lane; s < ns; s += nh, j++) {
+    s_h[s] = (uint8_t)lane;
+    s_att[s] = base + j;
+  }
+  h_next[lane] = base + j;
+  h_win[lane] = 0xFFFFFFFFu;
+}
+
 // per-workgroup statistics, flushed to the launch's stats words at exit
 struct Tally {
   uint64_t evaluated = 0, sequential = 0;
@@ -122,6 +139,7 @@ template <int LV>
 __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig, uint32_t count, uint32_t hmax,
                                                    uint32_t *stats) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfg<LV>::G;
+  static_assert(G <= 64, "slot layout assumes at most one slot per lane");
   __shared__ PersistLds<LV> lds;
   const int lane = threadIdx.x, t = lane & 15;
   const size_t wg = blockIdx.x;
@@ -146,19 +164,11 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
       if (!lds.queue_empty && nh < (int)hmax) nh = claim_tasks(ws.counters, count, hmax - nh, nh, lds.h_task,
                                                                lds.h_next, lds.queue_empty);
       lds.nheld = nh;
-      int ns = nh ? G : 0;
-      for (int s = 0; s < ns; s++) {
-        int h = s % nh;
-        lds.s_h[s] = (uint8_t)h;
-        lds.s_att[s] = lds.h_next[h] + (uint32_t)(s / nh);
-      }
-      for (int h = 0; h < nh; h++) {
-        lds.h_next[h] += (uint32_t)(ns / nh + (h < ns % nh ? 1 : 0));
-        lds.h_win[h] = 0xFFFFFFFFu;
-      }
-      lds.nslots = ns;
-      tally.evaluated += (uint64_t)ns;
+      lds.nslots = nh ? G : 0;
+      tally.evaluated += nh ? (uint64_t)G : 0u;
     }
+    wave_sync();
+    assign_slots(lds.nheld, lds.nslots, lds.h_next, lds.h_win, lds.s_h, lds.s_att, lane);
     wave_sync();
     const int ns = lds.nslots;
     if (ns == 0) break;
@@ -311,6 +321,7 @@ template <int LV, int NW>
 __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t *sig, uint32_t count,
                                                      uint32_t hmax, uint32_t *stats) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfgW<LV, NW>::G, W = NW;
+  static_assert(G <= 64, "slot layout and winner search assume at most one slot per lane");
   __shared__ PersistWLds<LV, NW> lds;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, t = lane & 15;
   const size_t wg = blockIdx.x;
@@ -330,23 +341,19 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
   uint64_t ph_acc[5] = {0, 0, 0, 0, 0};
 #endif
   for (uint32_t batch = 0;; batch++) {
-    if (tid == 0) {
-      int nh = lds.nheld;
-      if (!lds.queue_empty && nh < (int)hmax) nh = claim_tasks(ws.counters, count, hmax - nh, nh, lds.h_task,
-                                                               lds.h_next, lds.queue_empty);
-      lds.nheld = nh;
-      int ns = nh ? G : 0;
-      for (int s = 0; s < ns; s++) {
-        int h = s % nh;
-        lds.s_h[s] = (uint8_t)h;
-        lds.s_att[s] = lds.h_next[h] + (uint32_t)(s / nh);
+    // thread 0 claims tasks; then lane h < nheld of wave 0 lays out held task
+    // h's slots (assign_slots)
+    if (wave == 0) {
+      if (lane == 0) {
+        int nh = lds.nheld;
+        if (!lds.queue_empty && nh < (int)hmax) nh = claim_tasks(ws.counters, count, hmax - nh, nh, lds.h_task,
+                                                                 lds.h_next, lds.queue_empty);
+        lds.nheld = nh;
+        lds.nslots = nh ? G : 0;
+        tally.evaluated += nh ? (uint64_t)G : 0u;
       }
-      for (int h = 0; h < nh; h++) {
-        lds.h_next[h] += (uint32_t)(ns / nh + (h < ns % nh ? 1 : 0));
-        lds.h_win[h] = 0xFFFFFFFFu;
-      }
-      lds.nslots = ns;
-      tally.evaluated += (uint64_t)ns;
+      wave_sync();
+      assign_slots(lds.nheld, lds.nslots, lds.h_next, lds.h_win, lds.s_h, lds.s_att, lane);
     }
     __syncthreads();
     const int ns = lds.nslots;
@@ -406,11 +413,13 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
     PHASE_MARK(4);
     // copy each signed task's smallest passing candidate out; wave w handles held tasks w, w + 4, ...
     for (int h = wave; h < lds.nheld; h += W) {
-      uint32_t win = lds.h_win[h];
+      const uint32_t win = lds.h_win[h];
       if (win == 0xFFFFFFFFu) continue;
-      int s = -1;
-      for (int q = 0; q < ns; q++)
-        if (lds.s_h[q] == h && lds.s_att[q] == win) s = q;
+      // the slot that evaluated the winning nonce, found by one ballot over
+      // all slots (G <= 64); h_win only ever takes a slot's s_att, so it exists
+      const uint64_t hit = __ballot(lane < ns && lds.s_h[lane] == h && lds.s_att[lane] == win);
+      if (hit == 0) continue;
+      const int s = (int)__builtin_ctzll(hit);
       copy_sig_row<P<LV>::SIG>((const uint32_t *)(stg + s * sig_stride<LV>()),
                                sig + (size_t)lds.h_task[h] * P<LV>::SIG, lane);
     }
