@@ -84,27 +84,17 @@ __device__ __forceinline__ int claim_tasks(uint32_t *queue, uint32_t count, uint
   return nh;
 }
 
-// Slot layout of one batch, run by lanes 0 .. nh - 1 of one wavefront (nh <= 64):
-// slot s evaluates held task s mod nh at that task's nonce index
-// h_next + s / nh, so each task's slots try consecutive nonces.  Lane h writes
-// the slots of task h, advances its h_next past them and clears its h_win.
-__device__ __forceinline__ void assign_slots(int nh, int ns, uint32_t *h_next, uint32_t *h_win, uint8_t *s_h,
-                                             uint32_t *s_att, int lane) {
-  if (lane >= nh) return;
-  const uint32_t base = h_next[lane];
-  uint32_t j = 0;
-  for (int s = lane; s < ns; s += nh, j++) {
-    s_h[s] = (uint8_t)lane;
-    s_att[s] = base + j;
-  }
-  h_next[lane] = base + j;
-  h_win[lane] = 0xFFFFFFFFu;
-}
-
-// per-workgroup statistics, flushed to the launch's stats words at exit
+// Per-workgroup statistics, flushed to the launch's stats words at exit.  It
+// lives in LDS, updated by one thread, so that it holds no registers through
+// the batch loop (the loop kernels sit at the 256-VGPR limit of two waves per
+// SIMD).
 struct Tally {
-  uint64_t evaluated = 0, sequential = 0;
-  uint32_t dropped = 0;
+  uint64_t evaluated, sequential;
+  uint32_t dropped;
+  __device__ void clear() {
+    evaluated = sequential = 0;
+    dropped = 0;
+  }
   __device__ void flush(uint32_t *stats) const {
     if (evaluated) atomicAdd((unsigned long long *)&stats[2], (unsigned long long)evaluated);
     if (sequential) atomicAdd((unsigned long long *)&stats[6], (unsigned long long)sequential);
@@ -129,6 +119,7 @@ struct PersistLds {
   uint32_t s_att[PCfg<LV>::G];
   uint8_t s_h[PCfg<LV>::G];
   int nheld, nslots, queue_empty;
+  Tally tally;
 };
 
 // ws.counters[0] is the work queue (next task to claim).  stats (32-bit words,
@@ -139,7 +130,6 @@ template <int LV>
 __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig, uint32_t count, uint32_t hmax,
                                                    uint32_t *stats) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfg<LV>::G;
-  static_assert(G <= 64, "slot layout assumes at most one slot per lane");
   __shared__ PersistLds<LV> lds;
   const int lane = threadIdx.x, t = lane & 15;
   const size_t wg = blockIdx.x;
@@ -147,8 +137,8 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
   int32_t *wb = sc.w + wg * G * K * N;
   uint8_t *w1b = sc.w1 + wg * G * w1_stride<LV>();
   const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
-  Tally tally;  // kept by lane 0, added to stats once at exit
   if (lane == 0) {
+    lds.tally.clear();
     lds.nheld = 0;
     lds.queue_empty = 0;
   }
@@ -164,11 +154,26 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
       if (!lds.queue_empty && nh < (int)hmax) nh = claim_tasks(ws.counters, count, hmax - nh, nh, lds.h_task,
                                                                lds.h_next, lds.queue_empty);
       lds.nheld = nh;
-      lds.nslots = nh ? G : 0;
-      tally.evaluated += nh ? (uint64_t)G : 0u;
+      const int ns = nh ? G : 0;
+      // slot s evaluates held task s mod nh at that task's nonce index
+      // h_next + s / nh (kept as running counters: no division per slot)
+      int h = 0;
+      uint32_t j = 0;
+      for (int s = 0; s < ns; s++) {
+        lds.s_h[s] = (uint8_t)h;
+        lds.s_att[s] = lds.h_next[h] + j;
+        if (++h == nh) {
+          h = 0;
+          j++;
+        }
+      }
+      for (h = 0; h < nh; h++) {
+        lds.h_next[h] += (uint32_t)(ns / nh + (h < ns % nh ? 1 : 0));
+        lds.h_win[h] = 0xFFFFFFFFu;
+      }
+      lds.nslots = ns;
+      lds.tally.evaluated += (uint64_t)ns;
     }
-    wave_sync();
-    assign_slots(lds.nheld, lds.nslots, lds.h_next, lds.h_win, lds.s_h, lds.s_att, lane);
     wave_sync();
     const int ns = lds.nslots;
     if (ns == 0) break;
@@ -220,11 +225,11 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
       int nh = lds.nheld, o = 0;
       for (int h = 0; h < nh; h++) {
         if (lds.h_win[h] != 0xFFFFFFFFu) {
-          tally.sequential += (uint64_t)lds.h_win[h] + 1;
+          lds.tally.sequential += (uint64_t)lds.h_win[h] + 1;
           continue;
         }
         if (lds.h_next[h] >= (uint32_t)PCfg<LV>::MAX_ATTEMPTS) {
-          tally.dropped++;
+          lds.tally.dropped++;
           continue;
         }
         lds.h_task[o] = lds.h_task[h];
@@ -235,7 +240,7 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
     }
     wave_sync();
   }
-  if (lane == 0) tally.flush(stats);
+  if (lane == 0) lds.tally.flush(stats);
   PHASE_FLUSH();
 }
 
@@ -278,6 +283,7 @@ struct PersistWLds {
   uint32_t s_att[PCfgW<LV, NW>::G];
   uint8_t s_h[PCfgW<LV, NW>::G];
   int nheld, nslots, queue_empty;
+  Tally tally;
 };
 
 // Copy an NB-byte signature from a 4-byte aligned global row to a destination
@@ -321,7 +327,7 @@ template <int LV, int NW>
 __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t *sig, uint32_t count,
                                                      uint32_t hmax, uint32_t *stats) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfgW<LV, NW>::G, W = NW;
-  static_assert(G <= 64, "slot layout and winner search assume at most one slot per lane");
+  static_assert(G <= 64, "the winner search takes one slot per lane");
   __shared__ PersistWLds<LV, NW> lds;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, t = lane & 15;
   const size_t wg = blockIdx.x;
@@ -330,8 +336,8 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
   uint8_t *w1b = sc.w1 + wg * G * w1_stride<LV>();
   uint8_t *stg = sc.stage + wg * G * sig_stride<LV>();
   const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
-  Tally tally;  // kept by thread 0, added to stats once at exit
   if (tid == 0) {
+    lds.tally.clear();
     lds.nheld = 0;
     lds.queue_empty = 0;
   }
@@ -341,19 +347,30 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
   uint64_t ph_acc[5] = {0, 0, 0, 0, 0};
 #endif
   for (uint32_t batch = 0;; batch++) {
-    // thread 0 claims tasks; then lane h < nheld of wave 0 lays out held task
-    // h's slots (assign_slots)
-    if (wave == 0) {
-      if (lane == 0) {
-        int nh = lds.nheld;
-        if (!lds.queue_empty && nh < (int)hmax) nh = claim_tasks(ws.counters, count, hmax - nh, nh, lds.h_task,
-                                                                 lds.h_next, lds.queue_empty);
-        lds.nheld = nh;
-        lds.nslots = nh ? G : 0;
-        tally.evaluated += nh ? (uint64_t)G : 0u;
+    if (tid == 0) {
+      int nh = lds.nheld;
+      if (!lds.queue_empty && nh < (int)hmax) nh = claim_tasks(ws.counters, count, hmax - nh, nh, lds.h_task,
+                                                               lds.h_next, lds.queue_empty);
+      lds.nheld = nh;
+      const int ns = nh ? G : 0;
+      // slot s evaluates held task s mod nh at that task's nonce index
+      // h_next + s / nh (kept as running counters: no division per slot)
+      int h = 0;
+      uint32_t j = 0;
+      for (int s = 0; s < ns; s++) {
+        lds.s_h[s] = (uint8_t)h;
+        lds.s_att[s] = lds.h_next[h] + j;
+        if (++h == nh) {
+          h = 0;
+          j++;
+        }
       }
-      wave_sync();
-      assign_slots(lds.nheld, lds.nslots, lds.h_next, lds.h_win, lds.s_h, lds.s_att, lane);
+      for (h = 0; h < nh; h++) {
+        lds.h_next[h] += (uint32_t)(ns / nh + (h < ns % nh ? 1 : 0));
+        lds.h_win[h] = 0xFFFFFFFFu;
+      }
+      lds.nslots = ns;
+      lds.tally.evaluated += (uint64_t)ns;
     }
     __syncthreads();
     const int ns = lds.nslots;
@@ -428,11 +445,11 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
       int nh = lds.nheld, o = 0;
       for (int h = 0; h < nh; h++) {
         if (lds.h_win[h] != 0xFFFFFFFFu) {
-          tally.sequential += (uint64_t)lds.h_win[h] + 1;
+          lds.tally.sequential += (uint64_t)lds.h_win[h] + 1;
           continue;
         }
         if (lds.h_next[h] >= (uint32_t)PCfg<LV>::MAX_ATTEMPTS) {
-          tally.dropped++;
+          lds.tally.dropped++;
           continue;
         }
         lds.h_task[o] = lds.h_task[h];
@@ -443,7 +460,7 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
     }
     __syncthreads();
   }
-  if (tid == 0) tally.flush(stats);
+  if (tid == 0) lds.tally.flush(stats);
   PHASE_FLUSH();
 }
 

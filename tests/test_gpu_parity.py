@@ -423,6 +423,24 @@ def test_autotuner_picks_a_measured_candidate(ctx):
     c.close()
 
 
+def test_tuned_loop_kernels_keep_two_waves_per_simd():
+    """Every recorded (level, workgroup shape) of the Sign loop kernel fits two
+    wavefronts per SIMD: its registers stay within 256 VGPRs and its LDS within
+    half a CU.  One register more halves the resident workgroups, and the tuned
+    grids (512 / 1024 workgroups) would then run in two waves of launches."""
+    from paper_2211_12265_amd import autotune
+    from paper_2211_12265_amd import dilithium as dl
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    shapes = {(int(k.split("/")[0][1:]), v["waves"]) for k, v in autotune.load_cache().items()}
+    assert shapes
+    c = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    for level, waves in sorted(shapes):
+        c.set_param("persist.waves", waves)
+        resident, _ = c.persist_capacity(level)
+        assert resident * waves >= 2 * 4 * cus, (level, waves, resident)
+    c.close()
+
+
 @pytest.mark.parametrize("level", [2, 5])
 def test_message_lengths_at_block_boundaries(sctx, level):
     """mu = H(tr || M) with M ending on and around every SHAKE256 block boundary (the
