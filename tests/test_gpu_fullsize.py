@@ -1,7 +1,8 @@
-"""Full-size parity: 10,000-task batches in the launch configuration the benchmark times
-(persistent Sign with the automatic schedule, staged Verify), checked on outputs the oracle
-computes one by one for a random sample of tasks, plus properties that hold at any size
-(every signature verifies on the GPU, every level-2 flipped signature is rejected)."""
+"""Full-size parity: 10,000-task batches in the launch configurations the benchmark times
+(persistent Sign with the schedule the autotuner recorded for that workload, and with
+automatic schedules of one and four wavefronts per workgroup), checked on outputs the
+oracle computes one by one for a random sample of tasks, plus properties that hold at any
+size (every signature verifies on the GPU, every level-2 flipped signature is rejected)."""
 import numpy as np
 import pytest
 
@@ -12,15 +13,23 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("level,lengths,waves", [(2, "fixed32", 1), (2, "fixed32", 4), (3, "uniform", 1),
-                                                 (5, "uniform", 4)])
+@pytest.mark.parametrize("level,lengths,waves", [(2, "fixed32", 1), (2, "fixed32", 4), (2, "fixed32", "recorded"),
+                                                 (3, "uniform", 1), (3, "uniform", "recorded"),
+                                                 (5, "uniform", 4), (5, "uniform", "recorded")])
 def test_ten_thousand_tasks(level, lengths, waves):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    from paper_2211_12265_amd import autotune
     from paper_2211_12265_amd import dilithium as dl
     n = 10000
     ctx = dl.Context(0, mode=dl.MODE_PERSISTENT)
-    ctx.set_param("persist.waves", waves)
+    if waves == "recorded":
+        sched = autotune.cached_schedule(level, n, lengths)
+        assert sched is not None, "no recorded schedule for the benchmark workload"
+        autotune.apply_schedule(ctx, sched)
+        ctx.set_param("graph", 1)
+    else:
+        ctx.set_param("persist.waves", waves)
     pkl, skl, sgl = dl.sizes(level)
     seeds = workload.keygen_seeds(n, seed=level)
     pk = torch.zeros((n, pkl), dtype=torch.uint8, device="cuda")
