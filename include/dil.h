@@ -20,7 +20,9 @@
  *     is msg[msg_off[i] .. msg_off[i+1]) with msg_off holding count + 1
  *     uint64 entries on the device (lengths may be 0; any alignment).
  *   - key_idx may be NULL (task i uses key row i) or a device array of count
- *     uint32 key-row indices (resident key tables).
+ *     uint32 key-row indices (resident key tables).  Every index must name a
+ *     row of the key buffer or table: the device reads the rows without
+ *     bounds checks (the serving engine checks its requests on the host).
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = default stream).
  *     Calls that finish synchronously say so.  Output i always belongs to
  *     input i, whatever order the device processes tasks in.
@@ -185,8 +187,10 @@ int dil_server_stats(dil_server *s, uint64_t *batches, double *host_seconds);
  * after the call starts.  Sign writes its signature to sig_out + sig_out_off[i];
  * Verify reads sig_in + sig_in_off[i] and writes verdict[i] (1/0; -1 for Sign).
  * done_ns[i] receives the completion time on the same clock.  Blocks until
- * every request is done; returns DIL_EINVAL for malformed traces and DIL_EHIP
- * if a batch fails or no batch completes for 60 s. */
+ * every request is done; returns DIL_EINVAL for malformed traces (checked on
+ * the host before any work starts: unknown level or op, a key row outside the
+ * level's table, unsorted arrivals, bad message offsets, missing signature
+ * arrays) and DIL_EHIP if a batch fails or no batch completes for 60 s. */
 int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *level, const uint32_t *key,
                    const uint8_t *msg, const uint64_t *msg_off, const uint8_t *sig_in, const uint64_t *sig_in_off,
                    const uint64_t *arrival_ns, uint8_t *sig_out, const uint64_t *sig_out_off, int32_t *verdict,
@@ -219,7 +223,8 @@ int dil_ntt_mul_batch(dil_ctx *ctx, const int32_t *a, const int32_t *b, int32_t 
 
 /* Primitive: ExpandA rejection sampling (Sec. 2.3, Sec. 3.4) of count
  * polynomials from 34-byte inputs seeds[count][34] (SHAKE128, 3 bytes ->
- * 23-bit candidate, kept if < q) -> out[count][256] canonical int32. */
+ * 23-bit candidate, kept if < q) -> out[count][256] canonical int32.
+ * count must be below 2^32 (DIL_EINVAL otherwise). */
 int dil_expand_a_batch(dil_ctx *ctx, const uint8_t *seeds34, int32_t *out, uint64_t count, void *stream);
 
 #ifdef __cplusplus

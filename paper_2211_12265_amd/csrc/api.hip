@@ -548,7 +548,10 @@ int dil_ctx_create(dil_ctx **out, int device, size_t workspace_bytes) {
   }
   memset(c->host_counters, 0, 64);
   e = hipMalloc((void **)&c->dev_stats, 256);
-  if (e == hipSuccess) e = hipMemset(c->dev_stats, 0, 256);
+  if (e == hipSuccess) {
+    e = hipMemset(c->dev_stats, 0, 256);
+    if (e != hipSuccess) hipFree(c->dev_stats);
+  }
   if (e != hipSuccess) {
     hipHostFree(c->host_counters);
     delete c;
@@ -557,6 +560,7 @@ int dil_ctx_create(dil_ctx **out, int device, size_t workspace_bytes) {
   if (workspace_bytes) {
     e = hipMalloc(&c->ws_mem, workspace_bytes);
     if (e != hipSuccess) {
+      hipFree(c->dev_stats);
       hipHostFree(c->host_counters);
       delete c;
       return DIL_ENOMEM;
@@ -862,6 +866,7 @@ int dil_expand_a_batch(dil_ctx *ctx, const uint8_t *seeds34, int32_t *out, uint6
   if (!ctx) return DIL_EINVAL;
   if (count == 0) return DIL_OK;
   if (!seeds34 || !out) return fail(ctx, DIL_EINVAL, "null buffer");
+  if (count > (uint64_t)UINT32_MAX) return fail(ctx, DIL_EINVAL, "count above 2^32 - 1");
   hipSetDevice(ctx->device);
   expand_a_seed_k<<<blocks_for(count, EA_WG), EA_WG, 0, (hipStream_t)stream>>>(seeds34, out, count);
   LAUNCHCHK(ctx);

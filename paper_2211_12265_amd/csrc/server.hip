@@ -187,9 +187,14 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
   if (n == 0) return DIL_OK;
   if (!op || !level || !key || !msg || !msg_off || !arrival_ns || !verdict || !done_ns) return sfail(s, DIL_EINVAL, "null array");
   hipSetDevice(s->device);
+  uint32_t nkeys[NLV] = {0, 0, 0};
+  for (int li = 0; li < NLV; li++)
+    if (s->ks[li]) dil_keyset_info(s->ks[li], nullptr, &nkeys[li], nullptr);
   for (uint32_t i = 0; i < n; i++) {
     int li = lv_index(level[i]);
     if (li < 0 || !s->ks[li] || op[i] > 1) return sfail(s, DIL_EINVAL, "request names an unknown level or op");
+    // key rows are read on the device without bounds checks
+    if (key[i] >= nkeys[li]) return sfail(s, DIL_EINVAL, "request names a key row outside its level's table");
     if (i && arrival_ns[i] < arrival_ns[i - 1]) return sfail(s, DIL_EINVAL, "arrivals must be sorted");
     if (msg_off[i + 1] < msg_off[i] || msg_off[i + 1] - msg_off[i] > s->max_msg)
       return sfail(s, DIL_EINVAL, "bad message offset or message larger than the staging buffer");

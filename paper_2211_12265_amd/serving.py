@@ -61,6 +61,28 @@ def sig_size(level: int) -> int:
     return dl.sizes(level)[2]
 
 
+def check_requests(reqs: Requests, n_keys: Dict[int, int]) -> None:
+    """Reject a malformed trace before any of it runs: the key-table calls read key rows on
+    the device without bounds checks, so every request must name a level that has a table
+    (n_keys: level -> rows) and a row inside it."""
+    n = len(reqs)
+    if reqs.msg_off.size != n + 1 or (n and (np.diff(reqs.msg_off) < 0).any()):
+        raise ValueError("msg_off must hold n + 1 non-decreasing offsets")
+    if n and (np.diff(reqs.t_arrival) < 0).any():
+        raise ValueError("arrivals must be sorted")
+    if not np.isin(reqs.op, (SIGN, VERIFY)).all():
+        raise ValueError("op must be 0 (sign) or 1 (verify)")
+    for lv in np.unique(reqs.level):
+        lv = int(lv)
+        if lv not in n_keys:
+            raise ValueError(f"no key table for level {lv}")
+        keys = reqs.key[reqs.level == lv]
+        if (keys < 0).any() or (keys >= n_keys[lv]).any():
+            raise ValueError(f"a level-{lv} request names a key row outside its table ({n_keys[lv]} rows)")
+    if (reqs.op == VERIFY).any() and (reqs.sig_in is None or reqs.sig_off is None):
+        raise ValueError("verify requests need signatures")
+
+
 def _gather(buf: np.ndarray, starts: np.ndarray, lens: np.ndarray) -> np.ndarray:
     """Concatenate buf[starts[i] : starts[i] + lens[i]] without a Python loop."""
     total = int(lens.sum())
@@ -192,6 +214,7 @@ class Server:
     # ---- the loop ----
     def serve(self, reqs: Requests, time_scale: float = 1.0) -> Results:
         """Run the request stream; arrivals are honoured in real time (t_arrival * time_scale)."""
+        check_requests(reqs, {lv: ks.n_keys for lv, ks in self.keysets.items()})
         n = len(reqs)
         res = Results(verdict=np.full(n, -1, np.int32), t_done=np.full(n, np.nan))
         cost = np.array([self._cost(reqs, i) for i in range(n)], dtype=np.int64)

@@ -87,3 +87,24 @@ def test_same_alone_and_in_mix(setup, engine):
         else:
             assert alone.verdict[0] == mixed.verdict[r]
     server.close()
+
+
+@pytest.mark.parametrize("engine", ["python", "native"])
+def test_out_of_range_key_rejected_before_any_work(setup, engine):
+    """A request naming a key row past its level's table is refused on the host (the device
+    reads key rows without bounds checks), and the engine then still serves a valid trace."""
+    dl, sv, ctx, keysets, host, reqs, flipped = setup
+    cls = sv.Server if engine == "python" else sv.NativeServer
+    server = cls(keysets, n_streams=2, max_batch=64, mem_budget=4 << 20, max_msg_bytes=1 << 20)
+    bad = sv.Requests(**vars(reqs))
+    bad.key = reqs.key.copy()
+    bad.key[int(np.argmax(reqs.level == 5))] = keysets[5].n_keys
+    with pytest.raises((ValueError, dl.DilError)) as err:
+        server.serve(bad)
+    if engine == "native":
+        assert err.value.code == -1   # DIL_EINVAL
+    res = server.serve(reqs)
+    server.close()
+    assert np.isfinite(res.t_done).all()
+    v = reqs.op == sv.VERIFY
+    assert np.array_equal(res.verdict[v] == 0, flipped[v])

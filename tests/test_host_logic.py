@@ -73,3 +73,30 @@ def test_input_generators_are_seeded():
     assert o1[0] == 0 and np.all(np.diff(o1.astype(np.int64)) >= 0)
     s = workload.keygen_seeds(4, seed=1)
     assert s.shape == (4, 32) and s.dtype == np.uint8
+
+
+def test_serving_trace_check_rejects_bad_requests():
+    """The Python serving loop refuses, before any device work, a trace whose key rows fall
+    outside their level's table (the device would read past the table), an unknown level
+    or op, unsorted arrivals and bad message offsets."""
+    import pytest
+    keys = {2: 12, 3: 7, 5: 5}
+    reqs = serving.build_requests(200, lam=1000.0, keys_per_level=keys, seed=3)
+    reqs.sig_in = np.zeros(1, np.uint8)
+    reqs.sig_off = np.zeros(len(reqs), np.int64)
+    serving.check_requests(reqs, keys)
+    bad_cases = []
+    r = serving.Requests(**vars(reqs)); r.key = reqs.key.copy(); r.key[np.argmax(reqs.level == 3)] = 7
+    bad_cases.append((r, keys))
+    r = serving.Requests(**vars(reqs)); r.key = reqs.key.copy(); r.key[0] = -1
+    bad_cases.append((r, keys))
+    bad_cases.append((reqs, {2: 12, 3: 7}))
+    r = serving.Requests(**vars(reqs)); r.op = reqs.op.copy(); r.op[5] = 2
+    bad_cases.append((r, keys))
+    r = serving.Requests(**vars(reqs)); r.t_arrival = reqs.t_arrival[::-1].copy()
+    bad_cases.append((r, keys))
+    r = serving.Requests(**vars(reqs)); r.msg_off = reqs.msg_off.copy(); r.msg_off[3] = r.msg_off[4] + 1
+    bad_cases.append((r, keys))
+    for r, k in bad_cases:
+        with pytest.raises(ValueError):
+            serving.check_requests(r, k)
