@@ -81,11 +81,12 @@ int dil_ctx_set_mode(dil_ctx *ctx, int mode);
  *                   value is DIL_EINVAL;
  *   "timing"        1 = record HIP events around the persistent Sign's setup
  *                   kernels and its loop kernel (read with dil_sign_timing);
- *   "graph"         1 = capture the launch sequence of persistent-mode Sign and
- *                   of Verify into hipGraphs, replayed when a call repeats
- *                   the same level, buffers, count and schedule (up to 16
- *                   graphs per context, least recently used evicted; dropped
- *                   when the workspace grows);
+ *   "graph"         1 = capture the launch sequences of persistent-mode Sign's
+ *                   setup stages and of Verify into hipGraphs, replayed when a
+ *                   call repeats the same level, buffers, count and schedule
+ *                   (up to 16 graphs per context, least recently used
+ *                   evicted; dropped when the workspace grows); the Sign loop
+ *                   kernel, a single launch, is always launched directly;
  *   "ntt.variant"   form of dil_ntt_mul_batch, for the optimisation ablation
  *                   of the NTT primitive (Sec. 3.2, Sec. 4.2); every form
  *                   returns the same words: 0 (default) levels merged in

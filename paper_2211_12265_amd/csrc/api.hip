@@ -393,18 +393,15 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   });
   if (rc) return rc;
   if (evs) HIPCHK(ctx, hipEventRecord(evs[1], st));
-  key[12] = 1;  // second graph: the loop kernel
-  rc = enqueue(ctx, key, st, [&](hipStream_t s) {
-    if (waves == 4)
-      sg_persistw_k<LV, 4><<<(unsigned)grid, 256, 0, s>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
-    else if (waves == 2)
-      sg_persistw_k<LV, 2><<<(unsigned)grid, 128, 0, s>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
-    else
-      sg_persist_k<LV><<<(unsigned)grid, 64, 0, s>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
-    LAUNCHCHK(ctx);
-    return DIL_OK;
-  });
-  if (rc) return rc;
+  // The loop kernel is one launch: it is launched directly, also when graphs
+  // are enabled (as a graph node it measured 2-4% slower).
+  if (waves == 4)
+    sg_persistw_k<LV, 4><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+  else if (waves == 2)
+    sg_persistw_k<LV, 2><<<(unsigned)grid, 128, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+  else
+    sg_persist_k<LV><<<(unsigned)grid, 64, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+  LAUNCHCHK(ctx);
   if (evs) {
     HIPCHK(ctx, hipEventRecord(evs[2], st));
     ctx->ev_count++;
