@@ -100,6 +100,42 @@ __global__ void __launch_bounds__(256) kg_seed_k(const uint8_t *seeds, uint8_t *
 constexpr int EA_ROW = RATE128 / 4 + 1;  // 43 words: odd stride, conflict-free staging
 constexpr int EA_STEP = 4;                // unfinished streams tested per step
 constexpr int EA_WG = 64;                 // one wavefront per workgroup (11 KiB of LDS)
+// Blocks after which another permutation is always needed: a block holds
+// RATE128 / 3 = 56 candidates, so at least ceil(N / 56) = 5 blocks are squeezed.
+constexpr int EA_SURE = (N + RATE128 / 3 - 1) / (RATE128 / 3) - 1;
+
+// One compaction step for up to EA_STEP streams Ls[u] (act[u]: stream u of
+// the step is unfinished), split in two halves so that independent work can
+// be issued between them: ea_probe reads the candidates from LDS and the
+// streams' counters; ea_commit ballots, stores the accepted values and
+// advances the counters.
+struct EaProbe {
+  uint32_t tv[EA_STEP];
+  int cL[EA_STEP];
+};
+__device__ __forceinline__ EaProbe ea_probe(const uint32_t *rows, const int Ls[EA_STEP], int ctr, int wi,
+                                            uint32_t sh) {
+  EaProbe p;
+#pragma unroll
+  for (int u = 0; u < EA_STEP; u++) {
+    const uint32_t *rL = rows + Ls[u] * EA_ROW;
+    p.tv[u] = __builtin_amdgcn_alignbit(rL[wi + 1], rL[wi], sh) & 0x7FFFFFu;
+    p.cL[u] = __builtin_amdgcn_readlane(ctr, Ls[u]);  // the streams' lanes are distinct
+  }
+  return p;
+}
+__device__ __forceinline__ void ea_commit(const EaProbe &p, const int Ls[EA_STEP], const bool act[EA_STEP], bool cand,
+                                          int32_t *out0, int &ctr, int lane) {
+#pragma unroll
+  for (int u = 0; u < EA_STEP; u++) {
+    const bool ok = act[u] && cand && p.tv[u] < (uint32_t)Q;
+    const uint64_t m = __ballot(ok);
+    const int pos =
+        p.cL[u] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    if (ok && pos < N) out0[(size_t)Ls[u] * N + pos] = (int32_t)p.tv[u];
+    if (act[u] && lane == Ls[u]) ctr = min(N, p.cL[u] + (int)__popcll(m));
+  }
+}
 
 __device__ __forceinline__ void expand_a_squeeze_wave(uint32_t s[50], int32_t *out0, uint32_t *rows, int lane,
                                                       bool valid) {
@@ -110,6 +146,39 @@ __device__ __forceinline__ void expand_a_squeeze_wave(uint32_t s[50], int32_t *o
   const bool cand = lane < RATE128 / 3;
   const int wi = cand ? (3 * lane) >> 2 : 0;
   const uint32_t sh = cand ? 8u * (uint32_t)((3 * lane) & 3) : 0u;
+  // Blocks 0 .. EA_SURE - 1: the next permutation is certain, so it runs
+  // during the compaction of the staged block (the state and the LDS rows are
+  // independent): every stream is tested in 64 / EA_STEP steps, and the 24
+  // rounds are spread over them, so the Keccak ALU work covers the latency of
+  // the steps' LDS reads and ballots.
+  static_assert(64 / EA_STEP == 16, "the round schedule below assumes 16 steps of 4 streams");
+  for (int blk = 0; blk < EA_SURE; blk++) {
+#pragma unroll
+    for (int w = 0; w < RATE128 / 4; w++) row[w] = s[w];
+    wave_sync();
+    const uint64_t pending = __ballot(ctr < N);
+#pragma unroll 1
+    for (int it = 0; it < 8; it++) {  // two steps and three rounds per iteration
+      int La[EA_STEP], Lb[EA_STEP];
+      bool aa[EA_STEP], ab[EA_STEP];
+#pragma unroll
+      for (int u = 0; u < EA_STEP; u++) {
+        La[u] = 2 * EA_STEP * it + u;
+        Lb[u] = La[u] + EA_STEP;
+        aa[u] = (pending >> La[u]) & 1;
+        ab[u] = (pending >> Lb[u]) & 1;
+      }
+      const EaProbe pa = ea_probe(rows, La, ctr, wi, sh);
+      keccak_round(s, 3 * it);
+      keccak_round(s, 3 * it + 1);
+      ea_commit(pa, La, aa, cand, out0, ctr, lane);
+      const EaProbe pb = ea_probe(rows, Lb, ctr, wi, sh);
+      keccak_round(s, 3 * it + 2);
+      ea_commit(pb, Lb, ab, cand, out0, ctr, lane);
+    }
+    wave_sync();
+  }
+  // later blocks: compact first, then permute only if a stream is unfinished
   for (;;) {
 #pragma unroll
     for (int w = 0; w < RATE128 / 4; w++) row[w] = s[w];
@@ -126,25 +195,8 @@ __device__ __forceinline__ void expand_a_squeeze_wave(uint32_t s[50], int32_t *o
         Ls[u] = act[u] ? __builtin_ctzll(pending) : 0;
         pending &= pending - 1;
       }
-      uint32_t tv[EA_STEP];
-      bool ok[EA_STEP];
-      int cL[EA_STEP];
-#pragma unroll
-      for (int u = 0; u < EA_STEP; u++) {
-        const uint32_t *rL = rows + Ls[u] * EA_ROW;
-        tv[u] = __builtin_amdgcn_alignbit(rL[wi + 1], rL[wi], sh) & 0x7FFFFFu;
-        ok[u] = act[u] && cand && tv[u] < (uint32_t)Q;
-        cL[u] = __builtin_amdgcn_readlane(ctr, Ls[u]);  // the streams' lanes are distinct
-      }
-#pragma unroll
-      for (int u = 0; u < EA_STEP; u++) {
-        if (!act[u]) continue;  // wave-uniform
-        const uint64_t m = __ballot(ok[u]);
-        const int pos =
-            cL[u] + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        if (ok[u] && pos < N) out0[(size_t)Ls[u] * N + pos] = (int32_t)tv[u];
-        if (lane == Ls[u]) ctr = min(N, cL[u] + (int)__popcll(m));
-      }
+      const EaProbe p = ea_probe(rows, Ls, ctr, wi, sh);
+      ea_commit(p, Ls, act, cand, out0, ctr, lane);
     }
     wave_sync();
     if (__ballot(ctr < N) == 0) break;
