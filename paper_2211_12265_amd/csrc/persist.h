@@ -3,16 +3,17 @@
 // The paper's host scheduler (Sec. 4.3) refills idle execution units between
 // kernel rounds and predicts nonces for unfinished tasks, keeping the valid
 // signature with the smallest nonce.  Here the whole rejection loop runs in
-// one launch: each wavefront (one 64-lane workgroup) claims tasks from a
-// global atomic counter and owns them until they are signed.  Per batch it
-// evaluates G candidate iterations ("slots"); when it holds fewer than G
-// tasks, the spare slots evaluate later iterations kappa + l*m of the same
-// tasks.  Iterations of one task are assigned in increasing order and every
-// earlier iteration has already failed, so the smallest passing kappa of the
-// batch is the sequential algorithm's answer and is written straight to the
-// task's signature row.  Stages run back to back inside the batch:
-//   ExpandMask (one lane per stream) -> w = A y per slot (4 groups) ->
-//   ctilde and SampleInBall (one lane per slot) -> checks per slot.
+// one launch: each workgroup (one wavefront in sg_persist_k, two or four in
+// sg_persistw_k) claims tasks from a global atomic counter and owns them
+// until they are signed.  Per batch it evaluates G candidate iterations
+// ("slots"); when it holds fewer than G tasks, the spare slots evaluate later
+// iterations kappa + l*m of the same tasks.  Iterations of one task are
+// assigned in increasing order and every earlier iteration has already
+// failed, so the smallest passing kappa of the batch is the sequential
+// algorithm's answer and becomes the task's signature.  Stages run back to
+// back inside the batch:
+//   ExpandMask (one lane per stream) -> w = A y per slot (4 groups of 16
+//   lanes) -> ctilde and SampleInBall (two lanes per slot) -> checks per slot.
 #pragma once
 #include "kernels.h"
 
