@@ -851,23 +851,32 @@ __global__ void __launch_bounds__(64) vf_main_k(const uint8_t *pk, const uint32_
   using PP = P<LV>;
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L, BETA = Lv<LV>::BETA;
   constexpr int32_t G1 = Lv<LV>::GAMMA1;
+  // The signature's bytes are read only to unpack z; t1 (from pk) and the
+  // packed w1' rows are used only after that, so the three share one region
+  // (less LDS per workgroup, more resident workgroups).  pk is fetched into
+  // registers up front and written to the region once z is unpacked.
+  constexpr int SIGW = PP::SIG / 4 + 3, PKW = PP::PK / 4, W1W = K * PP::W1B / 4 + 1;
+  constexpr int PKPER = (PKW + 63) / 64;
   __shared__ int32_t trl[4 * NTT_LDS_GROUP];
   __shared__ int32_t zh[L * HAT_POLY];
-  __shared__ uint32_t sigw[PP::SIG / 4 + 3];
-  __shared__ uint32_t pkw[PP::PK / 4 + 2];
-  __shared__ uint32_t w1b[K * PP::W1B / 4 + 1];
+  __shared__ uint32_t region[SIGW > PKW + 2 + W1W ? SIGW : PKW + 2 + W1W];
+  uint32_t *const sigw = region, *const pkw = region, *const w1b = region + PKW + 2;
   uint32_t task = blockIdx.x;
   if (task >= count) return;
   int lane = threadIdx.x, g = lane >> 4, t = lane & 15;
   int32_t *tr = trl + g * NTT_LDS_GROUP;
   size_t key = key_idx ? key_idx[task] : task;
-  g2l_bytes<PP::SIG>(sig + (size_t)task * PP::SIG, sigw, lane);
-  if (lane < 2) sigw[PP::SIG / 4 + 1 + lane] = 0;
+  uint32_t pkv[PKPER];
   if (!ws.t1h) {
     const uint32_t *pkg = (const uint32_t *)(pk + key * PP::PK);
-    g2l_words<PP::PK / 4>(pkg, pkw, lane);
-    if (lane < 2) pkw[PP::PK / 4 + lane] = 0;
+#pragma unroll
+    for (int q = 0; q < PKPER; q++) {
+      const int i = lane + 64 * q;
+      pkv[q] = i < PKW ? pkg[i] : 0u;
+    }
   }
+  g2l_bytes<PP::SIG>(sig + (size_t)task * PP::SIG, sigw, lane);
+  if (lane < 2) sigw[PP::SIG / 4 + 1 + lane] = 0;
   wave_sync();
   const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
   int32_t ch[16];
@@ -894,6 +903,15 @@ __global__ void __launch_bounds__(64) vf_main_k(const uint8_t *pk, const uint32_
   }
   bad = wave_any(bad);
   wave_sync();
+  if (!ws.t1h) {  // z is unpacked: the region now takes t1
+#pragma unroll
+    for (int q = 0; q < PKPER; q++) {
+      const int i = lane + 64 * q;
+      if (i < PKW) pkw[i] = pkv[q];
+    }
+    if (lane < 2) pkw[PKW + lane] = 0;
+    wave_sync();
+  }
   const uint32_t *hm = ws.hmask + (size_t)task * K * 8;
   for (int i = g; i < K; i += 4) {
     const int32_t *Ai = ws.A + (kix(ws, task) * K + i) * L * N;
