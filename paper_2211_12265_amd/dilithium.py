@@ -96,6 +96,20 @@ def sizes(level: int) -> Tuple[int, int, int]:
     return pk.value, sk.value, sg.value
 
 
+def _require(checks) -> None:
+    """Host-side size checks of a call's buffers, before anything is launched: the kernels
+    index rows and offsets without bounds checks, so an undersized tensor would be read or
+    written past its end on the device.  checks: (tensor or None, minimum bytes, required
+    element size or 0, name); None tensors are skipped."""
+    for t, nbytes, esize, name in checks:
+        if t is None:
+            continue
+        if esize and t.element_size() != esize:
+            raise ValueError(f"{name}: elements of {esize} bytes expected, got {t.dtype}")
+        if t.numel() * t.element_size() < nbytes:
+            raise ValueError(f"{name}: {nbytes} bytes needed, tensor holds {t.numel() * t.element_size()}")
+
+
 def _ptr(t) -> Optional[int]:
     if t is None:
         return None
@@ -153,11 +167,16 @@ class Context:
 
     def keygen(self, level: int, seeds, pk, sk, stream=None):
         n = seeds.shape[0]
+        pkl, skl, _ = sizes(level)
+        _require([(seeds, 32 * n, 1, "seeds"), (pk, pkl * n, 1, "pk"), (sk, skl * n, 1, "sk")])
         self._check(self.lib.dil_keygen_batch(self.h, level, _ptr(seeds), _ptr(pk), _ptr(sk), n, _stream(stream)))
 
     def sign(self, level: int, sk, msg, msg_off, sig, key_idx=None, stream=None, rnd=None):
         """rnd: optional uint8 device tensor [count, 64], the rho' of each task (randomized signing)."""
         n = msg_off.shape[0] - 1
+        _, skl, sgl = sizes(level)
+        _require([(msg_off, 8 * (n + 1), 8, "msg_off"), (sig, sgl * n, 1, "sig"),
+                  (sk, skl * (n if key_idx is None else 1), 1, "sk"), (key_idx, 4 * n, 4, "key_idx")])
         if rnd is None:
             self._check(self.lib.dil_sign_batch(self.h, level, _ptr(sk), _ptr(key_idx), _ptr(msg) or _ptr(msg_off),
                                                 _ptr(msg_off), _ptr(sig), n, _stream(stream)))
@@ -170,6 +189,9 @@ class Context:
 
     def verify(self, level: int, pk, msg, msg_off, sig, verdict, key_idx=None, stream=None):
         n = msg_off.shape[0] - 1
+        pkl, _, sgl = sizes(level)
+        _require([(msg_off, 8 * (n + 1), 8, "msg_off"), (sig, sgl * n, 1, "sig"), (verdict, 4 * n, 4, "verdict"),
+                  (pk, pkl * (n if key_idx is None else 1), 1, "pk"), (key_idx, 4 * n, 4, "key_idx")])
         self._check(self.lib.dil_verify_batch(self.h, level, _ptr(pk), _ptr(key_idx), _ptr(msg) or _ptr(msg_off),
                                               _ptr(msg_off), _ptr(sig), _ptr(verdict), n, _stream(stream)))
 
@@ -232,10 +254,14 @@ class KeySet:
 
     def sign(self, ctx: Context, key_idx, msg, msg_off, sig, stream=None):
         n = msg_off.shape[0] - 1
+        _require([(msg_off, 8 * (n + 1), 8, "msg_off"), (sig, sizes(self.level)[2] * n, 1, "sig"),
+                  (key_idx, 4 * n, 4, "key_idx")])
         ctx._check(self.lib.dil_sign_keyset(ctx.h, self.h, _ptr(key_idx), _ptr(msg) or _ptr(msg_off), _ptr(msg_off),
                                             _ptr(sig), n, _stream(stream)))
 
     def verify(self, ctx: Context, key_idx, msg, msg_off, sig, verdict, stream=None):
         n = msg_off.shape[0] - 1
+        _require([(msg_off, 8 * (n + 1), 8, "msg_off"), (sig, sizes(self.level)[2] * n, 1, "sig"),
+                  (verdict, 4 * n, 4, "verdict"), (key_idx, 4 * n, 4, "key_idx")])
         ctx._check(self.lib.dil_verify_keyset(ctx.h, self.h, _ptr(key_idx), _ptr(msg) or _ptr(msg_off),
                                               _ptr(msg_off), _ptr(sig), _ptr(verdict), n, _stream(stream)))

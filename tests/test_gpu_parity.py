@@ -343,9 +343,12 @@ def test_keyset_sign_verify_parity(sctx, level):
         expect = oracle.verify_batch(level, pk.cpu().numpy(), msg, off, bad, key_idx=kidx)
         assert np.array_equal(v.cpu().numpy(), expect)
         assert expect.sum() == n - len(range(0, n, 3))
-    with pytest.raises(dl.DilError):
-        ks_pk.sign(sctx, None, dev(msg), dev(off.astype(np.int64)), torch.zeros((n, 8), dtype=torch.uint8,
-                                                                                device="cuda"))
+    with pytest.raises(dl.DilError):   # a table without secret keys cannot sign
+        ks_pk.sign(sctx, None, dev(msg), dev(off.astype(np.int64)),
+                   torch.zeros((n, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda"))
+    with pytest.raises(ValueError):    # an undersized output is refused before any launch
+        ks_sk.sign(sctx, dev(kidx.astype(np.int32)), dev(msg), dev(off.astype(np.int64)),
+                   torch.zeros((n, 8), dtype=torch.uint8, device="cuda"))
     for ks in (ks_both, ks_pk, ks_sk):
         ks.close()
 

@@ -100,3 +100,23 @@ def test_serving_trace_check_rejects_bad_requests():
     for r, k in bad_cases:
         with pytest.raises(ValueError):
             serving.check_requests(r, k)
+
+
+def test_binding_rejects_undersized_buffers():
+    """The ctypes binding checks buffer sizes and element widths on the host before a call
+    is launched (the kernels index rows and offsets without bounds checks)."""
+    import pytest
+    import torch
+    from paper_2211_12265_amd.dilithium import _require
+    n = 5
+    off = torch.zeros(n + 1, dtype=torch.int64)
+    sig = torch.zeros((n, 2420), dtype=torch.uint8)
+    _require([(off, 8 * (n + 1), 8, "msg_off"), (sig, 2420 * n, 1, "sig"), (None, 4 * n, 4, "key_idx")])
+    with pytest.raises(ValueError):
+        _require([(off[:n], 8 * (n + 1), 8, "msg_off")])
+    with pytest.raises(ValueError):
+        _require([(off.to(torch.int32), 8 * (n + 1), 8, "msg_off")])
+    with pytest.raises(ValueError):
+        _require([(sig[:n - 1], 2420 * n, 1, "sig")])
+    with pytest.raises(ValueError):
+        _require([(torch.zeros(n, dtype=torch.int64), 4 * n, 4, "key_idx")])
