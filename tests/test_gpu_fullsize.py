@@ -65,6 +65,42 @@ def test_ten_thousand_tasks(level, lengths, waves):
     ctx.close()
 
 
+@pytest.mark.parametrize("level", [2, 5])
+def test_ten_thousand_tasks_randomized(level):
+    """Randomized Sign (caller-supplied rho' per task) at the benchmark's size and recorded
+    schedule: sampled signatures equal the oracle's for the same rho', and every signature
+    verifies on the GPU."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import autotune
+    from paper_2211_12265_amd import dilithium as dl
+    n = 10000
+    lengths = "fixed32" if level == 2 else "uniform"
+    ctx = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    autotune.apply_schedule(ctx, autotune.cached_schedule(level, n, lengths))
+    pkl, skl, sgl = dl.sizes(level)
+    seeds = workload.keygen_seeds(n, seed=300 + level)
+    pk = torch.zeros((n, pkl), dtype=torch.uint8, device="cuda")
+    sk = torch.zeros((n, skl), dtype=torch.uint8, device="cuda")
+    ctx.keygen(level, torch.from_numpy(seeds).cuda(), pk, sk)
+    lens = workload.fixed_lengths(n, 32) if lengths == "fixed32" else workload.uniform_lengths(n, 32, 4096, seed=301)
+    msg, off = workload.messages(lens, seed=301)
+    rnd = workload.random_bytes("test/rnd", 300 + level, (n, 64))
+    gm, go = torch.from_numpy(msg).cuda(), torch.from_numpy(off.astype(np.int64)).cuda()
+    sig = torch.zeros((n, sgl), dtype=torch.uint8, device="cuda")
+    ctx.sign(level, sk, gm, go, sig, rnd=torch.from_numpy(rnd).cuda())
+    ver = torch.zeros(n, dtype=torch.int32, device="cuda")
+    ctx.verify(level, pk, gm, go, sig, ver)
+    torch.cuda.synchronize()
+    assert int(ver.sum()) == n
+    idx = np.sort(np.random.default_rng(302).choice(n, size=32, replace=False))
+    sub_msg = np.concatenate([msg[int(off[i]):int(off[i + 1])] for i in idx])
+    sub_off = np.concatenate([[0], np.cumsum(lens[idx])]).astype(np.uint64)
+    osig, _ = oracle.sign_batch(level, sk.cpu().numpy()[idx], sub_msg, sub_off, rnd=rnd[idx])
+    assert np.array_equal(sig.cpu().numpy()[idx], osig)
+    ctx.close()
+
+
 @pytest.mark.parametrize("mode", ["staged", "persistent"])
 @pytest.mark.parametrize("level", [2, 3, 5])
 def test_single_task(mode, level):
