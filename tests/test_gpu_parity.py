@@ -256,7 +256,7 @@ def test_empty_batch_and_bad_level(ctx):
         ctx.sign(4, z, z, torch.zeros(2, dtype=torch.int64, device="cuda"), z)
 
 
-@pytest.mark.parametrize("level", [2, 5])
+@pytest.mark.parametrize("level", [2, 3, 5])
 @pytest.mark.parametrize("waves,grid,hmax", [(1, 1, 1), (1, 3, 2), (1, 7, 16), (1, 0, 0),
                                              (2, 1, 1), (2, 5, 3), (2, 0, 0),
                                              (4, 1, 1), (4, 3, 5), (4, 2, 64), (4, 0, 0)])
