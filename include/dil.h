@@ -21,8 +21,9 @@
  *     uint64 entries on the device (lengths may be 0; any alignment).
  *   - key_idx may be NULL (task i uses key row i) or a device array of count
  *     uint32 key-row indices (resident key tables).  Every index must name a
- *     row of the key buffer or table: the device reads the rows without
- *     bounds checks (the serving engine checks its requests on the host).
+ *     row of the key buffer: the batch entry points read the rows without
+ *     bounds checks.  The key-table entry points check them on the device
+ *     (see dil_sign_keyset).
  *   - Work is enqueued on `stream` (a hipStream_t; NULL = default stream).
  *     Calls that finish synchronously say so.  Output i always belongs to
  *     input i, whatever order the device processes tasks in.
@@ -33,7 +34,8 @@
  *       DIL_EHIP    a HIP launch/copy failed (dil_last_error() has the text);
  *       DIL_EMSG    a decreasing msg_off entry was found (detected on the
  *                   device; reported by calls that synchronise, and by
- *                   dil_ctx_check()).
+ *                   dil_ctx_check()); a key-table index outside its table
+ *                   is reported the same way, as DIL_EINVAL.
  *     A malformed signature is not an error: its verdict is 0 (Alg. 3).
  *   - One context serves one host thread at a time; calls that overlap on
  *     one context race on its workspace.
@@ -154,7 +156,10 @@ int dil_keyset_destroy(dil_keyset *ks);
 int dil_keyset_info(const dil_keyset *ks, int *level, uint32_t *n_keys, size_t *device_bytes);
 /* dil_sign_batch / dil_verify_batch against a key table: task i uses key row
  * key_idx[i] (device array), or row i when key_idx is NULL.  Outputs are
- * identical to the batch entry points given the same key rows. */
+ * identical to the batch entry points given the same key rows.  An index
+ * outside the table is replaced by row 0 on the device before any key row is
+ * read, and the error is reported as DIL_EINVAL by the next call that
+ * synchronises (staged-mode Sign itself, or dil_ctx_check()). */
 int dil_sign_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx, const uint8_t *msg,
                     const uint64_t *msg_off, uint8_t *sig, uint32_t count, void *stream);
 int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx, const uint8_t *msg,

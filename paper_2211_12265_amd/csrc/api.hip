@@ -92,7 +92,7 @@ size_t ws_need(size_t cap) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
   size_t muw1 = ((size_t)P<LV>::MUW1 + 255) & ~(size_t)255;
   size_t per = muw1 + 64 + 32 + 256 + (size_t)K * L * 1024 + (size_t)(L + K) * 1024 + 2 * (size_t)K * 1024 +
-               (size_t)L * 1024 + (size_t)K * 1024 + (size_t)K * 32 + 4 * 4;
+               (size_t)L * 1024 + (size_t)K * 1024 + (size_t)K * 32 + 5 * 4;
   return cap * per + 16 * 256 + 4096;
 }
 
@@ -111,7 +111,8 @@ size_t pscr_need(size_t grid, int waves) {
 }
 
 template <int LV>
-int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws, size_t grid = 0, PScr *sc = nullptr, int waves = 1) {
+int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws, size_t grid = 0, PScr *sc = nullptr, int waves = 1,
+             uint32_t **kidx = nullptr) {
   size_t need = ws_need<LV>(cap) + (sc ? pscr_need<LV>(grid, waves) : 0);
   if (need > ctx->ws_bytes) {
     if (ctx->ws_mem) {
@@ -156,6 +157,8 @@ int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws, size_t grid = 0, PScr *sc = nullp
   ws.flag = (int32_t *)take(cap * 4);
   ws.active0 = (uint32_t *)take(cap * 4);
   ws.active1 = (uint32_t *)take(cap * 4);
+  uint32_t *kid = (uint32_t *)take(cap * 4);  // checked key indices of key-table calls
+  if (kidx) *kidx = kid;
   if (sc) {
     size_t G = persist_slots<LV>(waves);
     size_t w1s = ((size_t)K * P<LV>::W1B + 255) & ~(size_t)255;
@@ -168,15 +171,17 @@ int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws, size_t grid = 0, PScr *sc = nullp
   return DIL_OK;
 }
 
-// read and clear the device-side message-offset error flag (synchronises `st`)
+// read and clear the device-side input error words (synchronises `st`):
+// dev_stats[8] a decreasing msg_off entry, dev_stats[9] a key index outside a
+// key table
 int take_msg_error(dil_ctx *ctx, hipStream_t st) {
-  uint32_t flag = 0;
-  HIPCHK(ctx, hipMemcpyAsync(ctx->host_counters + 8, ctx->dev_stats + 8, 4, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->host_counters + 8, ctx->dev_stats + 8, 8, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
-  flag = ctx->host_counters[8];
-  if (flag) {
-    HIPCHK(ctx, hipMemsetAsync(ctx->dev_stats + 8, 0, 4, st));
+  const uint32_t msg_flag = ctx->host_counters[8], key_flag = ctx->host_counters[9];
+  if (msg_flag || key_flag) {
+    HIPCHK(ctx, hipMemsetAsync(ctx->dev_stats + 8, 0, 8, st));
     HIPCHK(ctx, hipStreamSynchronize(st));
+    if (key_flag) return fail(ctx, DIL_EINVAL, "key index outside the key table (those tasks used key row 0)");
     return fail(ctx, DIL_EMSG, "decreasing msg_off entry (those messages were treated as empty)");
   }
   return DIL_OK;
@@ -270,15 +275,25 @@ int keygen_impl(dil_ctx *ctx, const uint8_t *seeds, uint8_t *pk, uint8_t *sk, ui
   return DIL_OK;
 }
 
-// Resident key tables replace the per-task A-hat / NTT(s) arrays (no ExpandA, no secret NTTs)
-void use_keyset(Ws &ws, const dil_keyset *ks, const uint32_t *key_idx) {
+// Resident key tables replace the per-task A-hat / NTT(s) arrays (no ExpandA,
+// no secret NTTs).  A caller's key_idx is read only once, by keys_check_k
+// (check_keys below), which writes a copy with every index inside the table
+// to `checked`; every other kernel of the call reads that copy, which this
+// returns (nullptr when the call has no key_idx: task i uses row i).
+const uint32_t *use_keyset(Ws &ws, const dil_keyset *ks, const uint32_t *key_idx, uint32_t *checked) {
   ws.A = ks->A;
   ws.s1h = ks->s1h;
   ws.s2h = ks->s2h;
   ws.t0h = ks->t0h;
   ws.t1h = ks->t1h;
   ws.tr = ks->tr;
-  ws.kmap = key_idx;
+  ws.kmap = key_idx ? checked : nullptr;
+  return ws.kmap;
+}
+void check_keys(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx, uint32_t *checked, uint32_t count,
+                hipStream_t st) {
+  if (ks && key_idx)
+    keys_check_k<<<blocks_for(count, 256), 256, 0, st>>>(key_idx, ks->nkeys, checked, count, ctx->dev_stats + 9);
 }
 
 // The setup stages are independent of each other: mu/rho' hash chains (one lane
@@ -311,9 +326,13 @@ int sign_staged(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const 
                 const uint8_t *rnd = nullptr) {
   constexpr int L = Lv<LV>::L;
   Ws ws;
-  int rc = ws_carve<LV>(ctx, count, ws);
+  uint32_t *kid = nullptr;
+  int rc = ws_carve<LV>(ctx, count, ws, 0, nullptr, 1, &kid);
   if (rc) return rc;
-  if (ks) use_keyset(ws, ks, key_idx);
+  if (ks) {
+    check_keys(ctx, ks, key_idx, kid, count, st);
+    key_idx = use_keyset(ws, ks, key_idx, kid);
+  }
   HIPCHK(ctx, hipMemsetAsync(ws.counters, 0, 16 * 4, st));
   rc = sign_setup<LV>(ctx, ws, sk, key_idx, msg, msg_off, count, st, ks, ctx->dev_stats + 8, false, rnd);
   if (rc) return rc;
@@ -376,16 +395,19 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   grid = std::max<uint64_t>(grid, 1);
   Ws ws;
   PScr sc;
-  rc = ws_carve<LV>(ctx, count, ws, grid, &sc, waves);
+  uint32_t *kid = nullptr;
+  rc = ws_carve<LV>(ctx, count, ws, grid, &sc, waves, &kid);
   if (rc) return rc;
-  if (ks) use_keyset(ws, ks, key_idx);
-  uint64_t key[16] = {1, (uint64_t)LV, (uint64_t)sk, (uint64_t)key_idx, (uint64_t)msg, (uint64_t)msg_off,
+  const uint32_t *key_in = key_idx;
+  if (ks) key_idx = use_keyset(ws, ks, key_idx, kid);
+  uint64_t key[16] = {1, (uint64_t)LV, (uint64_t)sk, (uint64_t)key_in, (uint64_t)msg, (uint64_t)msg_off,
                       (uint64_t)sig, count, (uint64_t)ks, grid, hmax, (uint64_t)ctx->ws_mem, 0, (uint64_t)waves,
                       (uint64_t)rnd, 0};
   hipEvent_t *evs = ctx->timing ? ctx->ev[ctx->ev_count % dil_ctx::RING] : nullptr;
   if (evs) HIPCHK(ctx, hipEventRecord(evs[0], st));
   rc = enqueue(ctx, key, st, [&](hipStream_t s) {
     zero_words_k<<<1, 64, 0, s>>>(ws.counters, 16, ctx->dev_stats, 8);
+    check_keys(ctx, ks, key_in, kid, count, s);
     int r2 = sign_setup<LV>(ctx, ws, sk, key_idx, msg, msg_off, count, s, ks, ctx->dev_stats + 8, true, rnd);
     if (r2) return r2;
     LAUNCHCHK(ctx);
@@ -417,13 +439,16 @@ int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const 
                 const dil_keyset *ks = nullptr) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
   Ws ws;
-  int rc = ws_carve<LV>(ctx, count, ws);
+  uint32_t *kid = nullptr;
+  int rc = ws_carve<LV>(ctx, count, ws, 0, nullptr, 1, &kid);
   if (rc) return rc;
-  if (ks) use_keyset(ws, ks, key_idx);
-  uint64_t key[16] = {2, (uint64_t)LV, (uint64_t)pk, (uint64_t)key_idx, (uint64_t)msg, (uint64_t)msg_off,
+  const uint32_t *key_in = key_idx;
+  if (ks) key_idx = use_keyset(ws, ks, key_idx, kid);
+  uint64_t key[16] = {2, (uint64_t)LV, (uint64_t)pk, (uint64_t)key_in, (uint64_t)msg, (uint64_t)msg_off,
                       (uint64_t)sig, (uint64_t)verdict, count, (uint64_t)ks, (uint64_t)ctx->ws_mem, 0, 0, 0, 0, 0};
   return enqueue(ctx, key, st, [&](hipStream_t s) {
     zero_words_k<<<1, 64, 0, s>>>(ws.counters, 16, nullptr, 0);
+    check_keys(ctx, ks, key_in, kid, count, s);
     // Three independent fronts: the tr / mu hash chain (needed only by the
     // final hash), ExpandA, and SampleInBall + hint decoding.  Outside the
     // staged form the first two run on side streams and are joined where

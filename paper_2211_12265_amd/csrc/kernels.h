@@ -58,6 +58,21 @@ __global__ void zero_words_k(uint32_t *a, int na, uint32_t *b, int nb) {
   if (b && i < nb) b[i] = 0;
 }
 
+// Key-table calls: copy key_idx into the workspace with every index outside
+// the table replaced by row 0 and the error word set, so no later kernel reads
+// past the table; the host reports the error at its next check.
+__global__ void __launch_bounds__(256) keys_check_k(const uint32_t *key_idx, uint32_t nkeys, uint32_t *out,
+                                                   uint32_t count, uint32_t *err) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  uint32_t k = key_idx[i];
+  if (k >= nkeys) {
+    k = 0;
+    *err = 1u;
+  }
+  out[i] = k;
+}
+
 // ------------------------------------------------------------------------
 // KeyGen (Alg. 1)
 // ------------------------------------------------------------------------

@@ -353,6 +353,39 @@ def test_keyset_sign_verify_parity(sctx, level):
         ks.close()
 
 
+def test_keyset_out_of_range_key_index(sctx):
+    """A key-table call whose key_idx names a row past the table: the device replaces that
+    index by row 0 before any kernel reads a key row, the call reports DIL_EINVAL at its next
+    check, and every output equals the oracle's for the replaced indices."""
+    from paper_2211_12265_amd import dilithium as dl
+    level, nkeys, n = 2, 5, 12
+    pk, sk = _keygen(sctx, level, workload.keygen_seeds(nkeys, seed=95))
+    ks = dl.KeySet(sctx, level, pk=pk, sk=sk)
+    kidx = np.random.default_rng(95).integers(0, nkeys, size=n).astype(np.uint32)
+    bad = kidx.copy()
+    bad[3] = nkeys + 7
+    fixed = bad.copy()
+    fixed[3] = 0
+    msg, off = workload.messages(workload.fixed_lengths(n, 32), seed=95)
+    dmsg, doff = dev(msg), dev(off.astype(np.int64))
+    sig = torch.zeros((n, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
+    with pytest.raises(dl.DilError) as ei:
+        ks.sign(sctx, dev(bad.astype(np.int32)), dmsg, doff, sig)
+        sctx.check()
+    assert ei.value.code == dl.DIL_EINVAL
+    torch.cuda.synchronize()
+    osig, _ = oracle.sign_batch(level, sk.cpu().numpy(), msg, off, key_idx=fixed)
+    assert np.array_equal(sig.cpu().numpy(), osig)
+    sctx.check()   # reported once, then cleared
+    v = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    with pytest.raises(dl.DilError) as ei:
+        ks.verify(sctx, dev(bad.astype(np.int32)), dmsg, doff, sig, v)
+        sctx.check()
+    assert ei.value.code == dl.DIL_EINVAL
+    assert v.cpu().tolist() == [1] * n
+    ks.close()
+
+
 @pytest.mark.parametrize("level", [2, 5])
 def test_graph_replays_match_eager(level):
     """hipGraph replays of persistent Sign and of Verify, with eager work and synchronisation
