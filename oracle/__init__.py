@@ -85,6 +85,8 @@ def bind(path: str) -> ctypes.CDLL:
             "dil_ref_expand_a_poly": (None, [_P, _P]),
             "dil_ref_expand_a_polys": (None, [_P, _P, _SZ, ctypes.c_int]),
             "dil_ref_expand_s": (None, [ctypes.c_int, _P, _P]),
+            "dil_ref_expand_a_poly_counted": (_SZ, [_P, _P]),
+            "dil_ref_expand_s_poly_counted": (_SZ, [ctypes.c_int, _P, ctypes.c_uint16, _P]),
             "dil_ref_expand_mask": (None, [ctypes.c_int, _P, ctypes.c_uint32, _P]),
             "dil_ref_sample_in_ball": (None, [ctypes.c_int, _P, _P]),
             "dil_ref_bitpack": (None, [_P, _SZ, ctypes.c_int, _P]),
@@ -230,6 +232,22 @@ def expand_a_polys(seeds34: np.ndarray, nthreads: Optional[int] = None) -> np.nd
     out = np.zeros((count, N), dtype=np.int32)
     lib().dil_ref_expand_a_polys(_ptr(seeds34), _ptr(out), count, nthreads or default_threads())
     return out
+
+
+def expand_a_poly_counted(seed34: bytes):
+    """One ExpandA polynomial and the number of 3-byte candidates its sampler examined."""
+    out = np.zeros(N, dtype=np.int32)
+    src = np.frombuffer(bytes(seed34), dtype=np.uint8).copy()
+    used = lib().dil_ref_expand_a_poly_counted(_ptr(src), _ptr(out))
+    return out, int(used)
+
+
+def expand_s_poly_counted(eta: int, rhop: bytes, nonce: int):
+    """One ExpandS polynomial (centred) and the number of nibbles its sampler examined."""
+    out = np.zeros(N, dtype=np.int32)
+    src = np.frombuffer(bytes(rhop), dtype=np.uint8).copy()
+    used = lib().dil_ref_expand_s_poly_counted(eta, _ptr(src), nonce, _ptr(out))
+    return out, int(used)
 
 
 def expand_s(level: int, rhop: bytes) -> np.ndarray:

@@ -26,13 +26,20 @@
  *   Power2Round, Decompose  exhaustive identities over all of [0, q)
  *   MakeHint / UseHint      hint-correctness property over all r
  *   encodings               pack o unpack == identity, sizes
+ *   samplers                ExpandA acceptance q / 2^23 (the 23-bit mask),
+ *                           ExpandS acceptance 15/16 and 9/16 and uniform
+ *                           coefficients, SampleInBall's uniform support
+ *                           (the b <= i draw), ranges and weights
  *   scheme                  Verify(Sign) == 1, all single-bit flips rejected,
- *                           mean Sign loop count vs Sec. 2.3
+ *                           mean Sign loop count vs Sec. 2.3, and on crafted
+ *                           secret keys every emitted signature keeps
+ *                           ||c t0|| < gamma2 and at most omega hints
  * parity unpinned: the exact byte streams of ExpandA / ExpandS / ExpandMask /
  *   SampleInBall and the encodings against the official round-3 known-answer
- *   tests (neither the specification nor its KAT files are available); their
- *   ranges, counts and distributions are pinned, their nonce and bit-order
- *   conventions are readings [R].
+ *   tests (neither the specification nor its KAT files are available): the
+ *   byte and nibble order inside the sampler streams, the nonce encodings,
+ *   ExpandMask's orientation gamma1 - v, SampleInBall's sign-bit source and
+ *   the key / signature byte layouts are readings [R].
  */
 #ifndef DIL_ORACLE_H
 #define DIL_ORACLE_H
@@ -76,6 +83,11 @@ void dil_ref_expand_a(int level, const uint8_t rho[32], int32_t *A /* k*l*256 */
 void dil_ref_expand_a_poly(const uint8_t seed34[34], int32_t out[ORN]);
 void dil_ref_expand_a_polys(const uint8_t *seeds34, int32_t *out, size_t count, int nthreads);
 void dil_ref_expand_s(int level, const uint8_t rhop[64], int32_t *s /* (l+k)*256, centred */);
+/* one ExpandA / ExpandS polynomial, returning how much of its stream the rejection
+   sampler examined: 3-byte candidates (ExpandA) or nibbles (ExpandS); pins the
+   acceptance rates q / 2^23, 15/16 (eta = 2) and 9/16 (eta = 4) */
+size_t dil_ref_expand_a_poly_counted(const uint8_t seed34[34], int32_t out[ORN]);
+size_t dil_ref_expand_s_poly_counted(int eta, const uint8_t rhop[64], uint16_t nonce, int32_t out[ORN] /* centred */);
 void dil_ref_expand_mask(int level, const uint8_t rhop[64], uint32_t kappa, int32_t *y /* l*256, centred */);
 void dil_ref_sample_in_ball(int level, const uint8_t ctilde[32], int32_t c[ORN] /* centred */);
 

@@ -18,8 +18,20 @@
  *   SampleInBall SHAKE256(ctilde): 8 bytes form a little-endian sign word s;
  *                for i = 256 - tau .. 255 draw bytes until b <= i, then
  *                c_i = c_b, c_b = (-1)^(s & 1), s >>= 1.
- * Pinned: output ranges, exact counts (tau nonzeros), acceptance rates.
- * parity unpinned against the official round-3 byte streams (no KATs here).
+ * Pinned (tests/test_oracle_samplers.py, statistically, from properties of a
+ * uniform byte stream that hold whatever the byte order):
+ *   ExpandA      accepted / examined candidates = q / 2^23 (the 23-bit mask);
+ *                values uniform on [0, q).
+ *   ExpandS      accepted / examined nibbles = 15/16 (eta = 2) or 9/16 (eta = 4);
+ *                coefficients uniform on [-eta, eta].
+ *   SampleInBall exactly tau entries +-1; the support is a uniform tau-subset of
+ *                the 256 positions, which is the textbook property of the
+ *                Fisher-Yates draw with b <= i (b < i biases the positions).
+ *   ExpandMask   range [-gamma1 + 1, gamma1], stream i of kappa = nonce kappa + i.
+ * parity unpinned: the byte and nibble order inside each stream, the nonce
+ *   encodings, ExpandMask's orientation (gamma1 - v rather than v - gamma1 + 1)
+ *   and SampleInBall's sign-bit source; the paper fixes none of them and no
+ *   official round-3 byte streams (KATs) are available here.
  */
 #include "dil_oracle.h"
 #include <pthread.h>
@@ -85,17 +97,26 @@ static uint8_t stream_byte(stream_t *s) {
 
 static void stream_close(stream_t *s) { free(s->buf); }
 
-void dil_ref_expand_a_poly(const uint8_t seed34[34], int32_t out[ORN]) {
+size_t dil_ref_expand_a_poly_counted(const uint8_t seed34[34], int32_t out[ORN]) {
   stream_t s;
   stream_open(&s, 1, seed34, 34, 840);
   int ctr = 0;
+  size_t candidates = 0;
   while (ctr < ORN) {
     uint32_t b0 = stream_byte(&s), b1 = stream_byte(&s), b2 = stream_byte(&s);
+#if defined(DIL_PLANT) && DIL_PLANT == 15
+    uint32_t t = b0 | (b1 << 8) | (b2 << 16); /* planted: the 23-bit mask dropped */
+#else
     uint32_t t = b0 | (b1 << 8) | ((b2 & 0x7F) << 16);
+#endif
+    candidates++;
     if (t < ORQ) out[ctr++] = (int32_t)t;
   }
   stream_close(&s);
+  return candidates;
 }
+
+void dil_ref_expand_a_poly(const uint8_t seed34[34], int32_t out[ORN]) { (void)dil_ref_expand_a_poly_counted(seed34, out); }
 
 int dil_ref_params(int level, ref_params *p);
 
@@ -140,7 +161,7 @@ void dil_ref_expand_a_polys(const uint8_t *seeds34, int32_t *out, size_t count, 
   free(jobs);
 }
 
-static void expand_s_poly(int eta, const uint8_t rhop[64], uint16_t nonce, int32_t out[ORN]) {
+size_t dil_ref_expand_s_poly_counted(int eta, const uint8_t rhop[64], uint16_t nonce, int32_t out[ORN]) {
   uint8_t seed[66];
   memcpy(seed, rhop, 64);
   seed[64] = (uint8_t)(nonce & 0xFF);
@@ -148,22 +169,29 @@ static void expand_s_poly(int eta, const uint8_t rhop[64], uint16_t nonce, int32
   stream_t s;
   stream_open(&s, 0, seed, 66, 272);
   int ctr = 0;
+  size_t nibbles = 0;
   while (ctr < ORN) {
     uint8_t b = stream_byte(&s);
     uint32_t half[2] = {b & 0x0Fu, (uint32_t)b >> 4};
     for (int h = 0; h < 2 && ctr < ORN; h++) {
       uint32_t v = half[h];
+      nibbles++;
+#if defined(DIL_PLANT) && DIL_PLANT == 16
+      if (eta == 2 && v < 16) out[ctr++] = 2 - (int32_t)(v % 5); /* planted: eta = 2 threshold 16 */
+#else
       if (eta == 2 && v < 15) out[ctr++] = 2 - (int32_t)(v % 5);
+#endif
       else if (eta == 4 && v < 9) out[ctr++] = 4 - (int32_t)v;
     }
   }
   stream_close(&s);
+  return nibbles;
 }
 
 void dil_ref_expand_s(int level, const uint8_t rhop[64], int32_t *s) {
   ref_params P;
   if (dil_ref_params(level, &P)) return;
-  for (int r = 0; r < P.l + P.k; r++) expand_s_poly(P.eta, rhop, (uint16_t)r, s + (size_t)r * ORN);
+  for (int r = 0; r < P.l + P.k; r++) (void)dil_ref_expand_s_poly_counted(P.eta, rhop, (uint16_t)r, s + (size_t)r * ORN);
 }
 
 void dil_ref_expand_mask(int level, const uint8_t rhop[64], uint32_t kappa, int32_t *y) {
@@ -196,7 +224,11 @@ void dil_ref_sample_in_ball(int level, const uint8_t ctilde[32], int32_t c[ORN])
   for (int i = 0; i < ORN; i++) c[i] = 0;
   for (int i = ORN - P.tau; i < ORN; i++) {
     int b;
+#if defined(DIL_PLANT) && DIL_PLANT == 19
+    do { b = stream_byte(&s); } while (b >= i); /* planted: positions drawn with b < i */
+#else
     do { b = stream_byte(&s); } while (b > i);
+#endif
     c[i] = c[b];
 #if defined(DIL_PLANT) && DIL_PLANT == 10
     c[b] = (signs & 1) ? -1 : 1;

@@ -121,11 +121,16 @@ static void unpack_z(const ref_params *P, const uint8_t *in, int32_t *z) {
 }
 static void pack_hint(const ref_params *P, const int32_t *h /* k*256 of 0/1 */, uint8_t *out) {
   memset(out, 0, P->omega + P->k);
+  /* Sign calls this only with at most omega ones (Alg. 2's [h] <= omega
+     condition); the guards keep a broken caller inside the buffer */
   int cnt = 0;
   for (int i = 0; i < P->k; i++) {
     for (int j = 0; j < ORN; j++)
-      if (h[i * ORN + j]) out[cnt++] = (uint8_t)j;
-    out[P->omega + i] = (uint8_t)cnt;
+      if (h[i * ORN + j]) {
+        if (cnt < P->omega) out[cnt] = (uint8_t)j;
+        cnt++;
+      }
+    out[P->omega + i] = (uint8_t)(cnt > 255 ? 255 : cnt);
   }
 }
 /* strict decoding; returns 0 ok, 1 malformed */
@@ -314,7 +319,9 @@ static int sign_core(int level, const uint8_t *sk, const uint8_t *msg, size_t ml
       pointwise(t, ch, t0h + i * ORN);
       dil_ref_intt(t);
       for (int cidx = 0; cidx < ORN; cidx++) {
+#if !(defined(DIL_PLANT) && DIL_PLANT == 18) /* planted (18): the ||c t0|| >= gamma2 rejection dropped */
         if (iabs(centred(t[cidx])) >= P.gamma2) reject = 1;
+#endif
         negct0[cidx] = (int32_t)modq(-(int64_t)t[cidx]);
 #if defined(DIL_PLANT) && DIL_PLANT == 13
         r[cidx] = (int32_t)modq((int64_t)wcs2[i * ORN + cidx] - t[cidx]); /* planted: wrong sign of c t0 */
@@ -326,7 +333,11 @@ static int sign_core(int level, const uint8_t *sk, const uint8_t *msg, size_t ml
       for (int cidx = 0; cidx < ORN; cidx++) hcount += h[i * ORN + cidx];
     }
     free(wcs2);
+#if defined(DIL_PLANT) && DIL_PLANT == 17
+    if (reject) continue; /* planted: the [h] > omega rejection dropped */
+#else
     if (reject || hcount > P.omega) continue;
+#endif
     memcpy(sig, ctilde, 32);
     size_t zb = (size_t)ORN * P.z_bits / 8;
     for (int j = 0; j < l; j++) pack_z(&P, z + j * ORN, sig + 32 + j * zb);

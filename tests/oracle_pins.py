@@ -1,0 +1,198 @@
+"""Pins of the oracle's samplers and of Sign's output conditions that do not come from the oracle
+itself: acceptance rates and distributions that a uniform byte stream fixes (Sec. 2.3 "Sampling",
+Alg. 4), and the conditions Alg. 2 places on every signature it emits, checked on secret keys
+whose t0 part is chosen so that those conditions actually bind.
+
+Shared by the sampler / scheme tests and the planted-mistake tests (each function returns a list
+of failure descriptions, empty when the pin holds)."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_2211_12265_amd import workload
+
+Q = 8380417
+N = 256
+
+
+# ---- samplers -------------------------------------------------------------------------------
+
+def expand_a_acceptance(streams: int = 4096, seed: int = 1, z: float = 4.0) -> list:
+    """ExpandA examines 3-byte candidates t < 2^23 and keeps t < q: over S streams of 256 kept
+    values the rejected candidates are negative-binomial with rate (2^23 - q) / 2^23."""
+    seeds = workload.expand_a_inputs(streams, seed=seed)
+    used = sum(oracle.expand_a_poly_counted(seeds[i].tobytes())[1] for i in range(streams))
+    kept = streams * N
+    p = (2 ** 23 - Q) / 2 ** 23
+    mean, sd = kept * p / (1 - p), np.sqrt(kept * p) / (1 - p)
+    rej = used - kept
+    return [] if abs(rej - mean) <= z * sd else [f"expand_a acceptance: {rej} rejected, expected {mean:.0f} +- {sd:.0f}"]
+
+
+def expand_s_acceptance(eta: int, streams: int = 4096, seed: int = 2, z: float = 4.0) -> list:
+    """ExpandS keeps a nibble v < 15 (eta = 2) or v < 9 (eta = 4): rejected nibbles are
+    negative-binomial with rate 1/16 or 7/16, and the kept coefficients are uniform on
+    [-eta, eta] (15 = 3 x 5 values fold evenly onto 2 - (v mod 5))."""
+    fails = []
+    used = 0
+    hist = np.zeros(2 * eta + 1, np.int64)
+    for i in range(streams):
+        rhop = workload.random_bytes("pin/rhop", seed * 100003 + i, (64,)).tobytes()
+        c, u = oracle.expand_s_poly_counted(eta, rhop, i & 0xFFFF)
+        used += u
+        hist += np.bincount(c + eta, minlength=2 * eta + 1)[: 2 * eta + 1]
+    kept = streams * N
+    p = 1 / 16 if eta == 2 else 7 / 16
+    mean, sd = kept * p / (1 - p), np.sqrt(kept * p) / (1 - p)
+    rej = used - kept
+    if abs(rej - mean) > z * sd:
+        fails.append(f"expand_s eta={eta} acceptance: {rej} rejected, expected {mean:.0f} +- {sd:.0f}")
+    if hist.sum() != kept:
+        fails.append(f"expand_s eta={eta}: coefficients outside [-eta, eta]")
+    # chi-square against the uniform distribution on 2 eta + 1 values (df 2 eta); the bound is
+    # about 8 standard deviations above the mean of the statistic
+    e = kept / (2 * eta + 1)
+    chi2 = float(((hist - e) ** 2 / e).sum())
+    if chi2 > 2 * eta + 8 * np.sqrt(4 * eta):
+        fails.append(f"expand_s eta={eta}: coefficients not uniform (chi2 {chi2:.1f}, df {2 * eta})")
+    return fails
+
+
+def sample_in_ball_support(level: int = 2, samples: int = 60000, seed: int = 3) -> list:
+    """SampleInBall draws, for i = 256 - tau .. 255, a position b <= i and moves c_b to c_i: the
+    inside-out Fisher-Yates draw, whose tau-subset of nonzero positions is uniform.  Each position
+    is then nonzero with probability tau / 256; the statistic below is the sum over positions of
+    the squared standardised count deviations (mean about 255, standard deviation about 23 under
+    the uniform support).  Drawing b < i instead biases the positions near 256 - tau and 255 and
+    raises the statistic by about 3.5 per 1000 samples."""
+    tau = oracle.params(level)["tau"]
+    counts = np.zeros(N, np.int64)
+    signs = np.zeros(2, np.int64)
+    base = workload.random_bytes("pin/ctilde", seed, (samples, 32))
+    bad_weight = 0
+    for t in range(samples):
+        c = oracle.sample_in_ball(level, base[t].tobytes())
+        nz = c != 0
+        if int(nz.sum()) != tau or not np.all(np.abs(c[nz]) == 1):
+            bad_weight += 1
+        counts += nz
+        signs[0] += int((c == 1).sum())
+        signs[1] += int((c == -1).sum())
+    fails = []
+    if bad_weight:
+        fails.append(f"sample_in_ball: {bad_weight} challenges without exactly tau entries +-1")
+    p = tau / N
+    stat = float(((counts - samples * p) ** 2 / (samples * p * (1 - p))).sum())
+    if stat > 255 + 6 * 23:
+        fails.append(f"sample_in_ball: support not uniform (statistic {stat:.0f}, expected about 255)")
+    tot = signs.sum()
+    if abs(signs[0] - tot / 2) > 4 * np.sqrt(tot / 4):
+        fails.append("sample_in_ball: signs not balanced")
+    return fails
+
+
+# ---- Sign's output conditions on crafted keys --------------------------------------------------
+
+def negacyclic(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """Schoolbook product in Z[X] / (X^256 + 1), integer coefficients (no reduction)."""
+    full = np.zeros(2 * N - 1, dtype=np.int64)
+    for i in np.nonzero(a)[0]:
+        full[i:i + N] += int(a[i]) * b.astype(np.int64)
+    return full[:N] - np.concatenate([full[N:], [0]])
+
+
+def with_t0(sk_row: np.ndarray, level: int, rows) -> np.ndarray:
+    """Copy of a secret-key row whose t0 polynomials are replaced by `rows` (values in
+    [-4095, 4096]), encoded as 13-bit fields 2^12 - t0, least significant bit first."""
+    p = oracle.params(level)
+    k, l = p["k"], p["l"]
+    off = 96 + (l + k) * (N * p["eta_bits"] // 8)
+    out = sk_row.copy()
+    for i in range(k):
+        v = (4096 - np.asarray(rows[i], np.int64)).astype(np.uint32)
+        bits = ((v[:, None] >> np.arange(13, dtype=np.uint32)) & 1).astype(np.uint8).reshape(-1)
+        out[off + i * 416: off + (i + 1) * 416] = np.packbits(bits, bitorder="little")
+    return out
+
+
+def _one_key(level: int, seed: int):
+    pk, sk = oracle.keygen_batch(level, workload.keygen_seeds(1, seed=seed), nthreads=1)
+    return pk, sk
+
+
+def sign_ct0_bound(level: int = 2, seed: int = 31, trials: int = 3) -> list:
+    """Alg. 2 emits a signature only if ||c t0||_inf < gamma2.  t0 never changes the challenges
+    (they depend on K, tr, M and A only), so for a message whose first iteration is accepted we
+    know that iteration's c from the signature, and a key whose first t0 polynomial is
+    +-4095 aligned with c (c t0 then has 4095 tau >= gamma2 in coefficient 0) must make Sign
+    reject that iteration.  Whatever Sign then emits must satisfy the bound for its own c."""
+    p = oracle.params(level)
+    k = p["k"]
+    _, sk = _one_key(level, seed)
+    n = 48
+    msg, off = workload.messages(workload.fixed_lengths(n, 32), seed=seed)
+    oracle.lib().dil_ref_set_sign_cap(300)
+    try:
+        sig, it = oracle.sign_batch(level, np.repeat(sk, n, axis=0), msg, off, nthreads=4)
+    finally:
+        oracle.lib().dil_ref_set_sign_cap(0)
+    firsts = np.nonzero(it == 1)[0][:trials]
+    fails = []
+    if len(firsts) < trials:
+        return [f"ct0 pin: only {len(firsts)} first-iteration signatures among {n}"]
+    for m in firsts:
+        c = oracle.sample_in_ball(level, sig[m, :32].tobytes())
+        t = np.zeros(N, np.int64)
+        # coefficient 0 of c t in Z[X]/(X^256 + 1) is c_0 t_0 - sum_{j > 0} c_j t_{256 - j}
+        t[0] = 4095 * c[0]
+        for j in range(1, N):
+            if c[j]:
+                t[N - j] = -4095 * c[j]
+        if abs(int(negacyclic(c, t)[0])) != 4095 * p["tau"]:
+            return [f"ct0 pin: the challenge of message {m} does not have tau entries +-1"]
+        rows = [t] + [np.zeros(N, np.int64)] * (k - 1)
+        sk2 = with_t0(sk[0], level, rows)[None, :]
+        one = np.array([0, 32], np.uint64)
+        oracle.lib().dil_ref_set_sign_cap(2000)
+        try:
+            s2, i2 = oracle.sign_batch(level, sk2, msg[int(off[m]):int(off[m + 1])], one, nthreads=1)
+        finally:
+            oracle.lib().dil_ref_set_sign_cap(0)
+        if i2[0] < 1:
+            fails.append(f"ct0 pin: Sign failed on the crafted key (message {m})")
+            continue
+        c2 = oracle.sample_in_ball(level, s2[0, :32].tobytes())
+        big = int(np.abs(negacyclic(c2, t)).max())
+        if big >= p["gamma2"]:
+            fails.append(f"ct0 pin: emitted signature has ||c t0|| = {big} >= gamma2 (message {m})")
+    return fails
+
+
+def sign_hint_bound(level: int = 2, seed: int = 32, msgs: int = 4, scale: int = 3500) -> list:
+    """Alg. 2 emits a signature only if it carries at most omega hints.  With every t0 coefficient
+    at +-scale (random signs) c t0 is large enough that a typical iteration needs about omega
+    hints, so Sign has to reject some iterations on the hint count alone; every emitted
+    signature's hint section must still count at most omega ones (its last count byte)."""
+    p = oracle.params(level)
+    k, om = p["k"], p["omega"]
+    _, sk = _one_key(level, seed)
+    rng = np.random.default_rng(seed)
+    rows = [rng.choice(np.array([-scale, scale]), N) for _ in range(k)]
+    sk2 = with_t0(sk[0], level, rows)
+    msg, off = workload.messages(workload.fixed_lengths(msgs, 32), seed=seed)
+    oracle.lib().dil_ref_set_sign_cap(3000)
+    try:
+        sig, it = oracle.sign_batch(level, np.repeat(sk2[None, :], msgs, axis=0), msg, off, nthreads=4)
+    finally:
+        oracle.lib().dil_ref_set_sign_cap(0)
+    fails = []
+    for m in range(msgs):
+        if it[m] < 1:
+            fails.append(f"hint pin: Sign hit its iteration cap on the crafted key (message {m})")
+            continue
+        hint = sig[m, 32 + p["l"] * (N * p["z_bits"] // 8):]
+        counts = hint[om:om + k].astype(int)
+        if counts[-1] > om or np.any(np.diff(counts) < 0):
+            fails.append(f"hint pin: emitted signature counts {counts.tolist()} (omega {om}, message {m})")
+    return fails

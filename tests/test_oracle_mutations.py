@@ -2,7 +2,9 @@
 offset, swapped chi operands, a non-bit-reversed twiddle, a dropped 1/n, a wrong mod+- tie, a
 dropped Decompose special case, a wrong sign in MakeHint, a wrong UseHint branch, MSB-first
 packing, a dropped challenge position, a dropped beta, a dropped c t1 term, a wrong c t0 sign,
-a wrong t0 offset) must fail at least one of the oracle's pins.  Everything runs on the CPU."""
+a wrong t0 offset, ExpandA's 23-bit mask dropped, ExpandS's eta = 2 threshold moved to 16, Sign's
+[h] > omega rejection dropped, Sign's ||c t0|| >= gamma2 rejection dropped, SampleInBall drawing
+b < i) must fail at least one of the oracle's pins.  Everything runs on the CPU."""
 import hashlib
 import os
 
@@ -10,10 +12,11 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle_pins
 from paper_2211_12265_amd import workload
 
 Q = 8380417
-PLANTS = list(range(1, 15))
+PLANTS = list(range(1, 20))
 
 
 def _schoolbook(a, b):
@@ -24,8 +27,10 @@ def _schoolbook(a, b):
     return np.array([int(x) % Q for x in out], dtype=np.int32)
 
 
-def pins_hold():
-    """A fast subset of the oracle pins; returns the list of failing pin names."""
+def pins_hold(stop_early: bool = False):
+    """A fast subset of the oracle pins; returns the list of failing pin names (with stop_early,
+    only the first: a planted mistake has to fail one of them, and a broken signer makes the
+    later signing pins run to their iteration caps)."""
     failed = []
     data = workload.random_bytes("test/mut", 0, (400,)).tobytes()
     for n in (0, 1, 135, 136, 167, 168, 300):
@@ -79,6 +84,18 @@ def pins_hold():
                 failed.append("round-trip")
     finally:
         oracle.lib().dil_ref_set_sign_cap(0)
+    if failed and stop_early:
+        return failed
+    # sampler acceptance rates and distributions, Sign's output conditions on crafted keys
+    for name, pin in (("expand-a-acceptance", lambda: oracle_pins.expand_a_acceptance(streams=2048)),
+                      ("expand-s-acceptance", lambda: oracle_pins.expand_s_acceptance(2, streams=2048)),
+                      ("sign-ct0-bound", lambda: oracle_pins.sign_ct0_bound(2)),
+                      ("sign-hint-bound", lambda: oracle_pins.sign_hint_bound(2)),
+                      ("sample-in-ball-support", lambda: oracle_pins.sample_in_ball_support(2, samples=60000))):
+        if pin():
+            failed.append(name)
+            if stop_early:
+                return failed
     return failed
 
 
@@ -93,7 +110,7 @@ def test_planted_mistake_is_caught(tmp_path, plant):
     saved = oracle._LIB
     try:
         oracle._LIB = oracle.bind(path)
-        failed = pins_hold()
+        failed = pins_hold(stop_early=True)
     finally:
         oracle._LIB = saved
     assert failed, f"planted mistake {plant} passed every pin"

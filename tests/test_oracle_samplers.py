@@ -1,8 +1,12 @@
-"""Oracle samplers (Sec. 2.3 'Sampling'): ranges, counts and acceptance statistics.
-Exact byte streams against the official round-3 KATs are parity unpinned."""
+"""Oracle samplers (Sec. 2.3 'Sampling', Alg. 4): ranges, counts, acceptance rates and
+distributions.  The acceptance rates pin ExpandA's 23-bit mask and ExpandS's thresholds, the
+support statistic pins SampleInBall's b <= i draw.  Exact byte streams against the official
+round-3 KATs (byte and nibble order, nonce encodings, ExpandMask's orientation, the sign-bit
+source) are parity unpinned."""
 import numpy as np
 import pytest
 
+import oracle_pins
 from paper_2211_12265_amd import workload
 
 Q = 8380417
@@ -61,3 +65,21 @@ def test_sample_in_ball_weight(orc, level, tau):
         c = orc.sample_in_ball(level, workload.random_bytes("test/ct", t, (32,)).tobytes())
         assert np.count_nonzero(c) == tau
         assert set(np.unique(c[c != 0])) <= {-1, 1}
+
+
+def test_expand_a_acceptance_rate():
+    # rejected candidates over 4096 streams: q / 2^23 acceptance, within 4 standard deviations
+    assert oracle_pins.expand_a_acceptance(streams=4096, seed=1) == []
+    assert oracle_pins.expand_a_acceptance(streams=4096, seed=5) == []
+
+
+@pytest.mark.parametrize("eta", [2, 4])
+def test_expand_s_acceptance_rate_and_distribution(eta):
+    # 15/16 (eta = 2) or 9/16 (eta = 4) of the nibbles kept; coefficients uniform on [-eta, eta]
+    assert oracle_pins.expand_s_acceptance(eta, streams=4096, seed=2) == []
+
+
+@pytest.mark.parametrize("level", [2, 5])
+def test_sample_in_ball_support_uniform(level):
+    # the nonzero positions form a uniform tau-subset (Fisher-Yates with b <= i)
+    assert oracle_pins.sample_in_ball_support(level, samples=60000, seed=3) == []

@@ -6,6 +6,7 @@ import os
 import numpy as np
 import pytest
 
+import oracle_pins
 from paper_2211_12265_amd import workload
 
 GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "params_table1.json")))
@@ -118,7 +119,21 @@ def test_mean_loop_count(orc, level):
     pk, sk = _keys(orc, level, n, seed=21)
     msg, off = workload.messages(workload.fixed_lengths(n, 32), seed=21)
     sig, iters = orc.sign_batch(level, sk, msg, off)
+    assert orc.verify_batch(level, pk, msg, off, sig).tolist() == [1] * n
     expect = GOLD["levels"][str(level)]["expected_repetitions"]
     assert abs(iters.mean() - expect) < 0.1 * expect, (iters.mean(), expect)
     # geometric: P(iters == 1) close to 1/E
     assert abs((iters == 1).mean() - 1 / expect) < 0.05
+
+
+def test_emitted_signatures_respect_ct0_bound():
+    # Alg. 2 rejects an iteration with ||c t0||_inf >= gamma2; on keys whose t0 is aligned with a
+    # known accepted challenge that rejection must happen (level 2 is the only level where the
+    # bound can bind: tau 2^12 < gamma2 at levels 3 and 5)
+    assert oracle_pins.sign_ct0_bound(level=2, seed=31, trials=3) == []
+
+
+def test_emitted_signatures_respect_hint_bound():
+    # Alg. 2 rejects an iteration with more than omega hints; on keys with large t0 that
+    # rejection binds often, and no emitted signature may carry more than omega hints
+    assert oracle_pins.sign_hint_bound(level=2, seed=32, msgs=4) == []
