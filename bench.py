@@ -113,7 +113,8 @@ def verify_work(level: int, msg_lens: np.ndarray) -> float:
     return perms * PERM_OPS + xf * XFORM_OPS + pw * PW_OPS
 
 
-def cpu_baseline(level: int, seeds, msg, off, msg_desc: str, gpu_sig, min_seconds: float) -> dict:
+def cpu_baseline(level: int, seeds, msg, off, msg_desc: str, gpu_sig, min_seconds: float,
+                 single: int = 1000) -> dict:
     """The CPU oracle on the host's cores over the benchmark's own batch: the same keys (KeyGen from the
     same seeds, untimed) and the same messages.  Sign and Verify of the whole batch are repeated until
     min_seconds of wall time have passed and the median repetition gives the rate.  The oracle's
@@ -139,9 +140,21 @@ def cpu_baseline(level: int, seeds, msg, off, msg_desc: str, gpu_sig, min_second
         if t2 - start >= min_seconds:
             break
     sign_s, ver_s, wall = float(np.median(sign_t)), float(np.median(ver_t)), time.perf_counter() - start
+    # one host thread (the paper's CPU reference column is single-threaded), on the first
+    # `single` tasks of the same batch, once
+    m = min(single, n)
+    t0 = time.perf_counter()
+    s1, _ = oracle.sign_batch(level, sk[:m], msg[:int(off[m])], off[:m + 1], nthreads=1)
+    t1 = time.perf_counter()
+    v1 = oracle.verify_batch(level, pk[:m], msg[:int(off[m])], off[:m + 1], s1, nthreads=1)
+    t2 = time.perf_counter()
+    assert int(v1.sum()) == m and np.array_equal(s1, sig[:m])
+    single_thread = {"value": m / (t2 - t0), "unit": "sign+verify pairs/s", "cores": 1, "kind": "oracle",
+                     "sign_per_s": m / (t1 - t0), "verify_per_s": m / (t2 - t1),
+                     "sample": f"the first {m} tasks of the same batch, signed and verified once on one thread"}
     return {"value": n / (sign_s + ver_s), "unit": "sign+verify pairs/s", "cores": threads, "kind": "oracle",
             "sign_per_s": n / sign_s, "verify_per_s": n / ver_s, "repetitions": len(sign_t), "wall_s": wall,
-            "timed_batch_parity": parity,
+            "timed_batch_parity": parity, "single_thread": single_thread,
             "sample": f"the benchmark's whole batch ({n} Dilithium{level} sign + {n} verify, {msg_desc}, the same "
                       f"keys and messages as the GPU run), repeated {len(sign_t)} times ({wall:.1f} s wall, median "
                       f"repetition); plain C oracle on {threads} host threads"}
@@ -211,9 +224,11 @@ def micro_run(steps: int, warmup: int) -> dict:
     return res
 
 
-def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -> dict:
+def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int, short: bool = False) -> dict:
     """Serving loop on 1024 resident key pairs (512 / 307 / 205 at levels 2 / 3 / 5): first a
-    saturation probe (all requests at t = 0), then a Poisson stream at half that rate."""
+    saturation probe (all requests at t = 0), then a Poisson stream at half that rate.  `short`
+    (the default benchmark line): one saturation pass over n_requests and n_requests Poisson
+    arrivals, no load sweep."""
     import torch
     from paper_2211_12265_amd import dilithium as dl
     from paper_2211_12265_amd import serving as sv
@@ -235,11 +250,12 @@ def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -
     server.serve(warm)
     # saturation: at least 400k requests, all at t = 0, twice; the faster pass counts (a short probe
     # is dominated by its first and last batches)
-    sat_reqs = sv.build_requests(max(n_requests, 400_000), lam=0.0, keys_per_level=keys, seed=12)
+    sat_reqs = sv.build_requests(n_requests if short else max(n_requests, 400_000), lam=0.0, keys_per_level=keys,
+                                 seed=12)
     sv.attach_signatures(sat_reqs, ctx, keysets, seed=12)
-    sat_rate = max(len(sat_reqs) / server.serve(sat_reqs).wall for _ in range(2))
+    sat_rate = max(len(sat_reqs) / server.serve(sat_reqs).wall for _ in range(1 if short else 2))
     sweep = []
-    for frac in (0.25, 0.75):     # latency at a lighter and a heavier load, beside the 0.5 point
+    for frac in (() if short else (0.25, 0.75)):     # latency at a lighter and a heavier load, beside 0.5
         lam_f = frac * sat_rate
         cnt_f = int(min(max(n_requests // 2, lam_f * seconds / 2), 1_000_000))
         r_f = sv.build_requests(cnt_f, lam=lam_f, keys_per_level=keys, seed=14)
@@ -248,7 +264,7 @@ def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -
         sweep.append({"load": frac, "lambda_per_s": lam_f, "ops_per_s": s_f["ops_per_s"], "p50_ms": s_f["p50_ms"],
                       "p99_ms": s_f["p99_ms"]})
     lam = 0.5 * sat_rate
-    count = int(min(max(n_requests, lam * seconds), 2_000_000))
+    count = n_requests if short else int(min(max(n_requests, lam * seconds), 2_000_000))
     reqs = sv.build_requests(count, lam=lam, keys_per_level=keys, seed=13)
     flipped = sv.attach_signatures(reqs, ctx, keysets, seed=13)
     res = server.serve(reqs)
@@ -256,7 +272,7 @@ def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -
     summ["load_sweep"] = sweep
     verify = reqs.op == sv.VERIFY
     summ.update({"engine": "native dil_server", "lambda_per_s": lam, "saturated_ops_per_s": sat_rate,
-                 "streams": streams, "max_batch": max_batch,
+                 "streams": streams, "max_batch": max_batch, "trace": "short" if short else "full",
                  "resident_key_bytes": resident, "flipped_rejected": bool((res.verdict[verify & flipped] == 0).all()),
                  "valid_accepted": bool((res.verdict[verify & ~flipped] == 1).all()),
                  "mix": "70% verify / 30% sign, levels 2/3/5 at 50/30/20%, lognormal messages (median 256 B, "
@@ -266,6 +282,75 @@ def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int) -
         ks.close()
     ctx.close()
     return summ
+
+
+def staged_run(level: int, sk, pk, gm, go, ref_sig, steps: int = 5) -> dict:
+    """The plain staged form (one launch per stage, host-driven rejection loop) on the same keys,
+    messages and batch as the timed persistent run: Sign and Verify timed separately (median of
+    `steps`), signatures compared byte for byte with the persistent form's."""
+    import torch
+    from paper_2211_12265_amd import dilithium as dl
+    n = go.shape[0] - 1
+    ctx = dl.Context(0, mode=dl.MODE_STAGED)
+    sig = torch.zeros_like(ref_sig)
+    ver = torch.zeros(n, dtype=torch.int32, device="cuda")
+    ctx.sign(level, sk, gm, go, sig)
+    ctx.verify(level, pk, gm, go, sig, ver)
+    torch.cuda.synchronize()
+    ts, tv = [], []
+    for _ in range(steps):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        ctx.sign(level, sk, gm, go, sig)
+        e[1].record()
+        ctx.verify(level, pk, gm, go, sig, ver)
+        e[2].record()
+        torch.cuda.synchronize()
+        ts.append(e[0].elapsed_time(e[1]))
+        tv.append(e[1].elapsed_time(e[2]))
+    same = bool(torch.equal(sig, ref_sig))
+    ok = bool(int(ver.sum()) == n)
+    ctx.close()
+    sm, vm = float(np.median(ts)), float(np.median(tv))
+    return {"form": "staged (one launch per stage, host-driven rejection loop; Verify on one stream)",
+            "sign_per_s": n / (sm * 1e-3), "verify_per_s": n / (vm * 1e-3), "sign_ms_median": sm,
+            "verify_ms_median": vm, "value": n / ((sm + vm) * 1e-3), "unit": "sign+verify pairs/s",
+            "same_signatures_as_persistent": same, "all_verified": ok, "steps": steps}
+
+
+PROBE_KINDS = ["v_xor_b32", "v_add_u32", "v_bitop3_b32", "v_alignbit_b32", "v_mul_lo_u32", "v_mad_u64_u32"]
+
+
+def peak_run(iters: int = 4000, reps: int = 5) -> dict:
+    """Vector-ALU issue rates of the integer instructions the kernels use (dil_alu_probe): lane-ops/s
+    with eight workgroups of four wavefronts per CU (full occupancy, 8 waves per SIMD) and with one
+    workgroup per CU (one wave per SIMD), median of `reps` HIP-event-timed launches, against
+    the 256 CU x 4 SIMD x 32 lanes x 2.4 GHz = 78.6 T lane-ops/s the roofline divides by."""
+    import torch
+    from paper_2211_12265_amd import dilithium as dl
+    ctx = dl.Context(0)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out = torch.zeros(cus * 8 * 256, dtype=torch.int32, device="cuda")
+    rows = []
+    for kind, name in enumerate(PROBE_KINDS):
+        for per_cu, shape in ((8, "8 waves per SIMD"), (1, "1 wave per SIMD")):
+            groups = cus * per_cu
+            ctx.alu_probe(kind, 16, groups, out)
+            ts, n_instr = [], 0
+            for _ in range(reps):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                n_instr = ctx.alu_probe(kind, iters, groups, out)
+                b.record()
+                b.synchronize()
+                ts.append(a.elapsed_time(b))
+            ms = float(np.median(ts))
+            rate = n_instr / (ms * 1e-3)
+            rows.append({"instruction": name, "occupancy": shape, "groups": groups, "ms": ms,
+                         "lane_ops_per_s": rate, "frac_of_78.6T": rate / PEAK_INT32_OPS,
+                         "lanes_per_simd_per_clk_at_2.4GHz": rate / (cus * 4 * 2.4e9)})
+    ctx.close()
+    return {"cus": cus, "iters": iters, "rows": rows, "peak_used": PEAK_INT32_OPS}
 
 
 def ablation_run(level: int, n: int, msg_dist: str, steps: int = 10) -> list:
@@ -448,6 +533,11 @@ def main():
     ap.add_argument("--micro", action="store_true",
                     help="only time the primitive workloads (2^20-polynomial NTT product in each ablation form, "
                          "ExpandA) and print them as one JSON line")
+    ap.add_argument("--peak", action="store_true",
+                    help="only run the vector-ALU issue-rate probe behind the roofline peak and print one JSON line")
+    ap.add_argument("--no-staged", action="store_true", help="skip the staged-form timing in the default line")
+    ap.add_argument("--no-serving", action="store_true", help="skip the short serving trace in the default line")
+    ap.add_argument("--serving-short-requests", type=int, default=200000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (HBM counter calibration)")
     args = ap.parse_args()
@@ -468,6 +558,9 @@ def main():
 
     if args.micro:
         print(json.dumps({"micro": micro_run(args.steps, args.warmup)}), flush=True)
+        return
+    if args.peak:
+        print(json.dumps({"peak": peak_run()}), flush=True)
         return
     if args.ablation:
         print(json.dumps({"ablation": ablation_run(args.level, args.count, args.msg_dist),
@@ -603,6 +696,8 @@ def main():
                           if "traffic_detail" in kextra else None,
                           "kernel": kname}, **kextra),
     }
+    if args.mode == "persistent" and not args.no_staged:
+        out["staged"] = staged_run(level, sk, pk, g_msg, g_off, sig)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(level, seeds, msg, off, msg_desc,
                                            sig.cpu().numpy(), args.cpu_seconds)
@@ -612,6 +707,9 @@ def main():
     if args.serving:
         out["serving"] = serving_run(args.serving_requests, args.serving_seconds, args.serving_streams,
                                      args.serving_batch)
+    elif not args.no_serving:
+        out["serving"] = serving_run(args.serving_short_requests, args.serving_seconds, args.serving_streams,
+                                     args.serving_batch, short=True)
     ctx.close()
     print(json.dumps(out), flush=True)
 

@@ -99,11 +99,33 @@ int dil_ctx_set_mode(dil_ctx *ctx, int mode);
  *                   through HBM, c used as the intermediate); other values
  *                   are DIL_EINVAL. */
 int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value);
+/* Operations, for the workspace queries below. */
+#define DIL_OP_KEYGEN 0
+#define DIL_OP_SIGN 1
+#define DIL_OP_VERIFY 2
+
 /* Grow the context's workspace (synchronously) so that any call with up to
  * `count` tasks at `level` runs without allocating -- serving loops reserve the
  * largest batch they admit up front. */
 int dil_ctx_reserve(dil_ctx *ctx, int level, uint32_t count);
-/* Synchronise `stream` and report a device-detected input error (DIL_EMSG) once. */
+/* As dil_ctx_reserve, for calls of one kind only: op (DIL_OP_*) at `level`,
+ * against a resident key table (keyset != 0: A-hat and the NTT-domain secrets
+ * come from the table and take no workspace) or not, in the context's current
+ * Sign form and schedule knobs, with up to `count` tasks. */
+int dil_ctx_reserve_call(dil_ctx *ctx, int level, int op, int keyset, uint32_t count);
+/* Device bytes of workspace that one such call of exactly `count` tasks needs
+ * (the same layout the call carves: per-task rows, plus the persistent Sign
+ * kernel's per-workgroup scratch at the schedule that count gets).  Memory
+ * budgets of serving loops are accounted with this figure.  The workspace is
+ * allocated stream-ordered on the calling stream; growing it waits only for
+ * this context's previous call. */
+int dil_workspace_bytes(dil_ctx *ctx, int level, int op, int keyset, uint32_t count, size_t *bytes);
+/* Synchronise `stream` and report, once, the conditions the device detected
+ * since the last check: a decreasing msg_off entry (DIL_EMSG), a key-table
+ * index outside its table (DIL_EINVAL) and Sign tasks dropped at the per-task
+ * iteration limit, whose signature rows stay unwritten (DIL_EHIP; unreachable
+ * in practice).  dil_last_error() names every condition that was set; all are
+ * cleared. */
 int dil_ctx_check(dil_ctx *ctx, void *stream);
 /* Text of the last error on this context (static storage inside the context). */
 const char *dil_last_error(dil_ctx *ctx);
@@ -168,35 +190,35 @@ int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_id
 /* ---- Continuous-batching serving engine ----
  * Host-side dispatcher over key tables (one per level; NULL for a level not
  * served).  It keeps up to n_streams batches in flight, each on its own HIP
- * stream with its own context; whenever a stream is free it admits every
- * request that has arrived and fits mem_budget (device bytes of workspace
- * plus message bytes per in-flight request) and max_batch, splits it by
+ * stream with its own contexts; whenever a stream is free it admits the
+ * requests that have arrived, in arrival order, splits the batch by
  * (level, op) into dil_sign_keyset / dil_verify_keyset calls, and stages
  * messages, key indices and signatures through pinned buffers (max_msg_bytes
- * of message data per batch).  The (level, op) groups of a batch run
- * concurrently, each on a stream and context of its own; that needs more
- * hardware queues than HIP's default of 4 per process, so the process should
- * set GPU_MAX_HW_QUEUES (e.g. 16) before HIP starts.  mode is
- * DIL_MODE_STAGED or DIL_MODE_PERSISTENT for Sign; the persistent Sign calls
- * use four-wavefront workgroups ("persist.waves" = 4). */
+ * of message data per batch, at most max_batch requests).
+ * Device memory: at creation each stream reserves, for every (level, op)
+ * group, the workspace of a call of C requests (dil_workspace_bytes), where C
+ * (at most max_batch) is the largest count for which all streams' workspaces
+ * and device staging buffers fit mem_budget bytes; DIL_ENOMEM if not even
+ * C = 1 fits.  A batch then holds at most C requests of each group: a request
+ * that would exceed its group's C (or the message buffer) waits for the next
+ * batch, it never fails, and no call allocates while serving.
+ * The (level, op) groups of a batch run concurrently, each on a stream and
+ * context of its own; that needs more hardware queues than HIP's default of 4
+ * per process, so the process should set GPU_MAX_HW_QUEUES (e.g. 16) before
+ * HIP starts.  mode is DIL_MODE_STAGED or DIL_MODE_PERSISTENT for Sign; the
+ * persistent Sign calls use four-wavefront workgroups ("persist.waves" = 4). */
 typedef struct dil_server dil_server;
 int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset *ks3, dil_keyset *ks5,
                       int n_streams, uint32_t max_batch, size_t max_msg_bytes, size_t mem_budget, int mode);
 /* Waits for the device and frees the engine (not the key tables). */
 int dil_server_destroy(dil_server *s);
 const char *dil_server_last_error(dil_server *s);
-/* Batches launched and host seconds spent forming/launching them in the last run. */
-int dil_server_stats(dil_server *s, uint64_t *batches, double *host_seconds);
-/* Replay a request trace (HOST arrays, n requests in arrival order): request i
- * (op[i] 0 = Sign, 1 = Verify; level[i] in {2,3,5}; key row key[i]; message
- * msg[msg_off[i] .. msg_off[i+1])) becomes visible arrival_ns[i] nanoseconds
- * after the call starts.  Sign writes its signature to sig_out + sig_out_off[i];
- * Verify reads sig_in + sig_in_off[i] and writes verdict[i] (1/0; -1 for Sign).
- * done_ns[i] receives the completion time on the same clock.  Blocks until
- * every request is done; returns DIL_EINVAL for malformed traces (checked on
- * the host before any work starts: unknown level or op, a key row outside the
- * level's table, unsorted arrivals, bad message offsets, missing signature
- * arrays) and DIL_EHIP if a batch fails or no batch completes for 60 s. */
+/* Statistics (any pointer may be NULL): batches launched in the last run, of
+ * them those launched while another batch was still in flight, host seconds
+ * spent forming and launching them; and the per-group request cap C and the
+ * device bytes the engine reserved under its memory budget. */
+int dil_server_stats(dil_server *s, uint64_t *batches, double *host_seconds, uint64_t *overlapped,
+                     uint32_t *group_cap, size_t *reserved_bytes);
 int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *level, const uint32_t *key,
                    const uint8_t *msg, const uint64_t *msg_off, const uint8_t *sig_in, const uint64_t *sig_in_off,
                    const uint64_t *arrival_ns, uint8_t *sig_out, const uint64_t *sig_out_off, int32_t *verdict,
@@ -232,6 +254,16 @@ int dil_ntt_mul_batch(dil_ctx *ctx, const int32_t *a, const int32_t *b, int32_t 
  * 23-bit candidate, kept if < q) -> out[count][256] canonical int32.
  * count must be below 2^32 (DIL_EINVAL otherwise). */
 int dil_expand_a_batch(dil_ctx *ctx, const uint8_t *seeds34, int32_t *out, uint64_t count, void *stream);
+
+/* Diagnostic: the vector-ALU issue-rate probe behind the benchmark's peak.
+ * Launches `groups` workgroups of 256 lanes; every lane executes iters x 128
+ * instructions of one kind (0 v_xor_b32, 1 v_add_u32, 2 v_bitop3_b32,
+ * 3 v_alignbit_b32, 4 v_mul_lo_u32, 5 v_mad_u64_u32) in eight independent
+ * dependency chains and stores one word to out[groups * 256] (device).
+ * *instructions (optional) receives the lane-instructions the launch
+ * executes; dividing by its event-timed duration gives lane-ops/s. */
+int dil_alu_probe(dil_ctx *ctx, int kind, uint32_t iters, uint32_t groups, uint32_t *out, void *stream,
+                  uint64_t *instructions);
 
 #ifdef __cplusplus
 }

@@ -8,8 +8,10 @@
 #include <vector>
 
 #include "../../include/dil.h"
+#include "errwords.h"
 #include "ntt_ablation.h"
 #include "persist.h"
+#include "probe.h"
 
 using namespace dil;
 
@@ -47,6 +49,8 @@ struct dil_ctx {
   // side streams for independent setup stages (fork/join through events)
   hipStream_t side[2] = {nullptr, nullptr};
   hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
+  hipEvent_t done_ev = nullptr;                // recorded after each call's last enqueue
+  int pool_alloc = 0;                          // workspace from the stream-ordered allocator
 };
 
 struct dil_keyset {
@@ -87,104 +91,129 @@ void drop_graphs(dil_ctx *ctx) {
 
 bool valid_level(int lv) { return lv == 2 || lv == 3 || lv == 5; }
 
-template <int LV>
-size_t ws_need(size_t cap) {
-  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
-  size_t muw1 = ((size_t)P<LV>::MUW1 + 255) & ~(size_t)255;
-  size_t per = muw1 + 64 + 32 + 256 + (size_t)K * L * 1024 + (size_t)(L + K) * 1024 + 2 * (size_t)K * 1024 +
-               (size_t)L * 1024 + (size_t)K * 1024 + (size_t)K * 32 + 5 * 4;
-  return cap * per + 16 * 256 + 4096;
-}
+// The kinds of call a workspace is laid out for: each carves only the
+// per-task rows its kernels read or write.
+enum WsForm { WS_KEYGEN = 0, WS_SIGN_STAGED = 1, WS_SIGN_PERSIST = 2, WS_VERIFY = 3 };
 
 template <int LV>
 constexpr int persist_slots(int waves) {
   return waves == 1 ? PCfg<LV>::G : waves * PCfg<LV>::G;
 }
 
+// Lay out the workspace of a call of `cap` tasks at `base` (nullptr: only
+// count) and return its size in bytes.  Every row is 256-byte aligned.  With a
+// resident key table (keyset) A-hat and the NTT-domain secrets come from the
+// table and are not carved; the persistent form adds its per-workgroup scratch
+// for `grid` workgroups of `waves` wavefronts.
 template <int LV>
-size_t pscr_need(size_t grid, int waves) {
+size_t ws_layout(uint8_t *base, size_t cap, int form, bool keyset, size_t grid, int waves, Ws *ws, PScr *sc,
+                 uint32_t **kidx) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
-  size_t G = persist_slots<LV>(waves);
-  size_t w1s = ((size_t)K * P<LV>::W1B + 255) & ~(size_t)255;
-  size_t stage = waves > 1 ? sig_stride<LV>() : 0;
-  return grid * G * ((size_t)(L + K) * 1024 + w1s + stage) + 4 * 256;
+  const bool sign = form == WS_SIGN_STAGED || form == WS_SIGN_PERSIST, staged = form == WS_SIGN_STAGED;
+  size_t off = 0;
+  auto take = [&](bool used, size_t bytes) -> uint8_t * {
+    if (!used) return nullptr;
+    uint8_t *r = base ? base + off : nullptr;
+    off += (bytes + 255) & ~(size_t)255;
+    return r;
+  };
+  const size_t muw1_stride = ((size_t)P<LV>::MUW1 + 255) & ~(size_t)255;
+  Ws w{};
+  w.cap = cap;
+  w.muw1_stride = muw1_stride;
+  w.counters = (uint32_t *)take(true, 16 * 4);
+  w.muw1 = take(sign || form == WS_VERIFY, cap * muw1_stride);
+  w.rhop = take(sign || form == WS_KEYGEN, cap * 64);
+  w.ctilde = take(staged, cap * 32);
+  w.cpoly = (int8_t *)take(staged || form == WS_VERIFY, cap * 256);
+  w.A = (int32_t *)take(!keyset, cap * K * L * 1024);
+  w.s1h = (int32_t *)take(form == WS_KEYGEN || (sign && !keyset), cap * (form == WS_KEYGEN ? L + K : L) * 1024);
+  w.s2h = (int32_t *)take(sign && !keyset, cap * K * 1024);
+  w.t0h = (int32_t *)take(sign && !keyset, cap * K * 1024);
+  w.y = (int32_t *)take(staged, cap * L * 1024);
+  w.w = (int32_t *)take(staged, cap * K * 1024);
+  w.hmask = (uint32_t *)take(form == WS_VERIFY, cap * K * 32);
+  w.flag = (int32_t *)take(form == WS_VERIFY, cap * 4);
+  w.kappa = (uint32_t *)take(sign, cap * 4);
+  w.active0 = (uint32_t *)take(sign, cap * 4);
+  w.active1 = (uint32_t *)take(staged, cap * 4);
+  uint32_t *kid = (uint32_t *)take(keyset, cap * 4);  // checked key indices of key-table calls
+  PScr p{};
+  if (form == WS_SIGN_PERSIST) {
+    const size_t G = persist_slots<LV>(waves);
+    const size_t w1s = ((size_t)K * P<LV>::W1B + 255) & ~(size_t)255;
+    p.y = (int32_t *)take(true, grid * G * L * 1024);
+    p.w = (int32_t *)take(true, grid * G * K * 1024);
+    p.w1 = take(true, grid * G * w1s);
+    p.stage = take(waves > 1, grid * G * sig_stride<LV>());
+  }
+  if (ws) *ws = w;
+  if (sc) *sc = p;
+  if (kidx) *kidx = kid;
+  return off;
+}
+
+// Record the end of a call's work on its stream: a later workspace growth
+// waits for this event (the last call of the context) instead of the device.
+int mark_done(dil_ctx *ctx, hipStream_t st) {
+  if (!ctx->done_ev) HIPCHK(ctx, hipEventCreateWithFlags(&ctx->done_ev, hipEventDisableTiming));
+  HIPCHK(ctx, hipEventRecord(ctx->done_ev, st));
+  return DIL_OK;
+}
+
+// Make sure the context's workspace holds `need` bytes.  Growing it waits for
+// the context's own last call (calls on one context are ordered by contract),
+// drops the graphs that captured the old addresses and replaces the memory in
+// stream order on `st`, so other contexts and streams never stall on it.
+int ws_reserve_bytes(dil_ctx *ctx, size_t need, hipStream_t st) {
+  if (need <= ctx->ws_bytes) return DIL_OK;
+  if (ctx->done_ev) HIPCHK(ctx, hipEventSynchronize(ctx->done_ev));
+  drop_graphs(ctx);
+  if (ctx->ws_mem) {
+    // (hipFree would synchronise the whole device)
+    if (ctx->pool_alloc) HIPCHK(ctx, hipFreeAsync(ctx->ws_mem, st));
+    else HIPCHK(ctx, hipFree(ctx->ws_mem));
+    ctx->ws_mem = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  hipError_t e = ctx->pool_alloc ? hipMallocAsync(&ctx->ws_mem, need, st) : hipMalloc(&ctx->ws_mem, need);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->ws_mem = nullptr;
+    return fail(ctx, DIL_ENOMEM, "workspace allocation", e);
+  }
+  ctx->ws_bytes = need;
+  return DIL_OK;
 }
 
 template <int LV>
-int ws_carve(dil_ctx *ctx, size_t cap, Ws &ws, size_t grid = 0, PScr *sc = nullptr, int waves = 1,
-             uint32_t **kidx = nullptr) {
-  size_t need = ws_need<LV>(cap) + (sc ? pscr_need<LV>(grid, waves) : 0);
-  if (need > ctx->ws_bytes) {
-    if (ctx->ws_mem) {
-      hipDeviceSynchronize();
-      drop_graphs(ctx);
-      hipFree(ctx->ws_mem);
-      ctx->ws_mem = nullptr;
-      ctx->ws_bytes = 0;
-    }
-    hipError_t e = hipMalloc(&ctx->ws_mem, need);
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(ctx, DIL_ENOMEM, "workspace allocation", e);
-    }
-    ctx->ws_bytes = need;
-  }
-  constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
-  uint8_t *p = (uint8_t *)ctx->ws_mem;
-  auto take = [&](size_t bytes) {
-    uint8_t *r = p;
-    p += (bytes + 255) & ~(size_t)255;
-    return r;
-  };
-  ws.cap = cap;
+int ws_carve(dil_ctx *ctx, hipStream_t st, size_t cap, int form, bool keyset, Ws &ws, size_t grid = 0,
+             PScr *sc = nullptr, int waves = 1, uint32_t **kidx = nullptr) {
+  const size_t need = ws_layout<LV>(nullptr, cap, form, keyset, grid, waves, nullptr, nullptr, nullptr);
+  int rc = ws_reserve_bytes(ctx, need, st);
+  if (rc) return rc;
+  const size_t got = ws_layout<LV>((uint8_t *)ctx->ws_mem, cap, form, keyset, grid, waves, &ws, sc, kidx);
+  if (got > ctx->ws_bytes) return fail(ctx, DIL_ENOMEM, "workspace layout overflow");
   ws.kmap = nullptr;
   ws.t1h = nullptr;
   ws.tr = nullptr;
-  ws.muw1_stride = ((size_t)P<LV>::MUW1 + 255) & ~(size_t)255;
-  ws.counters = (uint32_t *)take(16 * 4);
-  ws.muw1 = take(cap * ws.muw1_stride);
-  ws.rhop = take(cap * 64);
-  ws.ctilde = take(cap * 32);
-  ws.cpoly = (int8_t *)take(cap * 256);
-  ws.A = (int32_t *)take(cap * K * L * 1024);
-  ws.s1h = (int32_t *)take(cap * (L + K) * 1024);
-  ws.s2h = (int32_t *)take(cap * K * 1024);
-  ws.t0h = (int32_t *)take(cap * K * 1024);
-  ws.y = (int32_t *)take(cap * L * 1024);
-  ws.w = (int32_t *)take(cap * K * 1024);
-  ws.hmask = (uint32_t *)take(cap * K * 32);
-  ws.kappa = (uint32_t *)take(cap * 4);
-  ws.flag = (int32_t *)take(cap * 4);
-  ws.active0 = (uint32_t *)take(cap * 4);
-  ws.active1 = (uint32_t *)take(cap * 4);
-  uint32_t *kid = (uint32_t *)take(cap * 4);  // checked key indices of key-table calls
-  if (kidx) *kidx = kid;
-  if (sc) {
-    size_t G = persist_slots<LV>(waves);
-    size_t w1s = ((size_t)K * P<LV>::W1B + 255) & ~(size_t)255;
-    sc->y = (int32_t *)take(grid * G * L * 1024);
-    sc->w = (int32_t *)take(grid * G * K * 1024);
-    sc->w1 = take(grid * G * w1s);
-    sc->stage = waves > 1 ? take(grid * G * sig_stride<LV>()) : nullptr;
-  }
-  if ((size_t)(p - (uint8_t *)ctx->ws_mem) > ctx->ws_bytes) return fail(ctx, DIL_ENOMEM, "workspace layout overflow");
   return DIL_OK;
 }
 
-// read and clear the device-side input error words (synchronises `st`):
-// dev_stats[8] a decreasing msg_off entry, dev_stats[9] a key index outside a
-// key table
+// Read and clear the device-detected error words (errwords.h) after the work
+// enqueued on `st`; synchronises `st`.
 int take_msg_error(dil_ctx *ctx, hipStream_t st) {
-  HIPCHK(ctx, hipMemcpyAsync(ctx->host_counters + 8, ctx->dev_stats + 8, 8, hipMemcpyDeviceToHost, st));
+  HIPCHK(ctx, hipMemcpyAsync(ctx->host_counters, ctx->dev_stats, 16 * 4, hipMemcpyDeviceToHost, st));
   HIPCHK(ctx, hipStreamSynchronize(st));
-  const uint32_t msg_flag = ctx->host_counters[8], key_flag = ctx->host_counters[9];
-  if (msg_flag || key_flag) {
-    HIPCHK(ctx, hipMemsetAsync(ctx->dev_stats + 8, 0, 8, st));
-    HIPCHK(ctx, hipStreamSynchronize(st));
-    if (key_flag) return fail(ctx, DIL_EINVAL, "key index outside the key table (those tasks used key row 0)");
-    return fail(ctx, DIL_EMSG, "decreasing msg_off entry (those messages were treated as empty)");
-  }
-  return DIL_OK;
+  const uint32_t dropped = ctx->host_counters[ERR_WORD_DROPPED], msg_flag = ctx->host_counters[ERR_WORD_MSG],
+                 key_flag = ctx->host_counters[ERR_WORD_KEY];
+  char text[sizeof ctx->err];
+  const int code = report_error_words(dropped, msg_flag, key_flag, text, sizeof text);
+  if (code == DIL_OK) return DIL_OK;
+  zero_words_k<<<1, 64, 0, st>>>(ctx->dev_stats + ERR_WORD_DROPPED, 1, ctx->dev_stats + ERR_WORD_MSG, 2);
+  LAUNCHCHK(ctx);
+  HIPCHK(ctx, hipStreamSynchronize(st));
+  return fail(ctx, code, text);
 }
 
 // Enqueue fn(stream) on st, or -- with graphs enabled -- replay the graph that
@@ -264,7 +293,7 @@ template <int LV>
 int keygen_impl(dil_ctx *ctx, const uint8_t *seeds, uint8_t *pk, uint8_t *sk, uint32_t count, hipStream_t st) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
   Ws ws;
-  int rc = ws_carve<LV>(ctx, count, ws);
+  int rc = ws_carve<LV>(ctx, st, count, WS_KEYGEN, false, ws);
   if (rc) return rc;
   kg_seed_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(seeds, pk, sk, ws, count);
   expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, EA_WG), EA_WG, 0, st>>>(pk, P<LV>::PK, nullptr, ws.A, count);
@@ -272,7 +301,7 @@ int keygen_impl(dil_ctx *ctx, const uint8_t *seeds, uint8_t *pk, uint8_t *sk, ui
   kg_main_k<LV><<<count, 64, 0, st>>>(ws, pk, sk, count);
   kg_tr_k<LV><<<blocks_for(count, 256), 256, 0, st>>>(pk, sk, count);
   LAUNCHCHK(ctx);
-  return DIL_OK;
+  return mark_done(ctx, st);
 }
 
 // Resident key tables replace the per-task A-hat / NTT(s) arrays (no ExpandA,
@@ -327,7 +356,7 @@ int sign_staged(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const 
   constexpr int L = Lv<LV>::L;
   Ws ws;
   uint32_t *kid = nullptr;
-  int rc = ws_carve<LV>(ctx, count, ws, 0, nullptr, 1, &kid);
+  int rc = ws_carve<LV>(ctx, st, count, WS_SIGN_STAGED, ks != nullptr, ws, 0, nullptr, 1, &kid);
   if (rc) return rc;
   if (ks) {
     check_keys(ctx, ks, key_idx, kid, count, st);
@@ -357,6 +386,8 @@ int sign_staged(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const 
   }
   ctx->stat_evaluated = evaluated;
   ctx->stat_sequential = evaluated;
+  rc = mark_done(ctx, st);
+  if (rc) return rc;
   return take_msg_error(ctx, st);
 }
 
@@ -379,24 +410,36 @@ int persist_occupancy(dil_ctx *ctx, int *occ) {
   return DIL_OK;
 }
 
+// Schedule of a persistent Sign call of `count` tasks: workgroups launched and
+// tasks each holds at a time (the "persist.*" knobs, else one wave of
+// resident workgroups sharing the tasks evenly).
+template <int LV>
+int persist_schedule(dil_ctx *ctx, uint32_t count, uint64_t *grid_out, uint64_t *hmax_out) {
+  const int G = persist_slots<LV>(ctx->persist_waves);
+  int occ = 1;
+  int rc = persist_occupancy<LV>(ctx, &occ);
+  if (rc) return rc;
+  const uint64_t pmax = (uint64_t)occ * ctx->cu_count, n = std::max<uint32_t>(count, 1);
+  uint64_t hmax = ctx->persist_hmax > 0 ? (uint64_t)ctx->persist_hmax : (n + pmax - 1) / pmax;
+  hmax = std::min<uint64_t>(std::max<uint64_t>(hmax, 1), G);
+  uint64_t grid = ctx->persist_grid > 0 ? (uint64_t)ctx->persist_grid : std::min<uint64_t>(pmax, (n + hmax - 1) / hmax);
+  *grid_out = std::max<uint64_t>(grid, 1);
+  *hmax_out = hmax;
+  return DIL_OK;
+}
+
 template <int LV>
 int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                     const uint64_t *msg_off, uint8_t *sig, uint32_t count, hipStream_t st,
                     const dil_keyset *ks = nullptr, const uint8_t *rnd = nullptr) {
   const int waves = ctx->persist_waves;
-  const int G = persist_slots<LV>(waves);
-  int occ = 1;
-  int rc = persist_occupancy<LV>(ctx, &occ);
+  uint64_t grid = 1, hmax = 1;
+  int rc = persist_schedule<LV>(ctx, count, &grid, &hmax);
   if (rc) return rc;
-  uint64_t pmax = (uint64_t)occ * ctx->cu_count;
-  uint64_t hmax = ctx->persist_hmax > 0 ? (uint64_t)ctx->persist_hmax : (count + pmax - 1) / pmax;
-  hmax = std::min<uint64_t>(std::max<uint64_t>(hmax, 1), G);
-  uint64_t grid = ctx->persist_grid > 0 ? (uint64_t)ctx->persist_grid : std::min<uint64_t>(pmax, (count + hmax - 1) / hmax);
-  grid = std::max<uint64_t>(grid, 1);
   Ws ws;
   PScr sc;
   uint32_t *kid = nullptr;
-  rc = ws_carve<LV>(ctx, count, ws, grid, &sc, waves, &kid);
+  rc = ws_carve<LV>(ctx, st, count, WS_SIGN_PERSIST, ks != nullptr, ws, grid, &sc, waves, &kid);
   if (rc) return rc;
   const uint32_t *key_in = key_idx;
   if (ks) key_idx = use_keyset(ws, ks, key_idx, kid);
@@ -430,7 +473,7 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   }
   ctx->last_stream = st;
   ctx->stats_pending = 1;
-  return DIL_OK;
+  return mark_done(ctx, st);
 }
 
 template <int LV>
@@ -440,13 +483,13 @@ int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const 
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
   Ws ws;
   uint32_t *kid = nullptr;
-  int rc = ws_carve<LV>(ctx, count, ws, 0, nullptr, 1, &kid);
+  int rc = ws_carve<LV>(ctx, st, count, WS_VERIFY, ks != nullptr, ws, 0, nullptr, 1, &kid);
   if (rc) return rc;
   const uint32_t *key_in = key_idx;
   if (ks) key_idx = use_keyset(ws, ks, key_idx, kid);
   uint64_t key[16] = {2, (uint64_t)LV, (uint64_t)pk, (uint64_t)key_in, (uint64_t)msg, (uint64_t)msg_off,
                       (uint64_t)sig, (uint64_t)verdict, count, (uint64_t)ks, (uint64_t)ctx->ws_mem, 0, 0, 0, 0, 0};
-  return enqueue(ctx, key, st, [&](hipStream_t s) {
+  rc = enqueue(ctx, key, st, [&](hipStream_t s) {
     zero_words_k<<<1, 64, 0, s>>>(ws.counters, 16, nullptr, 0);
     check_keys(ctx, ks, key_in, kid, count, s);
     // Three independent fronts: the tr / mu hash chain (needed only by the
@@ -480,6 +523,8 @@ int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const 
     LAUNCHCHK(ctx);
     return DIL_OK;
   });
+  if (rc) return rc;
+  return mark_done(ctx, st);
 }
 
 template <int LV>
@@ -579,15 +624,11 @@ int dil_ctx_create(dil_ctx **out, int device, size_t workspace_bytes) {
     delete c;
     return DIL_ENOMEM;
   }
-  if (workspace_bytes) {
-    e = hipMalloc(&c->ws_mem, workspace_bytes);
-    if (e != hipSuccess) {
-      hipFree(c->dev_stats);
-      hipHostFree(c->host_counters);
-      delete c;
-      return DIL_ENOMEM;
-    }
-    c->ws_bytes = workspace_bytes;
+  int pools = 0;
+  c->pool_alloc = hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, device) == hipSuccess && pools;
+  if (workspace_bytes && (ws_reserve_bytes(c, workspace_bytes, nullptr) || hipStreamSynchronize(nullptr) != hipSuccess)) {
+    dil_ctx_destroy(c);
+    return DIL_ENOMEM;
   }
   *out = c;
   return DIL_OK;
@@ -597,7 +638,15 @@ int dil_ctx_destroy(dil_ctx *ctx) {
   if (!ctx) return DIL_EINVAL;
   hipSetDevice(ctx->device);
   hipDeviceSynchronize();
-  if (ctx->ws_mem) hipFree(ctx->ws_mem);
+  if (ctx->ws_mem) {
+    if (ctx->pool_alloc) {
+      hipFreeAsync(ctx->ws_mem, nullptr);
+      hipStreamSynchronize(nullptr);
+    } else {
+      hipFree(ctx->ws_mem);
+    }
+  }
+  if (ctx->done_ev) hipEventDestroy(ctx->done_ev);
   if (ctx->host_counters) hipHostFree(ctx->host_counters);
   if (ctx->dev_stats) hipFree(ctx->dev_stats);
   drop_graphs(ctx);
@@ -782,19 +831,79 @@ int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_id
   });
 }
 
+}  // extern "C"
+
+namespace {
+// workspace bytes of one call (op DIL_OP_*, resident key table or not) of
+// `count` tasks in the context's current Sign form and schedule knobs; with
+// `upto` the layout covers every call of at most `count` tasks
+template <int LV>
+int call_bytes(dil_ctx *ctx, int op, bool keyset, uint32_t count, bool upto, size_t *bytes) {
+  if (op == DIL_OP_KEYGEN) {
+    *bytes = ws_layout<LV>(nullptr, count, WS_KEYGEN, false, 0, 1, nullptr, nullptr, nullptr);
+  } else if (op == DIL_OP_VERIFY) {
+    *bytes = ws_layout<LV>(nullptr, count, WS_VERIFY, keyset, 0, 1, nullptr, nullptr, nullptr);
+  } else if (op == DIL_OP_SIGN && ctx->mode == DIL_MODE_STAGED) {
+    *bytes = ws_layout<LV>(nullptr, count, WS_SIGN_STAGED, keyset, 0, 1, nullptr, nullptr, nullptr);
+  } else if (op == DIL_OP_SIGN) {
+    uint64_t grid = 1, hmax = 1;
+    int rc = persist_schedule<LV>(ctx, count, &grid, &hmax);
+    if (rc) return rc;
+    if (upto && ctx->persist_grid <= 0) {  // smaller calls launch at most min(count, resident) workgroups
+      int occ = 1;
+      rc = persist_occupancy<LV>(ctx, &occ);
+      if (rc) return rc;
+      grid = std::max<uint64_t>(grid, std::min<uint64_t>(std::max<uint32_t>(count, 1), (uint64_t)occ * ctx->cu_count));
+    }
+    *bytes = ws_layout<LV>(nullptr, count, WS_SIGN_PERSIST, keyset, grid, ctx->persist_waves, nullptr, nullptr,
+                           nullptr);
+  } else {
+    return fail(ctx, DIL_EINVAL, "op must be DIL_OP_KEYGEN, DIL_OP_SIGN or DIL_OP_VERIFY");
+  }
+  return DIL_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int dil_workspace_bytes(dil_ctx *ctx, int level, int op, int keyset, uint32_t count, size_t *bytes) {
+  if (!ctx || !valid_level(level) || !bytes) return fail(ctx, DIL_EINVAL, "bad context, level or output");
+  hipSetDevice(ctx->device);
+  return by_level(level, [&](auto lv) { return call_bytes<decltype(lv)::value>(ctx, op, keyset != 0, count, false, bytes); });
+}
+
+int dil_ctx_reserve_call(dil_ctx *ctx, int level, int op, int keyset, uint32_t count) {
+  if (!ctx || !valid_level(level)) return fail(ctx, DIL_EINVAL, "bad context or level");
+  hipSetDevice(ctx->device);
+  size_t need = 0;
+  int rc = by_level(level, [&](auto lv) { return call_bytes<decltype(lv)::value>(ctx, op, keyset != 0, count, true, &need); });
+  if (rc) return rc;
+  rc = ws_reserve_bytes(ctx, need, nullptr);
+  if (rc) return rc;
+  HIPCHK(ctx, hipStreamSynchronize(nullptr));
+  return DIL_OK;
+}
+
 int dil_ctx_reserve(dil_ctx *ctx, int level, uint32_t count) {
   if (!ctx || !valid_level(level)) return fail(ctx, DIL_EINVAL, "bad context or level");
   hipSetDevice(ctx->device);
-  return by_level(level, [&](auto lv) {
-    constexpr int LV = decltype(lv)::value;
-    int occ = 1;
-    int rc = persist_occupancy<LV>(ctx, &occ);
-    if (rc) return rc;
-    size_t grid = std::max<size_t>((size_t)occ * ctx->cu_count, (size_t)std::max<int64_t>(ctx->persist_grid, 0));
-    Ws ws;
-    PScr sc;
-    return ws_carve<LV>(ctx, count, ws, grid, &sc, ctx->persist_waves);
-  });
+  size_t need = 0;
+  const int saved = ctx->mode;
+  int rc = DIL_OK;
+  for (int op = DIL_OP_KEYGEN; op <= DIL_OP_VERIFY && !rc; op++)
+    for (int ks = 0; ks < 2 && !rc; ks++)
+      for (int m = DIL_MODE_STAGED; m <= DIL_MODE_PERSISTENT && !rc; m++) {
+        ctx->mode = m;
+        size_t b = 0;
+        rc = by_level(level, [&](auto lv) { return call_bytes<decltype(lv)::value>(ctx, op, ks != 0, count, true, &b); });
+        need = std::max(need, b);
+      }
+  ctx->mode = saved;
+  if (rc) return rc;
+  rc = ws_reserve_bytes(ctx, need, nullptr);
+  if (rc) return rc;
+  HIPCHK(ctx, hipStreamSynchronize(nullptr));
+  return DIL_OK;
 }
 
 int dil_persist_capacity(dil_ctx *ctx, int level, int *resident_groups, int *slots_per_batch) {
@@ -881,6 +990,25 @@ int dil_ntt_mul_batch(dil_ctx *ctx, const int32_t *a, const int32_t *b, int32_t 
     }
   }
   LAUNCHCHK(ctx);
+  return DIL_OK;
+}
+
+int dil_alu_probe(dil_ctx *ctx, int kind, uint32_t iters, uint32_t groups, uint32_t *out, void *stream,
+                  uint64_t *instructions) {
+  if (!ctx || !out || groups == 0) return fail(ctx, DIL_EINVAL, "bad probe arguments");
+  hipSetDevice(ctx->device);
+  const hipStream_t st = (hipStream_t)stream;
+  switch (kind) {
+    case 0: alu_probe_k<0><<<groups, PROBE_WG, 0, st>>>(out, iters); break;
+    case 1: alu_probe_k<1><<<groups, PROBE_WG, 0, st>>>(out, iters); break;
+    case 2: alu_probe_k<2><<<groups, PROBE_WG, 0, st>>>(out, iters); break;
+    case 3: alu_probe_k<3><<<groups, PROBE_WG, 0, st>>>(out, iters); break;
+    case 4: alu_probe_k<4><<<groups, PROBE_WG, 0, st>>>(out, iters); break;
+    case 5: alu_probe_k<5><<<groups, PROBE_WG, 0, st>>>(out, iters); break;
+    default: return fail(ctx, DIL_EINVAL, "probe kind must be 0..5");
+  }
+  LAUNCHCHK(ctx);
+  if (instructions) *instructions = (uint64_t)groups * PROBE_WG * iters * PROBE_INSTR_PER_ITER;
   return DIL_OK;
 }
 

@@ -3,11 +3,17 @@
 // Requests -- Sign or Verify of one message against one key row of a level's
 // dil_keyset -- become visible to the dispatcher at their arrival time.  The
 // dispatcher keeps up to n_streams batches in flight, each on its own HIP
-// stream with its own libdil context (workspace) and pinned staging buffers.
-// Whenever a stream is free it admits every arrived request that fits the
-// device-memory budget, splits the batch by (level, op) into
-// dil_sign_keyset / dil_verify_keyset calls, and enqueues the host->device
-// copies, the kernels and the device->host copies followed by an event.
+// stream with its own libdil contexts (workspaces) and pinned staging buffers.
+// Device memory: at creation every lane reserves, for each (level, op) group,
+// the workspace of a key-table call of C requests (dil_workspace_bytes), C the
+// largest count for which all lanes' workspaces and device staging buffers fit
+// the memory budget; no call allocates afterwards.  Whenever a stream is free
+// the dispatcher admits the arrived requests in order while each (level, op)
+// group of the batch holds at most C of them (and the messages fit the
+// staging buffer); the next request waits for the next batch.  The batch is
+// split by (level, op) into dil_sign_keyset / dil_verify_keyset calls, and the
+// host->device copies, the kernels and the device->host copies are enqueued,
+// followed by an event.
 // The (level, op) groups of a batch are independent: each runs on a stream and
 // context of its own, forked after the batch's copies in and joined before its
 // copies out, so a batch takes about as long as its slowest group.  This
@@ -51,7 +57,6 @@ struct Lane {
   uint32_t *h_key = nullptr, *d_key = nullptr;
   int32_t *h_ver = nullptr, *d_ver = nullptr;
   bool busy = false;
-  size_t bytes = 0;
   std::vector<Group> groups;
 };
 
@@ -62,11 +67,12 @@ struct dil_server {
   dil_keyset *ks[NLV] = {nullptr, nullptr, nullptr};
   size_t sig_bytes[NLV] = {0, 0, 0};
   uint32_t max_batch = 0;
-  size_t max_msg = 0, budget = 0;
+  uint32_t group_cap = 0;     // requests of one (level, op) group per batch (memory budget)
+  size_t max_msg = 0, budget = 0, reserved = 0;
   std::vector<Lane> lanes;
   char err[256] = {0};
   // statistics of the last run
-  uint64_t batches = 0;
+  uint64_t batches = 0, overlapped = 0;
   double host_s = 0;
 };
 
@@ -77,9 +83,19 @@ int sfail(dil_server *s, int code, const char *what) {
   return code;
 }
 
-size_t task_bytes(int li) {  // device workspace per in-flight task, used for admission
-  static const size_t b[NLV] = {48u << 10, 80u << 10, 120u << 10};
-  return b[li];
+// Device bytes one lane holds with every group context reserved for `cap`
+// requests (workspaces as the library lays them out, plus the staging buffers).
+int lane_bytes(dil_server *s, const Lane &ln, uint32_t cap, size_t staging, size_t *out) {
+  size_t total = staging;
+  for (int gi = 0; gi < NGROUP; gi++) {
+    if (!ln.gctx[gi]) continue;
+    size_t b = 0;
+    int rc = dil_workspace_bytes(ln.gctx[gi], kLevels[gi / 2], gi % 2 ? DIL_OP_VERIFY : DIL_OP_SIGN, 1, cap, &b);
+    if (rc) return rc;
+    total += b;
+  }
+  *out = total;
+  return DIL_OK;
 }
 
 }  // namespace
@@ -120,8 +136,7 @@ int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset 
            // a group call holds few tasks: four-wavefront workgroups give each
            // task 4 x 64 / l nonces per batch, so almost every task passes in
            // the first batch instead of needing a second or third
-           (gi % 2 == 1 || dil_ctx_set_param(ln.gctx[gi], "persist.waves", 4) == DIL_OK) &&
-           dil_ctx_reserve(ln.gctx[gi], kLevels[li], max_batch) == DIL_OK;
+           (gi % 2 == 1 || dil_ctx_set_param(ln.gctx[gi], "persist.waves", 4) == DIL_OK);
     }
     ok = ok && hipHostMalloc((void **)&ln.h_msg, max_msg_bytes, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc((void **)&ln.h_sig, max_batch * max_sig, hipHostMallocDefault) == hipSuccess &&
@@ -138,6 +153,39 @@ int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset 
       return DIL_ENOMEM;
     }
   }
+  // the largest per-group request count whose reservations fit the budget
+  const size_t staging = max_msg_bytes + max_batch * max_sig + 2 * (max_batch + 8) * 8 + 2 * max_batch * 4;
+  auto fits = [&](uint32_t cap, bool *ok) {
+    size_t per = 0;
+    if (lane_bytes(s, s->lanes[0], cap, staging, &per)) return DIL_EHIP;
+    *ok = per * s->lanes.size() <= mem_budget;
+    return DIL_OK;
+  };
+  uint32_t lo = 0, hi = max_batch;  // lo fits (0 = nothing fits yet), hi + 1 does not
+  for (uint32_t probe = 1; lo < hi; probe = lo + (hi - lo + 1) / 2) {
+    bool ok = false;
+    if (fits(probe, &ok)) {
+      dil_server_destroy(s);
+      return DIL_EHIP;
+    }
+    if (ok) lo = probe;
+    else hi = probe - 1;
+  }
+  if (lo == 0) {
+    dil_server_destroy(s);
+    return DIL_ENOMEM;  // not even one request per group fits the budget
+  }
+  s->group_cap = lo;
+  for (auto &ln : s->lanes)
+    for (int gi = 0; gi < NGROUP; gi++)
+      if (ln.gctx[gi] && dil_ctx_reserve_call(ln.gctx[gi], kLevels[gi / 2], gi % 2 ? DIL_OP_VERIFY : DIL_OP_SIGN, 1,
+                                              lo) != DIL_OK) {
+        dil_server_destroy(s);
+        return DIL_ENOMEM;
+      }
+  size_t per = 0;
+  lane_bytes(s, s->lanes[0], lo, staging, &per);
+  s->reserved = per * s->lanes.size();
   *out = s;
   return DIL_OK;
 }
@@ -172,10 +220,14 @@ int dil_server_destroy(dil_server *s) {
 
 const char *dil_server_last_error(dil_server *s) { return s ? s->err : "null server"; }
 
-int dil_server_stats(dil_server *s, uint64_t *batches, double *host_seconds) {
+int dil_server_stats(dil_server *s, uint64_t *batches, double *host_seconds, uint64_t *overlapped,
+                     uint32_t *group_cap, size_t *reserved_bytes) {
   if (!s) return DIL_EINVAL;
   if (batches) *batches = s->batches;
   if (host_seconds) *host_seconds = s->host_s;
+  if (overlapped) *overlapped = s->overlapped;
+  if (group_cap) *group_cap = s->group_cap;
+  if (reserved_bytes) *reserved_bytes = s->reserved;
   return DIL_OK;
 }
 
@@ -205,9 +257,8 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
   const auto t0 = clk::now();
   auto now_ns = [&]() { return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(clk::now() - t0).count(); };
   double host = 0;
-  uint64_t batches = 0;
+  uint64_t batches = 0, overlapped = 0;
   uint32_t head = 0, done = 0;
-  size_t inflight = 0;
   std::vector<Lane *> free_lanes;
   for (auto &ln : s->lanes) free_lanes.push_back(&ln);
   auto last_progress = clk::now();
@@ -235,7 +286,6 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
         }
         done += (uint32_t)g.req.size();
       }
-      inflight -= ln.bytes;
       ln.busy = false;
       ln.groups.clear();
       free_lanes.push_back(&ln);
@@ -247,13 +297,16 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
     if (!free_lanes.empty() && head < arrived) {
       auto h0 = clk::now();
       Lane &ln = *free_lanes.back();
-      size_t bytes = 0, mbytes = 0;
+      size_t mbytes = 0;
+      uint32_t per_group[NGROUP] = {};
       uint32_t end = head;
       while (end < arrived && end - head < s->max_batch) {
         size_t ml = msg_off[end + 1] - msg_off[end];
-        size_t b = task_bytes(lv_index(level[end])) + ml;
-        if (end > head && (inflight + bytes + b > s->budget || mbytes + ml > s->max_msg)) break;
-        bytes += b;
+        const int gi = 2 * lv_index(level[end]) + op[end];
+        // in arrival order: the first request whose group is full (its workspace
+        // reservation) or whose message does not fit waits for the next batch
+        if (per_group[gi] == s->group_cap || mbytes + ml > s->max_msg) break;
+        per_group[gi]++;
         mbytes += ml;
         end++;
       }
@@ -326,9 +379,10 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
              hipMemcpyAsync(ln.h_ver, ln.d_ver, t_pos * 4, hipMemcpyDeviceToHost, ln.st) == hipSuccess &&
              hipEventRecord(ln.ev, ln.st) == hipSuccess;
         if (!ok) return sfail(s, DIL_EHIP, "device-to-host copy");
+        bool others_busy = false;  // launched while another batch is still in flight
+        for (auto &other : s->lanes) others_busy |= &other != &ln && other.busy;
+        overlapped += others_busy ? 1 : 0;
         ln.busy = true;
-        ln.bytes = bytes;
-        inflight += bytes;
         head = end;
         batches++;
         progressed = true;
@@ -349,6 +403,7 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
     }
   }
   s->batches = batches;
+  s->overlapped = overlapped;
   s->host_s = host;
   return DIL_OK;
 }

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libdil.so")
 
 DIL_OK, DIL_EINVAL, DIL_ENOMEM, DIL_EHIP, DIL_EMSG = 0, -1, -2, -3, -4
 MODE_STAGED, MODE_PERSISTENT = 0, 1
+OP_KEYGEN, OP_SIGN, OP_VERIFY = 0, 1, 2
 
 EXPORTS = [
     "dil_ctx_create", "dil_ctx_destroy", "dil_ctx_set_mode", "dil_ctx_set_param", "dil_ctx_check",
@@ -25,7 +26,8 @@ EXPORTS = [
     "dil_ntt_mul_batch",
     "dil_expand_a_batch", "dil_keyset_create", "dil_keyset_destroy", "dil_keyset_info", "dil_sign_keyset",
     "dil_verify_keyset", "dil_persist_capacity", "dil_ctx_reserve", "dil_server_create", "dil_server_destroy",
-    "dil_server_last_error", "dil_server_stats", "dil_server_run",
+    "dil_server_last_error", "dil_server_stats", "dil_server_run", "dil_ctx_reserve_call", "dil_workspace_bytes",
+    "dil_alu_probe",
 ]
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -77,7 +79,14 @@ def load() -> ctypes.CDLL:
                                              ctypes.c_uint32, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int]),
         "dil_server_destroy": (ctypes.c_int, [_P]),
         "dil_server_last_error": (ctypes.c_char_p, [_P]),
-        "dil_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double)]),
+        "dil_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32),
+                                            ctypes.POINTER(ctypes.c_size_t)]),
+        "dil_alu_probe": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, _P, _P,
+                                         ctypes.POINTER(ctypes.c_uint64)]),
+        "dil_ctx_reserve_call": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32]),
+        "dil_workspace_bytes": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32,
+                                               ctypes.POINTER(ctypes.c_size_t)]),
         "dil_server_run": (ctypes.c_int, [_P, ctypes.c_uint32] + [_P] * 12),
     }
     for name, (res, args) in sig.items():
@@ -162,6 +171,16 @@ class Context:
     def reserve(self, level: int, count: int):
         self._check(self.lib.dil_ctx_reserve(self.h, level, count))
 
+    def reserve_call(self, level: int, op: int, keyset: bool, count: int):
+        """Reserve the workspace of calls of one kind (OP_*) with up to `count` tasks."""
+        self._check(self.lib.dil_ctx_reserve_call(self.h, level, op, int(keyset), count))
+
+    def workspace_bytes(self, level: int, op: int, keyset: bool, count: int) -> int:
+        """Device workspace bytes of one call of `count` tasks (the library's own layout)."""
+        b = ctypes.c_size_t()
+        self._check(self.lib.dil_workspace_bytes(self.h, level, op, int(keyset), count, ctypes.byref(b)))
+        return b.value
+
     def check(self, stream=None):
         self._check(self.lib.dil_ctx_check(self.h, _stream(stream)))
 
@@ -217,6 +236,14 @@ class Context:
 
     def ntt_mul(self, a, b, c, stream=None):
         self._check(self.lib.dil_ntt_mul_batch(self.h, _ptr(a), _ptr(b), _ptr(c), a.shape[0], _stream(stream)))
+
+    def alu_probe(self, kind: int, iters: int, groups: int, out, stream=None) -> int:
+        """Launch the ALU issue-rate probe; returns the lane-instructions it executes."""
+        if out.numel() * out.element_size() < groups * 256 * 4:
+            raise ValueError("probe output needs groups * 256 words")
+        n = ctypes.c_uint64()
+        self._check(self.lib.dil_alu_probe(self.h, kind, iters, groups, _ptr(out), _stream(stream), ctypes.byref(n)))
+        return n.value
 
     def expand_a(self, seeds34, out, stream=None):
         self._check(self.lib.dil_expand_a_batch(self.h, _ptr(seeds34), _ptr(out), seeds34.shape[0],

@@ -3,11 +3,18 @@
 Requests (mixed level 2/3/5 Sign and Verify, each against one key of a
 resident key table) arrive over time.  The loop keeps up to `n_streams`
 batches in flight, each on its own HIP stream with its own libdil context
-(workspace): whenever a stream is free, every request that has arrived and
-fits the device-memory budget is admitted as the next batch, split by
-(level, op) into key-table calls (dil_sign_keyset / dil_verify_keyset).
-Requests that arrive while earlier batches run are admitted as soon as a
-stream and memory free up, so their work overlaps on the device.
+(workspace): whenever a stream is free, the requests that have arrived are
+admitted in order as the next batch, split by (level, op) into key-table
+calls (dil_sign_keyset / dil_verify_keyset).  Requests that arrive while
+earlier batches run are admitted as soon as a stream frees up, so their work
+overlaps on the device.
+
+Device memory: every lane reserves up front the workspace of a key-table call
+of C requests for each (level, op) (the library's own layout, from
+dil_workspace_bytes), C the largest count for which all lanes' workspaces and
+device staging buffers fit the memory budget.  A batch holds at most C
+requests of each (level, op); the request that would exceed that waits for
+the next batch.  Nothing is allocated while serving.
 
 Host <-> device traffic goes through pinned staging buffers per stream
 (messages, key indices and input signatures up; signatures and verdicts
@@ -27,9 +34,6 @@ from . import dilithium as dl
 
 SIGN, VERIFY = 0, 1
 LEVELS = (2, 3, 5)
-# device bytes one admitted task holds while in flight (workspace rows + I/O), per level;
-# the workspace layout is in csrc/api.hip (ws_need) plus the persistent kernel's scratch share
-TASK_BYTES = {2: 48 << 10, 3: 80 << 10, 5: 120 << 10}
 
 
 @dataclass
@@ -103,8 +107,6 @@ class _Lane:
         if persistent:
             # few tasks per call: four-wavefront workgroups give each task 4 x 64 / l nonces per batch
             self.ctx.set_param("persist.waves", 4)
-        for lv in LEVELS:   # allocate the workspace for the largest admitted batch once
-            self.ctx.reserve(lv, max_tasks)
         pin = dict(pin_memory=True)
         self.h_msg = torch.empty(max_msg, dtype=torch.uint8, **pin)
         self.h_off = torch.empty(max_tasks + 8, dtype=torch.int64, **pin)
@@ -118,6 +120,18 @@ class _Lane:
         self.d_ver = torch.empty(max_tasks, dtype=torch.int32, device=device)
         self.event = None
         self.batch = None
+        self.staging_bytes = sum(t.numel() * t.element_size() for t in
+                                 (self.d_msg, self.d_off, self.d_key, self.d_sig, self.d_ver))
+
+    def workspace_need(self, cap: int) -> int:
+        """Workspace of the largest of this lane's calls with `cap` requests: the lane's calls
+        run one after another on its stream and share one context."""
+        return max(self.ctx.workspace_bytes(lv, op, True, cap) for lv in LEVELS for op in (dl.OP_SIGN, dl.OP_VERIFY))
+
+    def reserve(self, cap: int):
+        for lv in LEVELS:
+            for op in (dl.OP_SIGN, dl.OP_VERIFY):
+                self.ctx.reserve_call(lv, op, True, cap)
 
     def close(self):
         self.ctx.close()
@@ -136,6 +150,22 @@ class Server:
         self.lanes = [_Lane(torch, self.device, max_msg_bytes, max_batch, max_sig, persistent)
                       for _ in range(n_streams)]
         self.max_msg_bytes = max_msg_bytes
+        # the largest per-(level, op) request count whose reservations fit the budget
+        ln0 = self.lanes[0]
+        lane_bytes = lambda c: ln0.staging_bytes + ln0.workspace_need(c)
+        lo, hi = 0, max_batch
+        while lo < hi:
+            mid = (lo + hi + 1) // 2
+            if lane_bytes(mid) * n_streams <= mem_budget:
+                lo = mid
+            else:
+                hi = mid - 1
+        if lo == 0:
+            raise dl.DilError(dl.DIL_ENOMEM, "the memory budget does not hold one request per (level, op)")
+        self.group_cap = lo
+        self.reserved_bytes = lane_bytes(lo) * n_streams
+        for ln in self.lanes:
+            ln.reserve(lo)
 
     def close(self):
         for ln in self.lanes:
@@ -208,8 +238,18 @@ class Server:
         lane.event = None
         lane.batch = None
 
-    def _cost(self, reqs: Requests, i: int) -> int:
-        return TASK_BYTES[int(reqs.level[i])] + int(reqs.msg_off[i + 1] - reqs.msg_off[i])
+    def _admit(self, reqs: Requests, head: int, end: int) -> int:
+        """Requests head.. admitted in arrival order: at most group_cap of each (level, op) and
+        at most max_msg_bytes of message data; returns how many."""
+        grp = 2 * np.searchsorted(LEVELS, reqs.level[head:end]) + reqs.op[head:end]
+        nth = np.zeros(end - head, np.int64)       # rank of each request within its group
+        for g in np.unique(grp):
+            sel = grp == g
+            nth[sel] = np.arange(int(sel.sum()))
+        over = np.nonzero(nth >= self.group_cap)[0]
+        fit = int(over[0]) if over.size else end - head
+        m = np.cumsum(np.diff(reqs.msg_off[head:end + 1]))
+        return min(fit, int(np.searchsorted(m, self.max_msg_bytes, side="right")))
 
     # ---- the loop ----
     def serve(self, reqs: Requests, time_scale: float = 1.0) -> Results:
@@ -217,11 +257,9 @@ class Server:
         check_requests(reqs, {lv: ks.n_keys for lv, ks in self.keysets.items()})
         n = len(reqs)
         res = Results(verdict=np.full(n, -1, np.int32), t_done=np.full(n, np.nan))
-        cost = np.array([self._cost(reqs, i) for i in range(n)], dtype=np.int64)
-        lens = np.diff(reqs.msg_off)
         free = deque(self.lanes)
         busy: List[_Lane] = []
-        inflight_bytes = {}
+        overlapped = 0
         head = 0
         done = 0
         launch_s: List[float] = []
@@ -236,32 +274,25 @@ class Server:
                     k = lane.batch
                     cnt = sum(g[2].size for g in k)
                     self._collect(lane, res, time.perf_counter() - t0)
-                    inflight_bytes.pop(id(lane), None)
                     busy.remove(lane)
                     free.append(lane)
                     done += cnt
             # admission
             arrived = int(np.searchsorted(arrivals, now, side="right"))
             if free and head < arrived:
-                budget = self.mem_budget - sum(inflight_bytes.values())
-                end = min(arrived, head + self.max_batch)
-                c = np.cumsum(cost[head:end])
-                fit = int(np.searchsorted(c, budget, side="right"))
-                m = np.cumsum(lens[head:end])
-                fit = min(fit, int(np.searchsorted(m, self.max_msg_bytes, side="right")))
-                if fit == 0 and not busy:
-                    fit = 1  # always make progress
-                if fit > 0:
-                    lane = free.popleft()
-                    idx = np.arange(head, head + fit)
-                    tl = time.perf_counter()
-                    self._launch(lane, reqs, idx)
-                    launch_s.append(time.perf_counter() - tl)
-                    sizes.append(fit)
-                    inflight_bytes[id(lane)] = int(c[fit - 1])
-                    busy.append(lane)
-                    head += fit
-                    continue
+                fit = self._admit(reqs, head, min(arrived, head + self.max_batch))
+                if fit == 0:
+                    raise ValueError(f"request {head}'s message does not fit the staging buffer")
+                lane = free.popleft()
+                idx = np.arange(head, head + fit)
+                tl = time.perf_counter()
+                self._launch(lane, reqs, idx)
+                launch_s.append(time.perf_counter() - tl)
+                sizes.append(fit)
+                overlapped += 1 if busy else 0
+                busy.append(lane)
+                head += fit
+                continue
             if not busy and head >= arrived and head < n:
                 # idle until the next arrival
                 wait = arrivals[head] - (time.perf_counter() - t0)
@@ -272,6 +303,9 @@ class Server:
         res.batches = len(sizes)
         res.mean_batch = float(np.mean(sizes)) if sizes else 0.0
         res.host_launch_s = float(np.sum(launch_s))
+        res.overlapped = overlapped
+        res.group_cap = self.group_cap
+        res.reserved_bytes = self.reserved_bytes
         return res
 
 
@@ -323,8 +357,9 @@ class NativeServer:
                                      P(arr), P(sig_out), P(sig_out_off), P(verdict), P(done))
         if rc:
             raise dl.DilError(rc, self.lib.dil_server_last_error(self.h).decode(errors="replace"))
-        b, hs = ctypes.c_uint64(), ctypes.c_double()
-        self.lib.dil_server_stats(self.h, ctypes.byref(b), ctypes.byref(hs))
+        b, hs, ov, cap, rb = ctypes.c_uint64(), ctypes.c_double(), ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_size_t()
+        self.lib.dil_server_stats(self.h, ctypes.byref(b), ctypes.byref(hs), ctypes.byref(ov), ctypes.byref(cap),
+                                  ctypes.byref(rb))
         res = Results(verdict=verdict, t_done=done.astype(np.float64) * 1e-9)
         for r in np.nonzero(reqs.op == SIGN)[0]:
             o = int(sig_out_off[r])
@@ -334,6 +369,9 @@ class NativeServer:
         res.batches = int(b.value)
         res.mean_batch = n / max(int(b.value), 1)
         res.host_launch_s = hs.value
+        res.overlapped = int(ov.value)
+        res.group_cap = int(cap.value)
+        res.reserved_bytes = int(rb.value)
         return res
 
 
@@ -341,6 +379,8 @@ def latency_summary(res: Results, reqs: Requests) -> dict:
     lat = res.latency * 1e3
     out = {"requests": int(len(reqs)), "wall_s": res.wall, "ops_per_s": len(reqs) / res.wall,
            "batches": res.batches, "mean_batch": res.mean_batch, "host_launch_s": res.host_launch_s,
+           "batches_overlapped": getattr(res, "overlapped", None), "group_cap": getattr(res, "group_cap", None),
+           "reserved_bytes": getattr(res, "reserved_bytes", None),
            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
            "mean_ms": float(lat.mean()), "max_ms": float(lat.max())}
     for op, name in ((SIGN, "sign"), (VERIFY, "verify")):

@@ -1,6 +1,7 @@
 """Serving loop: mixed-level Sign/Verify requests through the continuous-batching
-loop give exactly the oracle's outputs, and each result is the same alone and in
-the mix (deterministic signing: tolerance 0 bytes)."""
+loop give exactly the oracle's outputs, every result is the same alone and in the
+mix (deterministic signing: tolerance 0 bytes), a memory budget below one batch
+makes requests wait for later batches instead of failing, and batches overlap."""
 import numpy as np
 import pytest
 
@@ -40,10 +41,14 @@ def setup():
 def test_serving_matches_oracle(setup, engine):
     dl, sv, ctx, keysets, host, reqs, flipped = setup
     cls = sv.Server if engine == "python" else sv.NativeServer
-    server = cls(keysets, n_streams=3, max_batch=64, mem_budget=4 << 20, max_msg_bytes=1 << 20)
+    server = cls(keysets, n_streams=3, max_batch=64, mem_budget=2 << 30, max_msg_bytes=1 << 20)
     res = server.serve(reqs)
     server.close()
     assert np.isfinite(res.t_done).all()
+    _check_against_oracle(sv, host, reqs, flipped, res)
+
+
+def _check_against_oracle(sv, host, reqs, flipped, res):
     for lv in (2, 3, 5):
         pk, sk = host[lv]
         s = np.nonzero((reqs.level == lv) & (reqs.op == sv.SIGN))[0]
@@ -70,10 +75,9 @@ def test_serving_matches_oracle(setup, engine):
 def test_same_alone_and_in_mix(setup, engine):
     dl, sv, ctx, keysets, host, reqs, flipped = setup
     cls = sv.Server if engine == "python" else sv.NativeServer
-    server = cls(keysets, n_streams=4, max_batch=128, mem_budget=64 << 20, max_msg_bytes=1 << 20)
+    server = cls(keysets, n_streams=4, max_batch=128, mem_budget=2 << 30, max_msg_bytes=1 << 20)
     mixed = server.serve(reqs)
-    rng = np.random.default_rng(3)
-    for r in rng.choice(len(reqs), size=24, replace=False):
+    for r in range(len(reqs)):
         one = sv.Requests(np.zeros(1), reqs.op[r:r + 1], reqs.level[r:r + 1], reqs.key[r:r + 1],
                           reqs.msg[reqs.msg_off[r]:reqs.msg_off[r + 1]].copy(),
                           np.array([0, reqs.msg_off[r + 1] - reqs.msg_off[r]], np.int64))
@@ -95,7 +99,7 @@ def test_out_of_range_key_rejected_before_any_work(setup, engine):
     reads key rows without bounds checks), and the engine then still serves a valid trace."""
     dl, sv, ctx, keysets, host, reqs, flipped = setup
     cls = sv.Server if engine == "python" else sv.NativeServer
-    server = cls(keysets, n_streams=2, max_batch=64, mem_budget=4 << 20, max_msg_bytes=1 << 20)
+    server = cls(keysets, n_streams=2, max_batch=64, mem_budget=2 << 30, max_msg_bytes=1 << 20)
     bad = sv.Requests(**vars(reqs))
     bad.key = reqs.key.copy()
     bad.key[int(np.argmax(reqs.level == 5))] = keysets[5].n_keys
@@ -108,3 +112,46 @@ def test_out_of_range_key_rejected_before_any_work(setup, engine):
     assert np.isfinite(res.t_done).all()
     v = reqs.op == sv.VERIFY
     assert np.array_equal(res.verdict[v] == 0, flipped[v])
+
+
+@pytest.mark.parametrize("engine", ["python", "native"])
+def test_budget_below_one_batch_queues_requests(setup, engine):
+    """With a memory budget that holds the workspaces of only a few requests per (level, op),
+    every request still completes with the oracle's output: the ones that do not fit a batch
+    wait for a later one.  The budget is a quarter of what the engine reserves for full
+    batches, so the per-group cap falls below the batch size."""
+    dl, sv, ctx, keysets, host, reqs, flipped = setup
+    cls = sv.Server if engine == "python" else sv.NativeServer
+    full = cls(keysets, n_streams=3, max_batch=64, mem_budget=64 << 30, max_msg_bytes=1 << 20)
+    first = full.serve(reqs)
+    full.close()
+    assert first.group_cap == 64
+    big = first.reserved_bytes
+    server = cls(keysets, n_streams=3, max_batch=64, mem_budget=big // 4, max_msg_bytes=1 << 20)
+    res = server.serve(reqs)
+    server.close()
+    assert 1 <= res.group_cap < 64 and res.reserved_bytes <= big // 4
+    assert np.isfinite(res.t_done).all()
+    grp = 2 * np.searchsorted([2, 3, 5], reqs.level) + reqs.op
+    largest = int(np.bincount(grp).max())
+    assert res.batches >= -(-largest // res.group_cap)
+    _check_against_oracle(sv, host, reqs, flipped, res)
+    # a budget below one request per group is refused when the engine is created
+    with pytest.raises(dl.DilError):
+        cls(keysets, n_streams=3, max_batch=64, mem_budget=1 << 20, max_msg_bytes=1 << 20)
+
+
+@pytest.mark.parametrize("engine", ["python", "native"])
+def test_batches_overlap(setup, engine):
+    """Every request at t = 0 with small batches: a lane is launched while another batch is
+    still in flight (the engine counts such launches)."""
+    dl, sv, ctx, keysets, host, reqs, flipped = setup
+    cls = sv.Server if engine == "python" else sv.NativeServer
+    server = cls(keysets, n_streams=4, max_batch=16, mem_budget=2 << 30, max_msg_bytes=1 << 20)
+    burst = sv.Requests(**vars(reqs))
+    burst.t_arrival = np.zeros(len(reqs))
+    res = server.serve(burst)
+    server.close()
+    assert res.batches >= len(reqs) // 16
+    assert res.overlapped > 0
+    _check_against_oracle(sv, host, reqs, flipped, res)

@@ -120,3 +120,41 @@ def test_binding_rejects_undersized_buffers():
         _require([(sig[:n - 1], 2420 * n, 1, "sig")])
     with pytest.raises(ValueError):
         _require([(torch.zeros(n, dtype=torch.int64), 4 * n, 4, "key_idx")])
+
+
+def test_error_word_reporting(tmp_path):
+    """The decision of which device-detected condition a context reports (csrc/errwords.h), on
+    the host with g++: every condition that is set is named, the code is the most severe one
+    (dropped Sign tasks, then an out-of-table key index, then a decreasing msg_off)."""
+    import subprocess
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "errwords_check.cpp"
+    src.write_text(r'''
+#include <stdio.h>
+#include "errwords.h"
+int main() {
+  char t[256];
+  for (int m = 0; m < 8; m++) {
+    int code = dil::report_error_words(m & 1, (m >> 1) & 1, (m >> 2) & 1, t, sizeof t);
+    printf("%d|%d|%s\n", m, code, t);
+  }
+  char small[8];
+  dil::report_error_words(1, 1, 1, small, sizeof small);   // truncated, still terminated
+  printf("8|%d|%s\n", (int)strlen(small), small);
+  return 0;
+}''')
+    exe = tmp_path / "errwords_check"
+    subprocess.run(["g++", "-std=c++17", "-include", "string.h", "-I",
+                    os.path.join(root, "paper_2211_12265_amd", "csrc"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.splitlines()
+    rows = {int(r.split("|")[0]): r.split("|", 2)[1:] for r in out}
+    from paper_2211_12265_amd import dilithium as dl
+    for m in range(8):
+        dropped, msg, key = m & 1, (m >> 1) & 1, (m >> 2) & 1
+        code, text = int(rows[m][0]), rows[m][1]
+        want = dl.DIL_EHIP if dropped else dl.DIL_EINVAL if key else dl.DIL_EMSG if msg else dl.DIL_OK
+        assert code == want, (m, code)
+        assert ("iteration limit" in text) == bool(dropped)
+        assert ("msg_off" in text) == bool(msg)
+        assert ("key table" in text) == bool(key)
+    assert int(rows[8][0]) == 7
