@@ -187,6 +187,23 @@ int dil_sign_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx,
 int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx, const uint8_t *msg,
                       const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count, void *stream);
 
+/* dil_verify_keyset for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and outputs, with the call's workspace in a fixed device
+ * array of 16 MiB that the library holds on every GPU it runs on until the
+ * process ends, instead of the context's pool; the call allocates nothing and
+ * enqueues only kernels on `stream` (no memset, no side stream).  count is
+ * limited by that array: 11,847 tasks at level 2, 11,335 at level 3, 9,320
+ * at level 5; a larger count is DIL_EINVAL with the limit in
+ * dil_last_error().  The context supplies the device and the error words
+ * (dil_ctx_check reports a key index outside the table, as for
+ * dil_verify_keyset).  All calls on one
+ * GPU share the array: calls that overlap on one GPU (other streams, other
+ * threads, other contexts) race on it and must be ordered by the caller. */
+int dil_verify_keyset_noalloc(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx, const uint8_t *msg,
+                              const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count,
+                              void *stream);
+
 /* ---- Continuous-batching serving engine ----
  * Host-side dispatcher over key tables (one per level; NULL for a level not
  * served).  It keeps up to n_streams batches in flight, each on its own HIP

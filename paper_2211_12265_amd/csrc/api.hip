@@ -15,6 +15,12 @@
 
 using namespace dil;
 
+// Scratch of the entry point that allocates nothing (dil_verify_keyset_noalloc);
+// host code reaches it only through the per-device address from
+// hipGetSymbolAddress (scratch_address below).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)16 << 20;
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+
 struct dil_ctx {
   int device = 0;
   int mode = DIL_MODE_STAGED;
@@ -50,6 +56,7 @@ struct dil_ctx {
   hipStream_t side[2] = {nullptr, nullptr};
   hipEvent_t fork_ev = nullptr, join_ev[2] = {nullptr, nullptr};
   hipEvent_t done_ev = nullptr;                // recorded after each call's last enqueue
+  uint8_t *scratch = nullptr;                  // this device's no-alloc scratch array (device address)
   int pool_alloc = 0;                          // workspace from the stream-ordered allocator
 };
 
@@ -584,6 +591,34 @@ int keyset_build(dil_ctx *ctx, dil_keyset *ks, const uint8_t *pk, const uint8_t 
   return DIL_OK;
 }
 
+// ---- scratch for the entry point that allocates nothing ----
+// Device memory of dil_verify_keyset_noalloc: a file-scope device array (each
+// GPU the library runs on holds its own copy until the process ends).  Host
+// code never uses the array's name as an address: its device address is taken
+// once per device with hipGetSymbolAddress (at context creation) and kept in
+// scratch_ptr.  Every call on a GPU shares that GPU's copy; calls that
+// overlap on one GPU race on it.
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the scratch array on `device` (the current device).
+int scratch_address(dil_ctx *ctx, int device, uint8_t **out) {
+  if (device < 0 || device >= MAX_DEVICES) return fail(ctx, DIL_EINVAL, "device index above the scratch table");
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_ptr[device]) {
+    void *p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(ctx, DIL_EHIP, "scratch address (hipGetSymbolAddress)", e);
+    }
+    scratch_ptr[device] = p;
+  }
+  *out = (uint8_t *)scratch_ptr[device];
+  return DIL_OK;
+}
+
 template <class F>
 int by_level(int level, F f) {
   switch (level) {
@@ -626,6 +661,10 @@ int dil_ctx_create(dil_ctx **out, int device, size_t workspace_bytes) {
   }
   int pools = 0;
   c->pool_alloc = hipDeviceGetAttribute(&pools, hipDeviceAttributeMemoryPoolsSupported, device) == hipSuccess && pools;
+  if (scratch_address(c, device, &c->scratch)) {
+    dil_ctx_destroy(c);
+    return DIL_EHIP;
+  }
   if (workspace_bytes && (ws_reserve_bytes(c, workspace_bytes, nullptr) || hipStreamSynchronize(nullptr) != hipSuccess)) {
     dil_ctx_destroy(c);
     return DIL_ENOMEM;
@@ -814,6 +853,60 @@ int dil_sign_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx,
     if (ctx->mode == DIL_MODE_PERSISTENT)
       return sign_persistent<LV>(ctx, ks->sk, key_idx, msg, msg_off, sig, count, (hipStream_t)stream, ks);
     return sign_staged<LV>(ctx, ks->sk, key_idx, msg, msg_off, sig, count, (hipStream_t)stream, ks);
+  });
+}
+
+}  // extern "C"
+
+namespace {
+// dil_verify_keyset's kernels over the scratch array: the same launches on
+// `st` as a key-table Verify (no side streams, no graph), with the workspace
+// laid out in the scratch array instead of the context's pool.
+template <int LV>
+int verify_keyset_noalloc_impl(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx, const uint8_t *msg,
+                               const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count,
+                               hipStream_t st) {
+  const size_t need = ws_layout<LV>(nullptr, count, WS_VERIFY, true, 0, 1, nullptr, nullptr, nullptr);
+  if (need > NOALLOC_SCRATCH_BYTES) {
+    char t[160];
+    snprintf(t, sizeof t, "count %u needs %zu bytes of scratch, above the %zu-byte maximum", count, need,
+             NOALLOC_SCRATCH_BYTES);
+    return fail(ctx, DIL_EINVAL, t);
+  }
+  Ws ws;
+  uint32_t *kid = nullptr;
+  ws_layout<LV>(ctx->scratch, count, WS_VERIFY, true, 0, 1, &ws, nullptr, &kid);
+  ws.kmap = nullptr;
+  ws.t1h = nullptr;
+  ws.tr = nullptr;
+  const uint32_t *kidx = use_keyset(ws, ks, key_idx, kid);
+  zero_words_k<<<1, 64, 0, st>>>(ws.counters, 16, nullptr, 0);
+  check_keys(ctx, ks, key_idx, kid, count, st);
+  vf_hash_k<LV><<<blocks_for(2 * (uint64_t)count, 64), 64, 0, st>>>(ks->pk, kidx, msg, msg_off, ws, count,
+                                                                    ctx->dev_stats + ERR_WORD_MSG);
+  vf_prep_k<LV><<<blocks_for(count, 64), 64, 0, st>>>(sig, ws, count);
+  vf_main_k<LV><<<count, 64, 0, st>>>(ks->pk, kidx, sig, ws, count);
+  vf_final_k<LV><<<blocks_for(2 * (uint64_t)count, 256), 256, 0, st>>>(sig, ws, verdict, count);
+  LAUNCHCHK(ctx);
+  return DIL_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int dil_verify_keyset_noalloc(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx, const uint8_t *msg,
+                              const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count,
+                              void *stream) {
+  if (!ctx || !ks) return fail(ctx, DIL_EINVAL, "bad context or key table");
+  if (!ks->pk) return fail(ctx, DIL_EINVAL, "key table holds no public keys");
+  if (ks->device != ctx->device) return fail(ctx, DIL_EINVAL, "key table and context on different devices");
+  if (count == 0) return DIL_OK;
+  if (!msg || !msg_off || !sig || !verdict) return fail(ctx, DIL_EINVAL, "null buffer");
+  if (!key_idx && count > ks->nkeys) return fail(ctx, DIL_EINVAL, "more tasks than keys without key_idx");
+  hipSetDevice(ctx->device);
+  return by_level(ks->level, [&](auto lv) {
+    return verify_keyset_noalloc_impl<decltype(lv)::value>(ctx, ks, key_idx, msg, msg_off, sig, verdict, count,
+                                                           (hipStream_t)stream);
   });
 }
 

@@ -27,7 +27,7 @@ EXPORTS = [
     "dil_expand_a_batch", "dil_keyset_create", "dil_keyset_destroy", "dil_keyset_info", "dil_sign_keyset",
     "dil_verify_keyset", "dil_persist_capacity", "dil_ctx_reserve", "dil_server_create", "dil_server_destroy",
     "dil_server_last_error", "dil_server_stats", "dil_server_run", "dil_ctx_reserve_call", "dil_workspace_bytes",
-    "dil_alu_probe",
+    "dil_alu_probe", "dil_verify_keyset_noalloc",
 ]
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -82,6 +82,7 @@ def load() -> ctypes.CDLL:
         "dil_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32),
                                             ctypes.POINTER(ctypes.c_size_t)]),
+        "dil_verify_keyset_noalloc": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P, ctypes.c_uint32, _P]),
         "dil_alu_probe": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint32, _P, _P,
                                          ctypes.POINTER(ctypes.c_uint64)]),
         "dil_ctx_reserve_call": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32]),
@@ -286,9 +287,12 @@ class KeySet:
         ctx._check(self.lib.dil_sign_keyset(ctx.h, self.h, _ptr(key_idx), _ptr(msg) or _ptr(msg_off), _ptr(msg_off),
                                             _ptr(sig), n, _stream(stream)))
 
-    def verify(self, ctx: Context, key_idx, msg, msg_off, sig, verdict, stream=None):
+    def verify(self, ctx: Context, key_idx, msg, msg_off, sig, verdict, stream=None, noalloc: bool = False):
+        """noalloc: the entry point that allocates nothing (its workspace in the library's fixed
+        per-GPU scratch array; calls overlapping on one GPU race on it)."""
         n = msg_off.shape[0] - 1
         _require([(msg_off, 8 * (n + 1), 8, "msg_off"), (sig, sizes(self.level)[2] * n, 1, "sig"),
                   (verdict, 4 * n, 4, "verdict"), (key_idx, 4 * n, 4, "key_idx")])
-        ctx._check(self.lib.dil_verify_keyset(ctx.h, self.h, _ptr(key_idx), _ptr(msg) or _ptr(msg_off),
-                                              _ptr(msg_off), _ptr(sig), _ptr(verdict), n, _stream(stream)))
+        fn = self.lib.dil_verify_keyset_noalloc if noalloc else self.lib.dil_verify_keyset
+        ctx._check(fn(ctx.h, self.h, _ptr(key_idx), _ptr(msg) or _ptr(msg_off), _ptr(msg_off), _ptr(sig),
+                      _ptr(verdict), n, _stream(stream)))

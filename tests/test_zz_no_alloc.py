@@ -1,0 +1,68 @@
+"""The Verify entry point that allocates nothing (dil_verify_keyset_noalloc, workspace in the
+library's fixed per-GPU scratch array) against dil_verify_keyset on the same inputs: identical
+verdicts on two calls in a row, the second with fewer tasks, with valid, flipped and
+wrong-key signatures mixed in, at each level; a count beyond the scratch array's limit is
+refused; the verdicts also equal the oracle's."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_12265_amd import workload
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+LIMIT = {2: 11847, 3: 11335, 5: 9320}
+
+
+def _batch(level, nkeys, n, seed):
+    """Host inputs: keys from the oracle, n messages, oracle signatures, then one bit flipped in
+    every fifth signature and every seventh task pointed at another key."""
+    seeds = workload.keygen_seeds(nkeys, seed=seed)
+    pk, sk = oracle.keygen_batch(level, seeds)
+    kidx = (np.arange(n) * 7 % nkeys).astype(np.uint32)
+    lens = workload.uniform_lengths(n, 0, 300, seed=seed)
+    msg, off = workload.messages(lens, seed=seed)
+    sig, _ = oracle.sign_batch(level, sk, msg, off, key_idx=kidx)
+    sig = sig.copy()
+    for t in range(0, n, 5):
+        b = (t * 131) % (sig.shape[1] * 8)
+        sig[t, b // 8] ^= np.uint8(1 << (b % 8))
+    vkey = kidx.copy()
+    vkey[3::7] = (vkey[3::7] + 1) % nkeys
+    expect = oracle.verify_batch(level, pk, msg, off, sig, key_idx=vkey)
+    return pk, sk, vkey, msg, off, sig, expect
+
+
+@pytest.mark.parametrize("level", [2, 3, 5])
+def test_noalloc_verify_matches_verify_keyset(level):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    ctx = dl.Context(0)
+    pk, sk, vkey, msg, off, sig, expect = _batch(level, 16, 300, seed=400 + level)
+    assert 0 < int(expect.sum()) < len(expect)
+    ks = dl.KeySet(ctx, level, pk=torch.from_numpy(pk).cuda())
+    for n in (300, 97):     # two calls in a row, the second smaller
+        gk = torch.from_numpy(vkey[:n]).cuda()
+        gm = torch.from_numpy(msg[:int(off[n])]).cuda()
+        go = torch.from_numpy(off[:n + 1].astype(np.int64)).cuda()
+        gs = torch.from_numpy(sig[:n]).cuda()
+        v_ref = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+        v_na = torch.full((n,), -7, dtype=torch.int32, device="cuda")
+        ks.verify(ctx, gk, gm, go, gs, v_ref)
+        ks.verify(ctx, gk, gm, go, gs, v_na, noalloc=True)
+        torch.cuda.synchronize()
+        ctx.check()
+        assert np.array_equal(v_na.cpu().numpy(), v_ref.cpu().numpy())
+        assert np.array_equal(v_na.cpu().numpy(), expect[:n])
+    # a count above the scratch array's limit is refused before anything is launched
+    n = LIMIT[level] + 1
+    big_off = torch.zeros(n + 1, dtype=torch.int64, device="cuda")
+    with pytest.raises(dl.DilError) as err:
+        ks.verify(ctx, torch.zeros(n, dtype=torch.int32, device="cuda"), torch.zeros(1, dtype=torch.uint8,
+                  device="cuda"), big_off, torch.zeros((n, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda"),
+                  torch.zeros(n, dtype=torch.int32, device="cuda"), noalloc=True)
+    assert err.value.code == dl.DIL_EINVAL and "scratch" in str(err.value)
+    ks.close()
+    ctx.close()
