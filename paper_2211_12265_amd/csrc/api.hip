@@ -147,12 +147,12 @@ size_t ws_layout(uint8_t *base, size_t cap, int form, bool keyset, size_t grid, 
   uint32_t *kid = (uint32_t *)take(keyset, cap * 4);  // checked key indices of key-table calls
   PScr p{};
   if (form == WS_SIGN_PERSIST) {
-    const size_t G = persist_slots<LV>(waves);
-    const size_t w1s = ((size_t)K * P<LV>::W1B + 255) & ~(size_t)255;
-    p.y = (int32_t *)take(true, grid * G * L * 1024);
-    p.w = (int32_t *)take(true, grid * G * K * 1024);
-    p.w1 = take(true, grid * G * w1s);
-    p.stage = take(waves > 1, grid * G * sig_stride<LV>());
+    // the regions the loop kernels index with the same ScratchIdx (batch_sched.h)
+    const ScratchIdx si{(size_t)persist_slots<LV>(waves), (size_t)L, (size_t)K, w1_stride<LV>(), sig_stride<LV>()};
+    p.y = (int32_t *)take(true, si.y_size(grid) * sizeof(int32_t));
+    p.w = (int32_t *)take(true, si.w_size(grid) * sizeof(int32_t));
+    p.w1 = take(true, si.w1_size(grid));
+    p.stage = take(waves > 1, si.stage_size(grid));
   }
   if (ws) *ws = w;
   if (sc) *sc = p;

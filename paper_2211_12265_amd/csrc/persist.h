@@ -16,6 +16,7 @@
 //   lanes) -> ctilde and SampleInBall (two lanes per slot) -> checks per slot.
 #pragma once
 #include "kernels.h"
+#include "batch_sched.h"
 
 namespace dil {
 
@@ -34,8 +35,12 @@ struct PScr {
 };
 
 template <int LV>
-__device__ __forceinline__ size_t w1_stride() {
+__host__ __device__ __forceinline__ size_t w1_stride() {
   return ((size_t)Lv<LV>::K * P<LV>::W1B + 255) & ~(size_t)255;
+}
+template <int LV>
+__host__ __device__ __forceinline__ size_t sig_stride() {
+  return ((size_t)P<LV>::SIG + 255) & ~(size_t)255;
 }
 
 // Optional per-phase cycle accounting (compile with -DDIL_PHASE_TIMERS): lane 0
@@ -74,15 +79,13 @@ __device__ __forceinline__ void wave_sync_global() {
 // `count`; it is cleared before every launch.)
 __device__ __forceinline__ int claim_tasks(uint32_t *queue, uint32_t count, uint32_t want, int nh, uint32_t *h_task,
                                            uint32_t *h_next, int &queue_empty) {
-  uint32_t base = atomicAdd(queue, want);
-  uint32_t got = base >= count ? 0u : min(want, count - base);
-  if (got < want) queue_empty = 1;
-  for (uint32_t q = 0; q < got; q++) {
-    h_task[nh] = base + q;
-    h_next[nh] = 0;
-    nh++;
-  }
-  return nh;
+  return sched_claim(atomicAdd(queue, want), count, want, nh, h_task, h_next, queue_empty);
+}
+
+// the scratch offsets of a workgroup shape with G slots per batch
+template <int LV>
+__device__ __forceinline__ ScratchIdx scratch_idx(int G) {
+  return ScratchIdx{(size_t)G, (size_t)Lv<LV>::L, (size_t)Lv<LV>::K, w1_stride<LV>(), sig_stride<LV>()};
 }
 
 // Per-workgroup statistics, flushed to the launch's stats words at exit.  It
@@ -121,6 +124,10 @@ struct PersistLds {
   uint8_t s_h[PCfg<LV>::G];
   int nheld, nslots, queue_empty;
   Tally tally;
+  static_assert(PCfg<LV>::G <= 64, "slot indices are held in bytes and searched with one ballot");
+  static_assert(C_ROW >= N && RATE256 / 4 == 34, "challenge rows hold N coefficients, block rows one SHAKE256 block");
+  static_assert(sizeof(CheckLds<LV>::sigbuf) >= (size_t)(P<LV>::SIG + 3) / 4 * 4,
+                "the staged signature is copied out in whole words");
 };
 
 // ws.counters[0] is the work queue (next task to claim).  stats (32-bit words,
@@ -134,9 +141,10 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
   __shared__ PersistLds<LV> lds;
   const int lane = threadIdx.x, t = lane & 15;
   const size_t wg = blockIdx.x;
-  int32_t *yb = sc.y + wg * G * L * N;
-  int32_t *wb = sc.w + wg * G * K * N;
-  uint8_t *w1b = sc.w1 + wg * G * w1_stride<LV>();
+  const ScratchIdx si = scratch_idx<LV>(G);
+  int32_t *yb = sc.y + si.y(wg, 0, 0);
+  int32_t *wb = sc.w + si.w(wg, 0, 0);
+  uint8_t *w1b = sc.w1 + si.w1(wg, 0);
   const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
   if (lane == 0) {
     lds.tally.clear();
@@ -155,23 +163,7 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
       if (!lds.queue_empty && nh < (int)hmax) nh = claim_tasks(ws.counters, count, hmax - nh, nh, lds.h_task,
                                                                lds.h_next, lds.queue_empty);
       lds.nheld = nh;
-      const int ns = nh ? G : 0;
-      // slot s evaluates held task s mod nh at that task's nonce index
-      // h_next + s / nh (kept as running counters: no division per slot)
-      int h = 0;
-      uint32_t j = 0;
-      for (int s = 0; s < ns; s++) {
-        lds.s_h[s] = (uint8_t)h;
-        lds.s_att[s] = lds.h_next[h] + j;
-        if (++h == nh) {
-          h = 0;
-          j++;
-        }
-      }
-      for (h = 0; h < nh; h++) {
-        lds.h_next[h] += (uint32_t)(ns / nh + (h < ns % nh ? 1 : 0));
-        lds.h_win[h] = 0xFFFFFFFFu;
-      }
+      const int ns = sched_assign(nh, G, lds.h_next, lds.h_win, lds.s_h, lds.s_att);
       lds.nslots = ns;
       lds.tally.evaluated += (uint64_t)ns;
     }
@@ -183,15 +175,15 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
     if (lane < ns * L) {
       int s = lane / L, i = lane % L;
       uint32_t task = lds.h_task[lds.s_h[s]];
-      dev_expand_mask<LV>(ws.rhop + (size_t)task * 64, lds.s_att[s] * (uint32_t)L, i, yb + ((size_t)s * L + i) * N);
+      dev_expand_mask<LV>(ws.rhop + (size_t)task * 64, lds.s_att[s] * (uint32_t)L, i, yb + si.y(0, s, i));
     }
     wave_sync_global();
     PHASE_MARK(1);
     // ---- w = INTT(A NTT(y)) per slot ----
     for (int s = 0; s < ns; s++) {
       uint32_t task = lds.h_task[lds.s_h[s]];
-      dev_compute_w<LV>(yb + (size_t)s * L * N, ws.A + kix(ws, task) * K * L * N, wb + (size_t)s * K * N,
-                        w1b + s * w1_stride<LV>(), lds.u.wp.hat, lds.u.wp.tr + (lane >> 4) * NTT_LDS_GROUP,
+      dev_compute_w<LV>(yb + si.y(0, s, 0), ws.A + kix(ws, task) * K * L * N, wb + si.w(0, s, 0),
+                        w1b + si.w1(0, s), lds.u.wp.hat, lds.u.wp.tr + (lane >> 4) * NTT_LDS_GROUP,
                         lds.u.wp.w1buf, ftw, itw, lane);
       wave_sync();
     }
@@ -201,7 +193,7 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
     if ((lane >> 1) < ns) {
       const int s = lane >> 1;
       uint32_t task = lds.h_task[lds.s_h[s]];
-      dev_challenge_pair<LV>(ws.muw1 + (size_t)task * muw1_stride<LV>(), w1b + s * w1_stride<LV>(), lane & 1,
+      dev_challenge_pair<LV>(ws.muw1 + (size_t)task * muw1_stride<LV>(), w1b + si.w1(0, s), lane & 1,
                              lds.ct[s], lds.c[s], lds.bb[s]);
     }
     wave_sync();
@@ -209,9 +201,9 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
     // ---- checks, in slot order; the first pass of a task is its signature ----
     for (int s = 0; s < ns; s++) {
       int h = lds.s_h[s];
-      if (lds.h_win[h] != 0xFFFFFFFFu) continue;
+      if (lds.h_win[h] != SCHED_NONE) continue;
       uint32_t task = lds.h_task[h];
-      bool ok = dev_check<LV>(lds.c[s], lds.ct[s], yb + (size_t)s * L * N, wb + (size_t)s * K * N,
+      bool ok = dev_check<LV>(lds.c[s], lds.ct[s], yb + si.y(0, s, 0), wb + si.w(0, s, 0),
                               ws.s1h + kix(ws, task) * L * N, ws.s2h + kix(ws, task) * K * N,
                               ws.t0h + kix(ws, task) * K * N, lds.u.ck, ftw, itw, lane);
       if (ok) {
@@ -222,23 +214,9 @@ __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig,
     }
     PHASE_MARK(4);
     // ---- retire signed tasks ----
-    if (lane == 0) {
-      int nh = lds.nheld, o = 0;
-      for (int h = 0; h < nh; h++) {
-        if (lds.h_win[h] != 0xFFFFFFFFu) {
-          lds.tally.sequential += (uint64_t)lds.h_win[h] + 1;
-          continue;
-        }
-        if (lds.h_next[h] >= (uint32_t)PCfg<LV>::MAX_ATTEMPTS) {
-          lds.tally.dropped++;
-          continue;
-        }
-        lds.h_task[o] = lds.h_task[h];
-        lds.h_next[o] = lds.h_next[h];
-        o++;
-      }
-      lds.nheld = o;
-    }
+    if (lane == 0)
+      lds.nheld = sched_retire(lds.nheld, lds.h_task, lds.h_next, lds.h_win, (uint32_t)PCfg<LV>::MAX_ATTEMPTS,
+                               lds.tally.sequential, lds.tally.dropped);
     wave_sync();
   }
   if (lane == 0) lds.tally.flush(stats);
@@ -285,7 +263,15 @@ struct PersistWLds {
   uint8_t s_h[PCfgW<LV, NW>::G];
   int nheld, nslots, queue_empty;
   Tally tally;
+  static_assert(PCfgW<LV, NW>::G <= 64, "the winner search takes one slot per lane of one ballot");
+  static_assert(C_ROW >= N && RATE256 / 4 == 34, "challenge rows hold N coefficients, block rows one SHAKE256 block");
+  static_assert(sizeof(CheckLds<LV>::sigbuf) >= (size_t)(P<LV>::SIG + 3) / 4 * 4,
+                "the staged signature is copied in whole words");
 };
+// two workgroups of the four-wavefront shape per CU (160 KiB of LDS)
+static_assert(2 * sizeof(PersistWLds<2, 4>) <= 160 * 1024 && 2 * sizeof(PersistWLds<3, 4>) <= 160 * 1024 &&
+                  2 * sizeof(PersistWLds<5, 4>) <= 160 * 1024,
+              "four-wavefront loop workgroups must fit two per CU");
 
 // Copy an NB-byte signature from a 4-byte aligned global row to a destination
 // row at any byte alignment with one wavefront: each lane requests all the
@@ -319,11 +305,6 @@ __device__ __forceinline__ void copy_sig_row(const uint32_t *src, uint8_t *dst, 
   }
 }
 
-template <int LV>
-__host__ __device__ __forceinline__ size_t sig_stride() {
-  return ((size_t)P<LV>::SIG + 255) & ~(size_t)255;
-}
-
 template <int LV, int NW>
 __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t *sig, uint32_t count,
                                                      uint32_t hmax, uint32_t *stats) {
@@ -332,10 +313,11 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
   __shared__ PersistWLds<LV, NW> lds;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, t = lane & 15;
   const size_t wg = blockIdx.x;
-  int32_t *yb = sc.y + wg * G * L * N;
-  int32_t *wb = sc.w + wg * G * K * N;
-  uint8_t *w1b = sc.w1 + wg * G * w1_stride<LV>();
-  uint8_t *stg = sc.stage + wg * G * sig_stride<LV>();
+  const ScratchIdx si = scratch_idx<LV>(G);
+  int32_t *yb = sc.y + si.y(wg, 0, 0);
+  int32_t *wb = sc.w + si.w(wg, 0, 0);
+  uint8_t *w1b = sc.w1 + si.w1(wg, 0);
+  uint8_t *stg = sc.stage + si.stage(wg, 0);
   const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
   if (tid == 0) {
     lds.tally.clear();
@@ -353,23 +335,7 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
       if (!lds.queue_empty && nh < (int)hmax) nh = claim_tasks(ws.counters, count, hmax - nh, nh, lds.h_task,
                                                                lds.h_next, lds.queue_empty);
       lds.nheld = nh;
-      const int ns = nh ? G : 0;
-      // slot s evaluates held task s mod nh at that task's nonce index
-      // h_next + s / nh (kept as running counters: no division per slot)
-      int h = 0;
-      uint32_t j = 0;
-      for (int s = 0; s < ns; s++) {
-        lds.s_h[s] = (uint8_t)h;
-        lds.s_att[s] = lds.h_next[h] + j;
-        if (++h == nh) {
-          h = 0;
-          j++;
-        }
-      }
-      for (h = 0; h < nh; h++) {
-        lds.h_next[h] += (uint32_t)(ns / nh + (h < ns % nh ? 1 : 0));
-        lds.h_win[h] = 0xFFFFFFFFu;
-      }
+      const int ns = sched_assign(nh, G, lds.h_next, lds.h_win, lds.s_h, lds.s_att);
       lds.nslots = ns;
       lds.tally.evaluated += (uint64_t)ns;
     }
@@ -381,7 +347,7 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
     if (tid < ns * L) {
       int s = tid / L, i = tid % L;
       uint32_t task = lds.h_task[lds.s_h[s]];
-      dev_expand_mask<LV>(ws.rhop + (size_t)task * 64, lds.s_att[s] * (uint32_t)L, i, yb + ((size_t)s * L + i) * N);
+      dev_expand_mask<LV>(ws.rhop + (size_t)task * 64, lds.s_att[s] * (uint32_t)L, i, yb + si.y(0, s, i));
     }
     __threadfence_block();
     __syncthreads();
@@ -389,8 +355,8 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
     // w per slot, wave w takes slots w, w + 4, ...
     for (int s = wave; s < ns; s += W) {
       uint32_t task = lds.h_task[lds.s_h[s]];
-      dev_compute_w<LV>(yb + (size_t)s * L * N, ws.A + kix(ws, task) * K * L * N, wb + (size_t)s * K * N,
-                        w1b + s * w1_stride<LV>(), lds.u[wave].wp.hat,
+      dev_compute_w<LV>(yb + si.y(0, s, 0), ws.A + kix(ws, task) * K * L * N, wb + si.w(0, s, 0),
+                        w1b + si.w1(0, s), lds.u[wave].wp.hat,
                         lds.u[wave].wp.tr + (lane >> 4) * NTT_LDS_GROUP, lds.u[wave].wp.w1buf, ftw, itw, lane);
       wave_sync();
     }
@@ -403,7 +369,7 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
       const int s = (wave - (int)((wg + batch) % W) + W) % W * 32 + (lane >> 1);
       if (s < ns) {
         uint32_t task = lds.h_task[lds.s_h[s]];
-        dev_challenge_pair<LV>(ws.muw1 + (size_t)task * muw1_stride<LV>(), w1b + s * w1_stride<LV>(), lane & 1,
+        dev_challenge_pair<LV>(ws.muw1 + (size_t)task * muw1_stride<LV>(), w1b + si.w1(0, s), lane & 1,
                                lds.ct[s], lds.c[s], lds.bb[s]);
       }
     }
@@ -415,12 +381,12 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
       // another wave may lower h_win meanwhile: read it once, wave-uniformly
       if (__builtin_amdgcn_readfirstlane(lds.h_win[h]) < lds.s_att[s]) continue;
       uint32_t task = lds.h_task[h];
-      bool ok = dev_check<LV>(lds.c[s], lds.ct[s], yb + (size_t)s * L * N, wb + (size_t)s * K * N,
+      bool ok = dev_check<LV>(lds.c[s], lds.ct[s], yb + si.y(0, s, 0), wb + si.w(0, s, 0),
                               ws.s1h + kix(ws, task) * L * N, ws.s2h + kix(ws, task) * K * N,
                               ws.t0h + kix(ws, task) * K * N, lds.u[wave].ck, ftw, itw, lane);
       if (ok) {
         const uint32_t *sb = lds.u[wave].ck.sigbuf;
-        uint32_t *dst = (uint32_t *)(stg + s * sig_stride<LV>());
+        uint32_t *dst = (uint32_t *)(stg + si.stage(0, s));
         for (int w = lane; w < (P<LV>::SIG + 3) / 4; w += 64) dst[w] = sb[w];
         if (lane == 0) atomicMin(&lds.h_win[h], lds.s_att[s]);
       }
@@ -432,33 +398,19 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
     // copy each signed task's smallest passing candidate out; wave w handles held tasks w, w + 4, ...
     for (int h = wave; h < lds.nheld; h += W) {
       const uint32_t win = lds.h_win[h];
-      if (win == 0xFFFFFFFFu) continue;
+      if (win == SCHED_NONE) continue;
       // the slot that evaluated the winning nonce, found by one ballot over
       // all slots (G <= 64); h_win only ever takes a slot's s_att, so it exists
       const uint64_t hit = __ballot(lane < ns && lds.s_h[lane] == h && lds.s_att[lane] == win);
       if (hit == 0) continue;
       const int s = (int)__builtin_ctzll(hit);
-      copy_sig_row<P<LV>::SIG>((const uint32_t *)(stg + s * sig_stride<LV>()),
+      copy_sig_row<P<LV>::SIG>((const uint32_t *)(stg + si.stage(0, s)),
                                sig + (size_t)lds.h_task[h] * P<LV>::SIG, lane);
     }
     __syncthreads();
-    if (tid == 0) {
-      int nh = lds.nheld, o = 0;
-      for (int h = 0; h < nh; h++) {
-        if (lds.h_win[h] != 0xFFFFFFFFu) {
-          lds.tally.sequential += (uint64_t)lds.h_win[h] + 1;
-          continue;
-        }
-        if (lds.h_next[h] >= (uint32_t)PCfg<LV>::MAX_ATTEMPTS) {
-          lds.tally.dropped++;
-          continue;
-        }
-        lds.h_task[o] = lds.h_task[h];
-        lds.h_next[o] = lds.h_next[h];
-        o++;
-      }
-      lds.nheld = o;
-    }
+    if (tid == 0)
+      lds.nheld = sched_retire(lds.nheld, lds.h_task, lds.h_next, lds.h_win, (uint32_t)PCfg<LV>::MAX_ATTEMPTS,
+                               lds.tally.sequential, lds.tally.dropped);
     __syncthreads();
   }
   if (tid == 0) lds.tally.flush(stats);
