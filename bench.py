@@ -224,6 +224,99 @@ def micro_run(steps: int, warmup: int) -> dict:
     return res
 
 
+T0_FORMS = [(3, "basic: unpack kernel, t0 through HBM, NTT kernel (unpadded transpose)"),
+            (2, "fused kernel, same memory access pattern (t0 through HBM inside the kernel)"),
+            (1, "unpacking merged into the NTT's registers (unpadded transpose)"),
+            (0, "merged + padded transpose (the Sign setup's code path)")]
+
+
+def t0_ablation_run(steps: int, warmup: int, levels=(2, 5), counts=(10000, 100000)) -> dict:
+    """The NTT(t0) stage of signing (dil_t0_ntt_batch) in the four forms of the optimisation
+    ablation, on keys generated on the GPU; median HIP-event time per call.  Then the padding
+    step inside the Sign loop kernel: the level-2 benchmark batch signed with the recorded
+    schedule on padded ("persist.pad" 1) and unpadded (0) transposes, interleaved."""
+    import torch
+    from paper_2211_12265_amd import autotune
+    from paper_2211_12265_amd import dilithium as dl
+    from paper_2211_12265_amd import workload
+    ctx = dl.Context(0)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        ts = []
+        for _ in range(steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ts.append(a.elapsed_time(b))
+        return float(np.median(ts))
+
+    rows = []
+    for level in levels:
+        k = PER_LEVEL[level][0]
+        pkl, skl, _ = dl.sizes(level)
+        for n in counts:
+            pk = torch.zeros((n, pkl), dtype=torch.uint8, device="cuda")
+            sk = torch.zeros((n, skl), dtype=torch.uint8, device="cuda")
+            ctx.keygen(level, torch.from_numpy(workload.keygen_seeds(n, seed=level)).cuda(), pk, sk)
+            out = torch.empty((n, k, 256), dtype=torch.int32, device="cuda")
+            ref = None
+            nbytes = n * k * (416 + 1024)   # packed t0 read, NTT(t0) written
+            for variant, name in T0_FORMS:
+                ctx.set_param("t0.variant", variant)
+                ms = timed(lambda: ctx.t0_ntt(level, sk, out))
+                torch.cuda.synchronize()
+                if ref is None:
+                    ref = out.clone()
+                rows.append({"level": level, "keys": n, "variant": variant, "form": name, "ms": ms,
+                             "polys_per_s": n * k / ms * 1e3, "GB_per_s": nbytes / ms / 1e6,
+                             "alu_frac": n * k * XFORM_OPS / (ms / 1e3) / PEAK_INT32_OPS,
+                             "same_words_as_basic": bool(torch.equal(out, ref))})
+            ctx.set_param("t0.variant", 0)
+            del pk, sk, out, ref
+    ctx.close()
+    # padding inside the Sign loop kernel
+    level, n = 2, 10000
+    pkl, skl, sgl = dl.sizes(level)
+    sched = autotune.cached_schedule(level, n, "fixed32")
+    loop = {}
+    c0 = dl.Context(0)
+    sk = torch.zeros((n, skl), dtype=torch.uint8, device="cuda")
+    c0.keygen(level, torch.from_numpy(workload.keygen_seeds(n, seed=0)).cuda(),
+              torch.zeros((n, pkl), dtype=torch.uint8, device="cuda"), sk)
+    msg, off = workload.messages(workload.fixed_lengths(n, 32), seed=0)
+    gm, go = torch.from_numpy(msg).cuda(), torch.from_numpy(off.astype(np.int64)).cuda()
+    ctxs, sigs = {}, {}
+    for pad in (1, 0):
+        c = dl.Context(0, mode=dl.MODE_PERSISTENT)
+        autotune.apply_schedule(c, sched)
+        c.set_param("persist.pad", pad)
+        c.set_param("timing", 1)
+        ctxs[pad] = c
+        sigs[pad] = torch.zeros((n, sgl), dtype=torch.uint8, device="cuda")
+    times = {1: [], 0: []}
+    for _ in range(3):
+        for pad in (1, 0):
+            c = ctxs[pad]
+            for _ in range(warmup):
+                c.sign(level, sk, gm, go, sigs[pad])
+            c.set_param("timing", 1)
+            for _ in range(steps):
+                c.sign(level, sk, gm, go, sigs[pad])
+            torch.cuda.synchronize()
+            times[pad] += c.sign_timing(steps)[1]
+    for pad in (1, 0):
+        loop["padded" if pad else "unpadded"] = {"loop_ms_median": float(np.median(times[pad])),
+                                                 "schedule": sched}
+        ctxs[pad].close()
+    loop["same_signatures"] = bool(torch.equal(sigs[0], sigs[1]))
+    c0.close()
+    return {"t0_ntt": rows, "sign_loop_kernel_L2_10k": loop}
+
+
 def serving_run(n_requests: int, seconds: float, streams: int, max_batch: int, short: bool = False) -> dict:
     """Serving loop on 1024 resident key pairs (512 / 307 / 205 at levels 2 / 3 / 5): first a
     saturation probe (all requests at t = 0), then a Poisson stream at half that rate.  `short`
@@ -533,6 +626,9 @@ def main():
     ap.add_argument("--micro", action="store_true",
                     help="only time the primitive workloads (2^20-polynomial NTT product in each ablation form, "
                          "ExpandA) and print them as one JSON line")
+    ap.add_argument("--t0-ablation", action="store_true",
+                    help="only run the NTT(t0)-stage ablation (four forms) and the padded / unpadded Sign "
+                         "loop kernel, and print one JSON line")
     ap.add_argument("--peak", action="store_true",
                     help="only run the vector-ALU issue-rate probe behind the roofline peak and print one JSON line")
     ap.add_argument("--no-staged", action="store_true", help="skip the staged-form timing in the default line")
@@ -558,6 +654,10 @@ def main():
 
     if args.micro:
         print(json.dumps({"micro": micro_run(args.steps, args.warmup)}), flush=True)
+        return
+    if args.t0_ablation:
+        print(json.dumps({"t0_ablation": t0_ablation_run(steps=max(args.steps, 5), warmup=max(args.warmup, 2))}),
+              flush=True)
         return
     if args.peak:
         print(json.dumps({"peak": peak_run()}), flush=True)

@@ -97,7 +97,21 @@ int dil_ctx_set_mode(dil_ctx *ctx, int mode);
  *                   round trip per butterfly level, 3 unfused (forward NTT,
  *                   pointwise product and inverse NTT as three launches
  *                   through HBM, c used as the intermediate); other values
- *                   are DIL_EINVAL. */
+ *                   are DIL_EINVAL;
+ *   "t0.variant"    form of dil_t0_ntt_batch, for the optimisation ablation
+ *                   of the NTT(t0) stage of signing (Sec. 5, speedup
+ *                   breakdown); every form returns the same words: 0
+ *                   (default) unpacking merged into the NTT's registers,
+ *                   padded LDS transpose (the Sign setup's code path), 1 the
+ *                   same unpadded, 2 one fused kernel that stores t0 in HBM
+ *                   and reads it back, 3 an unpacking kernel then an NTT
+ *                   kernel through HBM; other values are DIL_EINVAL;
+ *   "persist.pad"   1 (default) or 0: 0 runs the four-wavefront Sign loop
+ *                   kernel with every NTT / INTT transpose on the unpadded
+ *                   (bank-conflicted) LDS layout, the padding step of the same
+ *                   ablation inside the loop; the signatures are identical; a
+ *                   persistent Sign call with 0 and another "persist.waves"
+ *                   value fails with DIL_EINVAL. */
 int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value);
 /* Operations, for the workspace queries below. */
 #define DIL_OP_KEYGEN 0
@@ -271,6 +285,16 @@ int dil_ntt_mul_batch(dil_ctx *ctx, const int32_t *a, const int32_t *b, int32_t 
  * 23-bit candidate, kept if < q) -> out[count][256] canonical int32.
  * count must be below 2^32 (DIL_EINVAL otherwise). */
 int dil_expand_a_batch(dil_ctx *ctx, const uint8_t *seeds34, int32_t *out, uint64_t count, void *stream);
+
+/* Stage of signing: t0-hat = NTT(t0) with t0 unpacked from each secret key
+ * (Alg. 2 precomputes NTT(t0); Sec. 5 uses this stage for its speedup
+ * breakdown), in the form "t0.variant" selects.  sk[count][SK] (rows of
+ * dil_sizes' sk bytes, 8-byte aligned) -> t0_hat[count][k][256] int32
+ * reduced to [0, q), natural NTT slot order (16-byte aligned; forms 2 and 3
+ * also use it as their intermediate).  Device buffers owned by the caller;
+ * asynchronous on `stream`; DIL_EINVAL for a bad level, null or misaligned
+ * buffers; count = 0 is a no-op. */
+int dil_t0_ntt_batch(dil_ctx *ctx, int level, const uint8_t *sk, int32_t *t0_hat, uint32_t count, void *stream);
 
 /* Diagnostic: the vector-ALU issue-rate probe behind the benchmark's peak.
  * Launches `groups` workgroups of 256 lanes; every lane executes iters x 128

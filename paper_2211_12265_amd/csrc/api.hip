@@ -10,6 +10,7 @@
 #include "../../include/dil.h"
 #include "errwords.h"
 #include "ntt_ablation.h"
+#include "t0_ablation.h"
 #include "persist.h"
 #include "probe.h"
 
@@ -36,6 +37,8 @@ struct dil_ctx {
   int persist_waves = 4;                       // wavefronts per persistent workgroup: 1, 2 or 4
   int timing = 0;                              // record HIP events around the persistent Sign phases
   int ntt_variant = 0;                         // form of dil_ntt_mul_batch (0 = production kernel)
+  int t0_variant = 0;                          // form of dil_t0_ntt_batch (0 = production code path)
+  int persist_pad = 1;                         // 0: four-wavefront loop kernel on unpadded LDS transposes
   static constexpr int RING = 64;
   hipEvent_t ev[RING][3] = {};                 // per timed call: before setup, before loop, after loop
   int ev_count = 0;                            // timed calls recorded since timing was (re)enabled
@@ -440,6 +443,8 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
                     const uint64_t *msg_off, uint8_t *sig, uint32_t count, hipStream_t st,
                     const dil_keyset *ks = nullptr, const uint8_t *rnd = nullptr) {
   const int waves = ctx->persist_waves;
+  if (!ctx->persist_pad && waves != 4)
+    return fail(ctx, DIL_EINVAL, "persist.pad = 0 exists for the four-wavefront loop kernel only");
   uint64_t grid = 1, hmax = 1;
   int rc = persist_schedule<LV>(ctx, count, &grid, &hmax);
   if (rc) return rc;
@@ -467,7 +472,9 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   if (evs) HIPCHK(ctx, hipEventRecord(evs[1], st));
   // The loop kernel is one launch: it is launched directly, also when graphs
   // are enabled (as a graph node it measured 2-4% slower).
-  if (waves == 4)
+  if (waves == 4 && !ctx->persist_pad)
+    sg_persistw_k<LV, 4, false><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+  else if (waves == 4)
     sg_persistw_k<LV, 4><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
   else if (waves == 2)
     sg_persistw_k<LV, 2><<<(unsigned)grid, 128, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
@@ -736,6 +743,12 @@ int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value) {
   } else if (!strcmp(name, "ntt.variant")) {
     if (value < 0 || value > 3) return fail(ctx, DIL_EINVAL, "ntt.variant must be 0..3");
     ctx->ntt_variant = (int)value;
+  } else if (!strcmp(name, "t0.variant")) {
+    if (value < 0 || value > 3) return fail(ctx, DIL_EINVAL, "t0.variant must be 0..3");
+    ctx->t0_variant = (int)value;
+  } else if (!strcmp(name, "persist.pad")) {
+    if (value != 0 && value != 1) return fail(ctx, DIL_EINVAL, "persist.pad must be 0 or 1");
+    ctx->persist_pad = (int)value;
   }
   else return fail(ctx, DIL_EINVAL, "unknown parameter");
   return DIL_OK;
@@ -1103,6 +1116,31 @@ int dil_alu_probe(dil_ctx *ctx, int kind, uint32_t iters, uint32_t groups, uint3
   LAUNCHCHK(ctx);
   if (instructions) *instructions = (uint64_t)groups * PROBE_WG * iters * PROBE_INSTR_PER_ITER;
   return DIL_OK;
+}
+
+int dil_t0_ntt_batch(dil_ctx *ctx, int level, const uint8_t *sk, int32_t *t0_hat, uint32_t count, void *stream) {
+  if (!ctx) return DIL_EINVAL;
+  if (level != 2 && level != 3 && level != 5) return fail(ctx, DIL_EINVAL, "level must be 2, 3 or 5");
+  if (count == 0) return DIL_OK;
+  if (!sk || !t0_hat) return fail(ctx, DIL_EINVAL, "null buffer");
+  if (((uintptr_t)sk & 7) || ((uintptr_t)t0_hat & 15))
+    return fail(ctx, DIL_EINVAL, "sk must be 8-byte and t0_hat 16-byte aligned");
+  hipSetDevice(ctx->device);
+  const hipStream_t st = (hipStream_t)stream;
+  const int variant = ctx->t0_variant;
+  return by_level(level, [&](auto lv) {
+    constexpr int LV = decltype(lv)::value;
+    switch (variant) {
+      case 0: t0_ntt_reg_k<LV, true><<<count, 64, 0, st>>>(sk, t0_hat, count); break;
+      case 1: t0_ntt_reg_k<LV, false><<<count, 64, 0, st>>>(sk, t0_hat, count); break;
+      case 2: t0_ntt_gmem_k<LV, true><<<count, 64, 0, st>>>(sk, t0_hat, count); break;
+      default:
+        t0_unpack_k<LV><<<blocks_for((uint64_t)count * Lv<LV>::K * 32, 256), 256, 0, st>>>(sk, t0_hat, count);
+        t0_ntt_gmem_k<LV, false><<<count, 64, 0, st>>>(sk, t0_hat, count);
+    }
+    LAUNCHCHK(ctx);
+    return DIL_OK;
+  });
 }
 
 int dil_expand_a_batch(dil_ctx *ctx, const uint8_t *seeds34, int32_t *out, uint64_t count, void *stream) {

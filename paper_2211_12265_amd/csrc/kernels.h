@@ -260,11 +260,12 @@ struct PolyLds {
 };
 
 // consecutive-layout values of the lane (16t .. 16t+15) from its strided values
+template <bool PAD = true>
 __device__ __forceinline__ void to_consecutive(const int32_t x[16], uint32_t v[16], int32_t *tr, int t) {
   int32_t y[16];
 #pragma unroll
   for (int r = 0; r < 16; r++) y[r] = x[r];
-  transpose_s2c(y, tr, t);
+  transpose_s2c<PAD>(y, tr, t);
 #pragma unroll
   for (int r = 0; r < 16; r++) v[r] = (uint32_t)y[r];
 }
@@ -471,7 +472,7 @@ __device__ __forceinline__ void dev_expand_mask(const uint8_t *rhop, uint32_t ka
 // w_out, HighBits(w) packed into w1_out (4-byte aligned, K * W1B bytes).
 // hat: L * HAT_POLY words of LDS; tr: this group's transpose region; w1buf: LDS
 // staging; ftw / itw: forward / inverse twiddles.
-template <int LV, class TW>
+template <int LV, bool PAD = true, class TW>
 __device__ __forceinline__ void dev_compute_w(const int32_t *y, const int32_t *A, int32_t *w_out, uint8_t *w1_out,
                                               int32_t *hat, int32_t *tr, uint32_t *w1buf, const TW &ftw,
                                               const TW &itw, int lane) {
@@ -481,7 +482,7 @@ __device__ __forceinline__ void dev_compute_w(const int32_t *y, const int32_t *A
   for (int j = g; j < L; j += 4) {
     int32_t x[16];
     load_strided(x, y + j * N, t);
-    ntt16(x, ftw, tr, t);
+    ntt16<TW, PAD>(x, ftw, tr, t);
 #pragma unroll
     for (int r = 0; r < 16; r++) hat[hat_idx(j, t, r)] = x[r];
   }
@@ -500,7 +501,7 @@ __device__ __forceinline__ void dev_compute_w(const int32_t *y, const int32_t *A
     int32_t x[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) x[r] = mont_reduce(acc[r]);
-    intt16(x, itw, tr, t);
+    intt16<TW, PAD>(x, itw, tr, t);
     int32_t w1[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) {
@@ -509,7 +510,7 @@ __device__ __forceinline__ void dev_compute_w(const int32_t *y, const int32_t *A
     }
     store_strided(x, w_out + i * N, t);
     uint32_t v[16];
-    to_consecutive(w1, v, tr, t);
+    to_consecutive<PAD>(w1, v, tr, t);
     pack16_to_lds<PP::W1BITS>(v, (uint8_t *)w1buf + i * PP::W1B, t);
   }
   wave_sync();
@@ -585,7 +586,7 @@ struct CheckLds {
 // candidate passes all four checks; the packed signature (ctilde, z, h) is
 // then in lds.sigbuf.  Polynomials whose norm already fails stop the
 // evaluation early.
-template <int LV, class TW>
+template <int LV, bool PAD = true, class TW>
 __device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctilde, const int32_t *y, const int32_t *w,
                                           const int32_t *s1h, const int32_t *s2h, const int32_t *t0h,
                                           CheckLds<LV> &lds, const TW &ftw, const TW &itw, int lane) {
@@ -599,7 +600,7 @@ __device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctild
   int32_t ch[16];
 #pragma unroll
   for (int r = 0; r < 16; r++) ch[r] = c[t + 16 * r];
-  ntt16(ch, ftw, tr, t);
+  ntt16<TW, PAD>(ch, ftw, tr, t);
   bool bad = false;
   // z = y + c s1
   for (int j = g; j < L; j += 4) {
@@ -607,7 +608,7 @@ __device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctild
     load_slots(s1, s1h + j * N, t);
 #pragma unroll
     for (int r = 0; r < 16; r++) x[r] = mont_mul(ch[r], s1[r]);
-    intt16(x, itw, tr, t);
+    intt16<TW, PAD>(x, itw, tr, t);
     int32_t yv[16];
     load_strided(yv, y + j * N, t);
     int32_t zv[16];
@@ -619,7 +620,7 @@ __device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctild
       zv[r] = G1 - z;
     }
     uint32_t v[16];
-    to_consecutive(zv, v, tr, t);
+    to_consecutive<PAD>(zv, v, tr, t);
     pack16_to_lds<PP::ZBITS>(v, sb + PP::OFF_Z + j * PP::ZB, t);
   }
   if (wave_any(bad)) return false;
@@ -629,7 +630,7 @@ __device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctild
     load_slots(s2, s2h + i * N, t);
 #pragma unroll
     for (int r = 0; r < 16; r++) x[r] = mont_mul(ch[r], s2[r]);
-    intt16(x, itw, tr, t);
+    intt16<TW, PAD>(x, itw, tr, t);
     int32_t wv[16];
     load_strided(wv, w + i * N, t);
     int32_t r1v[16];
@@ -644,7 +645,7 @@ __device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctild
     load_slots(u, t0h + i * N, t);
 #pragma unroll
     for (int r = 0; r < 16; r++) u[r] = mont_mul(ch[r], u[r]);
-    intt16(u, itw, tr, t);
+    intt16<TW, PAD>(u, itw, tr, t);
     int cnt = 0;
 #pragma unroll
     for (int r = 0; r < 16; r++) {

@@ -305,7 +305,9 @@ __device__ __forceinline__ void copy_sig_row(const uint32_t *src, uint8_t *dst, 
   }
 }
 
-template <int LV, int NW>
+// PAD = false runs every NTT / INTT transpose of the kernel on the unpadded
+// (bank-conflicted) LDS layout: the padding step of the optimisation ablation.
+template <int LV, int NW, bool PAD = true>
 __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t *sig, uint32_t count,
                                                      uint32_t hmax, uint32_t *stats) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfgW<LV, NW>::G, W = NW;
@@ -355,7 +357,7 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
     // w per slot, wave w takes slots w, w + 4, ...
     for (int s = wave; s < ns; s += W) {
       uint32_t task = lds.h_task[lds.s_h[s]];
-      dev_compute_w<LV>(yb + si.y(0, s, 0), ws.A + kix(ws, task) * K * L * N, wb + si.w(0, s, 0),
+      dev_compute_w<LV, PAD>(yb + si.y(0, s, 0), ws.A + kix(ws, task) * K * L * N, wb + si.w(0, s, 0),
                         w1b + si.w1(0, s), lds.u[wave].wp.hat,
                         lds.u[wave].wp.tr + (lane >> 4) * NTT_LDS_GROUP, lds.u[wave].wp.w1buf, ftw, itw, lane);
       wave_sync();
@@ -381,7 +383,7 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
       // another wave may lower h_win meanwhile: read it once, wave-uniformly
       if (__builtin_amdgcn_readfirstlane(lds.h_win[h]) < lds.s_att[s]) continue;
       uint32_t task = lds.h_task[h];
-      bool ok = dev_check<LV>(lds.c[s], lds.ct[s], yb + si.y(0, s, 0), wb + si.w(0, s, 0),
+      bool ok = dev_check<LV, PAD>(lds.c[s], lds.ct[s], yb + si.y(0, s, 0), wb + si.w(0, s, 0),
                               ws.s1h + kix(ws, task) * L * N, ws.s2h + kix(ws, task) * K * N,
                               ws.t0h + kix(ws, task) * K * N, lds.u[wave].ck, ftw, itw, lane);
       if (ok) {

@@ -27,7 +27,7 @@ EXPORTS = [
     "dil_expand_a_batch", "dil_keyset_create", "dil_keyset_destroy", "dil_keyset_info", "dil_sign_keyset",
     "dil_verify_keyset", "dil_persist_capacity", "dil_ctx_reserve", "dil_server_create", "dil_server_destroy",
     "dil_server_last_error", "dil_server_stats", "dil_server_run", "dil_ctx_reserve_call", "dil_workspace_bytes",
-    "dil_alu_probe", "dil_verify_keyset_noalloc",
+    "dil_alu_probe", "dil_verify_keyset_noalloc", "dil_t0_ntt_batch",
 ]
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -66,6 +66,7 @@ def load() -> ctypes.CDLL:
         "dil_sign_timing": (ctypes.c_int, [_P, _P, _P, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]),
         "dil_ntt_mul_batch": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_uint64, _P]),
         "dil_expand_a_batch": (ctypes.c_int, [_P, _P, _P, ctypes.c_uint64, _P]),
+        "dil_t0_ntt_batch": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_uint32, _P]),
         "dil_keyset_create": (ctypes.c_int, [_P, ctypes.c_int, _P, _P, ctypes.c_uint32, ctypes.POINTER(_P), _P]),
         "dil_keyset_destroy": (ctypes.c_int, [_P]),
         "dil_keyset_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_uint32),
@@ -245,6 +246,13 @@ class Context:
         n = ctypes.c_uint64()
         self._check(self.lib.dil_alu_probe(self.h, kind, iters, groups, _ptr(out), _stream(stream), ctypes.byref(n)))
         return n.value
+
+    def t0_ntt(self, level: int, sk, t0_hat, stream=None):
+        """t0_hat[n][k][256] = NTT(t0) of each secret key row, reduced to [0, q) (form per "t0.variant")."""
+        n = sk.shape[0]
+        k = {2: 4, 3: 6, 5: 8}[level]
+        _require([(sk, sizes(level)[1] * n, 1, "sk"), (t0_hat, 4 * k * 256 * n, 4, "t0_hat")])
+        self._check(self.lib.dil_t0_ntt_batch(self.h, level, _ptr(sk), _ptr(t0_hat), n, _stream(stream)))
 
     def expand_a(self, seeds34, out, stream=None):
         self._check(self.lib.dil_expand_a_batch(self.h, _ptr(seeds34), _ptr(out), seeds34.shape[0],

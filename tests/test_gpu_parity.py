@@ -514,3 +514,101 @@ def test_message_lengths_at_block_boundaries(sctx, level):
     sctx.verify(level, pk, dev(msg), dev(off.astype(np.int64)), sig, v, key_idx=dev(kidx))
     torch.cuda.synchronize()
     assert v.cpu().numpy().tolist() == [1] * n
+
+
+def _t0_hat_oracle(level, sk_rows):
+    """NTT(t0) of each key from the oracle: t0 unpacked from the sk bytes (13-bit fields,
+    coefficient 2^12 - v), then the oracle's NTT, reduced to [0, q)."""
+    p = {2: (4, 4, 96), 3: (6, 5, 128), 5: (8, 7, 96)}[level]
+    k, l, eb = p
+    off = 96 + (l + k) * eb
+    out = np.zeros((sk_rows.shape[0], k, 256), dtype=np.int32)
+    for t in range(sk_rows.shape[0]):
+        for i in range(k):
+            v = oracle.bitunpack(sk_rows[t, off + 416 * i: off + 416 * (i + 1)].tobytes(), 256, 13)
+            t0 = (4096 - v.astype(np.int64)) % oracle.Q
+            out[t, i] = oracle.ntt(t0.astype(np.int32))
+    return out
+
+
+@pytest.mark.parametrize("level", [2, 3, 5])
+@pytest.mark.parametrize("count", [1, 37])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_t0_ntt_forms_match_oracle(ctx, level, count, variant):
+    """The NTT(t0) stage in each form of the optimisation ablation (dil_t0_ntt_batch,
+    "t0.variant") returns the oracle's NTT of the unpacked t0."""
+    seeds = workload.keygen_seeds(count, seed=80 + level)
+    _, sk = oracle.keygen_batch(level, seeds)
+    k = {2: 4, 3: 6, 5: 8}[level]
+    out = torch.full((count, k, 256), -1, dtype=torch.int32, device="cuda")
+    ctx.set_param("t0.variant", variant)
+    try:
+        ctx.t0_ntt(level, dev(sk), out)
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_param("t0.variant", 0)
+    assert np.array_equal(out.cpu().numpy(), _t0_hat_oracle(level, sk))
+
+
+@pytest.mark.parametrize("level", [2, 5])
+def test_t0_ntt_forms_agree_at_batch_size(ctx, level):
+    """10,000 keys (the benchmark's Sign batch): all four forms return the same words, and
+    sampled keys equal the oracle's."""
+    n = 10000
+    seeds = workload.keygen_seeds(n, seed=level)
+    from paper_2211_12265_amd import dilithium as dl
+    pkl, skl, _ = dl.sizes(level)
+    gpk = torch.zeros((n, pkl), dtype=torch.uint8, device="cuda")
+    gsk = torch.zeros((n, skl), dtype=torch.uint8, device="cuda")
+    ctx.keygen(level, dev(seeds), gpk, gsk)
+    k = {2: 4, 3: 6, 5: 8}[level]
+    outs = []
+    for variant in range(4):
+        out = torch.full((n, k, 256), -1, dtype=torch.int32, device="cuda")
+        ctx.set_param("t0.variant", variant)
+        try:
+            ctx.t0_ntt(level, gsk, out)
+            torch.cuda.synchronize()
+        finally:
+            ctx.set_param("t0.variant", 0)
+        outs.append(out)
+    for v in range(1, 4):
+        assert torch.equal(outs[v], outs[0]), v
+    idx = np.unique(np.concatenate([np.random.default_rng(5).choice(n, 24, replace=False), [0, n - 1]]))
+    assert np.array_equal(outs[0].cpu().numpy()[idx], _t0_hat_oracle(level, gsk.cpu().numpy()[idx]))
+
+
+def test_t0_ntt_rejects_bad_arguments(ctx):
+    from paper_2211_12265_amd import dilithium as dl
+    with pytest.raises(dl.DilError):
+        ctx.set_param("t0.variant", 4)
+    sk = torch.zeros((2, 2528), dtype=torch.uint8, device="cuda")
+    out = torch.zeros((2, 4, 256), dtype=torch.int32, device="cuda")
+    with pytest.raises(dl.DilError):
+        ctx._check(ctx.lib.dil_t0_ntt_batch(ctx.h, 4, sk.data_ptr(), out.data_ptr(), 2, None))
+    with pytest.raises(ValueError):
+        ctx.t0_ntt(2, sk, out[:1])
+
+
+@pytest.mark.parametrize("level", [2, 3, 5])
+def test_unpadded_loop_kernel_matches_oracle(level):
+    """The four-wavefront Sign loop kernel on the unpadded LDS transposes ("persist.pad" = 0,
+    the padding step of the ablation) signs exactly as the oracle; other shapes reject it."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    c = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    c.set_param("persist.waves", 4)
+    c.set_param("persist.pad", 0)
+    n = 300
+    seeds = workload.keygen_seeds(n, seed=90 + level)
+    pk, sk = _keygen(c, level, seeds)
+    msg, off = workload.messages(workload.uniform_lengths(n, 0, 500, seed=91), seed=91)
+    sig = _sign(c, level, sk, msg, off)
+    osig, iters = oracle.sign_batch(level, sk.cpu().numpy(), msg, off)
+    assert np.array_equal(sig.cpu().numpy(), osig)
+    assert c.sign_stats()[1] == int(iters.sum())
+    c.set_param("persist.waves", 2)
+    with pytest.raises(dl.DilError):
+        _sign(c, level, sk, msg, off)
+    c.close()
