@@ -446,10 +446,16 @@ def peak_run(iters: int = 4000, reps: int = 5) -> dict:
     return {"cus": cus, "iters": iters, "rows": rows, "peak_used": PEAK_INT32_OPS}
 
 
-def ablation_run(level: int, n: int, msg_dist: str, steps: int = 10) -> list:
+# schedules of the one- and two-wavefront shapes the autotuner picked at level 2 (10,000 tasks), used
+# by the ablation when it is told not to tune (the four-wavefront shape uses the recorded schedule)
+FIXED_SHAPE_SCHEDULES = {1: {"waves": 1, "hmax": 3, "grid": 2048}, 2: {"waves": 2, "hmax": 6, "grid": 1024}}
+
+
+def ablation_run(level: int, n: int, msg_dist: str, steps: int = 10, tune: bool = True) -> list:
     """Runtime-selectable execution forms timed on the same keys and messages: the staged form
-    (one launch per stage, host-driven loop), the persistent kernel in both workgroup shapes with
-    its autotuned schedule, and hipGraph replay on / off."""
+    (one launch per stage, host-driven loop), the persistent kernel in each workgroup shape with
+    its autotuned schedule (tune=False: fixed schedules, so that a profiler sees a short, fixed
+    launch sequence), and hipGraph replay on / off."""
     import torch
     from paper_2211_12265_amd import autotune
     from paper_2211_12265_amd import dilithium as dl
@@ -472,9 +478,12 @@ def ablation_run(level: int, n: int, msg_dist: str, steps: int = 10) -> list:
         sig = torch.zeros((n, sgl), dtype=torch.uint8, device="cuda")
         ver = torch.zeros(n, dtype=torch.int32, device="cuda")
         sched = None
-        if waves:
+        if waves and tune:
             t = autotune.tune_sign(ctx, level, lambda: ctx.sign(level, sk, gm, go, sig), count=n, waves=(waves,))
             sched = {k: t["best"][k] for k in ("waves", "hmax", "grid")}
+        elif waves:
+            sched = FIXED_SHAPE_SCHEDULES.get(waves) or autotune.cached_schedule(level, n, msg_dist)
+            autotune.apply_schedule(ctx, sched)
         ctx.set_param("graph", graph)
         for _ in range(2):
             ctx.sign(level, sk, gm, go, sig)
@@ -663,7 +672,8 @@ def main():
         print(json.dumps({"peak": peak_run()}), flush=True)
         return
     if args.ablation:
-        print(json.dumps({"ablation": ablation_run(args.level, args.count, args.msg_dist),
+        print(json.dumps({"ablation": ablation_run(args.level, args.count, args.msg_dist, steps=max(args.steps, 3),
+                                                   tune=not args.no_tune),
                           "level": args.level, "batch": args.count, "msg_dist": args.msg_dist}), flush=True)
         return
     if args.serving_only:
