@@ -536,9 +536,10 @@ def e2e_run(level: int, n: int, msg_dist: str, stream_counts, chunks_per_stream=
     h_msg.numpy()[:] = msg
     h_sig, h_ver = pinned((n, sgl)), pinned((n,), torch.int32)
     rows = []
-    for S, cps in [(S, c) for S in stream_counts for c in chunks_per_stream]:
+    for S, cps, thr in [(S, c, t) for S in stream_counts for c in chunks_per_stream for t in (False, True)
+                        if S > 1 or not t]:
         chunk = -(-n // (S * cps))
-        p = HostPipeline(level, n_streams=S, chunk=chunk)
+        p = HostPipeline(level, n_streams=S, chunk=chunk, host_threads=thr)
         p.sign(h_sk, h_msg, off, h_sig)
         p.verify(h_pk, h_msg, off, h_sig, h_ver)
         torch.cuda.synchronize()
@@ -554,7 +555,8 @@ def e2e_run(level: int, n: int, msg_dist: str, stream_counts, chunks_per_stream=
             ts.append(t1 - t0)
             tv.append(t2 - t1)
         p.check()
-        rows.append({"streams": S, "chunks_per_stream": cps, "chunk": chunk, "sign_per_s": n / float(np.median(ts)),
+        rows.append({"streams": S, "chunks_per_stream": cps, "chunk": chunk, "host_threads": thr,
+                     "sign_per_s": n / float(np.median(ts)),
                      "verify_per_s": n / float(np.median(tv)), "all_verified": bool(int(h_ver.sum()) == n)})
         p.close()
     # a stream of whole batches: B batches of n tasks back to back in one call, batch b on stream
@@ -568,8 +570,8 @@ def e2e_run(level: int, n: int, msg_dist: str, stream_counts, chunks_per_stream=
         h_msg_b.numpy()[b * len(msg):(b + 1) * len(msg)] = msg
     off_b = np.concatenate([off[:-1] + b * int(off[-1]) for b in range(B)] + [[B * int(off[-1])]]).astype(np.int64)
     h_sig_b, h_ver_b = pinned((B * n, sgl)), pinned((B * n,), torch.int32)
-    for S in batch_streams:
-        p = HostPipeline(level, n_streams=S, chunk=n)
+    for S, thr in [(S, t) for S in batch_streams for t in (False, True) if S > 1 or not t]:
+        p = HostPipeline(level, n_streams=S, chunk=n, host_threads=thr)
         p.sign(h_sk_b, h_msg_b, off_b, h_sig_b)
         p.verify(h_pk_b, h_msg_b, off_b, h_sig_b, h_ver_b)
         torch.cuda.synchronize()
@@ -585,7 +587,8 @@ def e2e_run(level: int, n: int, msg_dist: str, stream_counts, chunks_per_stream=
             ts.append(t1 - t0)
             tv.append(t2 - t1)
         p.check()
-        rows.append({"streams": S, "batches": B, "chunk": n, "sign_per_s": B * n / float(np.median(ts)),
+        rows.append({"streams": S, "batches": B, "chunk": n, "host_threads": thr,
+                     "sign_per_s": B * n / float(np.median(ts)),
                      "verify_per_s": B * n / float(np.median(tv)), "all_verified": bool(int(h_ver_b.sum()) == B * n),
                      "same_signatures": bool(np.array_equal(h_sig_b.numpy()[:n], h_sig_b.numpy()[(B - 1) * n:]))})
         p.close()

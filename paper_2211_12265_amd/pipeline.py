@@ -18,6 +18,7 @@ start.
 """
 from __future__ import annotations
 
+import threading
 from typing import List, Optional
 
 import numpy as np
@@ -43,6 +44,11 @@ class HostPipeline:
 
     n_streams: HIP streams (and libdil contexts) used; chunk: tasks per chunk.
     mode: Sign execution form of every context (dl.MODE_*).
+    host_threads: issue each stream's chunks from a host thread of its own (the
+    paper's one host thread per stream, Sec. 4.4), so that the copies and calls
+    of one stream are enqueued without waiting behind another stream's; the
+    C-ABI calls release the interpreter lock, and each thread uses only its
+    stream's context.  False issues every stream from the calling thread.
     Persistent Sign calls of different streams run at the same time, so each
     context gets an equal share of the GPU's resident four-wavefront
     workgroups (and as many held tasks per workgroup as its chunk needs)
@@ -51,11 +57,12 @@ class HostPipeline:
     """
 
     def __init__(self, level: int, n_streams: int = 4, chunk: int = 1250, mode: int = dl.MODE_PERSISTENT,
-                 device: int = 0):
+                 device: int = 0, host_threads: bool = False):
         import torch
         if n_streams < 1 or chunk < 1:
             raise ValueError("n_streams and chunk must be positive")
         self.level, self.S, self.chunk = level, n_streams, chunk
+        self.host_threads = host_threads
         self.pkl, self.skl, self.sgl = dl.sizes(level)
         self.dev = torch.device("cuda", device)
         self.ctx = [dl.Context(device, mode=mode) for _ in range(n_streams)]
@@ -106,18 +113,14 @@ class HostPipeline:
         self._plan, self._plan_key = plan, key
         return plan
 
-    def _run(self, op: str, keys, msg, off, sig, out):
+    def _issue(self, op: str, s: int, chunks, keys, msg, sig, out):
+        """Enqueue chunks on stream s: copies in, the C-ABI call, copy out."""
         import torch
-        plan = self.plan(off)
-        cur = torch.cuda.current_stream(self.dev)
-        for s in self.streams:
-            s.wait_stream(cur)
+        st, ctx = self.streams[s], self.ctx[s]
         kl = self.skl if op == "sign" else self.pkl
-        for i, c in enumerate(plan):
-            s = i % self.S
-            st, ctx = self.streams[s], self.ctx[s]
-            m = c.b - c.a
-            with torch.cuda.stream(st):
+        with torch.cuda.stream(st):
+            for c in chunks:
+                m = c.b - c.a
                 dk = self.d_key[s][:m * kl].view(m, kl)
                 dk.copy_(keys[c.a:c.b], non_blocking=True)
                 dm = self.d_msg[s][:c.o1 - c.o0]
@@ -135,6 +138,35 @@ class HostPipeline:
                     dv = self.d_ver[s][:m]
                     ctx.verify(self.level, dk, dm, do, ds, dv, stream=st)
                     out[c.a:c.b].copy_(dv, non_blocking=True)
+
+    def _run(self, op: str, keys, msg, off, sig, out):
+        import torch
+        plan = self.plan(off)
+        cur = torch.cuda.current_stream(self.dev)
+        for s in self.streams:
+            s.wait_stream(cur)
+        # chunk i goes to stream i mod S
+        groups = [plan[s::self.S] for s in range(self.S)]
+        if self.host_threads and self.S > 1:
+            errors = []
+
+            def work(s):
+                try:
+                    torch.cuda.set_device(self.dev)
+                    self._issue(op, s, groups[s], keys, msg, sig, out)
+                except BaseException as e:  # re-raised on the calling thread
+                    errors.append(e)
+
+            threads = [threading.Thread(target=work, args=(s,)) for s in range(self.S)]
+            for t in threads:
+                t.start()
+            for t in threads:
+                t.join()
+            if errors:
+                raise errors[0]
+        else:
+            for s in range(self.S):
+                self._issue(op, s, groups[s], keys, msg, sig, out)
         for s in self.streams:
             cur.wait_stream(s)
 

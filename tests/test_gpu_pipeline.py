@@ -10,8 +10,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-@pytest.mark.parametrize("level,n_streams,chunk", [(2, 3, 17), (3, 1, 64), (5, 4, 9)])
-def test_host_pipeline_matches_oracle(level, n_streams, chunk):
+@pytest.mark.parametrize("level,n_streams,chunk,threads", [(2, 3, 17, False), (3, 1, 64, False), (5, 4, 9, False),
+                                                           (2, 3, 17, True), (5, 4, 9, True)])
+def test_host_pipeline_matches_oracle(level, n_streams, chunk, threads):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2211_12265_amd import dilithium as dl
@@ -31,7 +32,7 @@ def test_host_pipeline_matches_oracle(level, n_streams, chunk):
     h_msg.numpy()[:len(msg)] = msg
     h_sig = pinned((n, sgl))
     h_ver = pinned((n,), torch.int32)
-    p = HostPipeline(level, n_streams=n_streams, chunk=chunk)
+    p = HostPipeline(level, n_streams=n_streams, chunk=chunk, host_threads=threads)
     p.sign(h_sk, h_msg, off, h_sig)
     torch.cuda.synchronize()
     p.check()
