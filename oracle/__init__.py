@@ -46,7 +46,8 @@ class _Params(ctypes.Structure):
                 ("omega", ctypes.c_int), ("gamma1", ctypes.c_int32), ("gamma2", ctypes.c_int32),
                 ("z_bits", ctypes.c_int), ("w1_bits", ctypes.c_int), ("eta_bits", ctypes.c_int),
                 ("pk_bytes", ctypes.c_size_t), ("sk_bytes", ctypes.c_size_t),
-                ("sig_bytes", ctypes.c_size_t), ("w1_poly_bytes", ctypes.c_size_t)]
+                ("sig_bytes", ctypes.c_size_t), ("w1_poly_bytes", ctypes.c_size_t),
+                ("mldsa", ctypes.c_int), ("tr_bytes", ctypes.c_int), ("ct_bytes", ctypes.c_int)]
 
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -98,6 +99,7 @@ def bind(path: str) -> ctypes.CDLL:
             "dil_ref_keygen_batch": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, ctypes.c_uint32, ctypes.c_int]),
             "dil_ref_sign_batch": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_uint32,
                                                   ctypes.c_int, _P]),
+            "dil_ref_mldsa_mu": (None, [_P, _P, _SZ, _P]),
             "dil_ref_sign_batch_rnd": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_uint32,
                                                       ctypes.c_int, _P]),
             "dil_ref_verify_batch": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_uint32,
@@ -314,6 +316,17 @@ def verify(level: int, pk: bytes, msg: bytes, sig: bytes) -> int:
     return lib().dil_ref_verify(level, _ptr(k), _ptr(m), len(msg), _ptr(s))
 
 
+def mldsa_mu(tr: bytes, msg: bytes) -> bytes:
+    """The ML-DSA message representative H(tr || 0 || 0 || M, 64) (pure signing, empty context)."""
+    if len(tr) != 64:
+        raise ValueError("tr must be 64 bytes")
+    t = np.frombuffer(bytes(tr), dtype=np.uint8).copy()
+    m = np.frombuffer(bytes(msg) + b"\0", dtype=np.uint8).copy()
+    mu = np.zeros(64, dtype=np.uint8)
+    lib().dil_ref_mldsa_mu(_ptr(t), _ptr(m), len(msg), _ptr(mu))
+    return mu.tobytes()
+
+
 def keygen_batch(level: int, seeds: np.ndarray, nthreads: Optional[int] = None):
     p = params(level)
     seeds = np.ascontiguousarray(seeds, dtype=np.uint8).reshape(-1, 32)
@@ -335,8 +348,9 @@ def _msg_arrays(msg: np.ndarray, msg_off: np.ndarray):
 def sign_batch(level: int, sk: np.ndarray, msg: np.ndarray, msg_off: np.ndarray,
                key_idx: Optional[np.ndarray] = None, nthreads: Optional[int] = None,
                rnd: Optional[np.ndarray] = None):
-    """Returns (sig [count, SIG] uint8, iterations [count] int32).  rnd: optional [count, 64] uint8,
-    the rho' of each task for the randomized variant (None: deterministic Sign)."""
+    """Returns (sig [count, SIG] uint8, iterations [count] int32).  rnd: optional per-task bytes for
+    the randomized variant, [count, 64] (rho' itself, levels 2/3/5) or [count, 32] (the rnd that
+    rho'' hashes, ML-DSA levels 44/65/87); None: deterministic Sign."""
     p = params(level)
     sk = np.ascontiguousarray(sk, dtype=np.uint8)
     msg, msg_off = _msg_arrays(msg, msg_off)
@@ -346,8 +360,9 @@ def sign_batch(level: int, sk: np.ndarray, msg: np.ndarray, msg_off: np.ndarray,
     ki = None if key_idx is None else np.ascontiguousarray(key_idx, dtype=np.uint32)
     if rnd is not None:
         rnd = np.ascontiguousarray(rnd, dtype=np.uint8)
-        if rnd.shape != (n, 64):
-            raise ValueError("rnd must be [count, 64] bytes")
+        rb = 32 if p["mldsa"] else 64
+        if rnd.shape != (n, rb):
+            raise ValueError(f"rnd must be [count, {rb}] bytes")
     rc = lib().dil_ref_sign_batch_rnd(level, _ptr(sk), None if ki is None else _ptr(ki), _ptr(msg), _ptr(msg_off),
                                       None if rnd is None else _ptr(rnd), _ptr(sig), n,
                                       nthreads or default_threads(), _ptr(iters))

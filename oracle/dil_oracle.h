@@ -1,5 +1,6 @@
 /*
- * Plain CPU oracle for batched CRYSTALS-Dilithium (round-3 parameter sets 2/3/5).
+ * Plain CPU oracle for batched CRYSTALS-Dilithium (round-3 parameter sets 2/3/5)
+ * and its FIPS 204 form ML-DSA-44/65/87 (levels 44/65/87).
  *
  * TEST INFRASTRUCTURE ONLY.  This library is the slow, obviously-correct
  * definition that the GPU path is checked against.  Only the test suite, the
@@ -34,6 +35,10 @@
  *                           mean Sign loop count vs Sec. 2.3, and on crafted
  *                           secret keys every emitted signature keeps
  *                           ||c t0|| < gamma2 and at most omega hints
+ * ML-DSA (levels 44/65/87) follows FIPS 204, which is neither in the paper nor
+ * available here: its readings are those of section "ML-DSA" in scheme.c, pinned
+ * by hashlib recomputation of the seed expansion, tr, mu and rho'' and by the
+ * scheme properties; parity unpinned against the FIPS 204 known-answer tests.
  * parity unpinned: the exact byte streams of ExpandA / ExpandS / ExpandMask /
  *   SampleInBall and the encodings against the official round-3 known-answer
  *   tests (neither the specification nor its KAT files are available): the
@@ -54,10 +59,19 @@ typedef struct {
   int32_t gamma1, gamma2;
   int z_bits, w1_bits, eta_bits;
   size_t pk_bytes, sk_bytes, sig_bytes, w1_poly_bytes;
+  int mldsa;     /* 0: round-3 Dilithium (levels 2/3/5); 1: FIPS 204 ML-DSA (44/65/87) */
+  int tr_bytes;  /* 32 (round 3) or 64 (ML-DSA) */
+  int ct_bytes;  /* ctilde: 32 (round 3); lambda / 4 = 32 / 48 / 64 (ML-DSA) */
 } ref_params;
 
-/* parameter set for level 2/3/5 (Tab. 1); returns 0 on success, -1 otherwise */
+/* parameter set for level 2/3/5 (Tab. 1), or 44/65/87 for ML-DSA-44/65/87 (the
+   same k, l, eta, tau, gamma1, gamma2, beta, omega as levels 2/3/5; the FIPS 204
+   differences are tr_bytes, ct_bytes and the hash inputs of the scheme functions);
+   returns 0 on success, -1 otherwise */
 int dil_ref_params(int level, ref_params *p);
+/* ML-DSA's message representative mu = H(tr || 0 || 0 || M, 64): the pure
+   signing interface with an empty context string (FIPS 204, not in the paper) */
+void dil_ref_mldsa_mu(const uint8_t tr[64], const uint8_t *msg, size_t mlen, uint8_t mu[64]);
 
 /* Keccak / SHAKE (Sec. 2.3 "Sampling": SHAKE128/256 as XOF, SHAKE256 as H) */
 void dil_ref_keccak_f1600(uint64_t st[25]);
@@ -89,7 +103,8 @@ void dil_ref_expand_s(int level, const uint8_t rhop[64], int32_t *s /* (l+k)*256
 size_t dil_ref_expand_a_poly_counted(const uint8_t seed34[34], int32_t out[ORN]);
 size_t dil_ref_expand_s_poly_counted(int eta, const uint8_t rhop[64], uint16_t nonce, int32_t out[ORN] /* centred */);
 void dil_ref_expand_mask(int level, const uint8_t rhop[64], uint32_t kappa, int32_t *y /* l*256, centred */);
-void dil_ref_sample_in_ball(int level, const uint8_t ctilde[32], int32_t c[ORN] /* centred */);
+/* ctilde: 32 bytes (round 3) or the ct_bytes of the ML-DSA level */
+void dil_ref_sample_in_ball(int level, const uint8_t *ctilde, int32_t c[ORN] /* centred */);
 
 /* generic b-bit LSB-first packing of n coefficients (values must lie in [0, 2^b)) */
 void dil_ref_bitpack(const uint32_t *v, size_t n, int b, uint8_t *out);
@@ -102,8 +117,9 @@ int dil_ref_keygen(int level, const uint8_t zeta[32], uint8_t *pk, uint8_t *sk);
 void dil_ref_set_sign_cap(int cap);
 int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, uint8_t *sig);
 /* the randomized variant of round-3 Sign: rho' is the 64 caller-supplied bytes rnd
-   instead of H(K || mu); same return values */
-int dil_ref_sign_rnd(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, const uint8_t rnd[64],
+   instead of H(K || mu); at the ML-DSA levels rnd is the 32-byte hedging input of
+   rho'' = H(K || rnd || mu) (dil_ref_sign uses 32 zero bytes); same return values */
+int dil_ref_sign_rnd(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, const uint8_t *rnd,
                      uint8_t *sig);
 /* returns 1 accept, 0 reject, -1 bad level */
 int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen, const uint8_t *sig);
@@ -114,7 +130,8 @@ int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen
 int dil_ref_keygen_batch(int level, const uint8_t *seeds, uint8_t *pk, uint8_t *sk, uint32_t count, int nthreads);
 int dil_ref_sign_batch(int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                        const uint64_t *msg_off, uint8_t *sig, uint32_t count, int nthreads, int32_t *iters);
-/* as dil_ref_sign_batch, task t signing with rho' = rnd[64 t .. 64 t + 64) (rnd NULL: deterministic) */
+/* as dil_ref_sign_batch, task t signing with rho' = rnd[64 t .. 64 t + 64) (rnd NULL: deterministic);
+   at the ML-DSA levels rnd rows are 32 bytes (rnd[32 t .. 32 t + 32)) */
 int dil_ref_sign_batch_rnd(int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                            const uint64_t *msg_off, const uint8_t *rnd, uint8_t *sig, uint32_t count, int nthreads,
                            int32_t *iters);

@@ -18,6 +18,21 @@
  *       strictly increasing within a polynomial, unused index bytes zero.
  *   Sign reduces t = A s1 + s2 to [0, q) before Power2Round; Sign's output is
  *   the first kappa in 0, l, 2l, ... whose candidate passes all four checks.
+ *
+ * ML-DSA (levels 44/65/87, FIPS 204 -- not in the paper, which covers round 3;
+ * the standard is not available here, so these readings are from its published
+ * algorithm, pinned by hashlib recomputation and the scheme properties only):
+ *   parameters k, l, eta, tau, gamma1, gamma2, beta, omega of levels 2/3/5;
+ *   lambda = 128 / 192 / 256, ctilde of lambda / 4 = 32 / 48 / 64 bytes
+ *   (rho, rho', K) = SHAKE256(xi || k || l, 128 B)   (one byte each for k and l)
+ *   tr = SHAKE256(pk, 64 B); sk = rho || K || tr (64 B) || s1 || s2 || t0
+ *                                                        sizes 2560 / 4032 / 4896
+ *   mu = SHAKE256(tr || 0x00 || 0x00 || M, 64 B)   (pure signing, empty context)
+ *   rho'' = SHAKE256(K || rnd || mu, 64 B), rnd 32 bytes (zeros: deterministic)
+ *   ctilde = SHAKE256(mu || packed w1, lambda / 4); SampleInBall absorbs all of it
+ *   sig = ctilde || z || h                              sizes 2420 / 3309 / 4627
+ *   ExpandA / ExpandS / ExpandMask, the encodings of t1, s, t0, z, w1 and h, the
+ *   strict hint decoding and the rejection conditions are those of round 3.
  */
 #include "dil_oracle.h"
 #include <pthread.h>
@@ -27,6 +42,19 @@
 int dil_ref_params(int level, ref_params *p) {
   memset(p, 0, sizeof *p);
   p->level = level;
+  p->tr_bytes = 32;
+  p->ct_bytes = 32;
+  if (level == 44 || level == 65 || level == 87) {  /* ML-DSA-44 / 65 / 87 */
+    const int base = level == 44 ? 2 : level == 65 ? 3 : 5;
+    dil_ref_params(base, p);
+    p->level = level;
+    p->mldsa = 1;
+    p->tr_bytes = 64;
+    p->ct_bytes = level == 44 ? 32 : level == 65 ? 48 : 64;
+    p->sk_bytes = 64 + (size_t)p->tr_bytes + (size_t)(p->l + p->k) * ORN * p->eta_bits / 8 + (size_t)p->k * ORN * 13 / 8;
+    p->sig_bytes = (size_t)p->ct_bytes + (size_t)p->l * ORN * p->z_bits / 8 + p->omega + p->k;
+    return 0;
+  }
   switch (level) {
     case 2:
       p->k = 4; p->l = 4; p->eta = 2; p->tau = 39; p->gamma1 = 1 << 17; p->gamma2 = 95232;
@@ -156,8 +184,11 @@ int dil_ref_keygen(int level, const uint8_t zeta[32], uint8_t *pk, uint8_t *sk) 
   ref_params P;
   if (dil_ref_params(level, &P)) return -1;
   const int k = P.k, l = P.l;
-  uint8_t seed[128];
-  dil_ref_shake256(zeta, 32, seed, 128);
+  uint8_t seed[128], in[34];
+  memcpy(in, zeta, 32);
+  in[32] = (uint8_t)k;  /* ML-DSA only: the k and l bytes after the seed */
+  in[33] = (uint8_t)l;
+  dil_ref_shake256(in, P.mldsa ? 34 : 32, seed, 128);
   const uint8_t *rho = seed, *rhop = seed + 32, *K = seed + 96;
   int32_t *A = (int32_t *)malloc(sizeof(int32_t) * k * l * ORN);
   int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (k + l) * ORN);
@@ -178,12 +209,12 @@ int dil_ref_keygen(int level, const uint8_t zeta[32], uint8_t *pk, uint8_t *sk) 
   }
   memcpy(pk, rho, 32);
   for (int i = 0; i < k; i++) pack_vals(t1 + i * ORN, ORN, 10, pk + 32 + i * 320);
-  uint8_t tr[32];
-  dil_ref_shake256(pk, P.pk_bytes, tr, 32);
+  uint8_t tr[64];
+  dil_ref_shake256(pk, P.pk_bytes, tr, (size_t)P.tr_bytes);
   memcpy(sk, rho, 32);
   memcpy(sk + 32, K, 32);
-  memcpy(sk + 64, tr, 32);
-  size_t eb = (size_t)ORN * P.eta_bits / 8, off = 96;
+  memcpy(sk + 64, tr, (size_t)P.tr_bytes);
+  size_t eb = (size_t)ORN * P.eta_bits / 8, off = 64 + (size_t)P.tr_bytes;
   for (int j = 0; j < l; j++, off += eb) pack_eta(&P, s + j * ORN, sk + off);
   for (int i = 0; i < k; i++, off += eb) pack_eta(&P, s + (l + i) * ORN, sk + off);
   for (int i = 0; i < k; i++, off += 416) pack_t0(t0 + i * ORN, sk + off);
@@ -193,6 +224,18 @@ int dil_ref_keygen(int level, const uint8_t zeta[32], uint8_t *pk, uint8_t *sk) 
 
 static void pack_w1(const ref_params *P, const int32_t *w1, uint8_t *out) {
   for (int i = 0; i < P->k; i++) pack_vals(w1 + i * ORN, ORN, P->w1_bits, out + i * P->w1_poly_bytes);
+}
+
+/* ML-DSA: mu = H(tr || IntegerToBytes(0, 1) || IntegerToBytes(|ctx|, 1) || ctx || M, 64)
+   with an empty context ctx */
+void dil_ref_mldsa_mu(const uint8_t tr[64], const uint8_t *msg, size_t mlen, uint8_t mu[64]) {
+  uint8_t *buf = (uint8_t *)malloc(66 + mlen);
+  memcpy(buf, tr, 64);
+  buf[64] = 0;  /* pure ML-DSA, not the pre-hash variant */
+  buf[65] = 0;  /* context length 0 */
+  memcpy(buf + 66, msg, mlen);
+  dil_ref_shake256(buf, 66 + mlen, mu, 64);
+  free(buf);
 }
 
 /* ---- Alg. 2 ---- */
@@ -211,7 +254,7 @@ static int sign_core(int level, const uint8_t *sk, const uint8_t *msg, size_t ml
   if (dil_ref_params(level, &P)) return -1;
   const int k = P.k, l = P.l;
   const uint8_t *rho = sk, *K = sk + 32, *tr = sk + 64;
-  size_t eb = (size_t)ORN * P.eta_bits / 8;
+  const size_t eb = (size_t)ORN * P.eta_bits / 8, so = 64 + (size_t)P.tr_bytes;  /* s1 offset in sk */
   int32_t *A = (int32_t *)malloc(sizeof(int32_t) * k * l * ORN);
   int32_t *s1h = (int32_t *)malloc(sizeof(int32_t) * l * ORN);
   int32_t *s2h = (int32_t *)malloc(sizeof(int32_t) * k * ORN);
@@ -222,34 +265,44 @@ static int sign_core(int level, const uint8_t *sk, const uint8_t *msg, size_t ml
   int32_t *w1 = (int32_t *)malloc(sizeof(int32_t) * k * ORN);
   int32_t *z = (int32_t *)malloc(sizeof(int32_t) * l * ORN);
   int32_t *h = (int32_t *)malloc(sizeof(int32_t) * k * ORN);
-  uint8_t *buf = (uint8_t *)malloc(64 + (size_t)k * P.w1_poly_bytes + mlen + 32);
+  uint8_t *buf = (uint8_t *)malloc(130 + (size_t)k * P.w1_poly_bytes + mlen);
 
-  /* mu = H(tr || M), rho' = H(K || mu) */
+  /* round 3: mu = H(tr || M), rho' = H(K || mu) (or the caller's 64 bytes);
+     ML-DSA: mu = H(tr || 0 || 0 || M), rho'' = H(K || rnd || mu), rnd 32 bytes */
   uint8_t mu[64], rhop[64];
-  memcpy(buf, tr, 32);
-  memcpy(buf + 32, msg, mlen);
-  dil_ref_shake256(buf, 32 + mlen, mu, 64);
-  if (rnd) {
-    memcpy(rhop, rnd, 64);
-  } else {
+  if (P.mldsa) {
+    dil_ref_mldsa_mu(tr, msg, mlen, mu);
     memcpy(buf, K, 32);
-    memcpy(buf + 32, mu, 64);
-    dil_ref_shake256(buf, 96, rhop, 64);
+    if (rnd) memcpy(buf + 32, rnd, 32);
+    else memset(buf + 32, 0, 32);
+    memcpy(buf + 64, mu, 64);
+    dil_ref_shake256(buf, 128, rhop, 64);
+  } else {
+    memcpy(buf, tr, 32);
+    memcpy(buf + 32, msg, mlen);
+    dil_ref_shake256(buf, 32 + mlen, mu, 64);
+    if (rnd) {
+      memcpy(rhop, rnd, 64);
+    } else {
+      memcpy(buf, K, 32);
+      memcpy(buf + 32, mu, 64);
+      dil_ref_shake256(buf, 96, rhop, 64);
+    }
   }
 
   dil_ref_expand_a(level, rho, A);
   for (int j = 0; j < l; j++) {
     int32_t t[ORN];
-    unpack_eta(&P, sk + 96 + j * eb, t);
+    unpack_eta(&P, sk + so + j * eb, t);
     to_canon(t, s1h + j * ORN, ORN);
     dil_ref_ntt(s1h + j * ORN);
   }
   for (int i = 0; i < k; i++) {
     int32_t t[ORN];
-    unpack_eta(&P, sk + 96 + (l + i) * eb, t);
+    unpack_eta(&P, sk + so + (l + i) * eb, t);
     to_canon(t, s2h + i * ORN, ORN);
     dil_ref_ntt(s2h + i * ORN);
-    unpack_t0(sk + 96 + (l + k) * eb + i * 416, t);
+    unpack_t0(sk + so + (l + k) * eb + i * 416, t);
     to_canon(t, t0h + i * ORN, ORN);
     dil_ref_ntt(t0h + i * ORN);
   }
@@ -277,8 +330,8 @@ static int sign_core(int level, const uint8_t *sk, const uint8_t *msg, size_t ml
     for (int i = 0; i < k; i++) dil_ref_decompose(w + i * ORN, w1 + i * ORN, r0tmp, ORN, P.gamma2);
     memcpy(buf, mu, 64);
     pack_w1(&P, w1, buf + 64);
-    uint8_t ctilde[32];
-    dil_ref_shake256(buf, 64 + (size_t)k * P.w1_poly_bytes, ctilde, 32);
+    uint8_t ctilde[64];
+    dil_ref_shake256(buf, 64 + (size_t)k * P.w1_poly_bytes, ctilde, (size_t)P.ct_bytes);
     int32_t c[ORN], ch[ORN];
     dil_ref_sample_in_ball(level, ctilde, c);
     to_canon(c, ch, ORN);
@@ -338,10 +391,10 @@ static int sign_core(int level, const uint8_t *sk, const uint8_t *msg, size_t ml
 #else
     if (reject || hcount > P.omega) continue;
 #endif
-    memcpy(sig, ctilde, 32);
-    size_t zb = (size_t)ORN * P.z_bits / 8;
-    for (int j = 0; j < l; j++) pack_z(&P, z + j * ORN, sig + 32 + j * zb);
-    pack_hint(&P, h, sig + 32 + l * zb);
+    const size_t ct = (size_t)P.ct_bytes, zb = (size_t)ORN * P.z_bits / 8;
+    memcpy(sig, ctilde, ct);
+    for (int j = 0; j < l; j++) pack_z(&P, z + j * ORN, sig + ct + j * zb);
+    pack_hint(&P, h, sig + ct + l * zb);
     break;
   }
   free(A); free(s1h); free(s2h); free(t0h); free(y); free(yh); free(w); free(w1); free(z); free(h); free(buf);
@@ -352,7 +405,7 @@ int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, 
   return sign_core(level, sk, msg, mlen, NULL, sig);
 }
 
-int dil_ref_sign_rnd(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, const uint8_t rnd[64],
+int dil_ref_sign_rnd(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, const uint8_t *rnd,
                      uint8_t *sig) {
   return sign_core(level, sk, msg, mlen, rnd, sig);
 }
@@ -362,23 +415,27 @@ int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen
   ref_params P;
   if (dil_ref_params(level, &P)) return -1;
   const int k = P.k, l = P.l;
-  size_t zb = (size_t)ORN * P.z_bits / 8;
+  const size_t zb = (size_t)ORN * P.z_bits / 8, ct = (size_t)P.ct_bytes;
   int32_t *z = (int32_t *)malloc(sizeof(int32_t) * l * ORN);
   int32_t *h = (int32_t *)malloc(sizeof(int32_t) * k * ORN);
   int32_t *A = (int32_t *)malloc(sizeof(int32_t) * k * l * ORN);
   int32_t *w1 = (int32_t *)malloc(sizeof(int32_t) * k * ORN);
-  uint8_t *buf = (uint8_t *)malloc(64 + (size_t)k * P.w1_poly_bytes + mlen + 32);
+  uint8_t *buf = (uint8_t *)malloc(130 + (size_t)k * P.w1_poly_bytes + mlen);
   int ok = 1;
-  for (int j = 0; j < l; j++) unpack_z(&P, sig + 32 + j * zb, z + j * ORN);
-  if (unpack_hint(&P, sig + 32 + l * zb, h)) ok = 0;
+  for (int j = 0; j < l; j++) unpack_z(&P, sig + ct + j * zb, z + j * ORN);
+  if (unpack_hint(&P, sig + ct + l * zb, h)) ok = 0;
   for (int i = 0; i < l * ORN && ok; i++)
     if (iabs(z[i]) >= P.gamma1 - P.beta) ok = 0;
   if (ok) {
-    uint8_t tr[32], mu[64], c2[32];
-    dil_ref_shake256(pk, P.pk_bytes, tr, 32);
-    memcpy(buf, tr, 32);
-    memcpy(buf + 32, msg, mlen);
-    dil_ref_shake256(buf, 32 + mlen, mu, 64);
+    uint8_t tr[64], mu[64], c2[64];
+    dil_ref_shake256(pk, P.pk_bytes, tr, (size_t)P.tr_bytes);
+    if (P.mldsa) {
+      dil_ref_mldsa_mu(tr, msg, mlen, mu);
+    } else {
+      memcpy(buf, tr, 32);
+      memcpy(buf + 32, msg, mlen);
+      dil_ref_shake256(buf, 32 + mlen, mu, 64);
+    }
     dil_ref_expand_a(level, pk, A);
     int32_t c[ORN], ch[ORN];
     dil_ref_sample_in_ball(level, sig, c);
@@ -404,8 +461,8 @@ int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen
     free(zh);
     memcpy(buf, mu, 64);
     pack_w1(&P, w1, buf + 64);
-    dil_ref_shake256(buf, 64 + (size_t)k * P.w1_poly_bytes, c2, 32);
-    if (memcmp(c2, sig, 32) != 0) ok = 0;
+    dil_ref_shake256(buf, 64 + (size_t)k * P.w1_poly_bytes, c2, ct);
+    if (memcmp(c2, sig, ct) != 0) ok = 0;
   }
   free(z); free(h); free(A); free(w1); free(buf);
   return ok;
@@ -433,7 +490,8 @@ static void *batch_worker(void *arg) {
       const uint8_t *m = j->msg + j->msg_off[t];
       size_t mlen = (size_t)(j->msg_off[t + 1] - j->msg_off[t]);
       if (j->op == 1) {
-        int it = sign_core(j->level, j->in_key + j->P.sk_bytes * key, m, mlen, j->rnd ? j->rnd + 64 * (size_t)t : NULL,
+        int it = sign_core(j->level, j->in_key + j->P.sk_bytes * key, m, mlen,
+                           j->rnd ? j->rnd + (j->P.mldsa ? 32 : 64) * (size_t)t : NULL,
                            j->sig + j->P.sig_bytes * t);
         if (j->iters) j->iters[t] = it;
       } else {
