@@ -1,6 +1,7 @@
 /*
- * libdil -- batched CRYSTALS-Dilithium (round-3 parameter sets 2, 3, 5) on
- * AMD Instinct MI355X (gfx950).  C ABI.
+ * libdil -- batched CRYSTALS-Dilithium (round-3 parameter sets 2, 3, 5, and
+ * their FIPS 204 form ML-DSA-44 / 65 / 87) on AMD Instinct MI355X (gfx950).
+ * C ABI.
  *
  * The operations are Dilithium.Gen, Dilithium.Sign (deterministic mode) and
  * Dilithium.Verify as given in Alg. 1, 2 and 3 of the paper, with the
@@ -11,6 +12,16 @@
  *   level 2: pk 1312 B, sk 2528 B, signature 2420 B
  *   level 3: pk 1952 B, sk 4000 B, signature 3293 B
  *   level 5: pk 2592 B, sk 4864 B, signature 4595 B
+ * Levels 44, 65 and 87 select ML-DSA-44 / 65 / 87 (FIPS 204, not covered by
+ * the paper): the lattice parameters of levels 2 / 3 / 5 with a 64-byte tr, a
+ * ctilde of 32 / 48 / 64 bytes that seeds SampleInBall whole, the key seed
+ * H(xi || k || l), mu = H(tr || 0x00 || 0x00 || M) (pure signing, empty
+ * context) and the mask seed rho'' = H(K || rnd || mu):
+ *   level 44: pk 1312 B, sk 2560 B, signature 2420 B
+ *   level 65: pk 1952 B, sk 4032 B, signature 3309 B
+ *   level 87: pk 2592 B, sk 4896 B, signature 4627 B
+ * Every batch and key-table entry point takes all six levels; the serving
+ * dispatcher (dil_server_*) and dil_t0_ntt_batch take levels 2, 3, 5 only.
  *
  * Conventions for every batch entry point:
  *   - Buffer pointers are DEVICE pointers (hipMalloc'd or torch tensors on the
@@ -29,7 +40,7 @@
  *     input i, whatever order the device processes tasks in.
  *   - count == 0 is a no-op returning DIL_OK.
  *   - Errors are returned, never written into outputs:
- *       DIL_EINVAL  level not in {2,3,5}, NULL pointer with count > 0, bad mode;
+ *       DIL_EINVAL  level not in {2,3,5,44,65,87}, NULL pointer with count > 0, bad mode;
  *       DIL_ENOMEM  the context cannot allocate its workspace;
  *       DIL_EHIP    a HIP launch/copy failed (dil_last_error() has the text);
  *       DIL_EMSG    a decreasing msg_off entry was found (detected on the
@@ -80,7 +91,9 @@ int dil_ctx_set_mode(dil_ctx *ctx, int mode);
  *   "persist.waves" wavefronts per persistent workgroup: 1 (64 / l candidate
  *                   slots per batch), 2 or 4 (default; W * (64 / l) slots,
  *                   the challenge hashes on two lanes per slot); any other
- *                   value is DIL_EINVAL;
+ *                   value is DIL_EINVAL; the ML-DSA levels are built for 4
+ *                   only (a persistent Sign call or dil_persist_capacity at
+ *                   level 44 / 65 / 87 with 1 or 2 is DIL_EINVAL);
  *   "timing"        1 = record HIP events around the persistent Sign's setup
  *                   kernels and its loop kernel (read with dil_sign_timing);
  *   "graph"         1 = capture the launch sequences of persistent-mode Sign's
@@ -111,7 +124,7 @@ int dil_ctx_set_mode(dil_ctx *ctx, int mode);
  *                   (bank-conflicted) LDS layout, the padding step of the same
  *                   ablation inside the loop; the signatures are identical; a
  *                   persistent Sign call with 0 and another "persist.waves"
- *                   value fails with DIL_EINVAL. */
+ *                   value, or at an ML-DSA level, fails with DIL_EINVAL. */
 int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value);
 /* Operations, for the workspace queries below. */
 #define DIL_OP_KEYGEN 0
@@ -144,15 +157,17 @@ int dil_ctx_check(dil_ctx *ctx, void *stream);
 /* Text of the last error on this context (static storage inside the context). */
 const char *dil_last_error(dil_ctx *ctx);
 
-/* Byte sizes for a level (Tab. 1 parameters, round-3 v3.1 layouts). */
+/* Byte sizes for a level (Tab. 1 parameters, round-3 v3.1 layouts; FIPS 204 for 44 / 65 / 87). */
 int dil_sizes(int level, size_t *pk_bytes, size_t *sk_bytes, size_t *sig_bytes);
 
 /* Dilithium.Gen (Alg. 1) with caller-supplied 32-byte seeds zeta:
- * seeds[count][32] -> pk[count][PK], sk[count][SK]. */
+ * seeds[count][32] -> pk[count][PK], sk[count][SK].  (ML-DSA levels expand
+ * H(xi || k || l) and store a 64-byte tr.) */
 int dil_keygen_batch(dil_ctx *ctx, int level, const uint8_t *seeds, uint8_t *pk, uint8_t *sk, uint32_t count,
                      void *stream);
 
-/* Dilithium.Sign (Alg. 2), deterministic (rho' = H(K || mu)):
+/* Dilithium.Sign (Alg. 2), deterministic (rho' = H(K || mu); ML-DSA levels:
+ * rho'' = H(K || 0^32 || mu), FIPS 204's deterministic variant):
  * sk rows [n_keys][SK], messages (msg, msg_off), sig[count][SIG].
  * Output equals sequential Sign: the first kappa = 0, l, 2l, ... that passes
  * all four rejection checks.  In DIL_MODE_STAGED the call returns after the
@@ -163,9 +178,12 @@ int dil_sign_batch(dil_ctx *ctx, int level, const uint8_t *sk, const uint32_t *k
 /* The randomized variant of round-3 Sign: as dil_sign_batch, but task i uses
  * rho' = rnd[64 i .. 64 i + 64) (caller-supplied random bytes, a device
  * buffer of count x 64 bytes, 4-byte aligned) instead of H(K || mu) (Alg. 2
- * computes rho' deterministically; every other step is the same).  rnd NULL
- * is deterministic Sign.  DIL_EINVAL for a misaligned rnd.  The caller owns
- * the randomness: the output is a deterministic function of (sk, M, rnd). */
+ * computes rho' deterministically; every other step is the same).  At the
+ * ML-DSA levels rnd holds 32 bytes per task (count x 32, 4-byte aligned) and
+ * is hashed into the mask seed, rho'' = H(K || rnd[32 i .. 32 i + 32) || mu)
+ * (FIPS 204's hedged signing).  rnd NULL is deterministic Sign.  DIL_EINVAL
+ * for a misaligned rnd.  The caller owns the randomness: the output is a
+ * deterministic function of (sk, M, rnd). */
 int dil_sign_batch_rnd(dil_ctx *ctx, int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                        const uint64_t *msg_off, const uint8_t *rnd, uint8_t *sig, uint32_t count, void *stream);
 

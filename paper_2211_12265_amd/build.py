@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdil.so")
 SOURCES = ["api.hip", "server.hip"]
-HEADERS = ["common.h", "keccak.h", "ntt.h", "poly.h", "sponge.h", "keccak_pair.h", "kernels.h", "ntt_ablation.h", "persist.h", "probe.h", "errwords.h", "batch_sched.h", "t0_ablation.h"]
+HEADERS = ["common.h", "keccak.h", "ntt.h", "poly.h", "sponge.h", "keccak_pair.h", "kernels.h", "ntt_ablation.h", "persist.h", "probe.h", "errwords.h", "batch_sched.h", "t0_ablation.h", "msg_words.h"]
 
 
 def hipcc() -> str:

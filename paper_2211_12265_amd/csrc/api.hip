@@ -43,7 +43,7 @@ struct dil_ctx {
   hipEvent_t ev[RING][3] = {};                 // per timed call: before setup, before loop, after loop
   int ev_count = 0;                            // timed calls recorded since timing was (re)enabled
   int cu_count = 0;                            // cached device properties
-  int occ[3][6] = {};                          // cached persistent-kernel occupancy [shape: 1/2/4 waves][level]
+  int occ[3][6] = {};                          // cached persistent-kernel occupancy [shape: 1/2/4 waves][lv_slot]
   // hipGraph replay of identical calls (same level, buffers, count and schedule)
   int use_graph = 0;
   hipStream_t cap_stream = nullptr;            // private stream the graphs are captured on
@@ -69,6 +69,7 @@ struct dil_keyset {
   int device = 0;
   void *mem = nullptr;
   uint8_t *pk = nullptr, *sk = nullptr, *tr = nullptr;   // key rows (copies) and tr = H(pk)
+  size_t bytes = 0;                                      // device memory held
   int32_t *A = nullptr, *s1h = nullptr, *s2h = nullptr, *t0h = nullptr, *t1h = nullptr;
 };
 
@@ -99,7 +100,10 @@ void drop_graphs(dil_ctx *ctx) {
   ctx->graphs.clear();
 }
 
-bool valid_level(int lv) { return lv == 2 || lv == 3 || lv == 5; }
+// round-3 levels 2 / 3 / 5 (Tab. 1) and the ML-DSA-44 / 65 / 87 parameter sets of FIPS 204
+bool valid_level(int lv) { return lv == 2 || lv == 3 || lv == 5 || lv == 44 || lv == 65 || lv == 87; }
+bool mldsa_level(int lv) { return lv == 44 || lv == 65 || lv == 87; }
+constexpr int lv_slot(int lv) { return lv == 2 ? 0 : lv == 3 ? 1 : lv == 5 ? 2 : lv == 44 ? 3 : lv == 65 ? 4 : 5; }
 
 // The kinds of call a workspace is laid out for: each carves only the
 // per-task rows its kernels read or write.
@@ -134,7 +138,7 @@ size_t ws_layout(uint8_t *base, size_t cap, int form, bool keyset, size_t grid, 
   w.counters = (uint32_t *)take(true, 16 * 4);
   w.muw1 = take(sign || form == WS_VERIFY, cap * muw1_stride);
   w.rhop = take(sign || form == WS_KEYGEN, cap * 64);
-  w.ctilde = take(staged, cap * 32);
+  w.ctilde = take(staged, cap * CT_STRIDE);
   w.cpoly = (int8_t *)take(staged || form == WS_VERIFY, cap * 256);
   w.A = (int32_t *)take(!keyset, cap * K * L * 1024);
   w.s1h = (int32_t *)take(form == WS_KEYGEN || (sign && !keyset), cap * (form == WS_KEYGEN ? L + K : L) * 1024);
@@ -410,11 +414,15 @@ int persist_occupancy(dil_ctx *ctx, int *occ) {
     ctx->cu_count = prop.multiProcessorCount;
   }
   const int w = ctx->persist_waves, si = w == 4 ? 2 : w == 2 ? 1 : 0;
-  int &o = ctx->occ[si][LV];
+  if (Lv<LV>::MLDSA && w != 4) return fail(ctx, DIL_EINVAL, "ML-DSA levels run the four-wavefront loop kernel only");
+  int &o = ctx->occ[si][lv_slot(LV)];
   if (!o) {
-    if (w == 4) HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_persistw_k<LV, 4>, 256, 0));
-    else if (w == 2) HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_persistw_k<LV, 2>, 128, 0));
-    else HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_persist_k<LV>, 64, 0));
+    if (w == 4) {
+      HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_persistw_k<LV, 4>, 256, 0));
+    } else if constexpr (!Lv<LV>::MLDSA) {
+      if (w == 2) HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_persistw_k<LV, 2>, 128, 0));
+      else HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_persist_k<LV>, 64, 0));
+    }
   }
   *occ = std::max(o, 1);
   return DIL_OK;
@@ -445,6 +453,9 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   const int waves = ctx->persist_waves;
   if (!ctx->persist_pad && waves != 4)
     return fail(ctx, DIL_EINVAL, "persist.pad = 0 exists for the four-wavefront loop kernel only");
+  // the one- and two-wavefront shapes and the unpadded ablation form are built for the round-3 levels only
+  if (Lv<LV>::MLDSA && (waves != 4 || !ctx->persist_pad))
+    return fail(ctx, DIL_EINVAL, "ML-DSA levels run the four-wavefront padded loop kernel (persist.waves = 4, persist.pad = 1)");
   uint64_t grid = 1, hmax = 1;
   int rc = persist_schedule<LV>(ctx, count, &grid, &hmax);
   if (rc) return rc;
@@ -472,14 +483,18 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   if (evs) HIPCHK(ctx, hipEventRecord(evs[1], st));
   // The loop kernel is one launch: it is launched directly, also when graphs
   // are enabled (as a graph node it measured 2-4% slower).
-  if (waves == 4 && !ctx->persist_pad)
-    sg_persistw_k<LV, 4, false><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
-  else if (waves == 4)
+  if constexpr (Lv<LV>::MLDSA) {
     sg_persistw_k<LV, 4><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
-  else if (waves == 2)
-    sg_persistw_k<LV, 2><<<(unsigned)grid, 128, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
-  else
-    sg_persist_k<LV><<<(unsigned)grid, 64, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+  } else {
+    if (waves == 4 && !ctx->persist_pad)
+      sg_persistw_k<LV, 4, false><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+    else if (waves == 4)
+      sg_persistw_k<LV, 4><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+    else if (waves == 2)
+      sg_persistw_k<LV, 2><<<(unsigned)grid, 128, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+    else
+      sg_persist_k<LV><<<(unsigned)grid, 64, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+  }
   LAUNCHCHK(ctx);
   if (evs) {
     HIPCHK(ctx, hipEventRecord(evs[2], st));
@@ -551,12 +566,13 @@ int keyset_build(dil_ctx *ctx, dil_keyset *ks, const uint8_t *pk, const uint8_t 
   bytes += rnd(n * K * L * 1024);
   if (sk) bytes += rnd(n * PP::SK) + rnd(n * L * 1024) + 2 * rnd(n * K * 1024);
   if (pk) bytes += rnd(n * PP::PK) + rnd(n * K * 1024);
-  bytes += rnd(n * 32);
+  bytes += rnd(n * PP::TRB);
   hipError_t e = hipMalloc(&ks->mem, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(ctx, DIL_ENOMEM, "key table allocation", e);
   }
+  ks->bytes = bytes;
   uint8_t *p = (uint8_t *)ks->mem;
   auto take = [&](size_t b) {
     uint8_t *r = p;
@@ -564,7 +580,7 @@ int keyset_build(dil_ctx *ctx, dil_keyset *ks, const uint8_t *pk, const uint8_t 
     return r;
   };
   ks->A = (int32_t *)take(n * K * L * 1024);
-  ks->tr = take(n * 32);
+  ks->tr = take(n * PP::TRB);
   if (sk) {
     ks->sk = take(n * PP::SK);
     ks->s1h = (int32_t *)take(n * L * 1024);
@@ -592,7 +608,7 @@ int keyset_build(dil_ctx *ctx, dil_keyset *ks, const uint8_t *pk, const uint8_t 
     ks_pk_k<LV><<<ks->nkeys, 64, 0, st>>>(ks->pk, ks->t1h, ks->nkeys);
     ks_tr_k<LV><<<blocks_for(n, 256), 256, 0, st>>>(ks->pk, ks->tr, ks->nkeys);
   } else {
-    HIPCHK(ctx, hipMemcpy2DAsync(ks->tr, 32, ks->sk + 64, PP::SK, 32, n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(ctx, hipMemcpy2DAsync(ks->tr, PP::TRB, ks->sk + 64, PP::SK, PP::TRB, n, hipMemcpyDeviceToDevice, st));
   }
   LAUNCHCHK(ctx);
   return DIL_OK;
@@ -627,13 +643,22 @@ int scratch_address(dil_ctx *ctx, int device, uint8_t **out) {
 }
 
 template <class F>
-int by_level(int level, F f) {
+int by_round3_level(int level, F f) {
   switch (level) {
     case 2: return f(std::integral_constant<int, 2>{});
     case 3: return f(std::integral_constant<int, 3>{});
     case 5: return f(std::integral_constant<int, 5>{});
   }
   return DIL_EINVAL;
+}
+template <class F>
+int by_level(int level, F f) {
+  switch (level) {
+    case 44: return f(std::integral_constant<int, 44>{});
+    case 65: return f(std::integral_constant<int, 65>{});
+    case 87: return f(std::integral_constant<int, 87>{});
+  }
+  return by_round3_level(level, f);
 }
 
 }  // namespace
@@ -844,11 +869,7 @@ int dil_keyset_info(const dil_keyset *ks, int *level, uint32_t *n_keys, size_t *
   if (!ks) return DIL_EINVAL;
   if (level) *level = ks->level;
   if (n_keys) *n_keys = ks->nkeys;
-  if (device_bytes) {
-    int32_t K = ks->level == 2 ? 4 : ks->level == 3 ? 6 : 8, L = ks->level == 2 ? 4 : ks->level == 3 ? 5 : 7;
-    size_t n = ks->nkeys;
-    *device_bytes = n * (K * L * 1024 + 32) + (ks->sk ? n * ((L + 2 * K) * 1024) : 0) + (ks->pk ? n * K * 1024 : 0);
-  }
+  if (device_bytes) *device_bytes = ks->bytes;
   return DIL_OK;
 }
 
@@ -1128,7 +1149,7 @@ int dil_t0_ntt_batch(dil_ctx *ctx, int level, const uint8_t *sk, int32_t *t0_hat
   hipSetDevice(ctx->device);
   const hipStream_t st = (hipStream_t)stream;
   const int variant = ctx->t0_variant;
-  return by_level(level, [&](auto lv) {
+  return by_round3_level(level, [&](auto lv) {
     constexpr int LV = decltype(lv)::value;
     switch (variant) {
       case 0: t0_ntt_reg_k<LV, true><<<count, 64, 0, st>>>(sk, t0_hat, count); break;

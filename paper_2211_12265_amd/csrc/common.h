@@ -53,17 +53,39 @@ constexpr int32_t zinv_scaled_m(int k) { return to_mont(cmod(cpow(PSI, 512 - brv
 
 // ---- level parameters (Tab. 1) ----
 template <int LV> struct Lv;
+// MLDSA: the FIPS 204 form (not in the paper); CT: bytes of ctilde
 template <> struct Lv<2> {
   static constexpr int K = 4, L = 4, ETA = 2, TAU = 39, BETA = 78, OMEGA = 80;
   static constexpr int32_t GAMMA1 = 1 << 17, GAMMA2 = (Q - 1) / 88;
+  static constexpr bool MLDSA = false;
+  static constexpr int CT = 32;
 };
 template <> struct Lv<3> {
   static constexpr int K = 6, L = 5, ETA = 4, TAU = 49, BETA = 196, OMEGA = 55;
   static constexpr int32_t GAMMA1 = 1 << 19, GAMMA2 = (Q - 1) / 32;
+  static constexpr bool MLDSA = false;
+  static constexpr int CT = 32;
 };
 template <> struct Lv<5> {
   static constexpr int K = 8, L = 7, ETA = 2, TAU = 60, BETA = 120, OMEGA = 75;
   static constexpr int32_t GAMMA1 = 1 << 19, GAMMA2 = (Q - 1) / 32;
+  static constexpr bool MLDSA = false;
+  static constexpr int CT = 32;
+};
+// ML-DSA-44 / 65 / 87 (FIPS 204): the lattice parameters of levels 2 / 3 / 5,
+// a 64-byte tr and a ctilde of lambda / 4 bytes; the key seed, mu and the mask
+// seed rho'' hash other inputs (see the KeyGen and Sign setup kernels)
+template <> struct Lv<44> : Lv<2> {
+  static constexpr bool MLDSA = true;
+  static constexpr int CT = 32;
+};
+template <> struct Lv<65> : Lv<3> {
+  static constexpr bool MLDSA = true;
+  static constexpr int CT = 48;
+};
+template <> struct Lv<87> : Lv<5> {
+  static constexpr bool MLDSA = true;
+  static constexpr int CT = 64;
 };
 // derived sizes (encodings follow the round-3 v3.1 byte layout)
 template <int LV> struct P : Lv<LV> {
@@ -76,16 +98,22 @@ template <int LV> struct P : Lv<LV> {
   static constexpr int W1B = N * W1BITS / 8;                         // packed w1 poly
   static constexpr int EB = N * EBITS / 8;                           // packed eta poly
   static constexpr int T1B = 320, T0B = 416;
+  static constexpr int TRB = B::MLDSA ? 64 : 32;                     // tr bytes
+  static constexpr int CT = B::CT;                                   // ctilde bytes
   static constexpr int PK = 32 + B::K * T1B;
-  static constexpr int SK = 96 + (B::L + B::K) * EB + B::K * T0B;
-  static constexpr int SIG = 32 + B::L * ZB + B::OMEGA + B::K;
-  static constexpr int OFF_S1 = 96, OFF_S2 = 96 + B::L * EB, OFF_T0 = 96 + (B::L + B::K) * EB;
-  static constexpr int OFF_Z = 32, OFF_H = 32 + B::L * ZB;
+  static constexpr int OFF_S1 = 64 + TRB;                            // sk = rho || K || tr || s1 || s2 || t0
+  static constexpr int OFF_S2 = OFF_S1 + B::L * EB, OFF_T0 = OFF_S1 + (B::L + B::K) * EB;
+  static constexpr int SK = OFF_T0 + B::K * T0B;
+  static constexpr int SIG = CT + B::L * ZB + B::OMEGA + B::K;       // sig = ctilde || z || h
+  static constexpr int OFF_Z = CT, OFF_H = CT + B::L * ZB;
   static constexpr int MUW1 = 64 + B::K * W1B;                       // mu || packed w1
 };
 static_assert(P<2>::PK == 1312 && P<2>::SK == 2528 && P<2>::SIG == 2420, "L2 sizes");
 static_assert(P<3>::PK == 1952 && P<3>::SK == 4000 && P<3>::SIG == 3293, "L3 sizes");
 static_assert(P<5>::PK == 2592 && P<5>::SK == 4864 && P<5>::SIG == 4595, "L5 sizes");
+static_assert(P<44>::PK == 1312 && P<44>::SK == 2560 && P<44>::SIG == 2420, "ML-DSA-44 sizes");
+static_assert(P<65>::PK == 1952 && P<65>::SK == 4032 && P<65>::SIG == 3309, "ML-DSA-65 sizes");
+static_assert(P<87>::PK == 2592 && P<87>::SK == 4896 && P<87>::SIG == 4627, "ML-DSA-87 sizes");
 
 // ---- device arithmetic ----
 // Montgomery reduction of a 64-bit value: returns a * 2^-32 mod q in (-q, q),

@@ -16,6 +16,7 @@
 // sequential chain of permutations is 1.5x shorter.  Both lanes of a pair must
 // be active together; different pairs may diverge.
 #pragma once
+#include "msg_words.h"
 #include "sponge.h"
 
 namespace dil {
@@ -94,80 +95,47 @@ __device__ __forceinline__ void shake256_absorb_pair(uint32_t a[25], int half, W
   }
 }
 
-// tr || M absorption, one SHAKE256 block at a time: PRE leading words of tr
-// (8 in the first block, 0 after), then message words from message byte m0 on.
-// A block's message part is fetched as the aligned dwords that cover it (NW + 1
-// for NW message words), with addresses clamped to M's last dword (no dword
-// outside [M's first, M's last] is read; none at all when M is empty).
-template <int NW>
-__device__ __forceinline__ void tr_msg_fetch(uint32_t D[NW + 1], const uint32_t *base, int64_t last, uint32_t sh,
-                                             int64_t m0) {
-  const int64_t d0 = (int64_t)((sh + (uint64_t)m0) >> 2);
-  // dwords from d0 on, clamped to the last one (a 32-bit offset from d0)
-  const int64_t span = last - d0;
-  const int dl = span < 0 ? 0 : span > NW ? NW : (int)span;
-  const uint32_t *b0 = base + (last >= 0 ? (d0 > last ? last : d0) : 0);
+// One SHAKE256 block of X = prefix || M on a pair (msg_words.h builds the
+// words): the first PRE words come from the prefix, the rest from the fetched
+// message dwords D; each lane absorbs its half of every 8-byte word.  All
+// indices are compile-time so the words stay in registers.
+template <int PB, int PRE>
+__device__ __forceinline__ void mw_mix(uint32_t a[25], int half, const uint32_t *pre, const uint32_t *D, uint32_t fs,
+                                       int r0, bool final_block) {
 #pragma unroll
-  for (int i = 0; i < NW + 1; i++) D[i] = last >= 0 ? b0[i < dl ? i : dl] : 0u;
-}
-// The fetched dwords are funnel-shifted by the byte misalignment sh, bytes past
-// the end of M masked, the padding added arithmetically, the lane's half of
-// each 8-byte word absorbed into the pair state and the block permuted.  Both
-// lanes of a pair build the whole block (their loads hit the same addresses).
-// All indices are compile-time so the words stay in registers.
-template <int PRE>
-__device__ __forceinline__ void tr_msg_mix(uint32_t a[25], int half, const uint32_t tr[8],
-                                           const uint32_t D[RATE256 / 4 - PRE + 1], uint32_t sh, int64_t m0,
-                                           uint64_t mlen, bool final_block) {
-  constexpr int WPB = RATE256 / 4;  // 34 words per block
-  // message bytes left at the block's first message word, clamped to a small
-  // range that keeps every per-word test below exact
-  const int64_t r64 = (int64_t)mlen - m0;
-  const int r0 = r64 < 0 ? -4 : r64 > 4 * WPB ? 4 * WPB + 4 : (int)r64;
-#pragma unroll
-  for (int j = 0; j < WPB; j++) {
-    uint32_t v;
-    if (j < PRE) {
-      v = tr[j];
-    } else {
-      const int k = j - PRE;
-      v = __builtin_amdgcn_alignbit(D[k + 1], D[k], 8 * sh);
-      const int rem = r0 - 4 * k;  // message bytes left from this word on
-      v = rem <= 0 ? 0u : rem < 4 ? v & ((1u << (8 * rem)) - 1u) : v;
-      if (rem >= 0 && rem < 4) v ^= 0x1Fu << (8 * rem);   // SHAKE suffix right after M
-    }
-    if (j == WPB - 1 && final_block) v ^= 0x80u << 24;    // final bit of the 10*1 padding
+  for (int j = 0; j < MW_WPB; j++) {
+    const uint32_t v = mw_word<PRE, PB % 4>(j, pre, D, fs, r0, final_block);
     a[j >> 1] ^= (j & 1) == half ? v : 0u;
   }
   keccak_f_pair(a, half);
 }
 
-// SHAKE256 absorption of tr || M, for mu = H(tr || M): tr is 32 bytes given as
-// eight little-endian words, M is mlen bytes at any alignment.  Lanes hash
-// messages of different lengths, so nothing per word depends on a branch.
-// Block b >= 1 carries message bytes from 136 b - 32 on, a multiple of 4, so
-// one funnel shift serves every block; the next block's dwords are requested
-// before the current block is permuted, so their latency overlaps it.  On
-// return the first output block is in the pairs' a[0 .. 17).
-__device__ __forceinline__ void absorb_tr_msg(uint32_t a[25], int half, const uint32_t tr[8], const uint8_t *msg,
-                                              uint64_t mlen) {
-  constexpr int WPB = RATE256 / 4;
+// SHAKE256 absorption of X = prefix || M for a message representative: the
+// prefix is tr (PB = 32, mu = H(tr || M)) or tr || 0x00 || 0x00 (PB = 66,
+// ML-DSA's mu with an empty context), given as PB / 4 little-endian words; M
+// is mlen bytes at any alignment.  Lanes hash messages of different lengths,
+// so nothing per word depends on a branch.  Both lanes of a pair build the
+// whole block (their loads hit the same addresses); the next block's dwords
+// are requested before the current block is permuted, so their latency
+// overlaps it.  On return the first output block is in the pairs' a[0 .. 17).
+template <int PB>
+__device__ __forceinline__ void absorb_prefix_msg(uint32_t a[25], int half, const uint32_t pre[PB / 4],
+                                                  const uint8_t *msg, uint64_t mlen) {
+  using Plan = MwPlan<PB>;
+  constexpr int PW = Plan::PW, DL = Plan::DL;
 #pragma unroll
   for (int i = 0; i < 25; i++) a[i] = 0;
-  const uint32_t sh = (uint32_t)((uintptr_t)msg & 3u);
-  const uint32_t *base = (const uint32_t *)(msg - sh);
-  const int64_t last = mlen ? (int64_t)((sh + mlen - 1) >> 2) : -1;  // last dword holding message bytes
-  const uint64_t nblk = (32 + mlen) / RATE256 + 1;
-  uint32_t D0[WPB - 8 + 1], Dn[WPB + 1];
-  tr_msg_fetch<WPB - 8>(D0, base, last, sh, 0);
-  if (nblk > 1) tr_msg_fetch<WPB>(Dn, base, last, sh, RATE256 - 32);
-  tr_msg_mix<8>(a, half, tr, D0, sh, 0, mlen, nblk == 1);
-  for (uint64_t b = 1; b < nblk; b++) {
-    uint32_t Dc[WPB + 1];
+  const Plan pl(msg, mlen);
+  uint32_t D0[MW_WPB - PW + 1], Dn[MW_WPB + 1];
+  mw_fetch<MW_WPB - PW, DL>(D0, pl.base, pl.last, pl.sh, Plan::m0(0));
+  if (pl.nblk > 1) mw_fetch<MW_WPB, DL>(Dn, pl.base, pl.last, pl.sh, Plan::m0(1));
+  mw_mix<PB, PW>(a, half, pre, D0, pl.fs, pl.r0(0), pl.nblk == 1);
+  for (uint64_t b = 1; b < pl.nblk; b++) {
+    uint32_t Dc[MW_WPB + 1];
 #pragma unroll
-    for (int i = 0; i < WPB + 1; i++) Dc[i] = Dn[i];
-    if (b + 1 < nblk) tr_msg_fetch<WPB>(Dn, base, last, sh, (int64_t)(b + 1) * RATE256 - 32);
-    tr_msg_mix<0>(a, half, tr, Dc, sh, (int64_t)b * RATE256 - 32, mlen, b == nblk - 1);
+    for (int i = 0; i < MW_WPB + 1; i++) Dc[i] = Dn[i];
+    if (b + 1 < pl.nblk) mw_fetch<MW_WPB, DL>(Dn, pl.base, pl.last, pl.sh, Plan::m0(b + 1));
+    mw_mix<PB, 0>(a, half, pre, Dc, pl.fs, pl.r0(b), b == pl.nblk - 1);
   }
 }
 
@@ -209,24 +177,27 @@ __device__ __forceinline__ void sample_in_ball_pair(uint32_t a[25], int half, in
 }
 
 // ctilde = H(mu || w1) and c = SampleInBall(ctilde) on a lane pair; mu and w1
-// rows 8-byte aligned.  ctilde_out: 8 words (both halves written).
+// rows 8-byte aligned.  ctilde is CT bytes (32 in round 3; lambda / 4 =
+// 32 / 48 / 64 for ML-DSA, whose SampleInBall absorbs all of it);
+// ctilde_out: CT / 4 words (both halves written).
 template <int LV>
 __device__ __forceinline__ void dev_challenge_pair(const uint8_t *mu, const uint8_t *w1, int half, uint32_t *ctilde_out,
                                                    int8_t *c, uint32_t *bw) {
+  constexpr int CW = P<LV>::CT / 8;  // 8-byte words of ctilde
   uint32_t a[25];
   shake256_absorb_pair<P<LV>::MUW1>(a, half, [&](int pos) {
     return pos < 64 ? *(const uint32_t *)(mu + pos + 4 * half) : *(const uint32_t *)(w1 + (pos - 64) + 4 * half);
   });
-  uint32_t ct[4];
+  uint32_t ct[CW];
 #pragma unroll
-  for (int w = 0; w < 4; w++) {
+  for (int w = 0; w < CW; w++) {
     ct[w] = a[w];
     ctilde_out[2 * w + half] = a[w];
   }
-  // SHAKE256(ctilde): 32 message bytes, then the padding
+  // SHAKE256(ctilde): CT message bytes, then the padding
 #pragma unroll
-  for (int i = 0; i < 25; i++) a[i] = i < 4 ? ct[i] : 0u;
-  if (!half) a[4] ^= 0x1Fu;
+  for (int i = 0; i < 25; i++) a[i] = i < CW ? ct[i] : 0u;
+  if (!half) a[CW] ^= 0x1Fu;
   else a[16] ^= 0x80u << 24;
   keccak_f_pair(a, half);
   sample_in_ball_pair<Lv<LV>::TAU>(a, half, c, bw);

@@ -20,7 +20,7 @@ namespace dil {
 struct Ws {
   uint8_t *muw1;     // [cap][MUW1 rounded to 256]
   uint8_t *rhop;     // [cap][64]   rho' (KeyGen: expanded secret seed; Sign: mask seed)
-  uint8_t *ctilde;   // [cap][32]
+  uint8_t *ctilde;   // [cap][CT_STRIDE]
   int8_t *cpoly;     // [cap][256]  challenge c, dense
   int32_t *A;        // [cap][K][L][256]  A-hat, canonical
   int32_t *s1h;      // [cap][L][256]  NTT(s1)   (KeyGen: s1, s2 centred, [cap][L+K][256])
@@ -39,8 +39,10 @@ struct Ws {
   // indexed by key row kmap[task] instead of by task.
   const uint32_t *kmap;
   const int32_t *t1h;   // [keys][K][256] NTT(t1 2^d), slots layout (verify), or null
-  const uint8_t *tr;    // [keys][32] tr = H(pk) (verify), or null
+  const uint8_t *tr;    // [keys][TRB] tr = H(pk) (verify), or null
 };
+
+constexpr int CT_STRIDE = 64;  // workspace row of a ctilde (the longest, ML-DSA-87's)
 
 // row of the per-key arrays used by task `task`
 __device__ __forceinline__ size_t kix(const Ws &ws, uint32_t task) { return ws.kmap ? ws.kmap[task] : task; }
@@ -76,14 +78,18 @@ __global__ void __launch_bounds__(256) keys_check_k(const uint32_t *key_idx, uin
 // ------------------------------------------------------------------------
 // KeyGen (Alg. 1)
 // ------------------------------------------------------------------------
-// (rho, rho', K) = H(zeta): rho -> pk and sk, K -> sk, rho' -> workspace
+// (rho, rho', K) = H(zeta): rho -> pk and sk, K -> sk, rho' -> workspace.
+// ML-DSA hashes xi || k || l (one byte each) instead of the bare seed.
 template <int LV>
 __global__ void __launch_bounds__(256) kg_seed_k(const uint8_t *seeds, uint8_t *pk, uint8_t *sk, Ws ws,
                                                  uint32_t count) {
   uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= count) return;
   uint32_t s[50];
-  shake_absorb<RATE256>(s, 32, SrcBytes{seeds + 32 * (size_t)t, 32});
+  const uint8_t *sd = seeds + 32 * (size_t)t;
+  shake_absorb<RATE256>(s, Lv<LV>::MLDSA ? 34 : 32, [&](uint64_t pos) -> uint64_t {
+    return pos < 32 ? load_le_bytes(sd + pos, 8) : (uint64_t)Lv<LV>::K | ((uint64_t)Lv<LV>::L << 8);
+  });
   uint64_t *pkw = (uint64_t *)(pk + (size_t)t * P<LV>::PK);
   uint64_t *skw = (uint64_t *)(sk + (size_t)t * P<LV>::SK);
   uint64_t *rw = (uint64_t *)(ws.rhop + (size_t)t * 64);
@@ -337,14 +343,14 @@ __global__ void __launch_bounds__(64) kg_main_k(Ws ws, uint8_t *pk, uint8_t *sk,
     pack16_to_lds<13>(v, skb + PP::OFF_T0 + i * PP::T0B, t);
   }
   wave_sync();
-  // copy the packed regions out (pk[32..PK), sk[96..SK)); rho, K, tr are written elsewhere
+  // copy the packed regions out (pk[32..PK), sk[OFF_S1..SK)); rho, K, tr are written elsewhere
   uint32_t *pkg = (uint32_t *)(pk + (size_t)task * PP::PK);
   for (int w = 8 + lane; w < PP::PK / 4; w += 64) pkg[w] = pkbuf[w];
   uint32_t *skg = (uint32_t *)(sk + (size_t)task * PP::SK);
-  for (int w = 24 + lane; w < PP::SK / 4; w += 64) skg[w] = lds.buf[w];
+  for (int w = PP::OFF_S1 / 4 + lane; w < PP::SK / 4; w += 64) skg[w] = lds.buf[w];
 }
 
-// tr = H(pk) into sk bytes 64..95
+// tr = H(pk) (TRB = 32 or 64 bytes) into sk bytes 64 .. 64 + TRB
 template <int LV>
 __global__ void __launch_bounds__(256) kg_tr_k(const uint8_t *pk, uint8_t *sk, uint32_t count) {
   uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -354,15 +360,19 @@ __global__ void __launch_bounds__(256) kg_tr_k(const uint8_t *pk, uint8_t *sk, u
   shake_absorb<RATE256>(s, P<LV>::PK, [&](uint64_t pos) { return *(const uint64_t *)(p + pos); });
   uint32_t *o = (uint32_t *)(sk + (size_t)t * P<LV>::SK + 64);
 #pragma unroll
-  for (int w = 0; w < 8; w++) o[w] = s[w];
+  for (int w = 0; w < P<LV>::TRB / 4; w++) o[w] = s[w];
 }
 
 // ------------------------------------------------------------------------
 // Sign (Alg. 2), staged
 // ------------------------------------------------------------------------
-// mu = H(tr || M), rho' = H(K || mu) on two lanes per task (keccak_pair.h);
-// initialises kappa and the active list.  rnd (randomized signing, 64 bytes
-// per task, 4-byte aligned) replaces H(K || mu) as rho' when it is not null.
+// mu and the mask seed on two lanes per task (keccak_pair.h); initialises
+// kappa and the active list.
+//   round 3: mu = H(tr || M); rho' = H(K || mu), or the task's 64 rnd bytes
+//            themselves (randomized signing) when rnd is not null;
+//   ML-DSA:  mu = H(tr || 0x00 || 0x00 || M); rho'' = H(K || rnd || mu) with
+//            the task's 32 rnd bytes, or 32 zero bytes when rnd is null.
+// rnd rows are 4-byte aligned.
 template <int LV>
 __global__ void __launch_bounds__(256) sg_prep_k(const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                                                  const uint64_t *msg_off, const uint8_t *rnd, Ws ws, uint32_t count,
@@ -380,12 +390,13 @@ __global__ void __launch_bounds__(256) sg_prep_k(const uint8_t *sk, const uint32
   uint64_t mlen = 0;
   if (o1 >= o0) mlen = o1 - o0;
   else if (!half) atomicOr(err, 1u);  // decreasing msg_off: message treated as empty
+  constexpr int TW = P<LV>::TRB / 4;
   uint32_t a[25];
-  uint32_t trw[8];
+  uint32_t trw[TW];
   const uint32_t *skw = (const uint32_t *)(skr + 64);  // tr inside the 8-byte aligned sk row
 #pragma unroll
-  for (int i = 0; i < 8; i++) trw[i] = skw[i];
-  absorb_tr_msg(a, half, trw, msg + o0, mlen);
+  for (int i = 0; i < TW; i++) trw[i] = skw[i];
+  absorb_prefix_msg<Lv<LV>::MLDSA ? 66 : 32>(a, half, trw, msg + o0, mlen);
   uint32_t mu[8];  // this lane's halves of mu's eight 8-byte words
   uint32_t *muw = (uint32_t *)(ws.muw1 + (size_t)t * muw1_stride<LV>());
 #pragma unroll
@@ -394,7 +405,18 @@ __global__ void __launch_bounds__(256) sg_prep_k(const uint8_t *sk, const uint32
     muw[2 * i + half] = a[i];
   }
   uint32_t *rp = (uint32_t *)(ws.rhop + (size_t)t * 64);
-  if (rnd) {
+  if constexpr (Lv<LV>::MLDSA) {
+    // rho'' = H(K || rnd || mu): 128 bytes, one block
+    const uint32_t *Kw = (const uint32_t *)(skr + 32);
+    const uint32_t *rw = rnd ? (const uint32_t *)(rnd + (size_t)t * 32) : nullptr;
+#pragma unroll
+    for (int i = 0; i < 25; i++)
+      a[i] = i < 4 ? Kw[2 * i + half] : i < 8 ? (rw ? rw[2 * (i - 4) + half] : 0u) : i < 16 ? mu[i - 8] : 0u;
+    a[16] ^= half ? 0x80u << 24 : 0x1Fu;
+    keccak_f_pair(a, half);
+#pragma unroll
+    for (int i = 0; i < 8; i++) rp[2 * i + half] = a[i];
+  } else if (rnd) {
     const uint32_t *rw = (const uint32_t *)(rnd + (size_t)t * 64);
 #pragma unroll
     for (int i = 0; i < 8; i++) rp[2 * i + half] = rw[2 * i + half];
@@ -427,9 +449,9 @@ __global__ void __launch_bounds__(64) sg_secret_k(const uint8_t *sk, const uint3
   int32_t *tr = lds.tr + g * NTT_LDS_GROUP;
   size_t key = key_idx ? key_idx[task] : task;
   const uint8_t *skr = sk + key * PP::SK;
-  // stage sk bytes 96..SK into LDS (sk rows are 8-byte aligned)
-  const uint32_t *skw = (const uint32_t *)(skr + 96);
-  constexpr int NW = (PP::SK - 96) / 4;
+  // stage sk bytes OFF_S1..SK into LDS (sk rows are 8-byte aligned)
+  const uint32_t *skw = (const uint32_t *)(skr + PP::OFF_S1);
+  constexpr int NW = (PP::SK - PP::OFF_S1) / 4;
   g2l_words<NW>(skw, lds.buf, lane);
   if (lane < 2) lds.buf[NW + lane] = 0;
   wave_sync();
@@ -549,24 +571,26 @@ __device__ __forceinline__ void sample_in_ball(uint32_t s[50], int8_t *c, uint8_
   }
 }
 
-// ctilde = H(mu || w1) (mu and packed w1 8-byte aligned); c = SampleInBall(ctilde) (one lane)
+// ctilde = H(mu || w1) of CT bytes (mu and packed w1 8-byte aligned);
+// c = SampleInBall(ctilde), seeded by all of ctilde (one lane)
 template <int LV>
 __device__ __forceinline__ void dev_challenge(const uint8_t *mu, const uint8_t *w1, uint32_t *ctilde_out, int8_t *c,
                                               uint8_t *blockbuf) {
+  constexpr int CW = P<LV>::CT / 4;
   uint32_t s[50];
   shake_absorb<RATE256>(s, P<LV>::MUW1, [&](uint64_t pos) {
     return pos < 64 ? *(const uint64_t *)(mu + pos) : *(const uint64_t *)(w1 + (pos - 64));
   });
-  uint32_t ct[8];
+  uint32_t ct[CW];
 #pragma unroll
-  for (int i = 0; i < 8; i++) {
+  for (int i = 0; i < CW; i++) {
     ct[i] = s[i];
     ctilde_out[i] = s[i];
   }
   keccak_zero(s);
 #pragma unroll
-  for (int i = 0; i < 8; i++) s[i] = ct[i];
-  s[8] = 0x1Fu;
+  for (int i = 0; i < CW; i++) s[i] = ct[i];
+  s[CW] = 0x1Fu;
   s[2 * (RATE256 / 8 - 1) + 1] ^= 0x80u << 24;
   keccak_f(s);
   sample_in_ball<Lv<LV>::TAU>(s, c, blockbuf);
@@ -667,7 +691,7 @@ __device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctild
   for (int i = 0; i < K; i++) total += lds.rowcnt[i];
   if (total > OMEGA) return false;
   // accepted: ctilde and the hint bytes
-  if (lane < 8) lds.sigbuf[lane] = ctilde[lane];
+  if (lane < PP::CT / 4) lds.sigbuf[lane] = ctilde[lane];
   for (int b = lane; b < OMEGA + K; b += 64) sb[PP::OFF_H + b] = 0;
   wave_sync();
   for (int i = g; i < K; i += 4) {
@@ -734,7 +758,7 @@ __global__ void __launch_bounds__(64) sg_chal_k(Ws ws, const uint32_t *active, u
   uint32_t task = active[a];
   int8_t *c = cl[threadIdx.x];
   const uint8_t *row = ws.muw1 + (size_t)task * muw1_stride<LV>();
-  dev_challenge<LV>(row, row + 64, (uint32_t *)(ws.ctilde + (size_t)task * 32), c, (uint8_t *)bb[threadIdx.x]);
+  dev_challenge<LV>(row, row + 64, (uint32_t *)(ws.ctilde + (size_t)task * CT_STRIDE), c, (uint8_t *)bb[threadIdx.x]);
   store_c_row(c, ws.cpoly + (size_t)task * N);
 }
 
@@ -748,7 +772,7 @@ __global__ void __launch_bounds__(64) sg_check_k(Ws ws, uint8_t *sig, const uint
   uint32_t task = active[blockIdx.x];
   int lane = threadIdx.x, t = lane & 15;
   const Tw ftw = ntt_lane_tw(t), itw = intt_lane_tw(t);
-  bool ok = dev_check<LV>(ws.cpoly + (size_t)task * N, (const uint32_t *)(ws.ctilde + (size_t)task * 32),
+  bool ok = dev_check<LV>(ws.cpoly + (size_t)task * N, (const uint32_t *)(ws.ctilde + (size_t)task * CT_STRIDE),
                           ws.y + (size_t)task * L * N, ws.w + (size_t)task * K * N, ws.s1h + kix(ws, task) * L * N,
                           ws.s2h + kix(ws, task) * K * N, ws.t0h + kix(ws, task) * K * N, lds, ftw, itw, lane);
   if (ok) {
@@ -763,8 +787,8 @@ __global__ void __launch_bounds__(64) sg_check_k(Ws ws, uint8_t *sig, const uint
 // ------------------------------------------------------------------------
 // Verify (Alg. 3), staged
 // ------------------------------------------------------------------------
-// tr = H(pk) (unless resident) and mu = H(tr || M), two lanes per task
-// (keccak_pair.h)
+// tr = H(pk) (unless resident) and mu = H(tr || M) (ML-DSA: H(tr || 0x00 ||
+// 0x00 || M)), two lanes per task (keccak_pair.h)
 template <int LV>
 __global__ void __launch_bounds__(64) vf_hash_k(const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
                                                 const uint64_t *msg_off, Ws ws, uint32_t count, uint32_t *err) {
@@ -774,18 +798,19 @@ __global__ void __launch_bounds__(64) vf_hash_k(const uint8_t *pk, const uint32_
   const int half = threadIdx.x & 1;
   if (t >= count) return;  // both lanes of a pair
   size_t key = key_idx ? key_idx[t] : t;
+  constexpr int TW = PP::TRB / 4;
   uint32_t a[25];
-  uint32_t trw[8];
+  uint32_t trw[TW];
   if (ws.tr) {
-    const uint32_t *tg = (const uint32_t *)(ws.tr + key * 32);
+    const uint32_t *tg = (const uint32_t *)(ws.tr + key * PP::TRB);
 #pragma unroll
-    for (int i = 0; i < 8; i++) trw[i] = tg[i];
+    for (int i = 0; i < TW; i++) trw[i] = tg[i];
   } else {
     const uint32_t *pkr = (const uint32_t *)(pk + key * PP::PK);
     shake256_absorb_pair<PP::PK>(a, half, [&](int pos) { return pkr[pos / 4 + half]; });
     // both lanes need all of tr: the partner's halves come over the DPP swap
 #pragma unroll
-    for (int i = 0; i < 4; i++) {
+    for (int i = 0; i < TW / 2; i++) {
       const uint32_t other = pair_swap(a[i]);
       trw[2 * i] = half ? other : a[i];
       trw[2 * i + 1] = half ? a[i] : other;
@@ -795,7 +820,7 @@ __global__ void __launch_bounds__(64) vf_hash_k(const uint8_t *pk, const uint32_
   uint64_t mlen = 0;
   if (o1 >= o0) mlen = o1 - o0;
   else if (!half) atomicOr(err, 1u);  // decreasing msg_off: message treated as empty
-  absorb_tr_msg(a, half, trw, msg + o0, mlen);
+  absorb_prefix_msg<Lv<LV>::MLDSA ? 66 : 32>(a, half, trw, msg + o0, mlen);
   uint32_t *muw = (uint32_t *)(ws.muw1 + (size_t)t * muw1_stride<LV>());
 #pragma unroll
   for (int i = 0; i < 8; i++) muw[2 * i + half] = a[i];
@@ -820,15 +845,15 @@ __global__ void __launch_bounds__(64) vf_prep_k(const uint8_t *sig, Ws ws, uint3
 #pragma unroll
   for (int j = 0; j < HB; j++) hb[j] = sg[PP::OFF_H + j];
   uint32_t s[50];
-  // SampleInBall(ctilde)
+  // SampleInBall(ctilde), all CT bytes of it
   keccak_zero(s);
 #pragma unroll
-  for (int w = 0; w < 4; w++) {
+  for (int w = 0; w < PP::CT / 8; w++) {
     uint64_t v = load_le_bytes(sg + 8 * w, 8);
     s[2 * w] = (uint32_t)v;
     s[2 * w + 1] = (uint32_t)(v >> 32);
   }
-  s[8] = 0x1Fu;
+  s[PP::CT / 4] = 0x1Fu;
   s[2 * (RATE256 / 8 - 1) + 1] ^= 0x80u << 24;
   keccak_f(s);
   int8_t *c = cl[threadIdx.x];
@@ -992,7 +1017,7 @@ __global__ void __launch_bounds__(256) vf_final_k(const uint8_t *sig, Ws ws, int
   const uint8_t *sg = sig + (size_t)t * P<LV>::SIG;
   uint32_t diff = 0;
 #pragma unroll
-  for (int w = 0; w < 4; w++) diff |= (uint32_t)load_le_bytes(sg + 8 * w + 4 * half, 4) ^ a[w];
+  for (int w = 0; w < P<LV>::CT / 8; w++) diff |= (uint32_t)load_le_bytes(sg + 8 * w + 4 * half, 4) ^ a[w];
   diff |= pair_swap(diff);
   if (!half) verdict[t] = (ws.flag[t] && diff == 0) ? 1 : 0;
 }
@@ -1033,9 +1058,9 @@ __global__ void __launch_bounds__(256) ks_tr_k(const uint8_t *pk, uint8_t *tr, u
   const uint8_t *p = pk + (size_t)key * P<LV>::PK;
   uint32_t s[50];
   shake_absorb<RATE256>(s, P<LV>::PK, [&](uint64_t pos) { return *(const uint64_t *)(p + pos); });
-  uint32_t *o = (uint32_t *)(tr + (size_t)key * 32);
+  uint32_t *o = (uint32_t *)(tr + (size_t)key * P<LV>::TRB);
 #pragma unroll
-  for (int w = 0; w < 8; w++) o[w] = s[w];
+  for (int w = 0; w < P<LV>::TRB / 4; w++) o[w] = s[w];
 }
 
 // ------------------------------------------------------------------------

@@ -117,7 +117,7 @@ struct PersistLds {
     CheckLds<LV> ck;
   } u;
   int8_t c[PCfg<LV>::G][C_ROW];
-  uint32_t ct[PCfg<LV>::G][8];
+  uint32_t ct[PCfg<LV>::G][P<LV>::CT / 4];
   uint32_t bb[PCfg<LV>::G][RATE256 / 4];
   uint32_t h_task[PCfg<LV>::G], h_next[PCfg<LV>::G], h_win[PCfg<LV>::G];
   uint32_t s_att[PCfg<LV>::G];
@@ -256,7 +256,7 @@ struct PersistWLds {
     CheckLds<LV> ck;
   } u[NW];
   int8_t c[PCfgW<LV, NW>::G][C_ROW];
-  uint32_t ct[PCfgW<LV, NW>::G][8];
+  uint32_t ct[PCfgW<LV, NW>::G][P<LV>::CT / 4];
   uint32_t bb[PCfgW<LV, NW>::G][RATE256 / 4];
   uint32_t h_task[PCfgW<LV, NW>::G], h_next[PCfgW<LV, NW>::G], h_win[PCfgW<LV, NW>::G];
   uint32_t s_att[PCfgW<LV, NW>::G];
@@ -270,7 +270,8 @@ struct PersistWLds {
 };
 // two workgroups of the four-wavefront shape per CU (160 KiB of LDS)
 static_assert(2 * sizeof(PersistWLds<2, 4>) <= 160 * 1024 && 2 * sizeof(PersistWLds<3, 4>) <= 160 * 1024 &&
-                  2 * sizeof(PersistWLds<5, 4>) <= 160 * 1024,
+                  2 * sizeof(PersistWLds<5, 4>) <= 160 * 1024 && 2 * sizeof(PersistWLds<44, 4>) <= 160 * 1024 &&
+                  2 * sizeof(PersistWLds<65, 4>) <= 160 * 1024 && 2 * sizeof(PersistWLds<87, 4>) <= 160 * 1024,
               "four-wavefront loop workgroups must fit two per CU");
 
 // Copy an NB-byte signature from a 4-byte aligned global row to a destination

@@ -99,6 +99,10 @@ def load() -> ctypes.CDLL:
     return L
 
 
+ROUND3_LEVELS = (2, 3, 5)
+MLDSA_LEVELS = (44, 65, 87)  # ML-DSA-44 / 65 / 87 (FIPS 204)
+
+
 def sizes(level: int) -> Tuple[int, int, int]:
     pk, sk, sg = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
     rc = load().dil_sizes(level, ctypes.byref(pk), ctypes.byref(sk), ctypes.byref(sg))
@@ -193,7 +197,8 @@ class Context:
         self._check(self.lib.dil_keygen_batch(self.h, level, _ptr(seeds), _ptr(pk), _ptr(sk), n, _stream(stream)))
 
     def sign(self, level: int, sk, msg, msg_off, sig, key_idx=None, stream=None, rnd=None):
-        """rnd: optional uint8 device tensor [count, 64], the rho' of each task (randomized signing)."""
+        """rnd: optional uint8 device tensor for randomized (hedged) signing: [count, 64], the rho' of each
+        task (levels 2 / 3 / 5), or [count, 32], the rnd that rho'' hashes (ML-DSA levels 44 / 65 / 87)."""
         n = msg_off.shape[0] - 1
         _, skl, sgl = sizes(level)
         _require([(msg_off, 8 * (n + 1), 8, "msg_off"), (sig, sgl * n, 1, "sig"),
@@ -202,8 +207,9 @@ class Context:
             self._check(self.lib.dil_sign_batch(self.h, level, _ptr(sk), _ptr(key_idx), _ptr(msg) or _ptr(msg_off),
                                                 _ptr(msg_off), _ptr(sig), n, _stream(stream)))
         else:
-            if tuple(rnd.shape) != (n, 64):
-                raise ValueError("rnd must be [count, 64] bytes")
+            rb = 32 if level in MLDSA_LEVELS else 64
+            if tuple(rnd.shape) != (n, rb):
+                raise ValueError(f"rnd must be [count, {rb}] bytes")
             self._check(self.lib.dil_sign_batch_rnd(self.h, level, _ptr(sk), _ptr(key_idx),
                                                     _ptr(msg) or _ptr(msg_off), _ptr(msg_off), _ptr(rnd), _ptr(sig),
                                                     n, _stream(stream)))
