@@ -8,7 +8,7 @@ Prints ONE JSON line (rank 0) with the roofline of the Sign loop kernel
 chip's 32-bit integer issue rate) and the CPU oracle's rate on the same batch.
 
   python bench.py [--steps K] [--warmup W] [--mode persistent|staged]
-                  [--count N] [--level 2|3|5] [--no-cpu-baseline]
+                  [--count N] [--level 2|3|5|44|65|87] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -34,14 +34,24 @@ sys.path.insert(0, ROOT)
 # pointwise products per Sign iteration and per fixed part of each operation:
 PERM_OPS, XFORM_OPS, PW_OPS = 7440, 7168, 1536
 PER_LEVEL = {
-    # level: (k, l)
-    2: (4, 4), 3: (6, 5), 5: (8, 7),
+    # level: (k, l); ML-DSA-44 / 65 / 87 share the lattice parameters of levels 2 / 3 / 5
+    2: (4, 4), 3: (6, 5), 5: (8, 7), 44: (4, 4), 65: (6, 5), 87: (8, 7),
 }
+MLDSA_BASE = {44: 2, 65: 3, 87: 5}
 # SHAKE blocks: rate 136 (SHAKE256), 168 (SHAKE128)
-W1_BYTES = {2: 4 * 192, 3: 6 * 128, 5: 8 * 128}
-PK_BYTES = {2: 1312, 3: 1952, 5: 2592}
-SK_BYTES = {2: 2528, 3: 4000, 5: 4864}
-SIG_BYTES = {2: 2420, 3: 3293, 5: 4595}
+W1_BYTES = {2: 4 * 192, 3: 6 * 128, 5: 8 * 128, 44: 4 * 192, 65: 6 * 128, 87: 8 * 128}
+PK_BYTES = {2: 1312, 3: 1952, 5: 2592, 44: 1312, 65: 1952, 87: 2592}
+SK_BYTES = {2: 2528, 3: 4000, 5: 4864, 44: 2560, 65: 4032, 87: 4896}
+SIG_BYTES = {2: 2420, 3: 3293, 5: 4595, 44: 2420, 65: 3309, 87: 4627}
+
+
+def level_name(level: int) -> str:
+    return f"ML-DSA-{level}" if level in MLDSA_BASE else f"Dilithium{level}"
+
+
+def mu_prefix(level: int) -> int:
+    """bytes hashed before the message for mu: tr (32), or ML-DSA's tr || 0x00 || 0x00 (66)"""
+    return 66 if level in MLDSA_BASE else 32
 # 256 CUs x 4 SIMDs x 32 lanes of simple 32-bit integer ops per clock x 2.4 GHz
 PEAK_INT32_OPS = 256 * 4 * 32 * 2.4e9   # 78.6 T int32 lane-ops/s
 
@@ -84,7 +94,8 @@ def perms_shake(inlen: int, outlen: int, rate: int) -> int:
 def sign_iteration_ops(level: int) -> float:
     """Algorithmic int32 ops of one Sign loop iteration (Alg. 2 loop body)."""
     k, l = PER_LEVEL[level]
-    it_perms = l * perms_shake(66, 576 if level == 2 else 640, 136) + perms_shake(64 + W1_BYTES[level], 32, 136) + 1
+    gamma1_17 = MLDSA_BASE.get(level, level) == 2
+    it_perms = l * perms_shake(66, 576 if gamma1_17 else 640, 136) + perms_shake(64 + W1_BYTES[level], 32, 136) + 1
     it_x = l + k + 1 + l + 2 * k          # NTT(y), INTT(w), NTT(c), INTT(c s1), INTT(c s2), INTT(c t0)
     it_pw = k * l + l + 2 * k             # A y, c s1, c s2, c t0
     return it_perms * PERM_OPS + it_x * XFORM_OPS + it_pw * PW_OPS
@@ -93,8 +104,8 @@ def sign_iteration_ops(level: int) -> float:
 def sign_setup_ops(level: int, msg_lens: np.ndarray) -> float:
     """Algorithmic int32 ops of the per-task part before the loop (mu, rho', ExpandA, NTT of s1, s2, t0)."""
     k, l = PER_LEVEL[level]
-    perms = sum(perms_shake(32 + int(m), 64, 136) for m in msg_lens)
-    perms += len(msg_lens) * (perms_shake(96, 64, 136) + k * l * 5)
+    perms = sum(perms_shake(mu_prefix(level) + int(m), 64, 136) for m in msg_lens)
+    perms += len(msg_lens) * (perms_shake(128 if level in MLDSA_BASE else 96, 64, 136) + k * l * 5)
     return perms * PERM_OPS + len(msg_lens) * (l + 2 * k) * XFORM_OPS
 
 
@@ -107,7 +118,7 @@ def verify_work(level: int, msg_lens: np.ndarray) -> float:
     k, l = PER_LEVEL[level]
     n = len(msg_lens)
     perms = n * (perms_shake(PK_BYTES[level], 32, 136) + k * l * 5 + 1 + perms_shake(64 + W1_BYTES[level], 32, 136))
-    perms += sum(perms_shake(32 + int(m), 64, 136) for m in msg_lens)
+    perms += sum(perms_shake(mu_prefix(level) + int(m), 64, 136) for m in msg_lens)
     xf = n * (l + k + 1 + k)
     pw = n * (k * l + k)
     return perms * PERM_OPS + xf * XFORM_OPS + pw * PW_OPS
@@ -155,7 +166,7 @@ def cpu_baseline(level: int, seeds, msg, off, msg_desc: str, gpu_sig, min_second
     return {"value": n / (sign_s + ver_s), "unit": "sign+verify pairs/s", "cores": threads, "kind": "oracle",
             "sign_per_s": n / sign_s, "verify_per_s": n / ver_s, "repetitions": len(sign_t), "wall_s": wall,
             "timed_batch_parity": parity, "single_thread": single_thread,
-            "sample": f"the benchmark's whole batch ({n} Dilithium{level} sign + {n} verify, {msg_desc}, the same "
+            "sample": f"the benchmark's whole batch ({n} {level_name(level)} sign + {n} verify, {msg_desc}, the same "
                       f"keys and messages as the GPU run), repeated {len(sign_t)} times ({wall:.1f} s wall, median "
                       f"repetition); plain C oracle on {threads} host threads"}
 
@@ -594,7 +605,7 @@ def e2e_run(level: int, n: int, msg_dist: str, stream_counts, chunks_per_stream=
         p.close()
     ctx.close()
     best = max(rows, key=lambda r: r["sign_per_s"] * r["verify_per_s"] / (r["sign_per_s"] + r["verify_per_s"]))
-    return {"what": f"Dilithium{level} batch {n}, host-resident pinned buffers, H2D + kernels + D2H per call, "
+    return {"what": f"{level_name(level)} batch {n}, host-resident pinned buffers, H2D + kernels + D2H per call, "
                     f"chunked over HIP streams, and {B} whole batches per call over HIP streams "
                     f"(rows with 'batches'; median of {reps})", "rows": rows, "best": best}
 
@@ -605,7 +616,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--count", type=int, default=10000)
-    ap.add_argument("--level", type=int, default=2, choices=[2, 3, 5])
+    ap.add_argument("--level", type=int, default=2, choices=[2, 3, 5, 44, 65, 87],
+                    help="round-3 level 2 / 3 / 5, or ML-DSA-44 / 65 / 87 (FIPS 204 form)")
     ap.add_argument("--mode", default="persistent", choices=["persistent", "staged"])
     ap.add_argument("--msg-dist", default="fixed32", choices=["fixed32", "uniform"],
                     help="32-byte messages, or lengths uniform on [32, 4096] (the level-3/5 configuration)")
@@ -730,9 +742,10 @@ def main():
         args.schedule = f"{cached['waves']},{cached['hmax']},{cached['grid']}"
         schedule_src = "autotuner (recorded)"
     elif args.mode == "persistent" and not args.no_tune:
+        # the ML-DSA levels are built in the four-wavefront shape only
         tuning = autotune.tune_sign(ctx, level, lambda: ctx.sign(level, sk, g_msg, g_off, sig), count=n,
                                     reps=args.tune_reps, rounds=args.tune_rounds,
-                                    waves=(args.waves,) if args.waves else (1, 2, 4))
+                                    waves=(args.waves,) if args.waves else (4,) if level in MLDSA_BASE else (1, 2, 4))
         schedule_src = "autotuner (this run)"
         if args.record_schedule:
             autotune.store_schedule(level, n, args.msg_dist, tuning["best"], args.record_schedule)
@@ -791,7 +804,7 @@ def main():
         "unit": "sign+verify pairs/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-        "config": {"workload": f"Dilithium{level} batch {n} sign + {n} verify, {msg_desc}, "
+        "config": {"workload": f"{level_name(level)} batch {n} sign + {n} verify, {msg_desc}, "
                                f"one key per task, device-resident buffers", "level": level, "batch": n,
                    "msg_len": 32 if args.msg_dist == "fixed32" else "uniform[32,4096]",
                    "sign_mode": args.mode, "hipgraph": bool(args.graph),

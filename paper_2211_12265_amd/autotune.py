@@ -60,7 +60,7 @@ def apply_schedule(ctx, sched: Dict) -> None:
 
 
 def slots_per_batch(level: int, waves: int = 1) -> int:
-    return waves * (64 // {2: 4, 3: 5, 5: 7}[level])
+    return waves * (64 // {2: 4, 3: 5, 5: 7, 44: 4, 65: 5, 87: 7}[level])
 
 
 def candidates(level: int, count: int, resident_groups: int, waves: int = 1) -> List[tuple]:

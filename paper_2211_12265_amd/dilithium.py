@@ -256,7 +256,9 @@ class Context:
     def t0_ntt(self, level: int, sk, t0_hat, stream=None):
         """t0_hat[n][k][256] = NTT(t0) of each secret key row, reduced to [0, q) (form per "t0.variant")."""
         n = sk.shape[0]
-        k = {2: 4, 3: 6, 5: 8}[level]
+        k = {2: 4, 3: 6, 5: 8}.get(level)
+        if k is None:
+            raise ValueError("dil_t0_ntt_batch takes the round-3 levels 2, 3 and 5")
         _require([(sk, sizes(level)[1] * n, 1, "sk"), (t0_hat, 4 * k * 256 * n, 4, "t0_hat")])
         self._check(self.lib.dil_t0_ntt_batch(self.h, level, _ptr(sk), _ptr(t0_hat), n, _stream(stream)))
 
