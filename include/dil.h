@@ -119,6 +119,15 @@ int dil_ctx_set_mode(dil_ctx *ctx, int mode);
  *                   same unpadded, 2 one fused kernel that stores t0 in HBM
  *                   and reads it back, 3 an unpacking kernel then an NTT
  *                   kernel through HBM; other values are DIL_EINVAL;
+ *   "persist.tail"  slots per held task in the batches of a four-wavefront
+ *                   workgroup once the work queue has run dry (rounded up to a
+ *                   multiple of 4, at most the batch's slots): shorter last
+ *                   batches, fewer speculative candidates; -1 (default) the
+ *                   level's setting (20 at levels 2 / 44, 12 at 3 / 65, full
+ *                   batches at 5 / 87), 0 full batches, 1..64 that many; a
+ *                   value above 0 with another "persist.waves" or
+ *                   "persist.pad" = 0 fails the Sign call with DIL_EINVAL;
+ *                   the signatures do not depend on it;
  *   "persist.pad"   1 (default) or 0: 0 runs the four-wavefront Sign loop
  *                   kernel with every NTT / INTT transpose on the unpadded
  *                   (bank-conflicted) LDS layout, the padding step of the same

@@ -34,6 +34,8 @@ struct dil_ctx {
   hipStream_t last_stream = nullptr;
   int stats_pending = 0;
   int64_t persist_grid = 0, persist_hmax = 0;  // 0 = automatic
+  int persist_tail = -1;                       // slots per held task once the work queue is empty
+                                               // (0 = all G; -1 = the level's default, PCfgW::TAIL_AUTO)
   int persist_waves = 4;                       // wavefronts per persistent workgroup: 1, 2 or 4
   int timing = 0;                              // record HIP events around the persistent Sign phases
   int ntt_variant = 0;                         // form of dil_ntt_mul_batch (0 = production kernel)
@@ -456,6 +458,10 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   // the one- and two-wavefront shapes and the unpadded ablation form are built for the round-3 levels only
   if (Lv<LV>::MLDSA && (waves != 4 || !ctx->persist_pad))
     return fail(ctx, DIL_EINVAL, "ML-DSA levels run the four-wavefront padded loop kernel (persist.waves = 4, persist.pad = 1)");
+  if (ctx->persist_tail > 0 && (waves != 4 || !ctx->persist_pad))
+    return fail(ctx, DIL_EINVAL, "persist.tail > 0 exists for the four-wavefront padded loop kernel only");
+  const int tail_slots = ctx->persist_tail >= 0 ? ctx->persist_tail
+                         : (waves == 4 && ctx->persist_pad) ? PCfgW<LV, 4>::TAIL_AUTO : 0;
   uint64_t grid = 1, hmax = 1;
   int rc = persist_schedule<LV>(ctx, count, &grid, &hmax);
   if (rc) return rc;
@@ -483,15 +489,20 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   if (evs) HIPCHK(ctx, hipEventRecord(evs[1], st));
   // The loop kernel is one launch: it is launched directly, also when graphs
   // are enabled (as a graph node it measured 2-4% slower).
+  const bool tail = tail_slots > 0;
+  const uint32_t sched = (uint32_t)hmax | (uint32_t)tail_slots << 8;  // hmax <= G <= 64, tail <= 64
   if constexpr (Lv<LV>::MLDSA) {
-    sg_persistw_k<LV, 4><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+    if (tail) sg_persistw_k<LV, 4, true, true><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, sched, ctx->dev_stats);
+    else sg_persistw_k<LV, 4><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, sched, ctx->dev_stats);
   } else {
     if (waves == 4 && !ctx->persist_pad)
-      sg_persistw_k<LV, 4, false><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+      sg_persistw_k<LV, 4, false><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, sched, ctx->dev_stats);
+    else if (waves == 4 && tail)
+      sg_persistw_k<LV, 4, true, true><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, sched, ctx->dev_stats);
     else if (waves == 4)
-      sg_persistw_k<LV, 4><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+      sg_persistw_k<LV, 4><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, sched, ctx->dev_stats);
     else if (waves == 2)
-      sg_persistw_k<LV, 2><<<(unsigned)grid, 128, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
+      sg_persistw_k<LV, 2><<<(unsigned)grid, 128, 0, st>>>(ws, sc, sig, count, sched, ctx->dev_stats);
     else
       sg_persist_k<LV><<<(unsigned)grid, 64, 0, st>>>(ws, sc, sig, count, (uint32_t)hmax, ctx->dev_stats);
   }
@@ -762,6 +773,10 @@ int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value) {
     if (!ctx->use_graph) drop_graphs(ctx);
   } else if (!strcmp(name, "persist.grid")) ctx->persist_grid = value;
   else if (!strcmp(name, "persist.hmax")) ctx->persist_hmax = value;
+  else if (!strcmp(name, "persist.tail")) {
+    if (value < -1 || value > 64) return fail(ctx, DIL_EINVAL, "persist.tail must be -1..64");
+    ctx->persist_tail = (int)value;
+  }
   else if (!strcmp(name, "persist.waves")) {
     if (value != 1 && value != 2 && value != 4) return fail(ctx, DIL_EINVAL, "persist.waves must be 1, 2 or 4");
     ctx->persist_waves = (int)value;

@@ -40,13 +40,26 @@ DIL_HD int sched_claim(uint32_t base, uint32_t count, uint32_t want, int nh, uin
   return nh;
 }
 
-// Lay out one batch of G slots over the nh held tasks: slot s evaluates held
-// task s mod nh at that task's nonce index h_next + s / nh (running counters,
-// no division per slot); every task's h_next then moves past the indices
-// handed out and its h_win is cleared.  Returns the number of slots in use
-// (G, or 0 when nothing is held).
-DIL_HD int sched_assign(int nh, int G, uint32_t *h_next, uint32_t *h_win, uint8_t *s_h, uint32_t *s_att) {
-  const int ns = nh ? G : 0;
+// Slots of the next batch: all G while the work queue can still refill the
+// workgroup.  Once it has run dry (the tail of the launch) and `tail` > 0, only
+// tail slots per held task, rounded up to a multiple of the W wavefronts and
+// at most G: the batch's w and check phases, which each wavefront runs slot by
+// slot, shorten with it, and the last tasks of a launch do not hold their
+// workgroup for full batches of speculative nonces.  0 when nothing is held.
+DIL_HD int sched_slots(int nh, int G, int W, int queue_empty, int tail) {
+  if (nh <= 0) return 0;
+  if (!queue_empty || tail <= 0) return G;
+  const int ns = (nh * tail + W - 1) / W * W;
+  return ns < G ? ns : G;
+}
+
+// Lay out one batch of ns slots (ns <= G; ns >= nh unless ns = 0) over the nh
+// held tasks: slot s evaluates held task s mod nh at that task's nonce index
+// h_next + s / nh (running counters, no division per slot); every task's
+// h_next then moves past the indices handed out and its h_win is cleared.
+// Returns ns (0 when nothing is held).
+DIL_HD int sched_assign(int nh, int ns, uint32_t *h_next, uint32_t *h_win, uint8_t *s_h, uint32_t *s_att) {
+  if (!nh) ns = 0;
   int h = 0;
   uint32_t j = 0;
   for (int s = 0; s < ns; s++) {

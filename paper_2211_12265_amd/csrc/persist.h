@@ -133,7 +133,7 @@ struct PersistLds {
 // ws.counters[0] is the work queue (next task to claim).  stats (32-bit words,
 // zeroed by the host): [2..3] candidates evaluated (u64), [5] tasks dropped at
 // MAX_ATTEMPTS, [6..7] sequential iterations = sum over tasks of (winning
-// index + 1) (u64)
+// index + 1) (u64).  hmax: tasks a workgroup holds at a time (1..G).
 template <int LV>
 __global__ void __launch_bounds__(64) sg_persist_k(Ws ws, PScr sc, uint8_t *sig, uint32_t count, uint32_t hmax,
                                                    uint32_t *stats) {
@@ -243,6 +243,11 @@ struct PCfgW {
   static constexpr int W = NW;
   static constexpr int GW = 64 / Lv<LV>::L;  // slots per wave
   static constexpr int G = W * GW;           // 4 waves: 64 / 48 / 36
+  // default tail slots per held task (sched_slots) of the four-wavefront
+  // kernel, from interleaved runs at 10,000 tasks: 20 at l = 4 and 12 at l = 5
+  // (4% shorter loop kernel than full batches); 0 at l = 7, where the tail
+  // kernel's registers no longer fit two wavefronts per SIMD
+  static constexpr int TAIL_AUTO = Lv<LV>::L == 4 ? 20 : Lv<LV>::L == 5 ? 12 : 0;
 };
 
 template <int LV, int NW>
@@ -308,9 +313,14 @@ __device__ __forceinline__ void copy_sig_row(const uint32_t *src, uint8_t *dst, 
 
 // PAD = false runs every NTT / INTT transpose of the kernel on the unpadded
 // (bank-conflicted) LDS layout: the padding step of the optimisation ablation.
-template <int LV, int NW, bool PAD = true>
+// sched = hmax | tail << 8: hmax (1..G) tasks a workgroup holds at a time;
+// with TAIL, tail slots per held task once the queue has run dry
+// (sched_slots), else full batches of G slots (tail is then 0).  TAIL is a
+// template switch so that the full-batch kernel keeps its register
+// allocation (two wavefronts per SIMD with no spills at every level).
+template <int LV, int NW, bool PAD = true, bool TAIL = false>
 __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t *sig, uint32_t count,
-                                                     uint32_t hmax, uint32_t *stats) {
+                                                     uint32_t sched, uint32_t *stats) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfgW<LV, NW>::G, W = NW;
   static_assert(G <= 64, "the winner search takes one slot per lane");
   __shared__ PersistWLds<LV, NW> lds;
@@ -335,10 +345,12 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
   for (uint32_t batch = 0;; batch++) {
     if (tid == 0) {
       int nh = lds.nheld;
-      if (!lds.queue_empty && nh < (int)hmax) nh = claim_tasks(ws.counters, count, hmax - nh, nh, lds.h_task,
-                                                               lds.h_next, lds.queue_empty);
+      const int hmax = (int)(sched & 0xFFu), tail = (int)(sched >> 8);
+      if (!lds.queue_empty && nh < hmax) nh = claim_tasks(ws.counters, count, (uint32_t)(hmax - nh), nh, lds.h_task,
+                                                          lds.h_next, lds.queue_empty);
       lds.nheld = nh;
-      const int ns = sched_assign(nh, G, lds.h_next, lds.h_win, lds.s_h, lds.s_att);
+      const int ns = sched_assign(nh, TAIL ? sched_slots(nh, G, W, lds.queue_empty, tail) : G, lds.h_next,
+                                  lds.h_win, lds.s_h, lds.s_att);
       lds.nslots = ns;
       lds.tally.evaluated += (uint64_t)ns;
     }

@@ -18,7 +18,10 @@
 // (or dropped at the attempt limit), and the evaluated / sequential counts
 // match.
 //
-// usage: sched_replay G L K count grid hmax p max_attempts seed
+// Batches of a workgroup whose queue has run dry take sched_slots' tail
+// slots per held task (tail = 0: all G), as the kernels do.
+//
+// usage: sched_replay G L K count grid hmax p max_attempts seed W tail
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -57,8 +60,8 @@ struct Wg {
 };
 
 int main(int argc, char **argv) {
-  if (argc != 10) {
-    fprintf(stderr, "usage: %s G L K count grid hmax p max_attempts seed\n", argv[0]);
+  if (argc != 12) {
+    fprintf(stderr, "usage: %s G L K count grid hmax p max_attempts seed W tail\n", argv[0]);
     return 2;
   }
   const int G = atoi(argv[1]), L = atoi(argv[2]), K = atoi(argv[3]);
@@ -68,7 +71,9 @@ int main(int argc, char **argv) {
   const double p = atof(argv[7]);
   const uint32_t max_attempts = (uint32_t)strtoul(argv[8], nullptr, 10);
   const uint64_t seed = strtoull(argv[9], nullptr, 10);
+  const int W = atoi(argv[10]), tail = atoi(argv[11]);
   CHECK(G >= 1 && G <= 64 && hmax >= 1 && (int)hmax <= G && grid >= 1);
+  CHECK(W >= 1 && G % W == 0 && tail >= 0 && tail <= 64);
   const uint64_t thresh = (uint64_t)(p * 18446744073709551615.0);
   auto passes = [&](uint32_t task, uint32_t nonce) {
     return mix64(seed * 0x9E3779B97F4A7C15ULL ^ ((uint64_t)task << 32 | nonce)) < thresh;
@@ -109,7 +114,11 @@ int main(int argc, char **argv) {
       }
       CHECK(nh >= 0 && nh <= (int)hmax);
       w.nheld = nh;
-      const int ns = sched_assign(nh, G, w.h_next, w.h_win, w.s_h, w.s_att);
+      const int want = sched_slots(nh, G, W, w.queue_empty, tail);
+      const int ns = sched_assign(nh, want, w.h_next, w.h_win, w.s_h, w.s_att);
+      CHECK(ns == want && ns <= G);
+      if (nh && (!w.queue_empty || tail == 0)) CHECK(ns == G);
+      if (nh && w.queue_empty && tail > 0) CHECK(ns >= nh && (ns == G || ns % W == 0) && ns >= std::min(G, nh * tail));
       w.evaluated += (uint64_t)ns;
       if (ns == 0) {
         CHECK(nh == 0 && (w.queue_empty || count == 0));
@@ -118,7 +127,6 @@ int main(int argc, char **argv) {
         continue;
       }
       batches++;
-      CHECK(ns == G);
       for (int s = 0; s < ns; s++) {
         CHECK(w.s_h[s] < nh);
         CHECK(w.h_task[w.s_h[s]] < count);
@@ -140,8 +148,9 @@ int main(int argc, char **argv) {
       }
       // check phase: slots in any order; skip once a smaller nonce passed
       for (int s = 0; s < G; s++) perm[s] = s;
-      std::shuffle(perm.begin(), perm.end(), rng);
-      for (int s : perm) {
+      std::shuffle(perm.begin(), perm.begin() + ns, rng);
+      for (int q = 0; q < ns; q++) {
+        const int s = perm[q];
         const int h = w.s_h[s];
         if (w.h_win[h] < w.s_att[s]) continue;
         if (passes(w.h_task[h], w.s_att[s])) w.h_win[h] = std::min(w.h_win[h], w.s_att[s]);

@@ -284,6 +284,52 @@ def test_persistent_schedules_match_oracle(level, waves, grid, hmax):
     c.close()
 
 
+@pytest.mark.parametrize("level", [2, 3, 5, 65])
+@pytest.mark.parametrize("grid,hmax,tail", [(1, 1, 1), (3, 5, 2), (5, 12, 16), (2, 64, 64), (0, 0, 12), (9, 4, 1)])
+def test_tail_batches_match_oracle(level, grid, hmax, tail):
+    """Short batches once the work queue is empty ("persist.tail": tail slots per held task,
+    rounded up to the four wavefronts) still give the sequential signatures, and fewer
+    candidates are evaluated than with full batches on the same schedule."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    c = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    c.set_param("persist.grid", grid)
+    c.set_param("persist.hmax", hmax)
+    n = 41
+    pk, sk = _keygen(c, level, workload.keygen_seeds(n, seed=80 + level))
+    msg, off = workload.messages(workload.uniform_lengths(n, 0, 300, seed=81), seed=81)
+    osig, iters = oracle.sign_batch(level, sk.cpu().numpy(), msg, off)
+    c.set_param("persist.tail", tail)
+    sig = _sign(c, level, sk, msg, off)
+    ev, seq = c.sign_stats()
+    assert np.array_equal(sig.cpu().numpy(), osig)
+    assert seq == int(iters.sum()) and ev >= seq
+    c.close()
+
+
+def test_tail_rejects_other_shapes(ctx):
+    from paper_2211_12265_amd import dilithium as dl
+    c = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    pk, sk = _keygen(c, 2, workload.keygen_seeds(2, seed=85))
+    msg, off = workload.messages(workload.fixed_lengths(2, 32), seed=85)
+    for bad in (65, -2):
+        with pytest.raises(dl.DilError):
+            c.set_param("persist.tail", bad)
+    c.set_param("persist.waves", 2)     # the automatic setting (-1) gives the other shapes full batches
+    osig, _ = oracle.sign_batch(2, sk.cpu().numpy(), msg, off)
+    assert np.array_equal(_sign(c, 2, sk, msg, off).cpu().numpy(), osig)
+    c.set_param("persist.waves", 4)
+    c.set_param("persist.tail", 8)
+    for name, value in (("persist.waves", 2), ("persist.pad", 0)):
+        c.set_param(name, value)
+        with pytest.raises(dl.DilError):
+            _sign(c, 2, sk, msg, off)
+        c.set_param(name, 4 if name == "persist.waves" else 1)
+    torch.cuda.synchronize()
+    c.close()
+
+
 def test_staged_stats_count_sequential_iterations(ctx):
     level = 2
     n = 50

@@ -14,18 +14,24 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2211_12265_amd", "csrc")
 
-# G, L, K, tasks, workgroups, hmax, pass probability, attempt limit
+# G, L, K, tasks, workgroups, hmax, pass probability, attempt limit, wavefronts, tail slots per task
 CASES = [
-    (64, 4, 4, 10000, 715, 14, 0.235, 16384),   # level 2, four wavefronts, automatic 3-per-CU grid
-    (64, 4, 4, 10000, 512, 16, 0.235, 16384),   # level 2 recorded schedule
-    (48, 5, 6, 10000, 512, 12, 0.196, 16384),   # level 3 recorded schedule
-    (36, 7, 8, 10000, 512, 16, 0.260, 16384),   # level 5 recorded schedule
-    (32, 4, 4, 10000, 1024, 6, 0.235, 16384),   # two wavefronts
-    (16, 4, 4, 10000, 2048, 3, 0.235, 16384),   # one wavefront
-    (9, 7, 8, 100, 20000, 1, 0.260, 16384),     # far more workgroups than tasks
-    (64, 4, 4, 0, 512, 16, 0.235, 16384),       # empty batch
-    (64, 4, 4, 3000, 64, 64, 0.010, 8),         # tasks dropped at the attempt limit
-    (12, 5, 6, 777, 100, 12, 0.500, 16384),     # hmax = G, ragged task count
+    (64, 4, 4, 10000, 715, 14, 0.235, 16384, 4, 0),   # level 2, four wavefronts, automatic 3-per-CU grid
+    (64, 4, 4, 10000, 512, 16, 0.235, 16384, 4, 0),   # level 2 recorded schedule
+    (48, 5, 6, 10000, 512, 12, 0.196, 16384, 4, 0),   # level 3 recorded schedule
+    (36, 7, 8, 10000, 512, 16, 0.260, 16384, 4, 0),   # level 5 recorded schedule
+    (32, 4, 4, 10000, 1024, 6, 0.235, 16384, 2, 0),   # two wavefronts
+    (16, 4, 4, 10000, 2048, 3, 0.235, 16384, 1, 0),   # one wavefront
+    (9, 7, 8, 100, 20000, 1, 0.260, 16384, 1, 0),     # far more workgroups than tasks
+    (64, 4, 4, 0, 512, 16, 0.235, 16384, 4, 0),       # empty batch
+    (64, 4, 4, 3000, 64, 64, 0.010, 8, 4, 0),         # tasks dropped at the attempt limit
+    (12, 5, 6, 777, 100, 12, 0.500, 16384, 1, 0),     # hmax = G, ragged task count
+    (64, 4, 4, 10000, 512, 16, 0.235, 16384, 4, 1),   # short tail batches: one slot per task (rounded to 4)
+    (64, 4, 4, 10000, 512, 16, 0.235, 16384, 4, 8),   # level 2, tail of 8 slots per task
+    (48, 5, 6, 10000, 512, 12, 0.196, 16384, 4, 12),  # level 3, tail of 12
+    (36, 7, 8, 10000, 512, 16, 0.260, 16384, 4, 5),   # level 5, tail of 5 (not a multiple of W)
+    (16, 4, 4, 10000, 2048, 3, 0.235, 16384, 1, 3),   # one wavefront, tail of 3
+    (64, 4, 4, 3000, 64, 64, 0.010, 8, 4, 2),         # attempt limit reached in tail batches
 ]
 
 
@@ -47,15 +53,18 @@ def test_kernels_use_the_replayed_code():
     assert '#include "batch_sched.h"' in src
     # both loop kernels assign and retire through batch_sched.h, and claim through it
     assert len(re.findall(r"sched_assign\(", src)) == 2
+    # the four-wavefront kernel's tail batches come from the replayed sched_slots
+    assert len(re.findall(r"sched_assign\(nh, TAIL \? sched_slots\(nh, G, W, lds.queue_empty, tail\) : G,", src)) == 1
+    assert len(re.findall(r"sched_assign\(nh, G, ", src)) == 1
     assert len(re.findall(r"sched_retire\(", src)) == 2
     assert "sched_claim(atomicAdd(" in src
     assert src.count("scratch_idx<LV>(G)") == 2
 
 
-@pytest.mark.parametrize("case", CASES, ids=[f"G{c[0]}-n{c[3]}-grid{c[4]}-h{c[5]}" for c in CASES])
+@pytest.mark.parametrize("case", CASES, ids=[f"G{c[0]}-n{c[3]}-grid{c[4]}-h{c[5]}-t{c[9]}" for c in CASES])
 @pytest.mark.parametrize("seed", [1, 2])
 def test_schedule_replay(replay, case, seed):
-    args = [str(x) for x in case] + [str(seed)]
+    args = [str(x) for x in case[:8]] + [str(seed)] + [str(x) for x in case[8:]]
     res = subprocess.run([replay] + args, capture_output=True, text=True, timeout=300)
     assert res.returncode == 0, res.stdout + res.stderr
     m = re.search(r"evaluated=(\d+) sequential=(\d+) dropped=(\d+)", res.stdout)
