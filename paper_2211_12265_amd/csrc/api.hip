@@ -45,7 +45,7 @@ struct dil_ctx {
   hipEvent_t ev[RING][3] = {};                 // per timed call: before setup, before loop, after loop
   int ev_count = 0;                            // timed calls recorded since timing was (re)enabled
   int cu_count = 0;                            // cached device properties
-  int occ[3][6] = {};                          // cached persistent-kernel occupancy [shape: 1/2/4 waves][lv_slot]
+  int occ[4][6] = {};                          // cached persistent-kernel occupancy [1/2/4 waves, 4 with tail][lv_slot]
   // hipGraph replay of identical calls (same level, buffers, count and schedule)
   int use_graph = 0;
   hipStream_t cap_stream = nullptr;            // private stream the graphs are captured on
@@ -407,7 +407,16 @@ int sign_staged(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, const 
   return take_msg_error(ctx, st);
 }
 
-// resident workgroups per CU of the persistent kernel in the context's shape (cached)
+// Tail slots per held task of the context's persistent Sign calls at level LV
+// ("persist.tail"; -1 = the level's default for the four-wavefront padded
+// kernel, full batches for the other shapes).
+template <int LV>
+int tail_slots(const dil_ctx *ctx) {
+  if (ctx->persist_tail >= 0) return ctx->persist_tail;
+  return ctx->persist_waves == 4 && ctx->persist_pad ? PCfgW<LV, 4>::TAIL_AUTO : 0;
+}
+
+// resident workgroups per CU of the persistent kernel the context's shape launches (cached)
 template <int LV>
 int persist_occupancy(dil_ctx *ctx, int *occ) {
   if (!ctx->cu_count) {
@@ -415,11 +424,15 @@ int persist_occupancy(dil_ctx *ctx, int *occ) {
     HIPCHK(ctx, hipGetDeviceProperties(&prop, ctx->device));
     ctx->cu_count = prop.multiProcessorCount;
   }
-  const int w = ctx->persist_waves, si = w == 4 ? 2 : w == 2 ? 1 : 0;
+  const int w = ctx->persist_waves;
+  const bool tail = w == 4 && tail_slots<LV>(ctx) > 0;
+  const int si = tail ? 3 : w == 4 ? 2 : w == 2 ? 1 : 0;
   if (Lv<LV>::MLDSA && w != 4) return fail(ctx, DIL_EINVAL, "ML-DSA levels run the four-wavefront loop kernel only");
   int &o = ctx->occ[si][lv_slot(LV)];
   if (!o) {
-    if (w == 4) {
+    if (tail) {
+      HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_persistw_k<LV, 4, true, true>, 256, 0));
+    } else if (w == 4) {
       HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_persistw_k<LV, 4>, 256, 0));
     } else if constexpr (!Lv<LV>::MLDSA) {
       if (w == 2) HIPCHK(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&o, sg_persistw_k<LV, 2>, 128, 0));
@@ -460,8 +473,7 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
     return fail(ctx, DIL_EINVAL, "ML-DSA levels run the four-wavefront padded loop kernel (persist.waves = 4, persist.pad = 1)");
   if (ctx->persist_tail > 0 && (waves != 4 || !ctx->persist_pad))
     return fail(ctx, DIL_EINVAL, "persist.tail > 0 exists for the four-wavefront padded loop kernel only");
-  const int tail_slots = ctx->persist_tail >= 0 ? ctx->persist_tail
-                         : (waves == 4 && ctx->persist_pad) ? PCfgW<LV, 4>::TAIL_AUTO : 0;
+  const int ntail = tail_slots<LV>(ctx);
   uint64_t grid = 1, hmax = 1;
   int rc = persist_schedule<LV>(ctx, count, &grid, &hmax);
   if (rc) return rc;
@@ -489,8 +501,8 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   if (evs) HIPCHK(ctx, hipEventRecord(evs[1], st));
   // The loop kernel is one launch: it is launched directly, also when graphs
   // are enabled (as a graph node it measured 2-4% slower).
-  const bool tail = tail_slots > 0;
-  const uint32_t sched = (uint32_t)hmax | (uint32_t)tail_slots << 8;  // hmax <= G <= 64, tail <= 64
+  const bool tail = ntail > 0;
+  const uint32_t sched = (uint32_t)hmax | (uint32_t)ntail << 8;  // hmax <= G <= 64, tail <= 64
   if constexpr (Lv<LV>::MLDSA) {
     if (tail) sg_persistw_k<LV, 4, true, true><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, sched, ctx->dev_stats);
     else sg_persistw_k<LV, 4><<<(unsigned)grid, 256, 0, st>>>(ws, sc, sig, count, sched, ctx->dev_stats);
