@@ -234,8 +234,8 @@ int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_id
  * array of 16 MiB that the library holds on every GPU it runs on until the
  * process ends, instead of the context's pool; the call allocates nothing and
  * enqueues only kernels on `stream` (no memset, no side stream).  count is
- * limited by that array: 11,847 tasks at level 2, 11,335 at level 3, 9,320
- * at level 5; a larger count is DIL_EINVAL with the limit in
+ * limited by that array: 11,847 tasks at level 2 or 44, 11,335 at level 3
+ * or 65, 9,320 at level 5 or 87; a larger count is DIL_EINVAL with the limit in
  * dil_last_error().  The context supplies the device and the error words
  * (dil_ctx_check reports a key index outside the table, as for
  * dil_verify_keyset).  All calls on one

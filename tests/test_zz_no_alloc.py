@@ -1,7 +1,7 @@
 """The Verify entry point that allocates nothing (dil_verify_keyset_noalloc, workspace in the
 library's fixed per-GPU scratch array) against dil_verify_keyset on the same inputs: identical
 verdicts on two calls in a row, the second with fewer tasks, with valid, flipped and
-wrong-key signatures mixed in, at each level; a count beyond the scratch array's limit is
+wrong-key signatures mixed in, at each level (ML-DSA's included); a count beyond the scratch array's limit is
 refused; the verdicts also equal the oracle's."""
 import numpy as np
 import pytest
@@ -12,7 +12,7 @@ from paper_2211_12265_amd import workload
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-LIMIT = {2: 11847, 3: 11335, 5: 9320}
+LIMIT = {2: 11847, 3: 11335, 5: 9320, 44: 11847, 65: 11335, 87: 9320}
 
 
 def _batch(level, nkeys, n, seed):
@@ -34,7 +34,7 @@ def _batch(level, nkeys, n, seed):
     return pk, sk, vkey, msg, off, sig, expect
 
 
-@pytest.mark.parametrize("level", [2, 3, 5])
+@pytest.mark.parametrize("level", [2, 3, 5, 44, 65, 87])
 def test_noalloc_verify_matches_verify_keyset(level):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
