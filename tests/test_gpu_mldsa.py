@@ -211,19 +211,23 @@ def test_tr_by_hashlib(ctx):
         assert skh[i, 64:128].tobytes() == hashlib.shake_256(pkh[i].tobytes()).digest(64)
 
 
-@pytest.mark.parametrize("level", [65])
+@pytest.mark.parametrize("level", [44, 65, 87])
 def test_ten_thousand_tasks(level):
-    """A 10,000-task batch (uniform 32..4096-byte messages) in the benchmark's launch
-    configuration: every key and signature equals the oracle's and every signature verifies."""
+    """A 10,000-task batch in the benchmark's launch configuration (recorded schedule, graph
+    replay, automatic tail batches; 32-byte messages at level 44, uniform 32..4096-byte ones at
+    65 / 87): every key and signature equals the oracle's and every signature verifies."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    from paper_2211_12265_amd import autotune
     from paper_2211_12265_amd import dilithium as dl
     n = 10000
     c = dl.Context(0, mode=dl.MODE_PERSISTENT)
     try:
         c.set_param("graph", 1)
+        mix = "fixed32" if level == 44 else "uniform"
+        autotune.apply_schedule(c, autotune.cached_schedule(level, n, mix))
         seeds = workload.keygen_seeds(n, seed=level)
-        lens = workload.uniform_lengths(n, 32, 4096, seed=level)
+        lens = workload.fixed_lengths(n, 32) if mix == "fixed32" else workload.uniform_lengths(n, 32, 4096, seed=level)
         msg, off = workload.messages(lens, seed=level)
         opk, osk = oracle.keygen_batch(level, seeds)
         osig, _ = oracle.sign_batch(level, osk, msg, off)
