@@ -523,14 +523,19 @@ def test_tuned_loop_kernels_keep_two_waves_per_simd():
     c.close()
 
 
-@pytest.mark.parametrize("level", [2, 5])
+@pytest.mark.parametrize("level", [2, 5, 44, 87])
 def test_message_lengths_at_block_boundaries(sctx, level):
     """mu = H(tr || M) with M ending on and around every SHAKE256 block boundary (the
-    first block holds tr and 104 message bytes, later ones 136) and starting at each of
-    the four byte alignments: Sign and Verify equal the oracle.  One contiguous CSR holds
+    first block holds tr and 104 message bytes, later ones 136; ML-DSA's first block holds
+    its 66-byte prefix and 70) and starting at each of the four byte alignments: Sign and
+    Verify equal the oracle.  One contiguous CSR holds
     a filler task of 0-3 bytes before every message to set that message's alignment."""
     from paper_2211_12265_amd import dilithium as dl
-    lens = [0, 1, 2, 3, 4, 5, 7, 103, 104, 105, 239, 240, 241, 375, 376, 377, 2000]
+    if level in (44, 87):
+        # ML-DSA: mu = H(tr || 0 || 0 || M), 70 message bytes in the first block
+        lens = [0, 1, 2, 3, 4, 5, 7, 69, 70, 71, 205, 206, 207, 341, 342, 343, 2000]
+    else:
+        lens = [0, 1, 2, 3, 4, 5, 7, 103, 104, 105, 239, 240, 241, 375, 376, 377, 2000]
     task_lens, key_of, real = [], [], []
     pos = 0
     for ln in lens:
