@@ -1,7 +1,9 @@
 """Continuous-batching request loop over libdil on one GPU.
 
-Requests (mixed level 2/3/5 Sign and Verify, each against one key of a
-resident key table) arrive over time.  The loop keeps up to `n_streams`
+Requests (mixed-level Sign and Verify, each against one key of a resident
+key table; levels 2/3/5, and ML-DSA 44/65/87 in the Python engines) arrive
+over time, replayed from a trace (`Server.serve`, `NativeServer.serve`) or
+submitted one by one from application threads (`Service`).  The loop keeps up to `n_streams`
 batches in flight, each on its own HIP stream with its own libdil context
 (workspace): whenever a stream is free, the requests that have arrived are
 admitted in order as the next batch, split by (level, op) into key-table
@@ -23,6 +25,7 @@ arrival -- includes queueing, both copies and the kernels.
 """
 from __future__ import annotations
 
+import threading
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -123,13 +126,13 @@ class _Lane:
         self.staging_bytes = sum(t.numel() * t.element_size() for t in
                                  (self.d_msg, self.d_off, self.d_key, self.d_sig, self.d_ver))
 
-    def workspace_need(self, cap: int) -> int:
+    def workspace_need(self, cap: int, levels=LEVELS) -> int:
         """Workspace of the largest of this lane's calls with `cap` requests: the lane's calls
         run one after another on its stream and share one context."""
-        return max(self.ctx.workspace_bytes(lv, op, True, cap) for lv in LEVELS for op in (dl.OP_SIGN, dl.OP_VERIFY))
+        return max(self.ctx.workspace_bytes(lv, op, True, cap) for lv in levels for op in (dl.OP_SIGN, dl.OP_VERIFY))
 
-    def reserve(self, cap: int):
-        for lv in LEVELS:
+    def reserve(self, cap: int, levels=LEVELS):
+        for lv in levels:
             for op in (dl.OP_SIGN, dl.OP_VERIFY):
                 self.ctx.reserve_call(lv, op, True, cap)
 
@@ -144,15 +147,16 @@ class Server:
         self.torch = torch
         self.device = torch.device("cuda", 0)
         self.keysets = keysets
+        self.levels = tuple(sorted(keysets))      # the levels this engine serves
         self.max_batch = max_batch
         self.mem_budget = mem_budget
-        max_sig = max_batch * max(sig_size(lv) for lv in LEVELS)
+        max_sig = max_batch * max(sig_size(lv) for lv in self.levels)
         self.lanes = [_Lane(torch, self.device, max_msg_bytes, max_batch, max_sig, persistent)
                       for _ in range(n_streams)]
         self.max_msg_bytes = max_msg_bytes
         # the largest per-(level, op) request count whose reservations fit the budget
         ln0 = self.lanes[0]
-        lane_bytes = lambda c: ln0.staging_bytes + ln0.workspace_need(c)
+        lane_bytes = lambda c: ln0.staging_bytes + ln0.workspace_need(c, self.levels)
         lo, hi = 0, max_batch
         while lo < hi:
             mid = (lo + hi + 1) // 2
@@ -165,7 +169,7 @@ class Server:
         self.group_cap = lo
         self.reserved_bytes = lane_bytes(lo) * n_streams
         for ln in self.lanes:
-            ln.reserve(lo)
+            ln.reserve(lo, self.levels)
 
     def close(self):
         for ln in self.lanes:
@@ -181,7 +185,7 @@ class Server:
         sig_np = lane.h_sig.numpy()
         groups = []
         m_pos = s_pos = t_pos = 0
-        for lv in LEVELS:
+        for lv in self.levels:
             for op in (SIGN, VERIFY):
                 sel = idx[(reqs.level[idx] == lv) & (reqs.op[idx] == op)]
                 if sel.size == 0:
@@ -241,7 +245,7 @@ class Server:
     def _admit(self, reqs: Requests, head: int, end: int) -> int:
         """Requests head.. admitted in arrival order: at most group_cap of each (level, op) and
         at most max_msg_bytes of message data; returns how many."""
-        grp = 2 * np.searchsorted(LEVELS, reqs.level[head:end]) + reqs.op[head:end]
+        grp = 2 * np.searchsorted(self.levels, reqs.level[head:end]) + reqs.op[head:end]
         nth = np.zeros(end - head, np.int64)       # rank of each request within its group
         for g in np.unique(grp):
             sel = grp == g
@@ -309,6 +313,156 @@ class Server:
         return res
 
 
+class Service:
+    """Interactive front end of the request loop.  `submit` queues one request and returns a
+    ticket at once (from any thread); a dispatcher thread admits the queued requests in order as
+    batches on the free streams, under the admission rules of `Server` (at most `group_cap`
+    requests of each (level, op) and `max_msg_bytes` of messages per batch), so requests
+    submitted while earlier batches run join the next one; `poll` returns a ticket's result once
+    it is done (None before) and `wait` blocks for it.  A result is the signature bytes of a Sign
+    request or the verdict (True / False) of a Verify request; it is handed out once."""
+
+    def __init__(self, keysets: Dict[int, "dl.KeySet"], n_streams: int = 4, max_batch: int = 4096,
+                 mem_budget: int = 2 << 30, max_msg_bytes: int = 64 << 20, persistent: bool = True):
+        self.server = Server(keysets, n_streams=n_streams, max_batch=max_batch, mem_budget=mem_budget,
+                             max_msg_bytes=max_msg_bytes, persistent=persistent)
+        self.n_keys = {lv: ks.n_keys for lv, ks in keysets.items()}
+        self._cv = threading.Condition()
+        self._pending: deque = deque()     # (ticket, level, op, key, msg, sig)
+        self._results: Dict[int, object] = {}
+        self._next = 0
+        self._stop = False
+        self._error: Optional[BaseException] = None
+        self.batches = 0
+        self._thread = threading.Thread(target=self._run, name="dil-service", daemon=True)
+        self._thread.start()
+
+    def submit(self, level: int, op: int, key: int, msg: bytes, sig: Optional[bytes] = None) -> int:
+        """Queue Sign (op 0) of `msg` with key row `key` of the level's table, or Verify (op 1) of
+        `sig` on it; the request is checked here, before anything runs."""
+        msg = bytes(msg)
+        if level not in self.n_keys:
+            raise ValueError(f"no key table for level {level}")
+        if op not in (SIGN, VERIFY):
+            raise ValueError("op must be 0 (sign) or 1 (verify)")
+        if not 0 <= key < self.n_keys[level]:
+            raise ValueError(f"key row {key} outside the level-{level} table ({self.n_keys[level]} rows)")
+        if len(msg) > self.server.max_msg_bytes:
+            raise ValueError("message larger than a batch's staging buffer")
+        if op == VERIFY:
+            if sig is None or len(sig) != sig_size(level):
+                raise ValueError(f"verify needs a {sig_size(level)}-byte signature")
+            sig = bytes(sig)
+        with self._cv:
+            if self._stop:
+                raise RuntimeError("service closed")
+            t = self._next
+            self._next += 1
+            self._pending.append((t, level, op, key, msg, sig))
+            self._cv.notify_all()
+        return t
+
+    def poll(self, ticket: int):
+        with self._cv:
+            if self._error is not None:
+                raise RuntimeError("the dispatcher failed") from self._error
+            return self._results.pop(ticket, None)
+
+    def wait(self, ticket: int, timeout: Optional[float] = None):
+        with self._cv:
+            ok = self._cv.wait_for(lambda: ticket in self._results or self._error is not None, timeout)
+            if self._error is not None:
+                raise RuntimeError("the dispatcher failed") from self._error
+            if not ok:
+                raise TimeoutError(f"ticket {ticket} not done")
+            return self._results.pop(ticket)
+
+    def close(self):
+        """Finish the queued requests, then stop the dispatcher and free the engine."""
+        with self._cv:
+            self._stop = True
+            self._cv.notify_all()
+        self._thread.join()
+        self.server.close()
+
+    # ---- dispatcher ----
+    def _take(self) -> list:
+        """The next batch from the queue (called with the lock held): requests in submission order
+        while every (level, op) group stays within group_cap and the messages within
+        max_msg_bytes."""
+        srv = self.server
+        count: Dict[tuple, int] = {}
+        nbytes = 0
+        out = []
+        while self._pending and len(out) < srv.max_batch:
+            t, lv, op, key, msg, sig = self._pending[0]
+            g = (lv, op)
+            if count.get(g, 0) >= srv.group_cap or nbytes + len(msg) > srv.max_msg_bytes:
+                break
+            count[g] = count.get(g, 0) + 1
+            nbytes += len(msg)
+            out.append(self._pending.popleft())
+        return out
+
+    @staticmethod
+    def _as_requests(batch: list) -> Requests:
+        n = len(batch)
+        lens = np.array([len(b[4]) for b in batch], np.int64)
+        msg = np.frombuffer(b"".join(b[4] for b in batch), np.uint8) if lens.sum() else np.zeros(0, np.uint8)
+        sigs = [b[5] for b in batch if b[2] == VERIFY]
+        sig_off = np.full(n, -1, np.int64)
+        pos = 0
+        for i, b in enumerate(batch):
+            if b[2] == VERIFY:
+                sig_off[i] = pos
+                pos += len(b[5])
+        return Requests(t_arrival=np.zeros(n), op=np.array([b[2] for b in batch], np.int8),
+                        level=np.array([b[1] for b in batch], np.int8),
+                        key=np.array([b[3] for b in batch], np.int32), msg=msg,
+                        msg_off=np.concatenate([[0], np.cumsum(lens)]).astype(np.int64),
+                        sig_in=np.frombuffer(b"".join(sigs), np.uint8) if sigs else np.zeros(0, np.uint8),
+                        sig_off=sig_off)
+
+    def _run(self):
+        srv = self.server
+        free = deque(srv.lanes)
+        busy: List[tuple] = []       # (lane, tickets, Results of the batch)
+        try:
+            while True:
+                for item in list(busy):
+                    lane, tickets, res = item
+                    if lane.event.query():
+                        srv._collect(lane, res, 0.0)
+                        out = {t: (res.sig[i].tobytes() if i in res.sig else bool(res.verdict[i] == 1))
+                               for i, t in enumerate(tickets)}
+                        with self._cv:
+                            self._results.update(out)
+                            self._cv.notify_all()
+                        busy.remove(item)
+                        free.append(lane)
+                batch = []
+                with self._cv:
+                    if free and self._pending:
+                        batch = self._take()
+                    elif not busy:
+                        if self._stop and not self._pending:
+                            return
+                        self._cv.wait(0.01)
+                if batch:
+                    reqs = self._as_requests(batch)
+                    lane = free.popleft()
+                    res = Results(verdict=np.full(len(batch), -1, np.int32), t_done=np.zeros(len(batch)))
+                    srv._launch(lane, reqs, np.arange(len(batch)))
+                    busy.append((lane, [b[0] for b in batch], res))
+                    self.batches += 1
+                elif busy:
+                    time.sleep(0.0001)
+        except BaseException as e:   # surfaced to every waiting caller
+            with self._cv:
+                self._error = e
+                self._cv.notify_all()
+
+
 class NativeServer:
     """The C++ serving engine of libdil (dil_server_*): same admission policy as `Server`, with batch
     formation, staging and harvesting in native code.  Requests are replayed from a trace with their
@@ -317,6 +471,8 @@ class NativeServer:
     def __init__(self, keysets: Dict[int, "dl.KeySet"], n_streams: int = 4, max_batch: int = 4096,
                  mem_budget: int = 2 << 30, max_msg_bytes: int = 64 << 20, persistent: bool = True):
         import ctypes
+        if set(keysets) - set(LEVELS):
+            raise ValueError("the native engine serves levels 2, 3 and 5 (use Server or Service for ML-DSA)")
         self.lib = dl.load()
         self.keysets = keysets
         h = ctypes.c_void_p()
@@ -422,7 +578,7 @@ def attach_signatures(reqs: Requests, ctx: "dl.Context", keysets: Dict[int, "dl.
     flips = np.random.default_rng([seed, 5]).random(n) < flip_rate
     fbits = np.random.default_rng([seed, 6]).integers(0, 1 << 30, size=n)
     flipped = np.zeros(n, bool)
-    for lv in LEVELS:
+    for lv in np.unique(reqs.level).tolist():
         sel = np.nonzero((reqs.level == lv) & (reqs.op == VERIFY))[0]
         if sel.size == 0:
             continue

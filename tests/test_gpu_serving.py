@@ -155,3 +155,71 @@ def test_batches_overlap(setup, engine):
     assert res.batches >= len(reqs) // 16
     assert res.overlapped > 0
     _check_against_oracle(sv, host, reqs, flipped, res)
+
+
+def test_service_submit_and_wait_from_threads():
+    """The interactive front end (`Service`): three threads submit mixed Sign / Verify requests
+    at levels 2 and ML-DSA-65 while earlier batches run; every ticket's result equals the
+    oracle's (signature bytes, verdict), results are handed out once, and bad requests are
+    refused at submission."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import threading
+    from paper_2211_12265_amd import dilithium as dl
+    from paper_2211_12265_amd import serving as sv
+    ctx = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    keysets, host = {}, {}
+    for lv, nk in ((2, 6), (65, 4)):
+        seeds = workload.keygen_seeds(nk, seed=300 + lv)
+        pk, sk = oracle.keygen_batch(lv, seeds)
+        host[lv] = (pk, sk)
+        keysets[lv] = dl.KeySet(ctx, lv, pk=torch.from_numpy(pk).cuda(), sk=torch.from_numpy(sk).cuda())
+    rng = np.random.default_rng(31)
+    n = 240
+    level = rng.choice([2, 65], size=n)
+    op = (rng.random(n) < 0.6).astype(int)      # 60% verify
+    key = np.array([rng.integers(0, 6 if lv == 2 else 4) for lv in level])
+    lens = workload.uniform_lengths(n, 0, 400, seed=31)
+    msgs = [workload.random_bytes("test/service", i, (int(lens[i]),)).tobytes() for i in range(n)]
+    # verify requests carry the oracle's signature, every fourth with one bit flipped
+    sig_in, expect = [None] * n, [None] * n
+    for i in range(n):
+        pk, sk = host[int(level[i])]
+        s, _ = oracle.sign(int(level[i]), sk[key[i]].tobytes(), msgs[i])
+        if op[i] == sv.SIGN:
+            expect[i] = s
+        else:
+            if i % 4 == 0:
+                b = bytearray(s)
+                b[i % len(b)] ^= 1
+                s = bytes(b)
+            sig_in[i] = s
+            expect[i] = bool(oracle.verify(int(level[i]), pk[key[i]].tobytes(), msgs[i], s) == 1)
+    svc = sv.Service(keysets, n_streams=3, max_batch=32, mem_budget=2 << 30, max_msg_bytes=1 << 20)
+    tickets = [None] * n
+
+    def client(part):
+        for i in range(part, n, 3):
+            tickets[i] = svc.submit(int(level[i]), int(op[i]), int(key[i]), msgs[i], sig_in[i])
+
+    threads = [threading.Thread(target=client, args=(p,)) for p in range(3)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    got = [svc.wait(t, timeout=120) for t in tickets]
+    assert got == expect
+    assert svc.poll(tickets[0]) is None            # handed out once
+    assert svc.batches > 1
+    with pytest.raises(ValueError):
+        svc.submit(2, sv.SIGN, 6, b"x")             # key row outside the table
+    with pytest.raises(ValueError):
+        svc.submit(65, sv.VERIFY, 0, b"x")          # verify without a signature
+    with pytest.raises(ValueError):
+        svc.submit(3, sv.SIGN, 0, b"x")             # no table for the level
+    svc.close()
+    with pytest.raises(RuntimeError):
+        svc.submit(2, sv.SIGN, 0, b"x")
+    for ks in keysets.values():
+        ks.close()
+    ctx.close()
