@@ -20,8 +20,8 @@
  *   level 44: pk 1312 B, sk 2560 B, signature 2420 B
  *   level 65: pk 1952 B, sk 4032 B, signature 3309 B
  *   level 87: pk 2592 B, sk 4896 B, signature 4627 B
- * Every batch and key-table entry point takes all six levels; the serving
- * dispatcher (dil_server_*) and dil_t0_ntt_batch take levels 2, 3, 5 only.
+ * Every batch, key-table and serving entry point takes all six levels;
+ * dil_t0_ntt_batch (an ablation primitive) takes levels 2, 3, 5 only.
  *
  * Conventions for every batch entry point:
  *   - Buffer pointers are DEVICE pointers (hipMalloc'd or torch tensors on the
@@ -246,8 +246,8 @@ int dil_verify_keyset_noalloc(dil_ctx *ctx, const dil_keyset *ks, const uint32_t
                               void *stream);
 
 /* ---- Continuous-batching serving engine ----
- * Host-side dispatcher over key tables (one per level; NULL for a level not
- * served).  It keeps up to n_streams batches in flight, each on its own HIP
+ * Host-side dispatcher over key tables (at most one per level, any of the six
+ * levels; a level without a table is not served).  It keeps up to n_streams batches in flight, each on its own HIP
  * stream with its own contexts; whenever a stream is free it admits the
  * requests that have arrived, in arrival order, splits the batch by
  * (level, op) into dil_sign_keyset / dil_verify_keyset calls, and stages
@@ -266,6 +266,12 @@ int dil_verify_keyset_noalloc(dil_ctx *ctx, const dil_keyset *ks, const uint32_t
  * HIP starts.  mode is DIL_MODE_STAGED or DIL_MODE_PERSISTENT for Sign; the
  * persistent Sign calls use four-wavefront workgroups ("persist.waves" = 4). */
 typedef struct dil_server dil_server;
+/* tables: n_tables key tables (host array of handles), each level at most
+ * once (a table's level comes from the table); DIL_EINVAL otherwise. */
+int dil_server_create_tables(dil_server **out, int device, dil_keyset *const *tables, int n_tables, int n_streams,
+                             uint32_t max_batch, size_t max_msg_bytes, size_t mem_budget, int mode);
+/* The same with the round-3 tables passed by level (ks2 / ks3 / ks5, each
+ * may be NULL). */
 int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset *ks3, dil_keyset *ks5,
                       int n_streams, uint32_t max_batch, size_t max_msg_bytes, size_t mem_budget, int mode);
 /* Waits for the device and frees the engine (not the key tables). */

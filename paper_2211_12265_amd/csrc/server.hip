@@ -34,9 +34,14 @@
 
 namespace {
 
-constexpr int NLV = 3;
-const int kLevels[NLV] = {2, 3, 5};
-int lv_index(int level) { return level == 2 ? 0 : level == 3 ? 1 : level == 5 ? 2 : -1; }
+// the levels a server can hold tables for: round 3, then ML-DSA-44 / 65 / 87
+constexpr int NLV = 6;
+const int kLevels[NLV] = {2, 3, 5, 44, 65, 87};
+int lv_index(int level) {
+  for (int i = 0; i < NLV; i++)
+    if (kLevels[i] == level) return i;
+  return -1;
+}
 
 struct Group {
   int li, op;                 // level index, 0 sign / 1 verify
@@ -64,8 +69,8 @@ struct Lane {
 
 struct dil_server {
   int device = 0;
-  dil_keyset *ks[NLV] = {nullptr, nullptr, nullptr};
-  size_t sig_bytes[NLV] = {0, 0, 0};
+  dil_keyset *ks[NLV] = {};
+  size_t sig_bytes[NLV] = {};
   uint32_t max_batch = 0;
   uint32_t group_cap = 0;     // requests of one (level, op) group per batch (memory budget)
   size_t max_msg = 0, budget = 0, reserved = 0;
@@ -102,16 +107,23 @@ int lane_bytes(dil_server *s, const Lane &ln, uint32_t cap, size_t staging, size
 
 extern "C" {
 
-int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset *ks3, dil_keyset *ks5,
-                      int n_streams, uint32_t max_batch, size_t max_msg_bytes, size_t mem_budget, int mode) {
-  if (!out || n_streams < 1 || max_batch < 1 || max_msg_bytes < 1) return DIL_EINVAL;
+int dil_server_create_tables(dil_server **out, int device, dil_keyset *const *tables, int n_tables, int n_streams,
+                             uint32_t max_batch, size_t max_msg_bytes, size_t mem_budget, int mode) {
+  if (!out || n_tables < 0 || (n_tables && !tables) || n_streams < 1 || max_batch < 1 || max_msg_bytes < 1)
+    return DIL_EINVAL;
   *out = nullptr;
+  dil_keyset *by_level[NLV] = {};
+  for (int i = 0; i < n_tables; i++) {
+    int level = 0;
+    if (!tables[i] || dil_keyset_info(tables[i], &level, nullptr, nullptr) != DIL_OK) return DIL_EINVAL;
+    const int li = lv_index(level);
+    if (li < 0 || by_level[li]) return DIL_EINVAL;  // one table per level
+    by_level[li] = tables[i];
+  }
   if (hipSetDevice(device) != hipSuccess) return DIL_EHIP;
   dil_server *s = new dil_server();
   s->device = device;
-  s->ks[0] = ks2;
-  s->ks[1] = ks3;
-  s->ks[2] = ks5;
+  for (int i = 0; i < NLV; i++) s->ks[i] = by_level[i];
   s->max_batch = max_batch;
   s->max_msg = max_msg_bytes;
   s->budget = mem_budget;
@@ -190,6 +202,15 @@ int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset 
   return DIL_OK;
 }
 
+int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset *ks3, dil_keyset *ks5,
+                      int n_streams, uint32_t max_batch, size_t max_msg_bytes, size_t mem_budget, int mode) {
+  dil_keyset *tables[3];
+  int n = 0;
+  for (dil_keyset *k : {ks2, ks3, ks5})
+    if (k) tables[n++] = k;
+  return dil_server_create_tables(out, device, tables, n, n_streams, max_batch, max_msg_bytes, mem_budget, mode);
+}
+
 int dil_server_destroy(dil_server *s) {
   if (!s) return DIL_EINVAL;
   hipSetDevice(s->device);
@@ -239,7 +260,7 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
   if (n == 0) return DIL_OK;
   if (!op || !level || !key || !msg || !msg_off || !arrival_ns || !verdict || !done_ns) return sfail(s, DIL_EINVAL, "null array");
   hipSetDevice(s->device);
-  uint32_t nkeys[NLV] = {0, 0, 0};
+  uint32_t nkeys[NLV] = {};
   for (int li = 0; li < NLV; li++)
     if (s->ks[li]) dil_keyset_info(s->ks[li], nullptr, &nkeys[li], nullptr);
   for (uint32_t i = 0; i < n; i++) {

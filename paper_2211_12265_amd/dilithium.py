@@ -25,7 +25,8 @@ EXPORTS = [
     "dil_keygen_batch", "dil_sign_batch", "dil_sign_batch_rnd", "dil_verify_batch", "dil_sign_stats", "dil_sign_timing",
     "dil_ntt_mul_batch",
     "dil_expand_a_batch", "dil_keyset_create", "dil_keyset_destroy", "dil_keyset_info", "dil_sign_keyset",
-    "dil_verify_keyset", "dil_persist_capacity", "dil_ctx_reserve", "dil_server_create", "dil_server_destroy",
+    "dil_verify_keyset", "dil_persist_capacity", "dil_ctx_reserve", "dil_server_create", "dil_server_create_tables",
+    "dil_server_destroy",
     "dil_server_last_error", "dil_server_stats", "dil_server_run", "dil_ctx_reserve_call", "dil_workspace_bytes",
     "dil_alu_probe", "dil_verify_keyset_noalloc", "dil_t0_ntt_batch",
 ]
@@ -78,6 +79,8 @@ def load() -> ctypes.CDLL:
         "dil_ctx_reserve": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_uint32]),
         "dil_server_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, _P, _P, ctypes.c_int,
                                              ctypes.c_uint32, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int]),
+        "dil_server_create_tables": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int, _P, ctypes.c_int, ctypes.c_int,
+                                                    ctypes.c_uint32, ctypes.c_size_t, ctypes.c_size_t, ctypes.c_int]),
         "dil_server_destroy": (ctypes.c_int, [_P]),
         "dil_server_last_error": (ctypes.c_char_p, [_P]),
         "dil_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double),

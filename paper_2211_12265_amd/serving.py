@@ -1,7 +1,7 @@
 """Continuous-batching request loop over libdil on one GPU.
 
 Requests (mixed-level Sign and Verify, each against one key of a resident
-key table; levels 2/3/5, and ML-DSA 44/65/87 in the Python engines) arrive
+key table; levels 2/3/5 and ML-DSA 44/65/87) arrive
 over time, replayed from a trace (`Server.serve`, `NativeServer.serve`) or
 submitted one by one from application threads (`Service`).  The loop keeps up to `n_streams`
 batches in flight, each on its own HIP stream with its own libdil context
@@ -471,15 +471,13 @@ class NativeServer:
     def __init__(self, keysets: Dict[int, "dl.KeySet"], n_streams: int = 4, max_batch: int = 4096,
                  mem_budget: int = 2 << 30, max_msg_bytes: int = 64 << 20, persistent: bool = True):
         import ctypes
-        if set(keysets) - set(LEVELS):
-            raise ValueError("the native engine serves levels 2, 3 and 5 (use Server or Service for ML-DSA)")
         self.lib = dl.load()
         self.keysets = keysets
         h = ctypes.c_void_p()
-        ks = [keysets[lv].h if lv in keysets else None for lv in LEVELS]
-        rc = self.lib.dil_server_create(ctypes.byref(h), 0, ks[0], ks[1], ks[2], n_streams, max_batch,
-                                        max_msg_bytes, mem_budget,
-                                        dl.MODE_PERSISTENT if persistent else dl.MODE_STAGED)
+        tables = (ctypes.c_void_p * max(len(keysets), 1))(*[keysets[lv].h.value for lv in sorted(keysets)])
+        rc = self.lib.dil_server_create_tables(ctypes.byref(h), 0, ctypes.cast(tables, ctypes.c_void_p), len(keysets),
+                                               n_streams, max_batch, max_msg_bytes, mem_budget,
+                                               dl.MODE_PERSISTENT if persistent else dl.MODE_STAGED)
         if rc:
             raise dl.DilError(rc, "server creation failed")
         self.h = h
@@ -503,8 +501,9 @@ class NativeServer:
                                       else np.zeros(1, np.uint8), dtype=np.uint8)
         sig_in_off = np.ascontiguousarray(np.maximum(reqs.sig_off, 0) if reqs.sig_off is not None
                                           else np.zeros(n, np.int64), dtype=np.uint64)
-        sizes = np.array([sig_size(int(lv)) for lv in LEVELS])
-        ss = np.where(reqs.op == SIGN, sizes[np.searchsorted(LEVELS, reqs.level)], 0).astype(np.uint64)
+        levels = tuple(sorted(self.keysets))
+        sizes = np.array([sig_size(int(lv)) for lv in levels])
+        ss = np.where(reqs.op == SIGN, sizes[np.searchsorted(levels, reqs.level)], 0).astype(np.uint64)
         sig_out_off = np.concatenate([[0], np.cumsum(ss)[:-1]]).astype(np.uint64)
         sig_out = np.zeros(max(int(ss.sum()), 1), np.uint8)
         verdict = np.full(n, -1, np.int32)

@@ -49,7 +49,7 @@ def test_serving_matches_oracle(setup, engine):
 
 
 def _check_against_oracle(sv, host, reqs, flipped, res):
-    for lv in (2, 3, 5):
+    for lv in np.unique(reqs.level).tolist():
         pk, sk = host[lv]
         s = np.nonzero((reqs.level == lv) & (reqs.op == sv.SIGN))[0]
         if s.size:
@@ -223,3 +223,43 @@ def test_service_submit_and_wait_from_threads():
     for ks in keysets.values():
         ks.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("engine", ["python", "native"])
+def test_serving_mldsa_tables(engine):
+    """Both engines serve key tables of ML-DSA levels beside round-3 ones (a trace mixing levels
+    2, 65 and 87): every signature and verdict equals the oracle's."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    from paper_2211_12265_amd import serving as sv
+    ctx = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    keys = {2: 6, 65: 5, 87: 4}
+    keysets, host = {}, {}
+    for lv, nk in keys.items():
+        pk, sk = oracle.keygen_batch(lv, workload.keygen_seeds(nk, seed=320 + lv))
+        host[lv] = (pk, sk)
+        keysets[lv] = dl.KeySet(ctx, lv, pk=torch.from_numpy(pk).cuda(), sk=torch.from_numpy(sk).cuda())
+    reqs = sv.build_requests(240, lam=20000.0, keys_per_level={2: 6, 3: 5, 5: 4}, seed=11)
+    reqs.level = np.where(reqs.level == 3, 65, np.where(reqs.level == 5, 87, reqs.level)).astype(np.int8)
+    flipped = sv.attach_signatures(reqs, ctx, keysets, flip_rate=0.1, seed=11)
+    cls = sv.Server if engine == "python" else sv.NativeServer
+    server = cls(keysets, n_streams=3, max_batch=64, mem_budget=2 << 30, max_msg_bytes=1 << 20)
+    res = server.serve(reqs)
+    server.close()
+    assert np.isfinite(res.t_done).all()
+    _check_against_oracle(sv, host, reqs, flipped, res)
+    for ks in keysets.values():
+        ks.close()
+    ctx.close()
+
+
+def test_native_server_rejects_duplicate_levels(setup):
+    dl, sv, ctx, keysets, host, reqs, flipped = setup
+    import ctypes
+    lib = dl.load()
+    h = ctypes.c_void_p()
+    tables = (ctypes.c_void_p * 2)(keysets[2].h.value, keysets[2].h.value)
+    rc = lib.dil_server_create_tables(ctypes.byref(h), 0, ctypes.cast(tables, ctypes.c_void_p), 2, 2, 64,
+                                      1 << 20, 2 << 30, dl.MODE_PERSISTENT)
+    assert rc == dl.DIL_EINVAL and not h.value
