@@ -100,6 +100,12 @@ def bind(path: str) -> ctypes.CDLL:
             "dil_ref_sign_batch": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, _P, ctypes.c_uint32,
                                                   ctypes.c_int, _P]),
             "dil_ref_mldsa_mu": (None, [_P, _P, _SZ, _P]),
+            "dil_ref_mldsa_sign_internal": (ctypes.c_int, [ctypes.c_int, _P, _P, _SZ, _P, _P]),
+            "dil_ref_mldsa_verify_internal": (ctypes.c_int, [ctypes.c_int, _P, _P, _SZ, _P]),
+            "dil_ref_sign_batch_ex": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_uint32,
+                                                     ctypes.c_int, _P]),
+            "dil_ref_verify_batch_ex": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _P, _P, _P, _P, _P, _P,
+                                                       ctypes.c_uint32, ctypes.c_int]),
             "dil_ref_sign_batch_rnd": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_uint32,
                                                       ctypes.c_int, _P]),
             "dil_ref_verify_batch": (ctypes.c_int, [ctypes.c_int, _P, _P, _P, _P, _P, _P, ctypes.c_uint32,
@@ -327,6 +333,32 @@ def mldsa_mu(tr: bytes, msg: bytes) -> bytes:
     return mu.tobytes()
 
 
+def mldsa_format(msg: bytes, ctx: bytes = b"") -> bytes:
+    """The formatted message M' = 0x00 || |ctx| || ctx || M of ML-DSA's pure signing."""
+    if len(ctx) > 255:
+        raise ValueError("context strings hold at most 255 bytes")
+    return bytes([0, len(ctx)]) + bytes(ctx) + bytes(msg)
+
+
+def mldsa_sign_internal(level: int, sk: bytes, mprime: bytes, rnd: Optional[bytes] = None) -> bytes:
+    p = params(level)
+    sig = np.zeros(p["sig_bytes"], dtype=np.uint8)
+    s = np.frombuffer(bytes(sk), dtype=np.uint8).copy()
+    m = np.frombuffer(bytes(mprime) + b"\0", dtype=np.uint8).copy()
+    r = None if rnd is None else np.frombuffer(bytes(rnd), dtype=np.uint8).copy()
+    if lib().dil_ref_mldsa_sign_internal(level, _ptr(s), _ptr(m), len(mprime), None if r is None else _ptr(r),
+                                         _ptr(sig)) < 0:
+        raise ValueError("internal signing exists at the ML-DSA levels only")
+    return sig.tobytes()
+
+
+def mldsa_verify_internal(level: int, pk: bytes, mprime: bytes, sig: bytes) -> int:
+    k = np.frombuffer(bytes(pk), dtype=np.uint8).copy()
+    m = np.frombuffer(bytes(mprime) + b"\0", dtype=np.uint8).copy()
+    s = np.frombuffer(bytes(sig), dtype=np.uint8).copy()
+    return lib().dil_ref_mldsa_verify_internal(level, _ptr(k), _ptr(m), len(mprime), _ptr(s))
+
+
 def keygen_batch(level: int, seeds: np.ndarray, nthreads: Optional[int] = None):
     p = params(level)
     seeds = np.ascontiguousarray(seeds, dtype=np.uint8).reshape(-1, 32)
@@ -347,10 +379,11 @@ def _msg_arrays(msg: np.ndarray, msg_off: np.ndarray):
 
 def sign_batch(level: int, sk: np.ndarray, msg: np.ndarray, msg_off: np.ndarray,
                key_idx: Optional[np.ndarray] = None, nthreads: Optional[int] = None,
-               rnd: Optional[np.ndarray] = None):
+               rnd: Optional[np.ndarray] = None, internal: bool = False):
     """Returns (sig [count, SIG] uint8, iterations [count] int32).  rnd: optional per-task bytes for
     the randomized variant, [count, 64] (rho' itself, levels 2/3/5) or [count, 32] (the rnd that
-    rho'' hashes, ML-DSA levels 44/65/87); None: deterministic Sign."""
+    rho'' hashes, ML-DSA levels 44/65/87); None: deterministic Sign.  internal: the messages are
+    ML-DSA formatted messages M' (mu = H(tr || M'))."""
     p = params(level)
     sk = np.ascontiguousarray(sk, dtype=np.uint8)
     msg, msg_off = _msg_arrays(msg, msg_off)
@@ -363,24 +396,25 @@ def sign_batch(level: int, sk: np.ndarray, msg: np.ndarray, msg_off: np.ndarray,
         rb = 32 if p["mldsa"] else 64
         if rnd.shape != (n, rb):
             raise ValueError(f"rnd must be [count, {rb}] bytes")
-    rc = lib().dil_ref_sign_batch_rnd(level, _ptr(sk), None if ki is None else _ptr(ki), _ptr(msg), _ptr(msg_off),
-                                      None if rnd is None else _ptr(rnd), _ptr(sig), n,
-                                      nthreads or default_threads(), _ptr(iters))
+    rc = lib().dil_ref_sign_batch_ex(level, int(internal), _ptr(sk), None if ki is None else _ptr(ki), _ptr(msg),
+                                     _ptr(msg_off), None if rnd is None else _ptr(rnd), _ptr(sig), n,
+                                     nthreads or default_threads(), _ptr(iters))
     if rc:
         raise ValueError("bad arguments")
     return sig, iters[:n]
 
 
 def verify_batch(level: int, pk: np.ndarray, msg: np.ndarray, msg_off: np.ndarray, sig: np.ndarray,
-                 key_idx: Optional[np.ndarray] = None, nthreads: Optional[int] = None) -> np.ndarray:
+                 key_idx: Optional[np.ndarray] = None, nthreads: Optional[int] = None,
+                 internal: bool = False) -> np.ndarray:
     pk = np.ascontiguousarray(pk, dtype=np.uint8)
     sig = np.ascontiguousarray(sig, dtype=np.uint8)
     msg, msg_off = _msg_arrays(msg, msg_off)
     n = msg_off.size - 1
     verdict = np.zeros(max(n, 1), dtype=np.int32)
     ki = None if key_idx is None else np.ascontiguousarray(key_idx, dtype=np.uint32)
-    rc = lib().dil_ref_verify_batch(level, _ptr(pk), None if ki is None else _ptr(ki), _ptr(msg), _ptr(msg_off),
-                                    _ptr(sig), _ptr(verdict), n, nthreads or default_threads())
+    rc = lib().dil_ref_verify_batch_ex(level, int(internal), _ptr(pk), None if ki is None else _ptr(ki), _ptr(msg),
+                                       _ptr(msg_off), _ptr(sig), _ptr(verdict), n, nthreads or default_threads())
     if rc:
         raise ValueError("bad arguments")
     return verdict[:n]

@@ -123,6 +123,15 @@ int dil_ref_sign_rnd(int level, const uint8_t *sk, const uint8_t *msg, size_t ml
                      uint8_t *sig);
 /* returns 1 accept, 0 reject, -1 bad level */
 int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen, const uint8_t *sig);
+/* ML-DSA's internal signing / verification (levels 44 / 65 / 87 only, -1
+   otherwise): the caller passes the formatted message M' and mu = H(tr || M',
+   64); M' = 0x00 || |ctx| || ctx || M is the pure form with context ctx (the
+   functions above use ctx empty), M' = 0x01 || |ctx| || ctx || OID || PH(M)
+   the pre-hash form.  rnd: 32 bytes or NULL (zeros). */
+int dil_ref_mldsa_sign_internal(int level, const uint8_t *sk, const uint8_t *mprime, size_t len, const uint8_t *rnd,
+                                uint8_t *sig);
+int dil_ref_mldsa_verify_internal(int level, const uint8_t *pk, const uint8_t *mprime, size_t len,
+                                  const uint8_t *sig);
 
 /* batched drivers: same argument conventions as the GPU C-ABI but host pointers, no stream.
    key_idx may be NULL (task i uses key i).  msg_off has count+1 entries (CSR).
@@ -135,6 +144,14 @@ int dil_ref_sign_batch(int level, const uint8_t *sk, const uint32_t *key_idx, co
 int dil_ref_sign_batch_rnd(int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                            const uint64_t *msg_off, const uint8_t *rnd, uint8_t *sig, uint32_t count, int nthreads,
                            int32_t *iters);
+/* the batch drivers with internal = 1: messages are formatted messages M'
+   (ML-DSA levels only; -1 otherwise) */
+int dil_ref_sign_batch_ex(int level, int internal, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                          const uint64_t *msg_off, const uint8_t *rnd, uint8_t *sig, uint32_t count, int nthreads,
+                          int32_t *iters);
+int dil_ref_verify_batch_ex(int level, int internal, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
+                            const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count,
+                            int nthreads);
 int dil_ref_verify_batch(int level, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
                          const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count,
                          int nthreads);

@@ -226,6 +226,17 @@ static void pack_w1(const ref_params *P, const int32_t *w1, uint8_t *out) {
   for (int i = 0; i < P->k; i++) pack_vals(w1 + i * ORN, ORN, P->w1_bits, out + i * P->w1_poly_bytes);
 }
 
+/* ML-DSA's internal signing and verification take the formatted message M'
+   (for the pure form 0x00 || |ctx| || ctx || M; for the pre-hash form 0x01 ||
+   |ctx| || ctx || OID || PH(M)) and hash mu = H(tr || M', 64) */
+static void mu_internal(const uint8_t tr[64], const uint8_t *mprime, size_t len, uint8_t mu[64]) {
+  uint8_t *buf = (uint8_t *)malloc(64 + len + 1);
+  memcpy(buf, tr, 64);
+  memcpy(buf + 64, mprime, len);
+  dil_ref_shake256(buf, 64 + len, mu, 64);
+  free(buf);
+}
+
 /* ML-DSA: mu = H(tr || IntegerToBytes(0, 1) || IntegerToBytes(|ctx|, 1) || ctx || M, 64)
    with an empty context ctx */
 void dil_ref_mldsa_mu(const uint8_t tr[64], const uint8_t *msg, size_t mlen, uint8_t mu[64]) {
@@ -248,7 +259,7 @@ void dil_ref_set_sign_cap(int cap) { g_sign_cap = cap > 0 ? cap : 100000; }
 /* rnd == NULL: deterministic Sign, rho' = H(K || mu) (Alg. 2 as printed).
    rnd != NULL: the randomized variant of the round-3 scheme, rho' = the 64
    caller-supplied bytes; every other step is unchanged. */
-static int sign_core(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, const uint8_t *rnd,
+static int sign_core(int level, int internal, const uint8_t *sk, const uint8_t *msg, size_t mlen, const uint8_t *rnd,
                      uint8_t *sig) {
   ref_params P;
   if (dil_ref_params(level, &P)) return -1;
@@ -271,7 +282,8 @@ static int sign_core(int level, const uint8_t *sk, const uint8_t *msg, size_t ml
      ML-DSA: mu = H(tr || 0 || 0 || M), rho'' = H(K || rnd || mu), rnd 32 bytes */
   uint8_t mu[64], rhop[64];
   if (P.mldsa) {
-    dil_ref_mldsa_mu(tr, msg, mlen, mu);
+    if (internal) mu_internal(tr, msg, mlen, mu);
+    else dil_ref_mldsa_mu(tr, msg, mlen, mu);
     memcpy(buf, K, 32);
     if (rnd) memcpy(buf + 32, rnd, 32);
     else memset(buf + 32, 0, 32);
@@ -402,16 +414,24 @@ static int sign_core(int level, const uint8_t *sk, const uint8_t *msg, size_t ml
 }
 
 int dil_ref_sign(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, uint8_t *sig) {
-  return sign_core(level, sk, msg, mlen, NULL, sig);
+  return sign_core(level, 0, sk, msg, mlen, NULL, sig);
 }
 
 int dil_ref_sign_rnd(int level, const uint8_t *sk, const uint8_t *msg, size_t mlen, const uint8_t *rnd,
                      uint8_t *sig) {
-  return sign_core(level, sk, msg, mlen, rnd, sig);
+  return sign_core(level, 0, sk, msg, mlen, rnd, sig);
+}
+
+int dil_ref_mldsa_sign_internal(int level, const uint8_t *sk, const uint8_t *mprime, size_t len, const uint8_t *rnd,
+                                uint8_t *sig) {
+  ref_params P;
+  if (dil_ref_params(level, &P) || !P.mldsa) return -1;
+  return sign_core(level, 1, sk, mprime, len, rnd, sig);
 }
 
 /* ---- Alg. 3 ---- */
-int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen, const uint8_t *sig) {
+static int verify_core(int level, int internal, const uint8_t *pk, const uint8_t *msg, size_t mlen,
+                       const uint8_t *sig) {
   ref_params P;
   if (dil_ref_params(level, &P)) return -1;
   const int k = P.k, l = P.l;
@@ -429,7 +449,9 @@ int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen
   if (ok) {
     uint8_t tr[64], mu[64], c2[64];
     dil_ref_shake256(pk, P.pk_bytes, tr, (size_t)P.tr_bytes);
-    if (P.mldsa) {
+    if (P.mldsa && internal) {
+      mu_internal(tr, msg, mlen, mu);
+    } else if (P.mldsa) {
       dil_ref_mldsa_mu(tr, msg, mlen, mu);
     } else {
       memcpy(buf, tr, 32);
@@ -468,9 +490,20 @@ int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen
   return ok;
 }
 
+int dil_ref_verify(int level, const uint8_t *pk, const uint8_t *msg, size_t mlen, const uint8_t *sig) {
+  return verify_core(level, 0, pk, msg, mlen, sig);
+}
+
+int dil_ref_mldsa_verify_internal(int level, const uint8_t *pk, const uint8_t *mprime, size_t len,
+                                  const uint8_t *sig) {
+  ref_params P;
+  if (dil_ref_params(level, &P) || !P.mldsa) return -1;
+  return verify_core(level, 1, pk, mprime, len, sig);
+}
+
 /* ---- threaded batch drivers (tasks are independent) ---- */
 typedef struct {
-  int op, level;
+  int op, level, internal;
   const uint8_t *in_key, *msg, *sig_in, *seeds, *rnd;
   const uint32_t *key_idx;
   const uint64_t *msg_off;
@@ -490,13 +523,13 @@ static void *batch_worker(void *arg) {
       const uint8_t *m = j->msg + j->msg_off[t];
       size_t mlen = (size_t)(j->msg_off[t + 1] - j->msg_off[t]);
       if (j->op == 1) {
-        int it = sign_core(j->level, j->in_key + j->P.sk_bytes * key, m, mlen,
+        int it = sign_core(j->level, j->internal, j->in_key + j->P.sk_bytes * key, m, mlen,
                            j->rnd ? j->rnd + (j->P.mldsa ? 32 : 64) * (size_t)t : NULL,
                            j->sig + j->P.sig_bytes * t);
         if (j->iters) j->iters[t] = it;
       } else {
-        j->verdict[t] = dil_ref_verify(j->level, j->in_key + j->P.pk_bytes * key, m, mlen,
-                                       j->sig_in + j->P.sig_bytes * t);
+        j->verdict[t] = verify_core(j->level, j->internal, j->in_key + j->P.pk_bytes * key, m, mlen,
+                                    j->sig_in + j->P.sig_bytes * t);
       }
     }
   }
@@ -528,12 +561,13 @@ int dil_ref_keygen_batch(int level, const uint8_t *seeds, uint8_t *pk, uint8_t *
   return run_batch(&j, count, nthreads);
 }
 
-int dil_ref_sign_batch_rnd(int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
-                           const uint64_t *msg_off, const uint8_t *rnd, uint8_t *sig, uint32_t count, int nthreads,
-                           int32_t *iters) {
+int dil_ref_sign_batch_ex(int level, int internal, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                          const uint64_t *msg_off, const uint8_t *rnd, uint8_t *sig, uint32_t count, int nthreads,
+                          int32_t *iters) {
   batch_job j;
   memset(&j, 0, sizeof j);
-  if (dil_ref_params(level, &j.P)) return -1;
+  if (dil_ref_params(level, &j.P) || (internal && !j.P.mldsa)) return -1;
+  j.internal = internal;
   for (uint32_t t = 0; t < count; t++)
     if (msg_off[t + 1] < msg_off[t]) return -1;
   j.op = 1; j.level = level; j.in_key = sk; j.key_idx = key_idx; j.msg = msg; j.msg_off = msg_off;
@@ -541,20 +575,33 @@ int dil_ref_sign_batch_rnd(int level, const uint8_t *sk, const uint32_t *key_idx
   return run_batch(&j, count, nthreads);
 }
 
+int dil_ref_sign_batch_rnd(int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
+                           const uint64_t *msg_off, const uint8_t *rnd, uint8_t *sig, uint32_t count, int nthreads,
+                           int32_t *iters) {
+  return dil_ref_sign_batch_ex(level, 0, sk, key_idx, msg, msg_off, rnd, sig, count, nthreads, iters);
+}
+
 int dil_ref_sign_batch(int level, const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                        const uint64_t *msg_off, uint8_t *sig, uint32_t count, int nthreads, int32_t *iters) {
   return dil_ref_sign_batch_rnd(level, sk, key_idx, msg, msg_off, NULL, sig, count, nthreads, iters);
 }
 
-int dil_ref_verify_batch(int level, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
-                         const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count,
-                         int nthreads) {
+int dil_ref_verify_batch_ex(int level, int internal, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
+                            const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count,
+                            int nthreads) {
   batch_job j;
   memset(&j, 0, sizeof j);
-  if (dil_ref_params(level, &j.P)) return -1;
+  if (dil_ref_params(level, &j.P) || (internal && !j.P.mldsa)) return -1;
+  j.internal = internal;
   for (uint32_t t = 0; t < count; t++)
     if (msg_off[t + 1] < msg_off[t]) return -1;
   j.op = 2; j.level = level; j.in_key = pk; j.key_idx = key_idx; j.msg = msg; j.msg_off = msg_off;
   j.sig_in = sig; j.verdict = verdict;
   return run_batch(&j, count, nthreads);
+}
+
+int dil_ref_verify_batch(int level, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
+                         const uint64_t *msg_off, const uint8_t *sig, int32_t *verdict, uint32_t count,
+                         int nthreads) {
+  return dil_ref_verify_batch_ex(level, 0, pk, key_idx, msg, msg_off, sig, verdict, count, nthreads);
 }

@@ -11,7 +11,10 @@ against the standard stays unpinned.  What is pinned, independently of the oracl
     ExpandS, ExpandMask: each pinned on its own for round 3);
   * SampleInBall seeded by the whole ctilde (tau entries of +-1; every byte of ctilde matters);
   * the scheme properties: Verify(Sign) accepts, bit flips and the other variant reject, the
-    deterministic signer is the hedged one with rnd = 0."""
+    deterministic signer is the hedged one with rnd = 0;
+  * internal signing on a formatted message M' (mu = H(tr || M')): with M' = 0 || |ctx| || ctx
+    || M it is pure signing with context ctx (recomputed with hashlib for a non-empty ctx), the
+    empty context gives the pure signatures, and another context rejects."""
 import hashlib
 
 import numpy as np
@@ -106,23 +109,27 @@ def test_keygen_recomputed(orc, level):
 
 
 @pytest.mark.parametrize("level", LEVELS)
-@pytest.mark.parametrize("hedged", [False, True])
-def test_sign_recomputed(orc, level, hedged):
-    """Every ML-DSA-specific step of Sign recomputed from the signature it emits."""
+@pytest.mark.parametrize("hedged,ctx", [(False, b""), (True, b""), (False, b"context string"), (True, b"\x01" * 255)])
+def test_sign_recomputed(orc, level, hedged, ctx):
+    """Every ML-DSA-specific step of Sign recomputed from the signature it emits (a non-empty
+    context through internal signing of the formatted message)."""
     p = orc.params(level)
     k, l, ct = p["k"], p["l"], p["ct_bytes"]
     xi = workload.random_bytes("test/mldsa-xi", 100 + level, (32,)).tobytes()
     pk, sk = orc.keygen(level, xi)
     msg = workload.random_bytes("test/mldsa-m", level, (77,)).tobytes()
     rnd = workload.random_bytes("test/mldsa-rnd", level, (32,)).tobytes() if hedged else bytes(32)
-    sig, iters = orc.sign_batch(level, np.frombuffer(sk, np.uint8)[None], np.frombuffer(msg, np.uint8),
-                                np.array([0, len(msg)], np.uint64),
-                                rnd=np.frombuffer(rnd, np.uint8)[None] if hedged else None)
+    mprime = bytes([0, len(ctx)]) + ctx + msg
+    sm = mprime if ctx else msg
+    sig, iters = orc.sign_batch(level, np.frombuffer(sk, np.uint8)[None], np.frombuffer(sm, np.uint8),
+                                np.array([0, len(sm)], np.uint64),
+                                rnd=np.frombuffer(rnd, np.uint8)[None] if hedged else None, internal=bool(ctx))
     sig, it = sig[0].tobytes(), int(iters[0])
     assert len(sig) == p["sig_bytes"] and it >= 1
     tr, K = sk[64:128], sk[32:64]
-    mu = _h(tr + b"\x00\x00" + msg, 64)
-    assert orc.mldsa_mu(tr, msg) == mu
+    mu = _h(tr + mprime, 64)
+    if not ctx:
+        assert orc.mldsa_mu(tr, msg) == mu
     rhopp = _h(K + rnd + mu, 64)
     ctilde = sig[:ct]
     c = orc.sample_in_ball(level, ctilde).astype(np.int64)
@@ -151,7 +158,8 @@ def test_sign_recomputed(orc, level, hedged):
     r = np.mod(w - cs2 + ct0, Q)
     hint = orc.make_hint(np.mod(-ct0, Q).reshape(-1).astype(np.int32), r.reshape(-1).astype(np.int32), p["gamma2"])
     assert np.array_equal(_decode_hint(p, np.frombuffer(sig[ct + l * zb:], np.uint8)), hint.reshape(k, N))
-    assert orc.verify(level, pk, msg, sig) == 1
+    assert orc.mldsa_verify_internal(level, pk, mprime, sig) == 1
+    assert orc.verify(level, pk, msg, sig) == (0 if ctx else 1)
 
 
 @pytest.mark.parametrize("level", LEVELS)
@@ -203,3 +211,30 @@ def test_round_trip_and_rejections(orc, level):
         assert not np.array_equal(pk2, pk)
         sig2, _ = orc.sign_batch(2, sk2, msg, off)
         assert orc.verify_batch(44, pk2, msg, off, sig2).sum() == 0
+
+
+@pytest.mark.parametrize("level", LEVELS)
+def test_internal_mode_batches(orc, level):
+    """Batch drivers on formatted messages: the empty context reproduces pure signing and
+    verification, a context binds the signature to it, and round-3 levels have no internal mode."""
+    n = 6
+    pk, sk = orc.keygen_batch(level, workload.keygen_seeds(n, seed=500 + level))
+    lens = workload.uniform_lengths(n, 0, 150, seed=level)
+    msg, off = workload.messages(lens, seed=level)
+    msgs = [msg[int(off[i]):int(off[i + 1])].tobytes() for i in range(n)]
+
+    def csr(parts):
+        buf = np.frombuffer(b"".join(parts), np.uint8) if sum(map(len, parts)) else np.zeros(0, np.uint8)
+        return buf, np.concatenate([[0], np.cumsum([len(x) for x in parts])]).astype(np.uint64)
+
+    pure, _ = orc.sign_batch(level, sk, msg, off)
+    fm, foff = csr([orc.mldsa_format(m) for m in msgs])
+    assert np.array_equal(orc.sign_batch(level, sk, fm, foff, internal=True)[0], pure)
+    assert orc.verify_batch(level, pk, fm, foff, pure, internal=True).tolist() == [1] * n
+    cm, coff = csr([orc.mldsa_format(m, b"app-%d" % i) for i, m in enumerate(msgs)])
+    csig, _ = orc.sign_batch(level, sk, cm, coff, internal=True)
+    assert orc.verify_batch(level, pk, cm, coff, csig, internal=True).tolist() == [1] * n
+    assert orc.verify_batch(level, pk, msg, off, csig).tolist() == [0] * n          # context dropped
+    assert orc.verify_batch(level, pk, fm, foff, csig, internal=True).tolist() == [0] * n
+    with pytest.raises(ValueError):
+        orc.sign_batch(BASE[level], sk[:, :orc.params(BASE[level])["sk_bytes"]], msg, off, internal=True)
