@@ -119,6 +119,15 @@ int dil_ctx_set_mode(dil_ctx *ctx, int mode);
  *                   same unpadded, 2 one fused kernel that stores t0 in HBM
  *                   and reads it back, 3 an unpacking kernel then an NTT
  *                   kernel through HBM; other values are DIL_EINVAL;
+ *   "mldsa.internal" 0 (default) or 1: 1 makes the Sign and Verify calls of
+ *                   the ML-DSA levels take formatted messages M' and hash
+ *                   mu = H(tr || M') (FIPS 204's internal functions): the
+ *                   caller builds M' = 0x00 || |ctx| || ctx || M for a
+ *                   context string ctx (at most 255 bytes), or 0x01 || |ctx|
+ *                   || ctx || OID || PH(M) for the pre-hash form; 0 hashes
+ *                   tr || 0x00 || 0x00 || M (empty context).  A Sign or
+ *                   Verify call at levels 2 / 3 / 5 with 1 fails with
+ *                   DIL_EINVAL;
  *   "persist.tail"  slots per held task in the batches of a four-wavefront
  *                   workgroup once the work queue has run dry (rounded up to a
  *                   multiple of 4, at most the batch's slots): shorter last

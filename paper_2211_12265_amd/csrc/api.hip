@@ -41,6 +41,7 @@ struct dil_ctx {
   int ntt_variant = 0;                         // form of dil_ntt_mul_batch (0 = production kernel)
   int t0_variant = 0;                          // form of dil_t0_ntt_batch (0 = production code path)
   int persist_pad = 1;                         // 0: four-wavefront loop kernel on unpadded LDS transposes
+  int mldsa_internal = 0;                      // 1: ML-DSA messages are formatted messages M' (mu = H(tr || M'))
   static constexpr int RING = 64;
   hipEvent_t ev[RING][3] = {};                 // per timed call: before setup, before loop, after loop
   int ev_count = 0;                            // timed calls recorded since timing was (re)enabled
@@ -105,6 +106,12 @@ void drop_graphs(dil_ctx *ctx) {
 // round-3 levels 2 / 3 / 5 (Tab. 1) and the ML-DSA-44 / 65 / 87 parameter sets of FIPS 204
 bool valid_level(int lv) { return lv == 2 || lv == 3 || lv == 5 || lv == 44 || lv == 65 || lv == 87; }
 bool mldsa_level(int lv) { return lv == 44 || lv == 65 || lv == 87; }
+// Sign / Verify calls on formatted messages ("mldsa.internal") exist at the ML-DSA levels only
+int check_form(dil_ctx *ctx, int level) {
+  if (ctx->mldsa_internal && !mldsa_level(level))
+    return fail(ctx, DIL_EINVAL, "mldsa.internal = 1 applies to the ML-DSA levels 44 / 65 / 87");
+  return DIL_OK;
+}
 constexpr int lv_slot(int lv) { return lv == 2 ? 0 : lv == 3 ? 1 : lv == 5 ? 2 : lv == 44 ? 3 : lv == 65 ? 4 : 5; }
 
 // The kinds of call a workspace is laid out for: each carves only the
@@ -355,7 +362,13 @@ int sign_setup(dil_ctx *ctx, Ws &ws, const uint8_t *sk, const uint32_t *key_idx,
     int rc = fork_side(ctx, st);
     if (rc) return rc;
   }
-  sg_prep_k<LV><<<blocks_for(2 * (uint64_t)count, 256), 256, 0, st>>>(sk, key_idx, msg, msg_off, rnd, ws, count, err);
+  const unsigned nb = blocks_for(2 * (uint64_t)count, 256);
+  bool internal = false;
+  if constexpr (Lv<LV>::MLDSA) internal = ctx->mldsa_internal;
+  if constexpr (Lv<LV>::MLDSA) {
+    if (internal) sg_prep_k<LV, true><<<nb, 256, 0, st>>>(sk, key_idx, msg, msg_off, rnd, ws, count, err);
+  }
+  if (!internal) sg_prep_k<LV><<<nb, 256, 0, st>>>(sk, key_idx, msg, msg_off, rnd, ws, count, err);
   if (!ks) {
     hipStream_t s1 = concurrent ? ctx->side[0] : st, s2 = concurrent ? ctx->side[1] : st;
     expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, EA_WG), EA_WG, 0, s1>>>(sk, P<LV>::SK, key_idx, ws.A, count);
@@ -486,7 +499,7 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   if (ks) key_idx = use_keyset(ws, ks, key_idx, kid);
   uint64_t key[16] = {1, (uint64_t)LV, (uint64_t)sk, (uint64_t)key_in, (uint64_t)msg, (uint64_t)msg_off,
                       (uint64_t)sig, count, (uint64_t)ks, grid, hmax, (uint64_t)ctx->ws_mem, 0, (uint64_t)waves,
-                      (uint64_t)rnd, 0};
+                      (uint64_t)rnd, (uint64_t)ctx->mldsa_internal};
   hipEvent_t *evs = ctx->timing ? ctx->ev[ctx->ev_count % dil_ctx::RING] : nullptr;
   if (evs) HIPCHK(ctx, hipEventRecord(evs[0], st));
   rc = enqueue(ctx, key, st, [&](hipStream_t s) {
@@ -528,6 +541,20 @@ int sign_persistent(dil_ctx *ctx, const uint8_t *sk, const uint32_t *key_idx, co
   return mark_done(ctx, st);
 }
 
+// Verify's tr / mu kernel in the context's message form
+template <int LV>
+void launch_vf_hash(const dil_ctx *ctx, hipStream_t st, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
+                    const uint64_t *msg_off, const Ws &ws, uint32_t count, uint32_t *err) {
+  const unsigned nb = blocks_for(2 * (uint64_t)count, 64);
+  if constexpr (Lv<LV>::MLDSA) {
+    if (ctx->mldsa_internal) {
+      vf_hash_k<LV, true><<<nb, 64, 0, st>>>(pk, key_idx, msg, msg_off, ws, count, err);
+      return;
+    }
+  }
+  vf_hash_k<LV><<<nb, 64, 0, st>>>(pk, key_idx, msg, msg_off, ws, count, err);
+}
+
 template <int LV>
 int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg, const uint64_t *msg_off,
                 const uint8_t *sig, int32_t *verdict, uint32_t count, hipStream_t st,
@@ -540,7 +567,8 @@ int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const 
   const uint32_t *key_in = key_idx;
   if (ks) key_idx = use_keyset(ws, ks, key_idx, kid);
   uint64_t key[16] = {2, (uint64_t)LV, (uint64_t)pk, (uint64_t)key_in, (uint64_t)msg, (uint64_t)msg_off,
-                      (uint64_t)sig, (uint64_t)verdict, count, (uint64_t)ks, (uint64_t)ctx->ws_mem, 0, 0, 0, 0, 0};
+                      (uint64_t)sig, (uint64_t)verdict, count, (uint64_t)ks, (uint64_t)ctx->ws_mem, 0, 0, 0, 0,
+                      (uint64_t)ctx->mldsa_internal};
   rc = enqueue(ctx, key, st, [&](hipStream_t s) {
     zero_words_k<<<1, 64, 0, s>>>(ws.counters, 16, nullptr, 0);
     check_keys(ctx, ks, key_in, kid, count, s);
@@ -556,8 +584,7 @@ int verify_impl(dil_ctx *ctx, const uint8_t *pk, const uint32_t *key_idx, const 
       if (r2) return r2;
     }
     hipStream_t s_hash = conc ? ctx->side[1] : s, s_ea = conc ? ctx->side[0] : s;
-    vf_hash_k<LV><<<blocks_for(2 * (uint64_t)count, 64), 64, 0, s_hash>>>(pk, key_idx, msg, msg_off, ws, count,
-                                                            ctx->dev_stats + 8);
+    launch_vf_hash<LV>(ctx, s_hash, pk, key_idx, msg, msg_off, ws, count, ctx->dev_stats + 8);
     if (!ks)
       expand_a_k<LV><<<blocks_for((uint64_t)count * K * L, EA_WG), EA_WG, 0, s_ea>>>(pk, P<LV>::PK, key_idx, ws.A,
                                                                                 count);
@@ -785,7 +812,10 @@ int dil_ctx_set_param(dil_ctx *ctx, const char *name, int64_t value) {
     if (!ctx->use_graph) drop_graphs(ctx);
   } else if (!strcmp(name, "persist.grid")) ctx->persist_grid = value;
   else if (!strcmp(name, "persist.hmax")) ctx->persist_hmax = value;
-  else if (!strcmp(name, "persist.tail")) {
+  else if (!strcmp(name, "mldsa.internal")) {
+    if (value != 0 && value != 1) return fail(ctx, DIL_EINVAL, "mldsa.internal must be 0 or 1");
+    ctx->mldsa_internal = (int)value;
+  } else if (!strcmp(name, "persist.tail")) {
     if (value < -1 || value > 64) return fail(ctx, DIL_EINVAL, "persist.tail must be -1..64");
     ctx->persist_tail = (int)value;
   }
@@ -838,6 +868,7 @@ int dil_sign_batch_rnd(dil_ctx *ctx, int level, const uint8_t *sk, const uint32_
   if (count == 0) return DIL_OK;
   if (!sk || !msg || !msg_off || !sig) return fail(ctx, DIL_EINVAL, "null buffer");
   if ((uintptr_t)rnd & 3) return fail(ctx, DIL_EINVAL, "rnd must be 4-byte aligned");
+  if (check_form(ctx, level)) return DIL_EINVAL;
   hipSetDevice(ctx->device);
   ctx->stats_pending = 0;
   return by_level(level, [&](auto lv) {
@@ -854,6 +885,7 @@ int dil_verify_batch(dil_ctx *ctx, int level, const uint8_t *pk, const uint32_t 
   if (!ctx || !valid_level(level)) return fail(ctx, DIL_EINVAL, "bad context or level");
   if (count == 0) return DIL_OK;
   if (!pk || !msg || !msg_off || !sig || !verdict) return fail(ctx, DIL_EINVAL, "null buffer");
+  if (check_form(ctx, level)) return DIL_EINVAL;
   hipSetDevice(ctx->device);
   return by_level(level, [&](auto lv) {
     return verify_impl<decltype(lv)::value>(ctx, pk, key_idx, msg, msg_off, sig, verdict, count,
@@ -907,6 +939,7 @@ int dil_sign_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_idx,
   if (count == 0) return DIL_OK;
   if (!msg || !msg_off || !sig) return fail(ctx, DIL_EINVAL, "null buffer");
   if (!key_idx && count > ks->nkeys) return fail(ctx, DIL_EINVAL, "more tasks than keys without key_idx");
+  if (check_form(ctx, ks->level)) return DIL_EINVAL;
   hipSetDevice(ctx->device);
   ctx->stats_pending = 0;
   return by_level(ks->level, [&](auto lv) {
@@ -943,8 +976,7 @@ int verify_keyset_noalloc_impl(dil_ctx *ctx, const dil_keyset *ks, const uint32_
   const uint32_t *kidx = use_keyset(ws, ks, key_idx, kid);
   zero_words_k<<<1, 64, 0, st>>>(ws.counters, 16, nullptr, 0);
   check_keys(ctx, ks, key_idx, kid, count, st);
-  vf_hash_k<LV><<<blocks_for(2 * (uint64_t)count, 64), 64, 0, st>>>(ks->pk, kidx, msg, msg_off, ws, count,
-                                                                    ctx->dev_stats + ERR_WORD_MSG);
+  launch_vf_hash<LV>(ctx, st, ks->pk, kidx, msg, msg_off, ws, count, ctx->dev_stats + ERR_WORD_MSG);
   vf_prep_k<LV><<<blocks_for(count, 64), 64, 0, st>>>(sig, ws, count);
   vf_main_k<LV><<<count, 64, 0, st>>>(ks->pk, kidx, sig, ws, count);
   vf_final_k<LV><<<blocks_for(2 * (uint64_t)count, 256), 256, 0, st>>>(sig, ws, verdict, count);
@@ -964,6 +996,7 @@ int dil_verify_keyset_noalloc(dil_ctx *ctx, const dil_keyset *ks, const uint32_t
   if (count == 0) return DIL_OK;
   if (!msg || !msg_off || !sig || !verdict) return fail(ctx, DIL_EINVAL, "null buffer");
   if (!key_idx && count > ks->nkeys) return fail(ctx, DIL_EINVAL, "more tasks than keys without key_idx");
+  if (check_form(ctx, ks->level)) return DIL_EINVAL;
   hipSetDevice(ctx->device);
   return by_level(ks->level, [&](auto lv) {
     return verify_keyset_noalloc_impl<decltype(lv)::value>(ctx, ks, key_idx, msg, msg_off, sig, verdict, count,
@@ -978,6 +1011,7 @@ int dil_verify_keyset(dil_ctx *ctx, const dil_keyset *ks, const uint32_t *key_id
   if (count == 0) return DIL_OK;
   if (!msg || !msg_off || !sig || !verdict) return fail(ctx, DIL_EINVAL, "null buffer");
   if (!key_idx && count > ks->nkeys) return fail(ctx, DIL_EINVAL, "more tasks than keys without key_idx");
+  if (check_form(ctx, ks->level)) return DIL_EINVAL;
   hipSetDevice(ctx->device);
   return by_level(ks->level, [&](auto lv) {
     return verify_impl<decltype(lv)::value>(ctx, ks->pk, key_idx, msg, msg_off, sig, verdict, count,

@@ -44,6 +44,15 @@ struct Ws {
 
 constexpr int CT_STRIDE = 64;  // workspace row of a ctilde (the longest, ML-DSA-87's)
 
+// bytes hashed before the message for mu: tr (round 3), tr || 0x00 || 0x00
+// (ML-DSA, empty context) or tr alone before a formatted message (ML-DSA's
+// internal form)
+template <int LV, bool INTERNAL>
+constexpr int mu_prefix_bytes() {
+  static_assert(!INTERNAL || Lv<LV>::MLDSA, "formatted messages exist at the ML-DSA levels only");
+  return !Lv<LV>::MLDSA ? 32 : INTERNAL ? 64 : 66;
+}
+
 // row of the per-key arrays used by task `task`
 __device__ __forceinline__ size_t kix(const Ws &ws, uint32_t task) { return ws.kmap ? ws.kmap[task] : task; }
 
@@ -371,9 +380,12 @@ __global__ void __launch_bounds__(256) kg_tr_k(const uint8_t *pk, uint8_t *sk, u
 //   round 3: mu = H(tr || M); rho' = H(K || mu), or the task's 64 rnd bytes
 //            themselves (randomized signing) when rnd is not null;
 //   ML-DSA:  mu = H(tr || 0x00 || 0x00 || M); rho'' = H(K || rnd || mu) with
-//            the task's 32 rnd bytes, or 32 zero bytes when rnd is null.
+//            the task's 32 rnd bytes, or 32 zero bytes when rnd is null;
+//            with INTERNAL the messages are formatted messages M' (a context
+//            string or the pre-hash form, built by the caller) and mu =
+//            H(tr || M').
 // rnd rows are 4-byte aligned.
-template <int LV>
+template <int LV, bool INTERNAL = false>
 __global__ void __launch_bounds__(256) sg_prep_k(const uint8_t *sk, const uint32_t *key_idx, const uint8_t *msg,
                                                  const uint64_t *msg_off, const uint8_t *rnd, Ws ws, uint32_t count,
                                                  uint32_t *err) {
@@ -396,7 +408,7 @@ __global__ void __launch_bounds__(256) sg_prep_k(const uint8_t *sk, const uint32
   const uint32_t *skw = (const uint32_t *)(skr + 64);  // tr inside the 8-byte aligned sk row
 #pragma unroll
   for (int i = 0; i < TW; i++) trw[i] = skw[i];
-  absorb_prefix_msg<Lv<LV>::MLDSA ? 66 : 32>(a, half, trw, msg + o0, mlen);
+  absorb_prefix_msg<mu_prefix_bytes<LV, INTERNAL>()>(a, half, trw, msg + o0, mlen);
   uint32_t mu[8];  // this lane's halves of mu's eight 8-byte words
   uint32_t *muw = (uint32_t *)(ws.muw1 + (size_t)t * muw1_stride<LV>());
 #pragma unroll
@@ -788,8 +800,9 @@ __global__ void __launch_bounds__(64) sg_check_k(Ws ws, uint8_t *sig, const uint
 // Verify (Alg. 3), staged
 // ------------------------------------------------------------------------
 // tr = H(pk) (unless resident) and mu = H(tr || M) (ML-DSA: H(tr || 0x00 ||
-// 0x00 || M)), two lanes per task (keccak_pair.h)
-template <int LV>
+// 0x00 || M), or H(tr || M') of formatted messages with INTERNAL), two lanes
+// per task (keccak_pair.h)
+template <int LV, bool INTERNAL = false>
 __global__ void __launch_bounds__(64) vf_hash_k(const uint8_t *pk, const uint32_t *key_idx, const uint8_t *msg,
                                                 const uint64_t *msg_off, Ws ws, uint32_t count, uint32_t *err) {
   using PP = P<LV>;
@@ -820,7 +833,7 @@ __global__ void __launch_bounds__(64) vf_hash_k(const uint8_t *pk, const uint32_
   uint64_t mlen = 0;
   if (o1 >= o0) mlen = o1 - o0;
   else if (!half) atomicOr(err, 1u);  // decreasing msg_off: message treated as empty
-  absorb_prefix_msg<Lv<LV>::MLDSA ? 66 : 32>(a, half, trw, msg + o0, mlen);
+  absorb_prefix_msg<mu_prefix_bytes<LV, INTERNAL>()>(a, half, trw, msg + o0, mlen);
   uint32_t *muw = (uint32_t *)(ws.muw1 + (size_t)t * muw1_stride<LV>());
 #pragma unroll
   for (int i = 0; i < 8; i++) muw[2 * i + half] = a[i];

@@ -1,11 +1,12 @@
 // The SHAKE256 input blocks of a message representative, X = prefix || M,
 // built word by word from the message bytes in memory: mu = H(tr || M) in
-// round 3 (Alg. 2 and 3), and mu = H(tr || 0x00 || 0x00 || M) in ML-DSA's pure
-// form with an empty context (FIPS 204, which the paper does not cover).
+// round 3 (Alg. 2 and 3), mu = H(tr || 0x00 || 0x00 || M) in ML-DSA's pure
+// form with an empty context and mu = H(tr || M') of a formatted message in
+// its internal form (FIPS 204, which the paper does not cover).
 //
 // The prefix is PB bytes: PB / 4 whole words given by the caller (tr), and
-// DL = PB % 4 zero bytes in the word where M begins (PB = 32: DL = 0; PB =
-// 66: DL = 2).  M has any length and any byte alignment.  Each 136-byte block
+// DL = PB % 4 zero bytes in the word where M begins (PB = 32 or 64: DL = 0;
+// PB = 66: DL = 2).  M has any length and any byte alignment.  Each 136-byte block
 // is 34 little-endian words; its message words are fetched as the aligned
 // dwords that cover them and funnel-shifted by one constant amount, bytes
 // past the end of M are masked, and the SHAKE suffix and padding are added

@@ -2,7 +2,7 @@
 // (paper_2211_12265_amd/csrc/msg_words.h), built with AddressSanitizer and
 // UndefinedBehaviorSanitizer by tests/test_host_msg_words.py.
 //
-// For a prefix of PB bytes (32: tr; 66: tr || 0x00 || 0x00), every byte
+// For a prefix of PB bytes (32 or 64: tr; 66: tr || 0x00 || 0x00), every byte
 // misalignment of M and every length from 0 to MAXLEN, it builds all SHAKE256
 // input blocks the way the device absorption does (first block with the
 // prefix words, later blocks with the next block's dwords fetched ahead) and
@@ -101,6 +101,7 @@ int main(int argc, char **argv) {
   const int pb = atoi(argv[1]), maxlen = atoi(argv[2]);
   uint64_t n;
   if (pb == 32) n = run<32>(maxlen);
+  else if (pb == 64) n = run<64>(maxlen);
   else if (pb == 66) n = run<66>(maxlen);
   else return 2;
   printf("ok PB=%d cases=%llu\n", pb, (unsigned long long)n);

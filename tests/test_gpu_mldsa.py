@@ -240,3 +240,70 @@ def test_ten_thousand_tasks(level):
         assert _verify(c, level, pk, msg, off, sig).sum() == n
     finally:
         c.close()
+
+
+def _csr(parts):
+    buf = np.frombuffer(b"".join(parts), np.uint8).copy() if sum(map(len, parts)) else np.zeros(0, np.uint8)
+    return buf, np.concatenate([[0], np.cumsum([len(x) for x in parts])]).astype(np.uint64)
+
+
+@pytest.mark.parametrize("level", LEVELS)
+def test_formatted_messages_parity(sctx, level):
+    """"mldsa.internal": Sign and Verify of formatted messages M' (context strings of 0..255
+    bytes) equal the oracle's internal functions, the empty context reproduces pure signing,
+    a signature does not verify under another context, and key tables take the same form."""
+    from paper_2211_12265_amd import dilithium as dl
+    n = 40
+    pk, sk = _keygen(sctx, level, workload.keygen_seeds(n, seed=260 + level))
+    lens = workload.uniform_lengths(n, 0, 300, seed=261 + level)
+    msg, off = workload.messages(lens, seed=261 + level)
+    msgs = [msg[int(off[i]):int(off[i + 1])].tobytes() for i in range(n)]
+    ctxs = [workload.random_bytes("test/mldsa-ctx", 7 * i + level, (i * 37 % 256,)).tobytes() for i in range(n)]
+    fm, foff = _csr([oracle.mldsa_format(m, c) for m, c in zip(msgs, ctxs)])
+    em, eoff = _csr([oracle.mldsa_format(m) for m in msgs])
+    rnd = workload.random_bytes("dil/mldsa-rnd", 100 + level, (n, 32))
+    osig, _ = oracle.sign_batch(level, sk.cpu().numpy(), fm, foff, internal=True)
+    ohedged, _ = oracle.sign_batch(level, sk.cpu().numpy(), fm, foff, rnd=rnd, internal=True)
+    pure = _sign(sctx, level, sk, msg, off).cpu().numpy()
+    sctx.set_param("mldsa.internal", 1)
+    try:
+        got = _sign(sctx, level, sk, fm, foff)
+        assert np.array_equal(got.cpu().numpy(), osig)
+        assert np.array_equal(_sign(sctx, level, sk, fm, foff, rnd=rnd).cpu().numpy(), ohedged)
+        assert np.array_equal(_sign(sctx, level, sk, em, eoff).cpu().numpy(), pure)
+        assert _verify(sctx, level, pk, fm, foff, got).tolist() == [1] * n
+        assert _verify(sctx, level, pk, em, eoff, got).tolist() == [int(not c) for c in ctxs]
+        ks = dl.KeySet(sctx, level, pk=pk, sk=sk)
+        try:
+            sig = torch.zeros((n, dl.sizes(level)[2]), dtype=torch.uint8, device="cuda")
+            ks.sign(sctx, None, dev(fm), dev(foff.astype(np.int64)), sig)
+            v = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+            ks.verify(sctx, None, dev(fm), dev(foff.astype(np.int64)), sig, v)
+            v_na = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+            ks.verify(sctx, None, dev(fm), dev(foff.astype(np.int64)), sig, v_na, noalloc=True)
+            torch.cuda.synchronize()
+            assert np.array_equal(sig.cpu().numpy(), osig)
+            assert v.cpu().numpy().tolist() == [1] * n and v_na.cpu().numpy().tolist() == [1] * n
+        finally:
+            ks.close()
+    finally:
+        sctx.set_param("mldsa.internal", 0)
+    # pure mode again on the same context
+    assert np.array_equal(_sign(sctx, level, sk, msg, off).cpu().numpy(), pure)
+
+
+def test_formatted_messages_only_at_mldsa_levels(ctx):
+    from paper_2211_12265_amd import dilithium as dl
+    pk, sk = _keygen(ctx, 2, workload.keygen_seeds(2, seed=270))
+    msg, off = workload.messages(workload.fixed_lengths(2, 32), seed=270)
+    with pytest.raises(dl.DilError):
+        ctx.set_param("mldsa.internal", 2)
+    ctx.set_param("mldsa.internal", 1)
+    try:
+        with pytest.raises(dl.DilError):
+            _sign(ctx, 2, sk, msg, off)
+        with pytest.raises(dl.DilError):
+            _verify(ctx, 2, pk, msg, off, torch.zeros((2, dl.sizes(2)[2]), dtype=torch.uint8, device="cuda"))
+    finally:
+        ctx.set_param("mldsa.internal", 0)
+    torch.cuda.synchronize()

@@ -1,7 +1,8 @@
 """The SHAKE256 input blocks of mu = H(prefix || M) as the Sign and Verify kernels build them from
 message bytes in memory (paper_2211_12265_amd/csrc/msg_words.h), replayed on the host under
 AddressSanitizer and UndefinedBehaviorSanitizer (tests/msg_words_replay.cpp): for the round-3
-prefix tr (32 bytes) and ML-DSA's tr || 0x00 || 0x00 (66 bytes), every byte misalignment of M and
+prefix tr (32 bytes), ML-DSA's tr || 0x00 || 0x00 (66 bytes) and its tr alone before a
+formatted message (64 bytes), every byte misalignment of M and
 every length up to five blocks, the blocks equal the padded definition and no dword outside the
 ones holding M's bytes is read."""
 import os
@@ -33,10 +34,10 @@ def test_kernels_use_the_replayed_code():
     assert '#include "msg_words.h"' in src
     assert "mw_fetch<" in src and "mw_word<" in src and "MwPlan<" in src
     kern = open(os.path.join(CSRC, "kernels.h")).read()
-    assert len(re.findall(r"absorb_prefix_msg<", kern)) == 2
+    assert len(re.findall(r"absorb_prefix_msg<mu_prefix_bytes<LV, INTERNAL>\(\)>", kern)) == 2
 
 
-@pytest.mark.parametrize("prefix", [32, 66])
+@pytest.mark.parametrize("prefix", [32, 64, 66])
 def test_blocks_match_definition(replay, prefix):
     res = subprocess.run([replay, str(prefix), "700"], capture_output=True, text=True, timeout=300)
     assert res.returncode == 0, res.stdout + res.stderr
