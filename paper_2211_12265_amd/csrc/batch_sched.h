@@ -77,6 +77,39 @@ DIL_HD int sched_assign(int nh, int ns, uint32_t *h_next, uint32_t *h_win, uint8
   return ns;
 }
 
+// The same batch laid out task by task: held task h takes c_h consecutive
+// slots (c_h = ns / nh, one more for h < ns mod nh) at its nonce indices
+// h_next, h_next + 1, ...; then h_next and h_win as in sched_assign.  A kernel
+// that gives each wavefront a contiguous range of slots then keeps most of a
+// task's candidates on one wavefront, one after another, so that the task's
+// A-hat and secret polynomials are fetched from cache after its first
+// candidate.  Returns ns (0 when nothing is held).
+DIL_HD int sched_assign_contig(int nh, int ns, uint32_t *h_next, uint32_t *h_win, uint8_t *s_h,
+                               uint32_t *s_att) {
+  if (!nh) ns = 0;
+  int s = 0;
+  for (int h = 0; h < nh; h++) {
+    const int cnt = ns / nh + (h < ns % nh ? 1 : 0);
+    for (int j = 0; j < cnt; j++, s++) {
+      s_h[s] = (uint8_t)h;
+      s_att[s] = h_next[h] + (uint32_t)j;
+    }
+    h_next[h] += (uint32_t)cnt;
+    h_win[h] = SCHED_NONE;
+  }
+  return ns;
+}
+
+// The range [lo, hi) of a batch's ns slots that wavefront `wave` of W takes
+// when each takes a contiguous range: ceil(ns / W) slots each, the last ones
+// fewer or none.
+DIL_HD void sched_wave_range(int ns, int W, int wave, int &lo, int &hi) {
+  const int pw = (ns + W - 1) / W;
+  lo = wave * pw;
+  hi = lo + pw < ns ? lo + pw : ns;
+  if (hi < lo) hi = lo;
+}
+
 // Drop the tasks signed in this batch (adding winning index + 1 to
 // `sequential`) and those that reached max_attempts without a passing nonce
 // (counted in `dropped`), keeping the rest in order.  Returns the new nh.

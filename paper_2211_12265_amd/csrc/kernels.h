@@ -506,13 +506,22 @@ __device__ __forceinline__ void dev_expand_mask(const uint8_t *rhop, uint32_t ka
 // w_out, HighBits(w) packed into w1_out (4-byte aligned, K * W1B bytes).
 // hat: L * HAT_POLY words of LDS; tr: this group's transpose region; w1buf: LDS
 // staging; ftw / itw: forward / inverse twiddles.
-template <int LV, bool PAD = true, class TW>
+// EARLY: the group's first A-hat polynomial (row g, column 0) is requested
+// before the NTT of y, and each next one before the current one is multiplied.
+// The fences of the NTT's LDS transposes keep the compiler from hoisting these
+// loads by itself, which leaves each load's latency exposed; requesting them
+// early costs 16 registers per lane, which only the l = 4 loop kernels have.
+template <int LV, bool PAD = true, bool EARLY = false, class TW>
 __device__ __forceinline__ void dev_compute_w(const int32_t *y, const int32_t *A, int32_t *w_out, uint8_t *w1_out,
                                               int32_t *hat, int32_t *tr, uint32_t *w1buf, const TW &ftw,
                                               const TW &itw, int lane) {
   using PP = P<LV>;
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L;
   int g = lane >> 4, t = lane & 15;
+  int32_t an[16];
+  if constexpr (EARLY) {
+    if (g < K) load_slots(an, A + (size_t)g * L * N, t);
+  }
   for (int j = g; j < L; j += 4) {
     int32_t x[16];
     load_strided(x, y + j * N, t);
@@ -526,11 +535,23 @@ __device__ __forceinline__ void dev_compute_w(const int32_t *y, const int32_t *A
     int64_t acc[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) acc[r] = 0;
-    for (int j = 0; j < L; j++) {
-      int32_t a[16];
-      load_slots(a, Ai + j * N, t);
+    if constexpr (EARLY) {
+      for (int j = 0; j < L; j++) {
+        int32_t a[16];
 #pragma unroll
-      for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * hat[hat_idx(j, t, r)];
+        for (int r = 0; r < 16; r++) a[r] = an[r];
+        if (j + 1 < L) load_slots(an, Ai + (j + 1) * N, t);
+        else if (i + 4 < K) load_slots(an, A + (size_t)(i + 4) * L * N, t);
+#pragma unroll
+        for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * hat[hat_idx(j, t, r)];
+      }
+    } else {
+      for (int j = 0; j < L; j++) {
+        int32_t a[16];
+        load_slots(a, Ai + j * N, t);
+#pragma unroll
+        for (int r = 0; r < 16; r++) acc[r] += (int64_t)a[r] * hat[hat_idx(j, t, r)];
+      }
     }
     int32_t x[16];
 #pragma unroll
@@ -621,8 +642,10 @@ struct CheckLds {
 // challenge (int8, natural order).  Returns true (wave-uniform) if the
 // candidate passes all four checks; the packed signature (ctilde, z, h) is
 // then in lds.sigbuf.  Polynomials whose norm already fails stop the
-// evaluation early.
-template <int LV, bool PAD = true, class TW>
+// evaluation early.  EARLY (as in dev_compute_w): the group's first s1-hat
+// and y polynomials are requested before the NTT of c, the next ones before
+// the current one's INTT, and a row's w and t0-hat together with its s2-hat.
+template <int LV, bool PAD = true, bool EARLY = false, class TW>
 __device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctilde, const int32_t *y, const int32_t *w,
                                           const int32_t *s1h, const int32_t *s2h, const int32_t *t0h,
                                           CheckLds<LV> &lds, const TW &ftw, const TW &itw, int lane) {
@@ -636,17 +659,35 @@ __device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctild
   int32_t ch[16];
 #pragma unroll
   for (int r = 0; r < 16; r++) ch[r] = c[t + 16 * r];
+  int32_t s1n[16], yn[16];
+  if constexpr (EARLY) {
+    if (g < L) {
+      load_slots(s1n, s1h + g * N, t);
+      load_strided(yn, y + g * N, t);
+    }
+  }
   ntt16<TW, PAD>(ch, ftw, tr, t);
   bool bad = false;
   // z = y + c s1
   for (int j = g; j < L; j += 4) {
-    int32_t s1[16], x[16];
-    load_slots(s1, s1h + j * N, t);
+    int32_t s1[16], x[16], yv[16];
+    if constexpr (EARLY) {
+#pragma unroll
+      for (int r = 0; r < 16; r++) {
+        s1[r] = s1n[r];
+        yv[r] = yn[r];
+      }
+      if (j + 4 < L) {
+        load_slots(s1n, s1h + (j + 4) * N, t);
+        load_strided(yn, y + (j + 4) * N, t);
+      }
+    } else {
+      load_slots(s1, s1h + j * N, t);
+    }
 #pragma unroll
     for (int r = 0; r < 16; r++) x[r] = mont_mul(ch[r], s1[r]);
     intt16<TW, PAD>(x, itw, tr, t);
-    int32_t yv[16];
-    load_strided(yv, y + j * N, t);
+    if constexpr (!EARLY) load_strided(yv, y + j * N, t);
     int32_t zv[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) {
@@ -662,13 +703,16 @@ __device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctild
   if (wave_any(bad)) return false;
   // r0 = LowBits(w - c s2), c t0 and the hint
   for (int i = g; i < K; i += 4) {
-    int32_t s2[16], x[16], u[16];
+    int32_t s2[16], x[16], u[16], wv[16];
     load_slots(s2, s2h + i * N, t);
+    if constexpr (EARLY) {
+      load_strided(wv, w + i * N, t);
+      load_slots(u, t0h + i * N, t);
+    }
 #pragma unroll
     for (int r = 0; r < 16; r++) x[r] = mont_mul(ch[r], s2[r]);
     intt16<TW, PAD>(x, itw, tr, t);
-    int32_t wv[16];
-    load_strided(wv, w + i * N, t);
+    if constexpr (!EARLY) load_strided(wv, w + i * N, t);
     int32_t r1v[16];
 #pragma unroll
     for (int r = 0; r < 16; r++) {
@@ -678,7 +722,7 @@ __device__ __forceinline__ bool dev_check(const int8_t *c, const uint32_t *ctild
       r1v[r] = r1;
       bad |= (r0 >= G2 - BETA) || (r0 <= -(G2 - BETA));
     }
-    load_slots(u, t0h + i * N, t);
+    if constexpr (!EARLY) load_slots(u, t0h + i * N, t);
 #pragma unroll
     for (int r = 0; r < 16; r++) u[r] = mont_mul(ch[r], u[r]);
     intt16<TW, PAD>(u, itw, tr, t);

@@ -237,6 +237,16 @@ namespace dil {
 // workgroup and batch index so the SIMDs stay balanced.  Passing candidates
 // are staged per slot and the smallest passing nonce of each task is copied
 // to the output after a barrier.
+//
+// At l = 4 (four wavefronts, padded transposes) the batch is laid out task by
+// task instead (sched_assign_contig) and wavefront w takes the contiguous
+// range sched_wave_range(ns, 4, w): it runs ExpandMask for its own slots
+// (one lane per stream, at most 16 slots x 4 streams) and goes on to their w
+// phase after a fence of its own, with no workgroup barrier between the two,
+// and its w and check phases request their operands early (EARLY in
+// dev_compute_w / dev_check).  A task's candidates then follow one another on
+// one wavefront and reuse its A-hat and secrets from cache.  The registers
+// this takes fit two wavefronts per SIMD at l = 4 only.
 // ---------------------------------------------------------------------------
 template <int LV, int NW>
 struct PCfgW {
@@ -322,7 +332,9 @@ template <int LV, int NW, bool PAD = true, bool TAIL = false>
 __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t *sig, uint32_t count,
                                                      uint32_t sched, uint32_t *stats) {
   constexpr int K = Lv<LV>::K, L = Lv<LV>::L, G = PCfgW<LV, NW>::G, W = NW;
+  constexpr bool CONTIG = NW == 4 && L == 4 && PAD;  // contiguous slot ranges per wavefront
   static_assert(G <= 64, "the winner search takes one slot per lane");
+  static_assert(!CONTIG || PCfgW<LV, NW>::GW * L <= 64, "a wavefront's own slots take one ExpandMask lane per stream");
   __shared__ PersistWLds<LV, NW> lds;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, t = lane & 15;
   const size_t wg = blockIdx.x;
@@ -349,8 +361,9 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
       if (!lds.queue_empty && nh < hmax) nh = claim_tasks(ws.counters, count, (uint32_t)(hmax - nh), nh, lds.h_task,
                                                           lds.h_next, lds.queue_empty);
       lds.nheld = nh;
-      const int ns = sched_assign(nh, TAIL ? sched_slots(nh, G, W, lds.queue_empty, tail) : G, lds.h_next,
-                                  lds.h_win, lds.s_h, lds.s_att);
+      const int want = TAIL ? sched_slots(nh, G, W, lds.queue_empty, tail) : G;
+      const int ns = CONTIG ? sched_assign_contig(nh, want, lds.h_next, lds.h_win, lds.s_h, lds.s_att)
+                            : sched_assign(nh, want, lds.h_next, lds.h_win, lds.s_h, lds.s_att);
       lds.nslots = ns;
       lds.tally.evaluated += (uint64_t)ns;
     }
@@ -358,19 +371,37 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
     const int ns = lds.nslots;
     if (ns == 0) break;
     PHASE_MARK(0);
-    // ExpandMask: one thread per (slot, i)
-    if (tid < ns * L) {
-      int s = tid / L, i = tid % L;
-      uint32_t task = lds.h_task[lds.s_h[s]];
-      dev_expand_mask<LV>(ws.rhop + (size_t)task * 64, lds.s_att[s] * (uint32_t)L, i, yb + si.y(0, s, i));
+    // the slots this wave takes in the w and check phases: w, w + W, ...
+    // (CONTIG: its own range [s_lo, s_hi))
+    int s_lo = wave, s_hi = ns;
+    if constexpr (CONTIG) sched_wave_range(ns, W, wave, s_lo, s_hi);
+    constexpr int s_step = CONTIG ? 1 : W;
+    if constexpr (CONTIG) {
+      // ExpandMask of the wave's own slots, one lane per (slot, i); the y
+      // rows it writes are read back by other lanes of the same wave only
+      if (s_lo + lane / L < s_hi) {
+        int s = s_lo + lane / L, i = lane % L;
+        uint32_t task = lds.h_task[lds.s_h[s]];
+        dev_expand_mask<LV>(ws.rhop + (size_t)task * 64, lds.s_att[s] * (uint32_t)L, i, yb + si.y(0, s, i));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else {
+      // ExpandMask: one thread per (slot, i)
+      if (tid < ns * L) {
+        int s = tid / L, i = tid % L;
+        uint32_t task = lds.h_task[lds.s_h[s]];
+        dev_expand_mask<LV>(ws.rhop + (size_t)task * 64, lds.s_att[s] * (uint32_t)L, i, yb + si.y(0, s, i));
+      }
+      __threadfence_block();
+      __syncthreads();
     }
-    __threadfence_block();
-    __syncthreads();
     PHASE_MARK(1);
-    // w per slot, wave w takes slots w, w + 4, ...
-    for (int s = wave; s < ns; s += W) {
+    // w per slot
+    for (int s = s_lo; s < s_hi; s += s_step) {
       uint32_t task = lds.h_task[lds.s_h[s]];
-      dev_compute_w<LV, PAD>(yb + si.y(0, s, 0), ws.A + kix(ws, task) * K * L * N, wb + si.w(0, s, 0),
+      dev_compute_w<LV, PAD, CONTIG>(yb + si.y(0, s, 0), ws.A + kix(ws, task) * K * L * N, wb + si.w(0, s, 0),
                         w1b + si.w1(0, s), lds.u[wave].wp.hat,
                         lds.u[wave].wp.tr + (lane >> 4) * NTT_LDS_GROUP, lds.u[wave].wp.w1buf, ftw, itw, lane);
       wave_sync();
@@ -391,12 +422,12 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
     __syncthreads();
     PHASE_MARK(3);
     // checks; a slot is skipped once a smaller nonce of its task has passed
-    for (int s = wave; s < ns; s += W) {
+    for (int s = s_lo; s < s_hi; s += s_step) {
       int h = lds.s_h[s];
       // another wave may lower h_win meanwhile: read it once, wave-uniformly
       if (__builtin_amdgcn_readfirstlane(lds.h_win[h]) < lds.s_att[s]) continue;
       uint32_t task = lds.h_task[h];
-      bool ok = dev_check<LV, PAD>(lds.c[s], lds.ct[s], yb + si.y(0, s, 0), wb + si.w(0, s, 0),
+      bool ok = dev_check<LV, PAD, CONTIG>(lds.c[s], lds.ct[s], yb + si.y(0, s, 0), wb + si.w(0, s, 0),
                               ws.s1h + kix(ws, task) * L * N, ws.s2h + kix(ws, task) * K * N,
                               ws.t0h + kix(ws, task) * K * N, lds.u[wave].ck, ftw, itw, lane);
       if (ok) {

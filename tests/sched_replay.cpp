@@ -19,9 +19,12 @@
 // match.
 //
 // Batches of a workgroup whose queue has run dry take sched_slots' tail
-// slots per held task (tail = 0: all G), as the kernels do.
+// slots per held task (tail = 0: all G), as the kernels do.  contig = 1 lays
+// the batch out task by task (sched_assign_contig) and checks the ranges of
+// sched_wave_range: they cover the batch, and each fits one wavefront's 64
+// ExpandMask lanes at L streams per slot.
 //
-// usage: sched_replay G L K count grid hmax p max_attempts seed W tail
+// usage: sched_replay G L K count grid hmax p max_attempts seed W tail contig
 #include <stdio.h>
 #include <stdlib.h>
 
@@ -60,8 +63,8 @@ struct Wg {
 };
 
 int main(int argc, char **argv) {
-  if (argc != 12) {
-    fprintf(stderr, "usage: %s G L K count grid hmax p max_attempts seed W tail\n", argv[0]);
+  if (argc != 13) {
+    fprintf(stderr, "usage: %s G L K count grid hmax p max_attempts seed W tail contig\n", argv[0]);
     return 2;
   }
   const int G = atoi(argv[1]), L = atoi(argv[2]), K = atoi(argv[3]);
@@ -71,7 +74,7 @@ int main(int argc, char **argv) {
   const double p = atof(argv[7]);
   const uint32_t max_attempts = (uint32_t)strtoul(argv[8], nullptr, 10);
   const uint64_t seed = strtoull(argv[9], nullptr, 10);
-  const int W = atoi(argv[10]), tail = atoi(argv[11]);
+  const int W = atoi(argv[10]), tail = atoi(argv[11]), contig = atoi(argv[12]);
   CHECK(G >= 1 && G <= 64 && hmax >= 1 && (int)hmax <= G && grid >= 1);
   CHECK(W >= 1 && G % W == 0 && tail >= 0 && tail <= 64);
   const uint64_t thresh = (uint64_t)(p * 18446744073709551615.0);
@@ -115,8 +118,22 @@ int main(int argc, char **argv) {
       CHECK(nh >= 0 && nh <= (int)hmax);
       w.nheld = nh;
       const int want = sched_slots(nh, G, W, w.queue_empty, tail);
-      const int ns = sched_assign(nh, want, w.h_next, w.h_win, w.s_h, w.s_att);
+      const int ns = contig ? sched_assign_contig(nh, want, w.h_next, w.h_win, w.s_h, w.s_att)
+                            : sched_assign(nh, want, w.h_next, w.h_win, w.s_h, w.s_att);
       CHECK(ns == want && ns <= G);
+      if (contig) {
+        // task by task: held task indices never decrease along the slots
+        for (int s = 1; s < ns; s++) CHECK(w.s_h[s] >= w.s_h[s - 1]);
+        int covered = 0;
+        for (int wave = 0; wave < W; wave++) {
+          int lo = -1, hi = -1;
+          sched_wave_range(ns, W, wave, lo, hi);
+          CHECK(lo >= 0 && hi >= lo && hi <= ns && (hi - lo) * L <= 64);
+          CHECK(hi == lo || lo == covered);
+          covered += hi - lo;
+        }
+        CHECK(covered == ns);
+      }
       if (nh && (!w.queue_empty || tail == 0)) CHECK(ns == G);
       if (nh && w.queue_empty && tail > 0) CHECK(ns >= nh && (ns == G || ns % W == 0) && ns >= std::min(G, nh * tail));
       w.evaluated += (uint64_t)ns;
