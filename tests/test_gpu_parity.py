@@ -308,6 +308,31 @@ def test_tail_batches_match_oracle(level, grid, hmax, tail):
     c.close()
 
 
+@pytest.mark.parametrize("level", [2, 44])
+@pytest.mark.parametrize("grid,hmax,tail", [(1, 3, 0), (2, 7, 5), (3, 13, 20), (1, 17, 0), (4, 33, 9), (2, 63, 1)])
+def test_task_by_task_batches_match_oracle(level, grid, hmax, tail):
+    """At l = 4 the loop kernel lays each batch out task by task and gives every wavefront a
+    contiguous range of slots: held-task counts that split the 64 slots unevenly (a task's
+    nonces then straddle two wavefronts), with full and with short tail batches, still give
+    the sequential signatures and the oracle's iteration count."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2211_12265_amd import dilithium as dl
+    c = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    c.set_param("persist.grid", grid)
+    c.set_param("persist.hmax", hmax)
+    c.set_param("persist.tail", tail)
+    n = 45
+    pk, sk = _keygen(c, level, workload.keygen_seeds(n, seed=90 + level))
+    msg, off = workload.messages(workload.uniform_lengths(n, 0, 300, seed=91), seed=91)
+    osig, iters = oracle.sign_batch(level, sk.cpu().numpy(), msg, off)
+    sig = _sign(c, level, sk, msg, off)
+    ev, seq = c.sign_stats()
+    assert np.array_equal(sig.cpu().numpy(), osig)
+    assert seq == int(iters.sum()) and ev >= seq
+    c.close()
+
+
 def test_tail_rejects_other_shapes(ctx):
     from paper_2211_12265_amd import dilithium as dl
     c = dl.Context(0, mode=dl.MODE_PERSISTENT)
