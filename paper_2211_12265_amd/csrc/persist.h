@@ -67,6 +67,9 @@ __host__ __device__ __forceinline__ size_t sig_stride() {
   } while (0)
 #endif
 
+// Global-memory stores of a wavefront made visible to its own later loads
+// (other lanes of the same wavefront), as between a wavefront's phases when
+// no workgroup barrier separates them.
 __device__ __forceinline__ void wave_sync_global() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
@@ -384,9 +387,7 @@ __global__ void __launch_bounds__(64 * NW) sg_persistw_k(Ws ws, PScr sc, uint8_t
         uint32_t task = lds.h_task[lds.s_h[s]];
         dev_expand_mask<LV>(ws.rhop + (size_t)task * 64, lds.s_att[s] * (uint32_t)L, i, yb + si.y(0, s, i));
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      wave_sync_global();
     } else {
       // ExpandMask: one thread per (slot, i)
       if (tid < ns * L) {
