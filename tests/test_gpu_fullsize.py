@@ -128,12 +128,13 @@ def test_single_task(mode, level):
     ctx.close()
 
 
-def test_long_messages():
-    """64 KiB messages (482 SHAKE256 blocks for mu) next to empty ones, at level 3."""
+@pytest.mark.parametrize("level", [3, 44, 87])
+def test_long_messages(level):
+    """64 KiB messages (482 SHAKE256 blocks for mu) next to empty ones, at level 3 and at two
+    ML-DSA levels (66-byte mu prefix)."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_2211_12265_amd import dilithium as dl
-    level = 3
     ctx = dl.Context(0, mode=dl.MODE_PERSISTENT)
     seeds = workload.keygen_seeds(4, seed=180)
     opk, osk = oracle.keygen_batch(level, seeds)
