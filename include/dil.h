@@ -46,7 +46,9 @@
  *       DIL_EMSG    a decreasing msg_off entry was found (detected on the
  *                   device; reported by calls that synchronise, and by
  *                   dil_ctx_check()); a key-table index outside its table
- *                   is reported the same way, as DIL_EINVAL.
+ *                   is reported the same way, as DIL_EINVAL;
+ *       DIL_ETIMEDOUT  dil_server_wait ran out of time (the request stays
+ *                   outstanding).
  *     A malformed signature is not an error: its verdict is 0 (Alg. 3).
  *   - One context serves one host thread at a time; calls that overlap on
  *     one context race on its workspace.
@@ -66,6 +68,7 @@ extern "C" {
 #define DIL_ENOMEM (-2)
 #define DIL_EHIP (-3)
 #define DIL_EMSG (-4)
+#define DIL_ETIMEDOUT (-5)
 
 /* Execution forms for Sign (dil_ctx_set_mode):
  *   DIL_MODE_STAGED      one kernel launch per pipeline stage, host-driven
@@ -296,6 +299,41 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
                    const uint8_t *msg, const uint64_t *msg_off, const uint8_t *sig_in, const uint64_t *sig_in_off,
                    const uint64_t *arrival_ns, uint8_t *sig_out, const uint64_t *sig_out_off, int32_t *verdict,
                    uint64_t *done_ns);
+
+/* Interactive mode of the same engine (continuous batching of requests that
+ * application threads submit one by one; the spec serving loop, not in
+ * the paper).  dil_server_start starts a dispatcher thread that forms batches
+ * as streams free up, under the admission rules above (requests in
+ * submission order, at most the group cap per (level, op), messages within
+ * max_msg_bytes), so that requests submitted while earlier batches run join
+ * the next one.  dil_server_run returns DIL_EINVAL while the mode is on.
+ * All buffers are host memory owned by the caller; the engine copies what it
+ * needs before dil_server_submit returns.  Thread-safe: any host thread may
+ * submit, poll and wait at once (start / stop / destroy from one thread).
+ *
+ * dil_server_submit: op 0 = Sign, 1 = Verify of msg[0 .. msg_len) with row
+ *   `key` of the level's key table; sig (Verify only) holds the level's
+ *   signature size (dil_sizes).  Writes a ticket.  DIL_EINVAL for an unknown
+ *   level or op, a key row outside its table, a message longer than
+ *   max_msg_bytes, a NULL pointer, or when the mode is off or stopping; the
+ *   dispatcher's error code once it has failed.
+ * dil_server_poll: *done = 1 and the result (Sign: the signature in sig_out,
+ *   *verdict = -1; Verify: *verdict = 1 accept / 0 reject) once the request
+ *   has finished, else *done = 0.  A result is handed out once; a ticket not
+ *   outstanding (unknown, or already handed out) gives DIL_EINVAL.
+ * dil_server_wait: as poll, blocking up to timeout_ms (< 0: no limit);
+ *   DIL_ETIMEDOUT if the request is still running then.
+ * dil_server_stop: finishes every submitted request, then stops the
+ *   dispatcher; results not yet collected stay available to poll / wait.
+ * A device failure or a batch with no progress for 60 s stops the
+ *   dispatcher; every later call returns its error (dil_server_last_error
+ *   has the text).  dil_server_stats counts the batches since start. */
+int dil_server_start(dil_server *s);
+int dil_server_submit(dil_server *s, int op, int level, uint32_t key, const uint8_t *msg, uint64_t msg_len,
+                      const uint8_t *sig, uint64_t *ticket);
+int dil_server_poll(dil_server *s, uint64_t ticket, int *done, int32_t *verdict, uint8_t *sig_out);
+int dil_server_wait(dil_server *s, uint64_t ticket, int32_t timeout_ms, int32_t *verdict, uint8_t *sig_out);
+int dil_server_stop(dil_server *s);
 
 /* Number of Sign loop iterations (candidate signatures) the last dil_sign_batch
  * on this context evaluated in total, and the number the sequential algorithm

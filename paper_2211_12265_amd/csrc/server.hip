@@ -22,12 +22,25 @@
 // GPU_MAX_HW_QUEUES (the benchmark uses 16).
 // Completed batches are harvested by polling the events; a request's
 // completion time is the poll that observed its batch's event.
+//
+// Two ways in: dil_server_run replays a whole trace of timed arrivals on the
+// calling thread, and the interactive mode (dil_server_start ... stop) runs the
+// same dispatcher on a thread of its own, fed by dil_server_submit from any
+// host thread; the caller collects each result once with dil_server_poll or
+// dil_server_wait.  Both share the batch formation, staging and harvesting
+// below; one server runs one of them at a time.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
 #include <algorithm>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <iterator>
+#include <mutex>
 #include <thread>
+#include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "../../include/dil.h"
@@ -45,8 +58,21 @@ int lv_index(int level) {
 
 struct Group {
   int li, op;                 // level index, 0 sign / 1 verify
-  std::vector<uint32_t> req;  // request ids
+  std::vector<uint32_t> req;  // requests of the batch (index within the batch)
   size_t m_pos = 0, m_len = 0, t_pos = 0, o_pos = 0, s_pos = 0;
+};
+
+// A request of the interactive mode, with its own copies of the bytes.
+struct SvcReq {
+  uint64_t ticket = 0;
+  int li = 0, op = 0;
+  uint32_t key = 0;
+  std::vector<uint8_t> msg, sig;
+};
+
+struct SvcRes {
+  int32_t verdict = -1;      // Verify: 1 / 0; Sign: -1
+  std::vector<uint8_t> sig;  // Sign: the signature
 };
 
 constexpr int NGROUP = 2 * NLV;  // (level, op) groups, index 2 * level index + op
@@ -63,6 +89,8 @@ struct Lane {
   int32_t *h_ver = nullptr, *d_ver = nullptr;
   bool busy = false;
   std::vector<Group> groups;
+  uint32_t base = 0;             // dil_server_run: trace index of the batch's first request
+  std::vector<SvcReq> inflight;  // interactive mode: the batch's requests
 };
 
 }  // namespace
@@ -76,9 +104,20 @@ struct dil_server {
   size_t max_msg = 0, budget = 0, reserved = 0;
   std::vector<Lane> lanes;
   char err[256] = {0};
-  // statistics of the last run
+  // statistics of the last run (interactive mode: since dil_server_start)
   uint64_t batches = 0, overlapped = 0;
   double host_s = 0;
+  // interactive mode; mu guards everything below and err while it is on
+  std::mutex mu;
+  std::condition_variable cv_done;  // results (or a dispatcher error) for waiters
+  std::condition_variable cv_in;    // new requests (or stop) for the dispatcher
+  std::thread svc;
+  bool svc_on = false, svc_stop = false;
+  int svc_rc = DIL_OK;              // the dispatcher's first error, returned by every later call
+  uint64_t next_ticket = 1;
+  std::deque<SvcReq> pending;
+  std::unordered_set<uint64_t> outstanding;          // submitted, result not yet handed out
+  std::unordered_map<uint64_t, SvcRes> results;
 };
 
 namespace {
@@ -101,6 +140,232 @@ int lane_bytes(dil_server *s, const Lane &ln, uint32_t cap, size_t staging, size
   }
   *out = total;
   return DIL_OK;
+}
+
+// One request as the batch stager reads it.
+struct ReqRef {
+  int li, op;
+  uint32_t key;
+  const uint8_t *msg;
+  uint64_t len;
+  const uint8_t *sig;  // Verify: sig_bytes[li] bytes
+};
+
+// How many of the next `avail` requests (in order) one batch admits: at most
+// max_batch, at most group_cap per (level, op) group (its workspace
+// reservation), and messages within the staging buffer; the first request
+// that does not fit waits for the next batch.  peek(i, &group, &len).
+template <class Peek>
+uint32_t admit_count(const dil_server *s, uint32_t avail, Peek peek) {
+  uint32_t per_group[NGROUP] = {};
+  size_t mbytes = 0;
+  uint32_t n = 0;
+  while (n < avail && n < s->max_batch) {
+    int gi = 0;
+    uint64_t ml = 0;
+    peek(n, &gi, &ml);
+    if (per_group[gi] == s->group_cap || mbytes + ml > s->max_msg) break;
+    per_group[gi]++;
+    mbytes += ml;
+    n++;
+  }
+  return n;
+}
+
+// Stage the nreq requests of one batch (get(r), r < nreq) into the lane's
+// pinned buffers, grouped by (level, op) in request order, and enqueue the
+// copies in, one key-table call per group on the group's own stream (forked
+// after the copies in, joined before the copies out), the copies out and the
+// lane's event.  Marks the lane busy; *overlap tells whether another lane's
+// batch was still in flight.
+template <class Get>
+int launch_batch(dil_server *s, Lane &ln, uint32_t nreq, Get get, bool *overlap) {
+  ln.groups.clear();
+  for (int li = 0; li < NLV; li++)
+    for (int o = 0; o < 2; o++) {
+      Group g;
+      g.li = li;
+      g.op = o;
+      for (uint32_t r = 0; r < nreq; r++) {
+        const ReqRef q = get(r);
+        if (q.li == li && q.op == o) g.req.push_back(r);
+      }
+      if (!g.req.empty()) ln.groups.push_back(std::move(g));
+    }
+  size_t m_pos = 0, t_pos = 0, o_pos = 0, s_pos = 0;
+  for (auto &g : ln.groups) {
+    size_t ss = s->sig_bytes[g.li];
+    g.m_pos = m_pos;
+    g.t_pos = t_pos;
+    g.o_pos = o_pos;
+    g.s_pos = s_pos;
+    uint64_t acc = 0;
+    for (size_t j = 0; j < g.req.size(); j++) {
+      const ReqRef q = get(g.req[j]);
+      if (q.len) memcpy(ln.h_msg + m_pos + acc, q.msg, q.len);
+      ln.h_off[o_pos + j] = acc;
+      acc += q.len;
+      ln.h_key[t_pos + j] = q.key;
+      if (g.op == 1) memcpy(ln.h_sig + s_pos + j * ss, q.sig, ss);
+    }
+    ln.h_off[o_pos + g.req.size()] = acc;
+    g.m_len = acc;
+    m_pos += acc;
+    t_pos += g.req.size();
+    o_pos += g.req.size() + 1;
+    s_pos += g.req.size() * ss;
+  }
+  bool ok = hipMemcpyAsync(ln.d_msg, ln.h_msg, std::max<size_t>(m_pos, 1), hipMemcpyHostToDevice, ln.st) ==
+                hipSuccess &&
+            hipMemcpyAsync(ln.d_off, ln.h_off, o_pos * 8, hipMemcpyHostToDevice, ln.st) == hipSuccess &&
+            hipMemcpyAsync(ln.d_key, ln.h_key, t_pos * 4, hipMemcpyHostToDevice, ln.st) == hipSuccess &&
+            (s_pos == 0 || hipMemcpyAsync(ln.d_sig, ln.h_sig, s_pos, hipMemcpyHostToDevice, ln.st) == hipSuccess);
+  if (!ok) return sfail(s, DIL_EHIP, "host-to-device copy");
+  if (hipEventRecord(ln.fork, ln.st) != hipSuccess) return sfail(s, DIL_EHIP, "fork");
+  for (auto &g : ln.groups) {
+    uint32_t cnt = (uint32_t)g.req.size();
+    const int gi = 2 * g.li + g.op;
+    hipStream_t gs = ln.gst[gi];
+    dil_ctx *gc = ln.gctx[gi];
+    if (hipStreamWaitEvent(gs, ln.fork, 0) != hipSuccess) return sfail(s, DIL_EHIP, "fork wait");
+    int rc;
+    if (g.op == 0)
+      rc = dil_sign_keyset(gc, s->ks[g.li], ln.d_key + g.t_pos, ln.d_msg + g.m_pos, ln.d_off + g.o_pos,
+                           ln.d_sig + g.s_pos, cnt, gs);
+    else
+      rc = dil_verify_keyset(gc, s->ks[g.li], ln.d_key + g.t_pos, ln.d_msg + g.m_pos, ln.d_off + g.o_pos,
+                             ln.d_sig + g.s_pos, ln.d_ver + g.t_pos, cnt, gs);
+    if (rc) {
+      snprintf(s->err, sizeof s->err, "batch call: %s", dil_last_error(gc));
+      return rc;
+    }
+    if (hipEventRecord(ln.gev[gi], gs) != hipSuccess || hipStreamWaitEvent(ln.st, ln.gev[gi], 0) != hipSuccess)
+      return sfail(s, DIL_EHIP, "join");
+  }
+  ok = (s_pos == 0 || hipMemcpyAsync(ln.h_sig, ln.d_sig, s_pos, hipMemcpyDeviceToHost, ln.st) == hipSuccess) &&
+       hipMemcpyAsync(ln.h_ver, ln.d_ver, t_pos * 4, hipMemcpyDeviceToHost, ln.st) == hipSuccess &&
+       hipEventRecord(ln.ev, ln.st) == hipSuccess;
+  if (!ok) return sfail(s, DIL_EHIP, "device-to-host copy");
+  bool others_busy = false;  // launched while another batch is still in flight
+  for (auto &other : s->lanes) others_busy |= &other != &ln && other.busy;
+  *overlap = others_busy;
+  ln.busy = true;
+  return DIL_OK;
+}
+
+// Hand every request of the lane's finished batch to put(r, op, sig, sig
+// bytes, verdict) (Sign: sig, verdict -1; Verify: no sig) and free the lane.
+template <class Put>
+void harvest_lane(dil_server *s, Lane &ln, Put put) {
+  for (auto &g : ln.groups) {
+    size_t ss = s->sig_bytes[g.li];
+    for (size_t j = 0; j < g.req.size(); j++) {
+      if (g.op == 0) put(g.req[j], 0, ln.h_sig + g.s_pos + j * ss, ss, -1);
+      else put(g.req[j], 1, (const uint8_t *)nullptr, (size_t)0, ln.h_ver[g.t_pos + j]);
+    }
+  }
+  ln.busy = false;
+  ln.groups.clear();
+}
+
+// The interactive mode's dispatcher thread.
+void svc_fail(dil_server *s, int code, const char *what) {
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->svc_rc == DIL_OK) {
+    s->svc_rc = code;
+    if (what) snprintf(s->err, sizeof s->err, "%s", what);
+  }
+  s->cv_done.notify_all();
+}
+
+void svc_loop_body(dil_server *s);
+
+void svc_loop(dil_server *s) {
+  try {
+    svc_loop_body(s);
+  } catch (...) {  // host allocation failure
+    svc_fail(s, DIL_ENOMEM, "dispatcher: host allocation failed");
+  }
+}
+
+void svc_loop_body(dil_server *s) {
+  using clk = std::chrono::steady_clock;
+  if (hipSetDevice(s->device) != hipSuccess) return svc_fail(s, DIL_EHIP, "hipSetDevice");
+  auto last_progress = clk::now();
+  for (;;) {
+    bool progressed = false;
+    // harvest
+    for (auto &ln : s->lanes) {
+      if (!ln.busy) continue;
+      hipError_t q = hipEventQuery(ln.ev);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return svc_fail(s, DIL_EHIP, "batch failed on the device");
+      std::vector<std::pair<uint64_t, SvcRes>> out;
+      out.reserve(ln.inflight.size());
+      harvest_lane(s, ln, [&](uint32_t r, int op, const uint8_t *sig, size_t ss, int32_t v) {
+        SvcRes res;
+        res.verdict = v;
+        if (op == 0) res.sig.assign(sig, sig + ss);
+        out.emplace_back(ln.inflight[r].ticket, std::move(res));
+      });
+      ln.inflight.clear();
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto &o : out) s->results.emplace(o.first, std::move(o.second));
+      }
+      s->cv_done.notify_all();
+      progressed = true;
+    }
+    // admit
+    Lane *free_lane = nullptr;
+    bool busy = false;
+    for (auto &ln : s->lanes) {
+      busy |= ln.busy;
+      if (!ln.busy && !free_lane) free_lane = &ln;
+    }
+    std::vector<SvcReq> batch;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      if (free_lane && !s->pending.empty()) {
+        const uint32_t n = admit_count(s, (uint32_t)std::min<size_t>(s->pending.size(), UINT32_MAX),
+                                       [&](uint32_t i, int *gi, uint64_t *len) {
+                                         *gi = 2 * s->pending[i].li + s->pending[i].op;
+                                         *len = s->pending[i].msg.size();
+                                       });
+        batch.assign(std::make_move_iterator(s->pending.begin()), std::make_move_iterator(s->pending.begin() + n));
+        s->pending.erase(s->pending.begin(), s->pending.begin() + n);
+      } else if (!busy && !progressed) {
+        if (s->svc_stop && s->pending.empty()) return;
+        // idle: wait for a submission (or stop); bounded so that stop is seen
+        s->cv_in.wait_for(lk, std::chrono::milliseconds(2));
+        last_progress = clk::now();
+        continue;
+      }
+    }
+    if (!batch.empty()) {
+      auto h0 = clk::now();
+      free_lane->inflight = std::move(batch);
+      const std::vector<SvcReq> &b = free_lane->inflight;
+      bool overlap = false;
+      int rc = launch_batch(s, *free_lane, (uint32_t)b.size(), [&](uint32_t r) {
+        return ReqRef{b[r].li, b[r].op, b[r].key, b[r].msg.data(), (uint64_t)b[r].msg.size(), b[r].sig.data()};
+      }, &overlap);
+      if (rc) return svc_fail(s, rc, nullptr);
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->batches++;
+        s->overlapped += overlap ? 1 : 0;
+        s->host_s += std::chrono::duration<double>(clk::now() - h0).count();
+      }
+      progressed = true;
+    }
+    if (progressed) {
+      last_progress = clk::now();
+    } else {
+      if (clk::now() - last_progress > std::chrono::seconds(60)) return svc_fail(s, DIL_EHIP, "no batch completed for 60 s");
+      std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+  }
 }
 
 }  // namespace
@@ -213,6 +478,12 @@ int dil_server_create(dil_server **out, int device, dil_keyset *ks2, dil_keyset 
 
 int dil_server_destroy(dil_server *s) {
   if (!s) return DIL_EINVAL;
+  bool on;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    on = s->svc_on;
+  }
+  if (on) dil_server_stop(s);
   hipSetDevice(s->device);
   hipDeviceSynchronize();
   for (auto &ln : s->lanes) {
@@ -244,6 +515,7 @@ const char *dil_server_last_error(dil_server *s) { return s ? s->err : "null ser
 int dil_server_stats(dil_server *s, uint64_t *batches, double *host_seconds, uint64_t *overlapped,
                      uint32_t *group_cap, size_t *reserved_bytes) {
   if (!s) return DIL_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
   if (batches) *batches = s->batches;
   if (host_seconds) *host_seconds = s->host_s;
   if (overlapped) *overlapped = s->overlapped;
@@ -257,6 +529,10 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
                    const uint64_t *arrival_ns, uint8_t *sig_out, const uint64_t *sig_out_off, int32_t *verdict,
                    uint64_t *done_ns) {
   if (!s) return DIL_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->svc_on) return sfail(s, DIL_EINVAL, "the interactive mode is on (dil_server_stop first)");
+  }
   if (n == 0) return DIL_OK;
   if (!op || !level || !key || !msg || !msg_off || !arrival_ns || !verdict || !done_ns) return sfail(s, DIL_EINVAL, "null array");
   hipSetDevice(s->device);
@@ -277,11 +553,9 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
   using clk = std::chrono::steady_clock;
   const auto t0 = clk::now();
   auto now_ns = [&]() { return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(clk::now() - t0).count(); };
-  double host = 0;
-  uint64_t batches = 0, overlapped = 0;
+  s->batches = s->overlapped = 0;
+  s->host_s = 0;
   uint32_t head = 0, done = 0;
-  std::vector<Lane *> free_lanes;
-  for (auto &ln : s->lanes) free_lanes.push_back(&ln);
   auto last_progress = clk::now();
   while (done < n) {
     bool progressed = false;
@@ -292,122 +566,46 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
       hipError_t q = hipEventQuery(ln.ev);
       if (q == hipErrorNotReady) continue;
       if (q != hipSuccess) return sfail(s, DIL_EHIP, "batch failed on the device");
-      uint64_t t = now_ns();
-      for (auto &g : ln.groups) {
-        size_t ss = s->sig_bytes[g.li];
-        for (size_t j = 0; j < g.req.size(); j++) {
-          uint32_t r = g.req[j];
-          done_ns[r] = t;
-          if (g.op == 0) {
-            memcpy(sig_out + sig_out_off[r], ln.h_sig + g.s_pos + j * ss, ss);
-            verdict[r] = -1;
-          } else {
-            verdict[r] = ln.h_ver[g.t_pos + j];
-          }
-        }
-        done += (uint32_t)g.req.size();
-      }
-      ln.busy = false;
-      ln.groups.clear();
-      free_lanes.push_back(&ln);
+      const uint64_t t = now_ns();
+      harvest_lane(s, ln, [&](uint32_t r, int o, const uint8_t *sig, size_t ss, int32_t v) {
+        const uint32_t i = ln.base + r;
+        done_ns[i] = t;
+        if (o == 0) memcpy(sig_out + sig_out_off[i], sig, ss);
+        verdict[i] = v;
+        done++;
+      });
       progressed = true;
     }
-    // admit
-    uint64_t tnow = now_ns();
-    uint32_t arrived = (uint32_t)(std::upper_bound(arrival_ns, arrival_ns + n, tnow) - arrival_ns);
-    if (!free_lanes.empty() && head < arrived) {
-      auto h0 = clk::now();
-      Lane &ln = *free_lanes.back();
-      size_t mbytes = 0;
-      uint32_t per_group[NGROUP] = {};
-      uint32_t end = head;
-      while (end < arrived && end - head < s->max_batch) {
-        size_t ml = msg_off[end + 1] - msg_off[end];
-        const int gi = 2 * lv_index(level[end]) + op[end];
-        // in arrival order: the first request whose group is full (its workspace
-        // reservation) or whose message does not fit waits for the next batch
-        if (per_group[gi] == s->group_cap || mbytes + ml > s->max_msg) break;
-        per_group[gi]++;
-        mbytes += ml;
-        end++;
+    // admit the arrived requests into a free lane
+    const uint64_t tnow = now_ns();
+    const uint32_t arrived = (uint32_t)(std::upper_bound(arrival_ns, arrival_ns + n, tnow) - arrival_ns);
+    Lane *free_lane = nullptr;
+    for (auto &ln : s->lanes)
+      if (!ln.busy) {
+        free_lane = &ln;
+        break;
       }
-      if (end > head) {
-        free_lanes.pop_back();
-        // group by (level, op) keeping arrival order within each group
-        ln.groups.clear();
-        for (int li = 0; li < NLV; li++)
-          for (int o = 0; o < 2; o++) {
-            Group g;
-            g.li = li;
-            g.op = o;
-            for (uint32_t r = head; r < end; r++)
-              if (lv_index(level[r]) == li && op[r] == o) g.req.push_back(r);
-            if (!g.req.empty()) ln.groups.push_back(std::move(g));
-          }
-        size_t m_pos = 0, t_pos = 0, o_pos = 0, s_pos = 0;
-        for (auto &g : ln.groups) {
-          size_t ss = s->sig_bytes[g.li];
-          g.m_pos = m_pos;
-          g.t_pos = t_pos;
-          g.o_pos = o_pos;
-          g.s_pos = s_pos;
-          uint64_t acc = 0;
-          for (size_t j = 0; j < g.req.size(); j++) {
-            uint32_t r = g.req[j];
-            size_t ml = msg_off[r + 1] - msg_off[r];
-            memcpy(ln.h_msg + m_pos + acc, msg + msg_off[r], ml);
-            ln.h_off[o_pos + j] = acc;
-            acc += ml;
-            ln.h_key[t_pos + j] = key[r];
-            if (g.op == 1) memcpy(ln.h_sig + s_pos + j * ss, sig_in + sig_in_off[r], ss);
-          }
-          ln.h_off[o_pos + g.req.size()] = acc;
-          g.m_len = acc;
-          m_pos += acc;
-          t_pos += g.req.size();
-          o_pos += g.req.size() + 1;
-          s_pos += g.req.size() * ss;
-        }
-        bool ok = hipMemcpyAsync(ln.d_msg, ln.h_msg, std::max<size_t>(m_pos, 1), hipMemcpyHostToDevice, ln.st) ==
-                      hipSuccess &&
-                  hipMemcpyAsync(ln.d_off, ln.h_off, o_pos * 8, hipMemcpyHostToDevice, ln.st) == hipSuccess &&
-                  hipMemcpyAsync(ln.d_key, ln.h_key, t_pos * 4, hipMemcpyHostToDevice, ln.st) == hipSuccess &&
-                  (s_pos == 0 ||
-                   hipMemcpyAsync(ln.d_sig, ln.h_sig, s_pos, hipMemcpyHostToDevice, ln.st) == hipSuccess);
-        if (!ok) return sfail(s, DIL_EHIP, "host-to-device copy");
-        if (hipEventRecord(ln.fork, ln.st) != hipSuccess) return sfail(s, DIL_EHIP, "fork");
-        for (auto &g : ln.groups) {
-          uint32_t cnt = (uint32_t)g.req.size();
-          const int gi = 2 * g.li + g.op;
-          hipStream_t gs = ln.gst[gi];
-          dil_ctx *gc = ln.gctx[gi];
-          if (hipStreamWaitEvent(gs, ln.fork, 0) != hipSuccess) return sfail(s, DIL_EHIP, "fork wait");
-          int rc;
-          if (g.op == 0)
-            rc = dil_sign_keyset(gc, s->ks[g.li], ln.d_key + g.t_pos, ln.d_msg + g.m_pos, ln.d_off + g.o_pos,
-                                 ln.d_sig + g.s_pos, cnt, gs);
-          else
-            rc = dil_verify_keyset(gc, s->ks[g.li], ln.d_key + g.t_pos, ln.d_msg + g.m_pos, ln.d_off + g.o_pos,
-                                   ln.d_sig + g.s_pos, ln.d_ver + g.t_pos, cnt, gs);
-          if (rc) {
-            snprintf(s->err, sizeof s->err, "batch call: %s", dil_last_error(gc));
-            return rc;
-          }
-          if (hipEventRecord(ln.gev[gi], gs) != hipSuccess || hipStreamWaitEvent(ln.st, ln.gev[gi], 0) != hipSuccess)
-            return sfail(s, DIL_EHIP, "join");
-        }
-        ok = (s_pos == 0 || hipMemcpyAsync(ln.h_sig, ln.d_sig, s_pos, hipMemcpyDeviceToHost, ln.st) == hipSuccess) &&
-             hipMemcpyAsync(ln.h_ver, ln.d_ver, t_pos * 4, hipMemcpyDeviceToHost, ln.st) == hipSuccess &&
-             hipEventRecord(ln.ev, ln.st) == hipSuccess;
-        if (!ok) return sfail(s, DIL_EHIP, "device-to-host copy");
-        bool others_busy = false;  // launched while another batch is still in flight
-        for (auto &other : s->lanes) others_busy |= &other != &ln && other.busy;
-        overlapped += others_busy ? 1 : 0;
-        ln.busy = true;
-        head = end;
-        batches++;
+    if (free_lane && head < arrived) {
+      auto h0 = clk::now();
+      const uint32_t cnt = admit_count(s, arrived - head, [&](uint32_t k, int *gi, uint64_t *len) {
+        const uint32_t r = head + k;
+        *gi = 2 * lv_index(level[r]) + op[r];
+        *len = msg_off[r + 1] - msg_off[r];
+      });
+      if (cnt) {
+        free_lane->base = head;
+        bool overlap = false;
+        int rc = launch_batch(s, *free_lane, cnt, [&](uint32_t k) {
+          const uint32_t r = head + k;
+          return ReqRef{lv_index(level[r]), op[r], key[r], msg + msg_off[r], msg_off[r + 1] - msg_off[r],
+                        op[r] == 1 ? sig_in + sig_in_off[r] : nullptr};
+        }, &overlap);
+        if (rc) return rc;
+        s->batches++;
+        s->overlapped += overlap ? 1 : 0;
+        head += cnt;
         progressed = true;
-        host += std::chrono::duration<double>(clk::now() - h0).count();
+        s->host_s += std::chrono::duration<double>(clk::now() - h0).count();
       }
     }
     if (progressed) last_progress = clk::now();
@@ -423,10 +621,111 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
       }
     }
   }
-  s->batches = batches;
-  s->overlapped = overlapped;
-  s->host_s = host;
   return DIL_OK;
+}
+
+int dil_server_start(dil_server *s) {
+  if (!s) return DIL_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->svc_on) return sfail(s, DIL_EINVAL, "the interactive mode is already on");
+  s->svc_stop = false;
+  s->svc_rc = DIL_OK;
+  s->pending.clear();
+  s->outstanding.clear();
+  s->results.clear();
+  s->batches = s->overlapped = 0;
+  s->host_s = 0;
+  try {
+    s->svc = std::thread(svc_loop, s);
+  } catch (...) {
+    return sfail(s, DIL_EHIP, "cannot start the dispatcher thread");
+  }
+  s->svc_on = true;
+  return DIL_OK;
+}
+
+int dil_server_submit(dil_server *s, int op, int level, uint32_t key, const uint8_t *msg, uint64_t msg_len,
+                      const uint8_t *sig, uint64_t *ticket) {
+  if (!s || !ticket) return DIL_EINVAL;
+  const int li = lv_index(level);
+  if (li < 0 || !s->ks[li] || (op != 0 && op != 1) || (msg_len && !msg) || (op == 1 && !sig))
+    return DIL_EINVAL;
+  uint32_t nkeys = 0;
+  dil_keyset_info(s->ks[li], nullptr, &nkeys, nullptr);
+  if (key >= nkeys || msg_len > s->max_msg) return DIL_EINVAL;  // key rows are read without bounds checks
+  try {
+    SvcReq q;
+    q.li = li;
+    q.op = op;
+    q.key = key;
+    q.msg.assign(msg, msg + msg_len);
+    if (op == 1) q.sig.assign(sig, sig + s->sig_bytes[li]);
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->svc_rc) return s->svc_rc;
+    if (!s->svc_on || s->svc_stop) return DIL_EINVAL;
+    q.ticket = s->next_ticket;
+    s->outstanding.insert(q.ticket);
+    s->pending.push_back(std::move(q));
+    *ticket = s->next_ticket++;
+  } catch (...) {
+    return DIL_ENOMEM;
+  }
+  s->cv_in.notify_one();
+  return DIL_OK;
+}
+
+namespace {
+// hand out a finished result (called with mu held)
+void take_result(dil_server *s, uint64_t ticket, int32_t *verdict, uint8_t *sig_out) {
+  auto it = s->results.find(ticket);
+  if (verdict) *verdict = it->second.verdict;
+  if (sig_out && !it->second.sig.empty()) memcpy(sig_out, it->second.sig.data(), it->second.sig.size());
+  s->results.erase(it);
+  s->outstanding.erase(ticket);
+}
+}  // namespace
+
+int dil_server_poll(dil_server *s, uint64_t ticket, int *done, int32_t *verdict, uint8_t *sig_out) {
+  if (!s || !done) return DIL_EINVAL;
+  std::lock_guard<std::mutex> lk(s->mu);
+  *done = 0;
+  if (!s->outstanding.count(ticket)) return DIL_EINVAL;
+  if (s->results.count(ticket)) {
+    take_result(s, ticket, verdict, sig_out);
+    *done = 1;
+    return DIL_OK;
+  }
+  return s->svc_rc;
+}
+
+int dil_server_wait(dil_server *s, uint64_t ticket, int32_t timeout_ms, int32_t *verdict, uint8_t *sig_out) {
+  if (!s) return DIL_EINVAL;
+  std::unique_lock<std::mutex> lk(s->mu);
+  if (!s->outstanding.count(ticket)) return DIL_EINVAL;
+  auto ready = [&]() { return s->results.count(ticket) || s->svc_rc != DIL_OK || !s->svc_on; };
+  if (timeout_ms < 0) s->cv_done.wait(lk, ready);
+  else s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready);
+  if (s->results.count(ticket)) {
+    take_result(s, ticket, verdict, sig_out);
+    return DIL_OK;
+  }
+  if (s->svc_rc) return s->svc_rc;
+  return s->svc_on ? DIL_ETIMEDOUT : DIL_EINVAL;
+}
+
+int dil_server_stop(dil_server *s) {
+  if (!s) return DIL_EINVAL;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (!s->svc_on) return sfail(s, DIL_EINVAL, "the interactive mode is not on");
+    s->svc_stop = true;
+  }
+  s->cv_in.notify_all();
+  s->svc.join();
+  std::lock_guard<std::mutex> lk(s->mu);
+  s->svc_on = false;
+  s->cv_done.notify_all();
+  return s->svc_rc;
 }
 
 }  // extern "C"

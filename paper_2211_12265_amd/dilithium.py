@@ -15,7 +15,7 @@ from typing import Optional, Tuple
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdil.so")
 
-DIL_OK, DIL_EINVAL, DIL_ENOMEM, DIL_EHIP, DIL_EMSG = 0, -1, -2, -3, -4
+DIL_OK, DIL_EINVAL, DIL_ENOMEM, DIL_EHIP, DIL_EMSG, DIL_ETIMEDOUT = 0, -1, -2, -3, -4, -5
 MODE_STAGED, MODE_PERSISTENT = 0, 1
 OP_KEYGEN, OP_SIGN, OP_VERIFY = 0, 1, 2
 
@@ -29,6 +29,7 @@ EXPORTS = [
     "dil_server_destroy",
     "dil_server_last_error", "dil_server_stats", "dil_server_run", "dil_ctx_reserve_call", "dil_workspace_bytes",
     "dil_alu_probe", "dil_verify_keyset_noalloc", "dil_t0_ntt_batch",
+    "dil_server_start", "dil_server_submit", "dil_server_poll", "dil_server_wait", "dil_server_stop",
 ]
 
 _LIB: Optional[ctypes.CDLL] = None
@@ -93,6 +94,13 @@ def load() -> ctypes.CDLL:
         "dil_workspace_bytes": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32,
                                                ctypes.POINTER(ctypes.c_size_t)]),
         "dil_server_run": (ctypes.c_int, [_P, ctypes.c_uint32] + [_P] * 12),
+        "dil_server_start": (ctypes.c_int, [_P]),
+        "dil_server_submit": (ctypes.c_int, [_P, ctypes.c_int, ctypes.c_int, ctypes.c_uint32, _P, ctypes.c_uint64,
+                                             _P, ctypes.POINTER(ctypes.c_uint64)]),
+        "dil_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_int32), _P]),
+        "dil_server_wait": (ctypes.c_int, [_P, ctypes.c_uint64, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P]),
+        "dil_server_stop": (ctypes.c_int, [_P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

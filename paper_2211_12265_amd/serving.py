@@ -3,7 +3,8 @@
 Requests (mixed-level Sign and Verify, each against one key of a resident
 key table; levels 2/3/5 and ML-DSA 44/65/87) arrive
 over time, replayed from a trace (`Server.serve`, `NativeServer.serve`) or
-submitted one by one from application threads (`Service`).  The loop keeps up to `n_streams`
+submitted one by one from application threads (`Service` over the Python
+engine, `NativeService` over the C++ engine's interactive mode).  The loop keeps up to `n_streams`
 batches in flight, each on its own HIP stream with its own libdil context
 (workspace): whenever a stream is free, the requests that have arrived are
 admitted in order as the next batch, split by (level, op) into key-table
@@ -528,6 +529,116 @@ class NativeServer:
         res.group_cap = int(cap.value)
         res.reserved_bytes = int(rb.value)
         return res
+
+
+class NativeService:
+    """The interactive front end of the C++ engine (dil_server_start / submit / poll / wait / stop):
+    the same interface as `Service`, with the dispatcher thread, batch formation and result
+    bookkeeping in native code.  A result is the signature bytes of a Sign request or the verdict
+    (True / False) of a Verify request; it is handed out once."""
+
+    def __init__(self, keysets: Dict[int, "dl.KeySet"], n_streams: int = 4, max_batch: int = 4096,
+                 mem_budget: int = 2 << 30, max_msg_bytes: int = 64 << 20, persistent: bool = True):
+        import ctypes
+        self.server = NativeServer(keysets, n_streams=n_streams, max_batch=max_batch, mem_budget=mem_budget,
+                                   max_msg_bytes=max_msg_bytes, persistent=persistent)
+        self.lib = self.server.lib
+        self._c = ctypes
+        self.n_keys = {lv: ks.n_keys for lv, ks in keysets.items()}
+        self.max_msg_bytes = max_msg_bytes
+        self._op = {}                      # ticket -> (op, level), for the result's shape
+        self._lock = threading.Lock()
+        rc = self.lib.dil_server_start(self.server.h)
+        if rc:
+            self.server.close()
+            raise dl.DilError(rc, "dil_server_start failed")
+
+    def _err(self, rc: int, what: str):
+        text = self.lib.dil_server_last_error(self.server.h).decode(errors="replace")
+        return dl.DilError(rc, f"{what}: {text}")
+
+    def submit(self, level: int, op: int, key: int, msg: bytes, sig: Optional[bytes] = None) -> int:
+        """Queue Sign (op 0) of `msg` with key row `key` of the level's table, or Verify (op 1) of
+        `sig` on it; malformed requests are refused here, before anything runs."""
+        c = self._c
+        if getattr(self, "server", None) is None:
+            raise RuntimeError("service closed")
+        msg = bytes(msg)
+        if level not in self.n_keys:
+            raise ValueError(f"no key table for level {level}")
+        if op not in (SIGN, VERIFY):
+            raise ValueError("op must be 0 (sign) or 1 (verify)")
+        if not 0 <= key < self.n_keys[level]:
+            raise ValueError(f"key row {key} outside the level-{level} table ({self.n_keys[level]} rows)")
+        if len(msg) > self.max_msg_bytes:
+            raise ValueError("message larger than a batch's staging buffer")
+        sbuf = None
+        if op == VERIFY:
+            if sig is None or len(sig) != sig_size(level):
+                raise ValueError(f"verify needs a {sig_size(level)}-byte signature")
+            sbuf = c.create_string_buffer(bytes(sig), len(sig))
+        mbuf = c.create_string_buffer(msg, max(len(msg), 1))
+        t = c.c_uint64()
+        rc = self.lib.dil_server_submit(self.server.h, op, level, key, c.cast(mbuf, c.c_void_p), len(msg),
+                                        c.cast(sbuf, c.c_void_p) if sbuf is not None else None, c.byref(t))
+        if rc:
+            raise self._err(rc, "submit")
+        with self._lock:
+            self._op[t.value] = (op, level)
+        return t.value
+
+    def _result(self, ticket: int, verdict, sbuf):
+        with self._lock:
+            op, _ = self._op.pop(ticket)
+        return sbuf.raw if op == SIGN else bool(verdict.value == 1)
+
+    def _buffers(self, ticket: int):
+        with self._lock:
+            if ticket not in self._op:
+                raise KeyError(f"ticket {ticket} is not outstanding")
+            op, level = self._op[ticket]
+        return self._c.c_int32(), self._c.create_string_buffer(sig_size(level))
+
+    def poll(self, ticket: int):
+        """The result once the request has finished, else None (also for a ticket whose result
+        was already handed out)."""
+        c = self._c
+        with self._lock:
+            if ticket not in self._op:
+                return None
+        verdict, sbuf = self._buffers(ticket)
+        done = c.c_int()
+        rc = self.lib.dil_server_poll(self.server.h, ticket, c.byref(done), c.byref(verdict), c.cast(sbuf, c.c_void_p))
+        if rc:
+            raise self._err(rc, "poll")
+        return self._result(ticket, verdict, sbuf) if done.value else None
+
+    def wait(self, ticket: int, timeout: Optional[float] = None):
+        c = self._c
+        verdict, sbuf = self._buffers(ticket)
+        ms = -1 if timeout is None else max(int(timeout * 1e3), 0)
+        rc = self.lib.dil_server_wait(self.server.h, ticket, ms, c.byref(verdict), c.cast(sbuf, c.c_void_p))
+        if rc == dl.DIL_ETIMEDOUT:
+            raise TimeoutError(f"ticket {ticket} not done")
+        if rc:
+            raise self._err(rc, "wait")
+        return self._result(ticket, verdict, sbuf)
+
+    @property
+    def batches(self) -> int:
+        b = self._c.c_uint64()
+        self.lib.dil_server_stats(self.server.h, self._c.byref(b), None, None, None, None)
+        return int(b.value)
+
+    def close(self):
+        """Finish the submitted requests, then stop the dispatcher and free the engine."""
+        if getattr(self, "server", None) is None:
+            return
+        rc = self.lib.dil_server_stop(self.server.h)
+        self.server.close()
+        self.server = None
+        if rc:
+            raise dl.DilError(rc, "the dispatcher failed")
 
 
 def latency_summary(res: Results, reqs: Requests) -> dict:

@@ -157,10 +157,12 @@ def test_batches_overlap(setup, engine):
     _check_against_oracle(sv, host, reqs, flipped, res)
 
 
-def test_service_submit_and_wait_from_threads():
-    """The interactive front end (`Service`): three threads submit mixed Sign / Verify requests
-    at levels 2 and ML-DSA-65 while earlier batches run; every ticket's result equals the
-    oracle's (signature bytes, verdict), results are handed out once, and bad requests are
+@pytest.mark.parametrize("front", ["Service", "NativeService"])
+def test_service_submit_and_wait_from_threads(front):
+    """The interactive front ends (`Service` over the Python engine, `NativeService` over
+    dil_server_start / submit / poll / wait / stop): three threads submit mixed Sign / Verify
+    requests at levels 2 and ML-DSA-65 while earlier batches run; every ticket's result equals
+    the oracle's (signature bytes, verdict), results are handed out once, and bad requests are
     refused at submission."""
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -195,7 +197,7 @@ def test_service_submit_and_wait_from_threads():
                 s = bytes(b)
             sig_in[i] = s
             expect[i] = bool(oracle.verify(int(level[i]), pk[key[i]].tobytes(), msgs[i], s) == 1)
-    svc = sv.Service(keysets, n_streams=3, max_batch=32, mem_budget=2 << 30, max_msg_bytes=1 << 20)
+    svc = getattr(sv, front)(keysets, n_streams=3, max_batch=32, mem_budget=2 << 30, max_msg_bytes=1 << 20)
     tickets = [None] * n
 
     def client(part):
@@ -263,3 +265,73 @@ def test_native_server_rejects_duplicate_levels(setup):
     rc = lib.dil_server_create_tables(ctypes.byref(h), 0, ctypes.cast(tables, ctypes.c_void_p), 2, 2, 64,
                                       1 << 20, 2 << 30, dl.MODE_PERSISTENT)
     assert rc == dl.DIL_EINVAL and not h.value
+
+
+def test_native_service_modes_and_errors():
+    """The C entry points of the interactive mode directly: a trace replay is refused while the
+    mode is on; poll reports an unfinished request and hands a result out once; wait with a
+    zero timeout returns a finished result; unknown tickets, bad rows and a stopped mode are
+    refused; stop finishes what was submitted, and the engine then replays a trace again."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import ctypes
+    from paper_2211_12265_amd import dilithium as dl
+    from paper_2211_12265_amd import serving as sv
+    ctx = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    pk, sk = oracle.keygen_batch(2, workload.keygen_seeds(3, seed=340))
+    ks = dl.KeySet(ctx, 2, pk=torch.from_numpy(pk).cuda(), sk=torch.from_numpy(sk).cuda())
+    server = sv.NativeServer({2: ks}, n_streams=2, max_batch=16, mem_budget=2 << 30, max_msg_bytes=1 << 16)
+    lib, h = server.lib, server.h
+    c = ctypes
+    msgs = [workload.random_bytes("test/native-service", i, (17 * i,)).tobytes() for i in range(12)]
+    assert lib.dil_server_start(h) == dl.DIL_OK
+    assert lib.dil_server_start(h) == dl.DIL_EINVAL            # already on
+    one = sv.Requests(np.zeros(1), np.array([sv.SIGN], np.int8), np.array([2], np.int8), np.array([0], np.int32),
+                      np.frombuffer(msgs[1], np.uint8).copy(), np.array([0, len(msgs[1])], np.int64))
+    with pytest.raises(dl.DilError):
+        server.serve(one)                                      # replay refused while the mode is on
+    t = c.c_uint64()
+    tickets = []
+    for i, m in enumerate(msgs):
+        buf = c.create_string_buffer(m, max(len(m), 1))
+        assert lib.dil_server_submit(h, sv.SIGN, 2, i % 3, c.cast(buf, c.c_void_p), len(m), None, c.byref(t)) == 0
+        tickets.append(t.value)
+    bad = c.create_string_buffer(b"x", 1)
+    assert lib.dil_server_submit(h, sv.SIGN, 2, 3, c.cast(bad, c.c_void_p), 1, None, c.byref(t)) == dl.DIL_EINVAL
+    assert lib.dil_server_submit(h, sv.VERIFY, 2, 0, c.cast(bad, c.c_void_p), 1, None, c.byref(t)) == dl.DIL_EINVAL
+    assert lib.dil_server_submit(h, sv.SIGN, 3, 0, c.cast(bad, c.c_void_p), 1, None, c.byref(t)) == dl.DIL_EINVAL
+    done, verdict = c.c_int(), c.c_int32()
+    assert lib.dil_server_poll(h, 10 ** 9, c.byref(done), c.byref(verdict), None) == dl.DIL_EINVAL
+    sbuf = c.create_string_buffer(dl.sizes(2)[2])
+    got = {}
+    for k, tk in enumerate(tickets):
+        if k % 2:
+            assert lib.dil_server_wait(h, tk, 60000, c.byref(verdict), c.cast(sbuf, c.c_void_p)) == dl.DIL_OK
+        else:
+            while True:
+                assert lib.dil_server_poll(h, tk, c.byref(done), c.byref(verdict), c.cast(sbuf, c.c_void_p)) == 0
+                if done.value:
+                    break
+        assert verdict.value == -1
+        got[k] = sbuf.raw
+        # handed out once
+        assert lib.dil_server_poll(h, tk, c.byref(done), c.byref(verdict), None) == dl.DIL_EINVAL
+    for k, m in enumerate(msgs):
+        assert got[k] == oracle.sign(2, sk[k % 3].tobytes(), m)[0]
+    # requests left to stop: it finishes them, and their results stay available
+    last = []
+    for i in range(5):
+        buf = c.create_string_buffer(msgs[i], max(len(msgs[i]), 1))
+        assert lib.dil_server_submit(h, sv.SIGN, 2, 1, c.cast(buf, c.c_void_p), len(msgs[i]), None, c.byref(t)) == 0
+        last.append(t.value)
+    assert lib.dil_server_stop(h) == dl.DIL_OK
+    assert lib.dil_server_stop(h) == dl.DIL_EINVAL             # not on
+    assert lib.dil_server_submit(h, sv.SIGN, 2, 0, c.cast(bad, c.c_void_p), 1, None, c.byref(t)) == dl.DIL_EINVAL
+    for i, tk in enumerate(last):
+        assert lib.dil_server_wait(h, tk, 0, c.byref(verdict), c.cast(sbuf, c.c_void_p)) == dl.DIL_OK
+        assert sbuf.raw == oracle.sign(2, sk[1].tobytes(), msgs[i])[0]
+    res = server.serve(one)                                    # replay works again
+    assert bytes(res.sig[0]) == oracle.sign(2, sk[0].tobytes(), msgs[1])[0]
+    server.close()
+    ks.close()
+    ctx.close()
