@@ -172,6 +172,44 @@ uint32_t admit_count(const dil_server *s, uint32_t avail, Peek peek) {
   return n;
 }
 
+// One request's byte copies into a lane's pinned staging buffers.
+struct CopyDesc {
+  const uint8_t *msg, *sig;
+  uint64_t len, sig_len;
+  uint8_t *msg_dst, *sig_dst;
+};
+
+// Run fn(lo, hi) over [0, n) in contiguous ranges: on the calling thread
+// alone for small jobs, else split over a few short-lived threads (the
+// batch's host copies are several MB at full batches and bound the
+// dispatcher's rate on one thread; a thread costs tens of microseconds).
+template <class Fn>
+void parallel_ranges(size_t n, size_t bytes, Fn fn) {
+  constexpr size_t kMinBytesPerThread = 512 * 1024;
+  const size_t hw = std::max<size_t>(1, std::thread::hardware_concurrency());
+  size_t t = std::min<size_t>({4, hw, bytes / kMinBytesPerThread, n});
+  if (t <= 1) {
+    fn((size_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  th.reserve(t - 1);
+  const size_t per = (n + t - 1) / t;
+  try {
+    for (size_t i = 1; i < t; i++) {
+      const size_t lo = std::min(n, i * per), hi = std::min(n, lo + per);
+      th.emplace_back([=]() { fn(lo, hi); });
+    }
+  } catch (...) {  // no more threads: the remaining ranges on this one
+    for (size_t i = 1 + th.size(); i < t; i++) {
+      const size_t lo = std::min(n, i * per), hi = std::min(n, lo + per);
+      fn(lo, hi);
+    }
+  }
+  fn((size_t)0, std::min(n, per));
+  for (auto &x : th) x.join();
+}
+
 // Stage the nreq requests of one batch (get(r), r < nreq) into the lane's
 // pinned buffers, grouped by (level, op) in request order, and enqueue the
 // copies in, one key-table call per group on the group's own stream (forked
@@ -180,19 +218,27 @@ uint32_t admit_count(const dil_server *s, uint32_t avail, Peek peek) {
 // batch was still in flight.
 template <class Get>
 int launch_batch(dil_server *s, Lane &ln, uint32_t nreq, Get get, bool *overlap) {
+  // one pass buckets the requests by (level, op), each bucket in request order
+  std::vector<uint32_t> bucket[NGROUP];
+  for (uint32_t r = 0; r < nreq; r++) {
+    const ReqRef q = get(r);
+    bucket[2 * q.li + q.op].push_back(r);
+  }
   ln.groups.clear();
-  for (int li = 0; li < NLV; li++)
-    for (int o = 0; o < 2; o++) {
-      Group g;
-      g.li = li;
-      g.op = o;
-      for (uint32_t r = 0; r < nreq; r++) {
-        const ReqRef q = get(r);
-        if (q.li == li && q.op == o) g.req.push_back(r);
-      }
-      if (!g.req.empty()) ln.groups.push_back(std::move(g));
-    }
-  size_t m_pos = 0, t_pos = 0, o_pos = 0, s_pos = 0;
+  for (int gi = 0; gi < NGROUP; gi++) {
+    if (bucket[gi].empty()) continue;
+    Group g;
+    g.li = gi / 2;
+    g.op = gi % 2;
+    g.req = std::move(bucket[gi]);
+    ln.groups.push_back(std::move(g));
+  }
+  // offsets, keys and the copies' sources and destinations, then the byte
+  // copies into the pinned staging buffers (disjoint, split over threads for
+  // large batches)
+  std::vector<CopyDesc> copies;
+  copies.reserve(nreq);
+  size_t m_pos = 0, t_pos = 0, o_pos = 0, s_pos = 0, bytes = 0;
   for (auto &g : ln.groups) {
     size_t ss = s->sig_bytes[g.li];
     g.m_pos = m_pos;
@@ -202,11 +248,18 @@ int launch_batch(dil_server *s, Lane &ln, uint32_t nreq, Get get, bool *overlap)
     uint64_t acc = 0;
     for (size_t j = 0; j < g.req.size(); j++) {
       const ReqRef q = get(g.req[j]);
-      if (q.len) memcpy(ln.h_msg + m_pos + acc, q.msg, q.len);
+      CopyDesc c;
+      c.msg = q.msg;
+      c.len = q.len;
+      c.msg_dst = ln.h_msg + m_pos + acc;
+      c.sig = g.op == 1 ? q.sig : nullptr;
+      c.sig_len = g.op == 1 ? ss : 0;
+      c.sig_dst = ln.h_sig + s_pos + j * ss;
+      copies.push_back(c);
+      bytes += c.len + c.sig_len;
       ln.h_off[o_pos + j] = acc;
       acc += q.len;
       ln.h_key[t_pos + j] = q.key;
-      if (g.op == 1) memcpy(ln.h_sig + s_pos + j * ss, q.sig, ss);
     }
     ln.h_off[o_pos + g.req.size()] = acc;
     g.m_len = acc;
@@ -215,6 +268,13 @@ int launch_batch(dil_server *s, Lane &ln, uint32_t nreq, Get get, bool *overlap)
     o_pos += g.req.size() + 1;
     s_pos += g.req.size() * ss;
   }
+  parallel_ranges(copies.size(), bytes, [&](size_t lo, size_t hi) {
+    for (size_t k = lo; k < hi; k++) {
+      const CopyDesc &c = copies[k];
+      if (c.len) memcpy(c.msg_dst, c.msg, c.len);
+      if (c.sig_len) memcpy(c.sig_dst, c.sig, c.sig_len);
+    }
+  });
   bool ok = hipMemcpyAsync(ln.d_msg, ln.h_msg, std::max<size_t>(m_pos, 1), hipMemcpyHostToDevice, ln.st) ==
                 hipSuccess &&
             hipMemcpyAsync(ln.d_off, ln.h_off, o_pos * 8, hipMemcpyHostToDevice, ln.st) == hipSuccess &&
@@ -567,12 +627,21 @@ int dil_server_run(dil_server *s, uint32_t n, const uint8_t *op, const uint8_t *
       if (q == hipErrorNotReady) continue;
       if (q != hipSuccess) return sfail(s, DIL_EHIP, "batch failed on the device");
       const uint64_t t = now_ns();
+      std::vector<CopyDesc> outs;  // signatures out of the lane's staging buffer
+      size_t bytes = 0;
       harvest_lane(s, ln, [&](uint32_t r, int o, const uint8_t *sig, size_t ss, int32_t v) {
         const uint32_t i = ln.base + r;
         done_ns[i] = t;
-        if (o == 0) memcpy(sig_out + sig_out_off[i], sig, ss);
+        if (o == 0) {
+          outs.push_back(CopyDesc{sig, nullptr, ss, 0, sig_out + sig_out_off[i], nullptr});
+          bytes += ss;
+        }
         verdict[i] = v;
         done++;
+      });
+      // the lane is reused only after this loop, so its staging buffer still holds them
+      parallel_ranges(outs.size(), bytes, [&](size_t lo, size_t hi) {
+        for (size_t k = lo; k < hi; k++) memcpy(outs[k].msg_dst, outs[k].msg, outs[k].len);
       });
       progressed = true;
     }

@@ -335,3 +335,19 @@ def test_native_service_modes_and_errors():
     server.close()
     ks.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("engine", ["native"])
+def test_large_batches_match_oracle(setup, engine):
+    """Batches of up to 2,048 requests, all arriving at once: the native engine stages a batch
+    of several MB (messages and verify signatures in, signatures out) on several host threads,
+    and every output still equals the oracle's."""
+    dl, sv, ctx, keysets, host, reqs, flipped = setup
+    keys = {lv: ks.n_keys for lv, ks in keysets.items()}
+    big = sv.build_requests(1500, lam=0.0, keys_per_level=keys, seed=17)
+    big_flipped = sv.attach_signatures(big, ctx, keysets, flip_rate=0.1, seed=17)
+    server = sv.NativeServer(keysets, n_streams=2, max_batch=2048, mem_budget=16 << 30, max_msg_bytes=64 << 20)
+    res = server.serve(big)
+    server.close()
+    assert res.batches <= 3
+    _check_against_oracle(sv, host, big, big_flipped, res)
