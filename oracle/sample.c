@@ -218,7 +218,11 @@ void dil_ref_sample_in_ball(int level, const uint8_t *ctilde, int32_t c[ORN]) {
   ref_params P;
   if (dil_ref_params(level, &P)) return;
   stream_t s;
+#if defined(DIL_PLANT) && DIL_PLANT == 23
+  stream_open(&s, 0, ctilde, 32, 136);  /* planted: only the first 32 bytes of ctilde seed it */
+#else
   stream_open(&s, 0, ctilde, (size_t)P.ct_bytes, 136);  /* ML-DSA: the whole lambda/4-byte ctilde seeds it */
+#endif
   uint64_t signs = 0;
   for (int i = 0; i < 8; i++) signs |= (uint64_t)stream_byte(&s) << (8 * i);
   for (int i = 0; i < ORN; i++) c[i] = 0;

@@ -188,7 +188,11 @@ int dil_ref_keygen(int level, const uint8_t zeta[32], uint8_t *pk, uint8_t *sk) 
   memcpy(in, zeta, 32);
   in[32] = (uint8_t)k;  /* ML-DSA only: the k and l bytes after the seed */
   in[33] = (uint8_t)l;
+#if defined(DIL_PLANT) && DIL_PLANT == 20
+  dil_ref_shake256(in, 32, seed, 128); /* planted: ML-DSA's k and l bytes left out of the seed expansion */
+#else
   dil_ref_shake256(in, P.mldsa ? 34 : 32, seed, 128);
+#endif
   const uint8_t *rho = seed, *rhop = seed + 32, *K = seed + 96;
   int32_t *A = (int32_t *)malloc(sizeof(int32_t) * k * l * ORN);
   int32_t *s = (int32_t *)malloc(sizeof(int32_t) * (k + l) * ORN);
@@ -245,7 +249,12 @@ void dil_ref_mldsa_mu(const uint8_t tr[64], const uint8_t *msg, size_t mlen, uin
   buf[64] = 0;  /* pure ML-DSA, not the pre-hash variant */
   buf[65] = 0;  /* context length 0 */
   memcpy(buf + 66, msg, mlen);
+#if defined(DIL_PLANT) && DIL_PLANT == 21
+  memmove(buf + 64, buf + 66, mlen); /* planted: the two zero bytes before M dropped */
+  dil_ref_shake256(buf, 64 + mlen, mu, 64);
+#else
   dil_ref_shake256(buf, 66 + mlen, mu, 64);
+#endif
   free(buf);
 }
 
@@ -288,7 +297,12 @@ static int sign_core(int level, int internal, const uint8_t *sk, const uint8_t *
     if (rnd) memcpy(buf + 32, rnd, 32);
     else memset(buf + 32, 0, 32);
     memcpy(buf + 64, mu, 64);
+#if defined(DIL_PLANT) && DIL_PLANT == 22
+    memmove(buf + 32, buf + 64, 64); /* planted: rnd left out of rho'' = H(K || mu) */
+    dil_ref_shake256(buf, 96, rhop, 64);
+#else
     dil_ref_shake256(buf, 128, rhop, 64);
+#endif
   } else {
     memcpy(buf, tr, 32);
     memcpy(buf + 32, msg, mlen);

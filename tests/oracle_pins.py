@@ -196,3 +196,58 @@ def sign_hint_bound(level: int = 2, seed: int = 32, msgs: int = 4, scale: int = 
         if counts[-1] > om or np.any(np.diff(counts) < 0):
             fails.append(f"hint pin: emitted signature counts {counts.tolist()} (omega {om}, message {m})")
     return fails
+
+
+# ---- ML-DSA hash inputs (FIPS 204 form; the paper covers round 3 only) ---------------------------
+
+def _shake256(data: bytes, n: int) -> bytes:
+    import hashlib
+    return hashlib.shake_256(data).digest(n)
+
+
+def mldsa_hash_inputs(level: int = 44, seed: int = 41) -> list:
+    """Every ML-DSA input to SHAKE256 that differs from round 3, recomputed with hashlib from what
+    the oracle emits: the KeyGen seed expansion H(xi || k || l), tr = H(pk, 64), mu = H(tr || 0 ||
+    0 || M), rho'' = H(K || rnd || mu) (through y = z - c s1 = ExpandMask(rho'', kappa)), and
+    SampleInBall seeded by the whole lambda / 4-byte ctilde (level 87: its last byte matters)."""
+    failed = []
+    p = oracle.params(level)
+    k, l, eta = p["k"], p["l"], p["eta"]
+    xi = workload.random_bytes("pins/mldsa-xi", seed, (32,)).tobytes()
+    pk, sk = oracle.keygen(level, xi)
+    exp = _shake256(xi + bytes([k, l]), 128)
+    if pk[:32] != exp[:32] or sk[32:64] != exp[96:]:
+        failed.append("mldsa-keygen-seed")
+    if sk[64:128] != _shake256(pk, 64):
+        failed.append("mldsa-tr")
+    tr, K = sk[64:128], sk[32:64]
+    msg = workload.random_bytes("pins/mldsa-m", seed, (45,)).tobytes()
+    mu = _shake256(tr + b"\x00\x00" + msg, 64)
+    if oracle.mldsa_mu(tr, msg) != mu:
+        failed.append("mldsa-mu")
+    rnd = workload.random_bytes("pins/mldsa-rnd", seed, (32,)).tobytes()
+    sig, iters = oracle.sign_batch(level, np.frombuffer(sk, np.uint8)[None], np.frombuffer(msg, np.uint8),
+                                   np.array([0, len(msg)], np.uint64), rnd=np.frombuffer(rnd, np.uint8)[None],
+                                   nthreads=1)
+    sig, it = sig[0].tobytes(), int(iters[0])
+    ct, zb, eb = p["ct_bytes"], N * p["z_bits"] // 8, N * p["eta_bits"] // 8
+    c = oracle.sample_in_ball(level, sig[:ct]).astype(np.int64)
+    ok = it >= 1
+    rhopp = _shake256(K + rnd + mu, 64)
+    y = oracle.expand_mask(level, rhopp, l * (it - 1)).astype(np.int64) if ok else None
+    for j in range(l if ok else 0):
+        z = p["gamma1"] - oracle.bitunpack(sig[ct + j * zb: ct + (j + 1) * zb], N, p["z_bits"]).astype(np.int64)
+        s1 = eta - oracle.bitunpack(sk[128 + j * eb: 128 + (j + 1) * eb], N, p["eta_bits"]).astype(np.int64)
+        d = np.mod(z - negacyclic(c, s1) - y[j], Q)
+        if d.any():
+            ok = False
+            break
+    if not ok:
+        failed.append("mldsa-rho-pp")
+    if level == 87 or p["ct_bytes"] > 32:
+        base = workload.random_bytes("pins/mldsa-ct", seed, (p["ct_bytes"],)).tobytes()
+        other = bytearray(base)
+        other[-1] ^= 1
+        if np.array_equal(oracle.sample_in_ball(level, base), oracle.sample_in_ball(level, bytes(other))):
+            failed.append("mldsa-sample-in-ball-ctilde")
+    return failed

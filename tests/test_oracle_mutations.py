@@ -4,7 +4,9 @@ dropped Decompose special case, a wrong sign in MakeHint, a wrong UseHint branch
 packing, a dropped challenge position, a dropped beta, a dropped c t1 term, a wrong c t0 sign,
 a wrong t0 offset, ExpandA's 23-bit mask dropped, ExpandS's eta = 2 threshold moved to 16, Sign's
 [h] > omega rejection dropped, Sign's ||c t0|| >= gamma2 rejection dropped, SampleInBall drawing
-b < i) must fail at least one of the oracle's pins.  Everything runs on the CPU."""
+b < i; and in the ML-DSA form: the k / l bytes left out of KeyGen's seed expansion, the two zero
+bytes of mu dropped, rnd left out of rho'', SampleInBall seeded by 32 bytes of a longer ctilde)
+must fail at least one of the oracle's pins.  Everything runs on the CPU."""
 import hashlib
 import os
 
@@ -16,7 +18,7 @@ import oracle_pins
 from paper_2211_12265_amd import workload
 
 Q = 8380417
-PLANTS = list(range(1, 20))
+PLANTS = list(range(1, 24))
 
 
 def _schoolbook(a, b):
@@ -82,6 +84,11 @@ def pins_hold(stop_early: bool = False):
             sig, it = oracle.sign_batch(level, sk, msg, off, nthreads=4)
             if (it < 1).any() or oracle.verify_batch(level, pk, msg, off, sig, nthreads=4).tolist() != [1] * 6:
                 failed.append("round-trip")
+        # the ML-DSA form's hash inputs, under the same iteration cap
+        for level in (44, 87):
+            if failed and stop_early:
+                break
+            failed += oracle_pins.mldsa_hash_inputs(level)
     finally:
         oracle.lib().dil_ref_set_sign_cap(0)
     if failed and stop_early:
