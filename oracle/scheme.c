@@ -234,11 +234,15 @@ static void pack_w1(const ref_params *P, const int32_t *w1, uint8_t *out) {
    (for the pure form 0x00 || |ctx| || ctx || M; for the pre-hash form 0x01 ||
    |ctx| || ctx || OID || PH(M)) and hash mu = H(tr || M', 64) */
 static void mu_internal(const uint8_t tr[64], const uint8_t *mprime, size_t len, uint8_t mu[64]) {
+#if defined(DIL_PLANT) && DIL_PLANT == 24
+  dil_ref_mldsa_mu(tr, mprime, len, mu); /* planted: the formatted message formatted again */
+#else
   uint8_t *buf = (uint8_t *)malloc(64 + len + 1);
   memcpy(buf, tr, 64);
   memcpy(buf + 64, mprime, len);
   dil_ref_shake256(buf, 64 + len, mu, 64);
   free(buf);
+#endif
 }
 
 /* ML-DSA: mu = H(tr || IntegerToBytes(0, 1) || IntegerToBytes(|ctx|, 1) || ctx || M, 64)

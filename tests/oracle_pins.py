@@ -208,8 +208,9 @@ def _shake256(data: bytes, n: int) -> bytes:
 def mldsa_hash_inputs(level: int = 44, seed: int = 41) -> list:
     """Every ML-DSA input to SHAKE256 that differs from round 3, recomputed with hashlib from what
     the oracle emits: the KeyGen seed expansion H(xi || k || l), tr = H(pk, 64), mu = H(tr || 0 ||
-    0 || M), rho'' = H(K || rnd || mu) (through y = z - c s1 = ExpandMask(rho'', kappa)), and
-    SampleInBall seeded by the whole lambda / 4-byte ctilde (level 87: its last byte matters)."""
+    0 || M), rho'' = H(K || rnd || mu) (through y = z - c s1 = ExpandMask(rho'', kappa)), the
+    internal form's mu = H(tr || M') (M' = 0 || 0 || M signs as M does), and SampleInBall seeded
+    by the whole lambda / 4-byte ctilde (level 87: its last byte matters)."""
     failed = []
     p = oracle.params(level)
     k, l, eta = p["k"], p["l"], p["eta"]
@@ -244,6 +245,9 @@ def mldsa_hash_inputs(level: int = 44, seed: int = 41) -> list:
             break
     if not ok:
         failed.append("mldsa-rho-pp")
+    # internal form: the formatted message of M with the empty context signs as M does
+    if oracle.mldsa_sign_internal(level, sk, b"\x00\x00" + msg) != oracle.sign(level, sk, msg)[0]:
+        failed.append("mldsa-internal-mu")
     if level == 87 or p["ct_bytes"] > 32:
         base = workload.random_bytes("pins/mldsa-ct", seed, (p["ct_bytes"],)).tobytes()
         other = bytearray(base)

@@ -5,7 +5,8 @@ packing, a dropped challenge position, a dropped beta, a dropped c t1 term, a wr
 a wrong t0 offset, ExpandA's 23-bit mask dropped, ExpandS's eta = 2 threshold moved to 16, Sign's
 [h] > omega rejection dropped, Sign's ||c t0|| >= gamma2 rejection dropped, SampleInBall drawing
 b < i; and in the ML-DSA form: the k / l bytes left out of KeyGen's seed expansion, the two zero
-bytes of mu dropped, rnd left out of rho'', SampleInBall seeded by 32 bytes of a longer ctilde)
+bytes of mu dropped, rnd left out of rho'', SampleInBall seeded by 32 bytes of a longer ctilde,
+the internal form's formatted message formatted again)
 must fail at least one of the oracle's pins.  Everything runs on the CPU."""
 import hashlib
 import os
@@ -18,7 +19,7 @@ import oracle_pins
 from paper_2211_12265_amd import workload
 
 Q = 8380417
-PLANTS = list(range(1, 24))
+PLANTS = list(range(1, 25))
 
 
 def _schoolbook(a, b):
