@@ -485,6 +485,8 @@ def ablation_run(level: int, n: int, msg_dist: str, steps: int = 10, tune: bool 
     forms = [("staged", dl.MODE_STAGED, None, 0), ("persistent 1-wave", dl.MODE_PERSISTENT, 1, 1),
              ("persistent 2-wave", dl.MODE_PERSISTENT, 2, 1), ("persistent 4-wave", dl.MODE_PERSISTENT, 4, 1),
              ("persistent 4-wave, no hipGraph", dl.MODE_PERSISTENT, 4, 0)]
+    if level in MLDSA_BASE:  # the ML-DSA levels run the four-wavefront loop kernel only
+        forms = [f for f in forms if f[2] in (None, 4)]
     for name, mode, waves, graph in forms:
         ctx = dl.Context(0, mode=mode)
         sig = torch.zeros((n, sgl), dtype=torch.uint8, device="cuda")
