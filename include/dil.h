@@ -276,7 +276,12 @@ int dil_verify_keyset_noalloc(dil_ctx *ctx, const dil_keyset *ks, const uint32_t
  * context of its own; that needs more hardware queues than HIP's default of 4
  * per process, so the process should set GPU_MAX_HW_QUEUES (e.g. 16) before
  * HIP starts.  mode is DIL_MODE_STAGED or DIL_MODE_PERSISTENT for Sign; the
- * persistent Sign calls use four-wavefront workgroups ("persist.waves" = 4). */
+ * persistent Sign calls use four-wavefront workgroups ("persist.waves" = 4).
+ * mode | DIL_SERVER_MLDSA_INTERNAL: the requests of the ML-DSA levels carry
+ * formatted messages M' ("mldsa.internal" = 1 on those groups: context
+ * strings, pre-hashed messages); round-3 requests are unaffected.  Other mode
+ * bits give DIL_EINVAL. */
+#define DIL_SERVER_MLDSA_INTERNAL 0x100
 typedef struct dil_server dil_server;
 /* tables: n_tables key tables (host array of handles), each level at most
  * once (a table's level comes from the table); DIL_EINVAL otherwise. */

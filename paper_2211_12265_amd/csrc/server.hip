@@ -445,6 +445,10 @@ int dil_server_create_tables(dil_server **out, int device, dil_keyset *const *ta
     if (li < 0 || by_level[li]) return DIL_EINVAL;  // one table per level
     by_level[li] = tables[i];
   }
+  const int ctx_mode = mode & 0xFF;
+  const bool mldsa_internal = (mode & DIL_SERVER_MLDSA_INTERNAL) != 0;
+  if ((mode & ~(0xFF | DIL_SERVER_MLDSA_INTERNAL)) || (ctx_mode != DIL_MODE_STAGED && ctx_mode != DIL_MODE_PERSISTENT))
+    return DIL_EINVAL;
   if (hipSetDevice(device) != hipSuccess) return DIL_EHIP;
   dil_server *s = new dil_server();
   s->device = device;
@@ -469,11 +473,13 @@ int dil_server_create_tables(dil_server **out, int device, dil_keyset *const *ta
       if (!s->ks[li]) continue;
       ok = hipStreamCreateWithFlags(&ln.gst[gi], hipStreamNonBlocking) == hipSuccess &&
            hipEventCreateWithFlags(&ln.gev[gi], hipEventDisableTiming) == hipSuccess &&
-           dil_ctx_create(&ln.gctx[gi], device, 0) == DIL_OK && dil_ctx_set_mode(ln.gctx[gi], mode) == DIL_OK &&
+           dil_ctx_create(&ln.gctx[gi], device, 0) == DIL_OK && dil_ctx_set_mode(ln.gctx[gi], ctx_mode) == DIL_OK &&
            // a group call holds few tasks: four-wavefront workgroups give each
            // task 4 x 64 / l nonces per batch, so almost every task passes in
            // the first batch instead of needing a second or third
-           (gi % 2 == 1 || dil_ctx_set_param(ln.gctx[gi], "persist.waves", 4) == DIL_OK);
+           (gi % 2 == 1 || dil_ctx_set_param(ln.gctx[gi], "persist.waves", 4) == DIL_OK) &&
+           // ML-DSA groups on formatted messages M' when asked (round-3 calls have no such form)
+           (!mldsa_internal || kLevels[li] < 44 || dil_ctx_set_param(ln.gctx[gi], "mldsa.internal", 1) == DIL_OK);
     }
     ok = ok && hipHostMalloc((void **)&ln.h_msg, max_msg_bytes, hipHostMallocDefault) == hipSuccess &&
          hipHostMalloc((void **)&ln.h_sig, max_batch * max_sig, hipHostMallocDefault) == hipSuccess &&

@@ -38,6 +38,7 @@ from . import dilithium as dl
 
 SIGN, VERIFY = 0, 1
 LEVELS = (2, 3, 5)
+DIL_SERVER_MLDSA_INTERNAL = 0x100   # mode flag of the native engine (include/dil.h)
 
 
 @dataclass
@@ -470,7 +471,10 @@ class NativeServer:
     arrival times (`serve`)."""
 
     def __init__(self, keysets: Dict[int, "dl.KeySet"], n_streams: int = 4, max_batch: int = 4096,
-                 mem_budget: int = 2 << 30, max_msg_bytes: int = 64 << 20, persistent: bool = True):
+                 mem_budget: int = 2 << 30, max_msg_bytes: int = 64 << 20, persistent: bool = True,
+                 mldsa_internal: bool = False):
+        """mldsa_internal: requests at the ML-DSA levels carry formatted messages M' (context
+        strings, pre-hashed messages); round-3 requests are unaffected."""
         import ctypes
         self.lib = dl.load()
         self.keysets = keysets
@@ -478,7 +482,8 @@ class NativeServer:
         tables = (ctypes.c_void_p * max(len(keysets), 1))(*[keysets[lv].h.value for lv in sorted(keysets)])
         rc = self.lib.dil_server_create_tables(ctypes.byref(h), 0, ctypes.cast(tables, ctypes.c_void_p), len(keysets),
                                                n_streams, max_batch, max_msg_bytes, mem_budget,
-                                               dl.MODE_PERSISTENT if persistent else dl.MODE_STAGED)
+                                               (dl.MODE_PERSISTENT if persistent else dl.MODE_STAGED) |
+                                               (DIL_SERVER_MLDSA_INTERNAL if mldsa_internal else 0))
         if rc:
             raise dl.DilError(rc, "server creation failed")
         self.h = h
@@ -538,10 +543,11 @@ class NativeService:
     (True / False) of a Verify request; it is handed out once."""
 
     def __init__(self, keysets: Dict[int, "dl.KeySet"], n_streams: int = 4, max_batch: int = 4096,
-                 mem_budget: int = 2 << 30, max_msg_bytes: int = 64 << 20, persistent: bool = True):
+                 mem_budget: int = 2 << 30, max_msg_bytes: int = 64 << 20, persistent: bool = True,
+                 mldsa_internal: bool = False):
         import ctypes
         self.server = NativeServer(keysets, n_streams=n_streams, max_batch=max_batch, mem_budget=mem_budget,
-                                   max_msg_bytes=max_msg_bytes, persistent=persistent)
+                                   max_msg_bytes=max_msg_bytes, persistent=persistent, mldsa_internal=mldsa_internal)
         self.lib = self.server.lib
         self._c = ctypes
         self.n_keys = {lv: ks.n_keys for lv, ks in keysets.items()}

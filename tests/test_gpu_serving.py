@@ -351,3 +351,62 @@ def test_large_batches_match_oracle(setup, engine):
     server.close()
     assert res.batches <= 3
     _check_against_oracle(sv, host, big, big_flipped, res)
+
+
+def test_native_engine_mldsa_internal_mode():
+    """DIL_SERVER_MLDSA_INTERNAL: the native engine's ML-DSA groups take formatted messages M'
+    (context strings here) while round-3 requests stay plain: every signature and verdict equals
+    the oracle's internal (ML-DSA) or plain (level 2) output.  Unknown mode bits are refused."""
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import ctypes
+    from paper_2211_12265_amd import dilithium as dl
+    from paper_2211_12265_amd import serving as sv
+    ctx = dl.Context(0, mode=dl.MODE_PERSISTENT)
+    keys = {2: 5, 65: 4, 87: 3}
+    keysets, host = {}, {}
+    for lv, nk in keys.items():
+        pk, sk = oracle.keygen_batch(lv, workload.keygen_seeds(nk, seed=360 + lv))
+        host[lv] = (pk, sk)
+        keysets[lv] = dl.KeySet(ctx, lv, pk=torch.from_numpy(pk).cuda(), sk=torch.from_numpy(sk).cuda())
+    lib = dl.load()
+    h = ctypes.c_void_p()
+    tables = (ctypes.c_void_p * 3)(*[keysets[lv].h.value for lv in sorted(keysets)])
+    assert lib.dil_server_create_tables(ctypes.byref(h), 0, ctypes.cast(tables, ctypes.c_void_p), 3, 2, 64,
+                                        1 << 20, 2 << 30, dl.MODE_PERSISTENT | 0x200) == dl.DIL_EINVAL
+    rng = np.random.default_rng(41)
+    n = 90
+    level = rng.choice([2, 65, 87], size=n)
+    op = (rng.random(n) < 0.5).astype(int)
+    key = np.array([rng.integers(0, keys[int(lv)]) for lv in level])
+    reqs, expect = [], []
+    for i in range(n):
+        lv = int(level[i])
+        pk, sk = host[lv]
+        m = workload.random_bytes("test/serve-internal", i, (int(rng.integers(0, 300)),)).tobytes()
+        if lv != 2:
+            m = oracle.mldsa_format(m, b"ctx-%d" % (i % 7))
+            s = oracle.mldsa_sign_internal(lv, sk[key[i]].tobytes(), m)
+        else:
+            s = oracle.sign(lv, sk[key[i]].tobytes(), m)[0]
+        if op[i] == sv.SIGN:
+            reqs.append((lv, sv.SIGN, int(key[i]), m, None))
+            expect.append(s)
+        else:
+            if i % 3 == 0:
+                b = bytearray(s)
+                b[i % len(b)] ^= 4
+                s = bytes(b)
+            reqs.append((lv, sv.VERIFY, int(key[i]), m, s))
+            ok = oracle.mldsa_verify_internal(lv, pk[key[i]].tobytes(), m, s) if lv != 2 else \
+                oracle.verify(lv, pk[key[i]].tobytes(), m, s)
+            expect.append(bool(ok == 1))
+    svc = sv.NativeService(keysets, n_streams=2, max_batch=32, mem_budget=2 << 30, max_msg_bytes=1 << 20,
+                           mldsa_internal=True)
+    tickets = [svc.submit(*r) for r in reqs]
+    got = [svc.wait(t, timeout=120) for t in tickets]
+    svc.close()
+    assert got == expect
+    for ks in keysets.values():
+        ks.close()
+    ctx.close()
